@@ -1,0 +1,248 @@
+"""Pins of the oracle's gradients, preconditioner and optimizer (no GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+
+def _loss_fixed_w(p, data, cfg, w, ref):
+    """Loss with the confidence weights frozen (stop-gradient of Sec. 3.5);
+    also returns whether the NN assignments equal the reference ones."""
+    fw = O.forward(p, data, cfg)
+    P = np.asarray(data["pts"], np.float64)
+    off = data["frame_off"]
+    T = len(off) - 1
+    tot, same = 0.0, True
+    for t in range(T):
+        a, b, _, _, cd = O.chamfer(fw["xhat"][t], P[off[t]:off[t + 1]])
+        same &= np.array_equal(a, ref["a"][t]) and np.array_equal(b, ref["b"][t])
+        tot += w[t] * cd
+    return tot / T, same
+
+
+def _perturb(p, flat_delta):
+    out = O.zeros_like_params(p)
+    i = 0
+    for l, g in enumerate(p["grid_p"]):
+        out["grid_p"][l] = g + flat_delta[i:i + g.size].reshape(g.shape)
+        i += g.size
+    out["grid_n"] = p["grid_n"] + flat_delta[i:i + p["grid_n"].size].reshape(p["grid_n"].shape)
+    i += p["grid_n"].size
+    mlp = []
+    for W, b in p["mlp"]:
+        W2 = W + flat_delta[i:i + W.size].reshape(W.shape)
+        i += W.size
+        b2 = b + flat_delta[i:i + b.size]
+        i += b.size
+        mlp.append((W2, b2))
+    out["mlp"] = mlp
+    return out
+
+
+@pytest.mark.parametrize("act,M", [("leaky", 2), ("relu", 0)])
+def test_full_loss_gradient_matches_central_differences(act, M):
+    cfg = synth.config_small(act=act, time_freqs=M, N=[50, 41, 47])
+    data = synth.make_workload(cfg)
+    p = O.to64(synth.random_state(cfg, 3))
+    fw = O.forward(p, data, cfg)
+    ls = O.losses(fw, data, cfg, 1, 3)
+    grads, _ = O.backward(p, data, cfg, fw, ls)
+    g = O.flatten_params(grads)
+    n = g.size
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    # every coordinate of a random subset covering all blocks
+    idx = np.unique(np.concatenate([rng.choice(n, 150, replace=False),
+                                    np.flatnonzero(np.abs(g) > 1e-8)[::7][:150]]))
+    checked = 0
+    for k in idx:
+        e = np.zeros(n)
+        e[k] = h
+        fp, s1 = _loss_fixed_w(_perturb(p, e), data, cfg, ls["w"], ls)
+        fm, s2 = _loss_fixed_w(_perturb(p, -e), data, cfg, ls["w"], ls)
+        if not (s1 and s2):
+            continue
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 2e-9, (k, fd, g[k])
+        checked += 1
+    assert checked > 0.9 * len(idx)
+    # directional derivative along a random direction
+    d = rng.normal(size=n)
+    d /= np.linalg.norm(d)
+    fp, s1 = _loss_fixed_w(_perturb(p, h * d), data, cfg, ls["w"], ls)
+    fm, s2 = _loss_fixed_w(_perturb(p, -h * d), data, cfg, ls["w"], ls)
+    assert s1 and s2
+    assert abs((fp - fm) / (2 * h) - g @ d) < 1e-7 * max(1, abs(g @ d))
+
+
+def test_full_loss_gradient_matches_torch_autograd():
+    # Independent derivative: the same forward written in torch float64 and
+    # differentiated by autograd, with assignments and weights taken from the
+    # oracle's forward.
+    cfg = synth.config_small()
+    data = synth.make_workload(cfg)
+    p = O.to64(synth.random_state(cfg, 4))
+    fw = O.forward(p, data, cfg)
+    ls = O.losses(fw, data, cfg, 0, 3)
+    grads, _ = O.backward(p, data, cfg, fw, ls)
+
+    X = torch.tensor(data["xyz"], dtype=torch.float64)
+    Nr = torch.tensor(data["nrm"], dtype=torch.float64)
+    P = torch.tensor(data["pts"], dtype=torch.float64)
+    off = data["frame_off"]
+    T, V = len(off) - 1, len(X)
+    gp = [torch.tensor(g, requires_grad=True) for g in p["grid_p"]]
+    gn = torch.tensor(p["grid_n"], requires_grad=True)
+    mlp = [(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True)) for W, b in p["mlp"]]
+
+    def tri(G, R, Q):
+        u = (Q.clamp(-1, 1) + 1) * 0.5 * (R - 1)
+        i0 = torch.clamp(torch.floor(u), max=R - 2)
+        f = u - i0
+        i0 = i0.long()
+        out = 0
+        for cz in (0, 1):
+            for cy in (0, 1):
+                for cx in (0, 1):
+                    w = ((f[:, 0] if cx else 1 - f[:, 0]) * (f[:, 1] if cy else 1 - f[:, 1])
+                         * (f[:, 2] if cz else 1 - f[:, 2]))
+                    node = ((i0[:, 2] + cz) * R + i0[:, 1] + cy) * R + i0[:, 0] + cx
+                    out = out + w[:, None] * G[node]
+        return out
+
+    zp = sum(tri(G, R, X) for G, R in zip(gp, cfg["levels"])) / len(gp)
+    zn = tri(gn, cfg["res_n"], Nr)
+    z = torch.cat([zn, zp], 1)
+    gam = torch.tensor(O.time_code(T, cfg["time_freqs"]))
+    Y = torch.cat([z.repeat(T, 1), gam.repeat_interleave(V, 0)], 1)
+    h = Y
+    for k, (W, b) in enumerate(mlp):
+        h = h @ W.T + b
+        if k < len(mlp) - 1:
+            h = torch.nn.functional.leaky_relu(h, 0.01)
+    w_, d_ = h[:, :3], h[:, 3:]
+    th = w_.norm(dim=1, keepdim=True)
+    k_ = w_ / th
+    Xt = X.repeat(T, 1)
+    # Rodrigues in axis-angle form (theta is far from 0 at this random state)
+    rot = (Xt * torch.cos(th) + torch.cross(k_, Xt, dim=1) * torch.sin(th)
+           + k_ * (k_ * Xt).sum(1, keepdim=True) * (1 - torch.cos(th)))
+    xh = (rot + torch.tanh(cfg["alpha_t"] * d_)).reshape(T, V, 3)
+    loss = 0
+    for t in range(T):
+        Pt = P[off[t]:off[t + 1]]
+        a = torch.from_numpy(ls["a"][t])
+        b = torch.from_numpy(ls["b"][t])
+        cd = ((xh[t] - Pt[a]) ** 2).sum(1).mean() + ((xh[t][b] - Pt) ** 2).sum(1).mean()
+        loss = loss + float(ls["w"][t]) * cd
+    loss = loss / T
+    assert abs(loss.item() - ls["loss"]) < 1e-13
+    loss.backward()
+    for G, g in zip(gp, grads["grid_p"]):
+        np.testing.assert_allclose(G.grad.numpy(), g, rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(gn.grad.numpy(), grads["grid_n"], rtol=1e-9, atol=1e-13)
+    for (W, b), (gW, gb) in zip(mlp, grads["mlp"]):
+        np.testing.assert_allclose(W.grad.numpy(), gW, rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(b.grad.numpy(), gb, rtol=1e-9, atol=1e-13)
+
+
+def test_first_step_grid_gradients_are_exactly_zero_at_paper_init():
+    # Sec. 3.1: zero grids and a zero last layer -> only the last layer gets a
+    # gradient on the first step.
+    cfg = synth.config_c1()
+    data = synth.make_workload(cfg)
+    p = O.to64(synth.init_params(cfg))
+    fw = O.forward(p, data, cfg)
+    ls = O.losses(fw, data, cfg, 0, cfg["n_steps"])
+    grads, _ = O.backward(p, data, cfg, fw, ls)
+    for g in grads["grid_p"] + [grads["grid_n"]]:
+        assert not g.any()
+    for gW, gb in grads["mlp"][:-1]:
+        assert not gW.any() and not gb.any()
+    assert np.abs(grads["mlp"][-1][0]).max() > 0
+
+
+def _dense_laplacian(R):
+    # explicit edge loop over the 6-neighbour lattice (free boundary)
+    n = R ** 3
+    Lm = np.zeros((n, n))
+    for iz in range(R):
+        for iy in range(R):
+            for ix in range(R):
+                a = (iz * R + iy) * R + ix
+                for dz, dy, dx in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+                    jz, jy, jx = iz + dz, iy + dy, ix + dx
+                    if jz < R and jy < R and jx < R:
+                        b = (jz * R + jy) * R + jx
+                        Lm[a, a] += 1
+                        Lm[b, b] += 1
+                        Lm[a, b] -= 1
+                        Lm[b, a] -= 1
+    return Lm
+
+
+@pytest.mark.parametrize("R,lam", [(2, 0.4), (3, 1.7), (5, 0.6), (6, 6.83)])
+def test_preconditioner_matches_dense_solve(R, lam):
+    rng = np.random.default_rng(R)
+    g = rng.normal(size=(R ** 3, 3))
+    A = np.eye(R ** 3) + lam * _dense_laplacian(R)
+    ref = np.linalg.solve(A, np.linalg.solve(A, g))
+    np.testing.assert_allclose(O.precond_dct(g, R, lam), ref, atol=1e-13)
+    x, _ = O.precond_cg(g, R, lam)
+    np.testing.assert_allclose(x, ref, atol=1e-11)
+    np.testing.assert_allclose(O.laplacian_apply(g, R), _dense_laplacian(R) @ g, atol=1e-13)
+
+
+def test_preconditioner_invariants():
+    R, lam = 7, 2.5
+    rng = np.random.default_rng(11)
+    a = rng.normal(size=(R ** 3, 2))
+    b = rng.normal(size=(R ** 3, 2))
+    Pf = lambda g, l=lam: O.precond_dct(g, R, l)
+    np.testing.assert_allclose(Pf(a, 0.0), a, atol=1e-14)                       # lambda=0: identity
+    np.testing.assert_allclose(Pf(2 * a - 3 * b), 2 * Pf(a) - 3 * Pf(b), atol=1e-13)  # linear
+    assert abs((Pf(a) * b).sum() - (a * Pf(b)).sum()) < 1e-12                   # symmetric
+    np.testing.assert_allclose(Pf(np.ones((R ** 3, 1))), 1.0, atol=1e-13)        # L 1 = 0
+    # a single DCT mode is scaled by (1 + lam mu_k)^-2
+    k = (2, 5, 1)        # (kz, ky, kx)
+    n = np.arange(R)
+    vz, vy, vx = (np.cos(np.pi * kk * (n + 0.5) / R) for kk in k)
+    mode = (vz[:, None, None] * vy[None, :, None] * vx[None, None, :]).reshape(-1, 1)
+    mu = sum(2 - 2 * np.cos(np.pi * kk / R) for kk in k)
+    np.testing.assert_allclose(Pf(mode), mode / (1 + lam * mu) ** 2, atol=1e-13)
+    # zero in, zero out (CG path included)
+    assert not O.precond_cg(np.zeros((R ** 3, 2)), R, lam)[0].any()
+
+
+def test_adam_first_step_and_torch():
+    rng = np.random.default_rng(12)
+    th = rng.normal(size=20)
+    g = rng.normal(size=20)
+    new, m, v = O.adam(th, g, np.zeros(20), np.zeros(20), 1, 0.01, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(new, th - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    # several steps against torch.optim.Adam in float64
+    x = torch.tensor(th, requires_grad=True)
+    opt = torch.optim.Adam([x], lr=0.003)
+    cur, m, v = th.copy(), np.zeros(20), np.zeros(20)
+    for k in range(1, 6):
+        gk = rng.normal(size=20)
+        x.grad = torch.tensor(gk)
+        opt.step()
+        cur, m, v = O.adam(cur, gk, m, v, k, 0.003, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(cur, x.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_step_reduces_loss_on_sphere():
+    # Oracle steps from the paper's identity start (Sec. 3.1) lower the mean
+    # Chamfer distance on the icosphere workload at every step.
+    cfg = synth.config_c1()
+    data = synth.make_workload(cfg)
+    p = O.to64(synth.init_params(cfg))
+    m, v = O.zeros_like_params(p), O.zeros_like_params(p)
+    losses = []
+    for e in range(5):
+        p, m, v, d = O.step(p, m, v, e + 1, data, cfg, e, cfg["n_steps"])
+        losses.append(float(np.mean(d["ls"]["cd"])))
+    assert np.all(np.diff(losses) < 0)
