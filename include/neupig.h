@@ -1,0 +1,243 @@
+/*
+ * neupig.h -- C ABI of the MI355X (gfx950) Neu-PiG optimization-step library.
+ *
+ * The library runs one full optimization step of Neu-PiG (Kaltheuner et al.,
+ * "Neu-PiG: Neural Preconditioned Grids for Fast Dynamic Surface
+ * Reconstruction on Long Sequences", arXiv 2602.22212) over all frames at
+ * once, on one GPU:
+ *   encode   multi-resolution latent-grid lookup at the reference vertices
+ *            (Sec. 3.2, level-averaged position grid + normal-direction grid)
+ *   decode   time-modulated MLP to a per-frame 6-DoF deformation, applied to
+ *            every vertex (Sec. 3.3, 3.4; exponential-map rotation head of the
+ *            supplementary rotation study, Table 11)
+ *   chamfer  bidirectional nearest-neighbour Chamfer distance per frame and
+ *            the confidence-weighted deformation loss (Sec. 3.5)
+ *   backward hand-written gradients of all of the above
+ *   precond  Sobolev preconditioning (I + lambda L)^-2 of the grid gradients
+ *            (Sec. 3.5, "Preconditioning")
+ *   adam     Adam update (Sec. 3.5, "Implementation Details")
+ *
+ * Problem statement (Sec. 3): a reference mesh (vertex positions and vertex
+ * normals at a key frame) and T unstructured point clouds go in; per-frame
+ * deformed vertices come out.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer named *_dev is device memory on the plan's GPU; the caller
+ *    owns it and must keep it alive until the work enqueued on the plan's
+ *    stream has finished. Pointers named *_host are host memory.
+ *  - Calls enqueue work on the stream given at plan creation and return
+ *    without waiting, unless documented as synchronizing.
+ *  - Floating-point inputs and outputs are float32 unless stated; per-frame
+ *    loss values are float64. Indices are int32 (V, N_t < 2^31), frame
+ *    offsets int64.
+ *  - A non-OK status leaves outputs untouched when the failure is found by
+ *    host-side validation (done before any launch). npg_last_error() returns
+ *    a message for the calling thread's last failure.
+ *  - Frames are 0-based: t = 0..T-1.
+ *
+ * Flat parameter vector (float32, length npg_param_count):
+ *   [ G_p level 0 | ... | G_p level L-1 | G_n | W_1 b_1 | ... | W_H+1 b_H+1 ]
+ *   level l:  R_l^3 nodes x F_p features, node (ix,iy,iz) at row
+ *             (iz*R_l + iy)*R_l + ix, features innermost; the grid spans
+ *             [-1,1]^3 with corner nodes on +-1; ix follows the first
+ *             coordinate.
+ *   G_n:      R_n^3 x F_n, same node order, looked up at the unit normal.
+ *   W_k:      [out][in] row-major, then b_k [out]. Layer 1 maps the decoder
+ *             input y = (z_n, z_p, gamma(t)) (Sec. 3.3, in this order) of
+ *             width F_n + F_p + (2M or 1) to the hidden width; H hidden
+ *             layers; the last layer maps to 6 outputs (omega, d).
+ * The same layout is used for gradients and the two Adam moment vectors.
+ */
+#ifndef NEUPIG_H
+#define NEUPIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NPG_MAX_LEVELS 16
+
+typedef enum {
+  NPG_OK = 0,
+  NPG_EINVAL = 1,      /* invalid argument (null pointer, bad size, non-finite input) */
+  NPG_ENOMEM = 2,      /* device allocation failed */
+  NPG_EHIP = 3,        /* a HIP runtime call failed */
+  NPG_ENOTCONV = 4,    /* warning: a preconditioner solve hit cg_maxit */
+  NPG_ENONFINITE = 5   /* a non-finite value was produced during a step */
+} npg_status;
+
+enum { NPG_ACT_RELU = 0, NPG_ACT_LEAKY = 1 };
+enum { NPG_PRECOND_CG = 0, NPG_PRECOND_DCT = 1 };
+
+/* Hyper-parameters. Every reading the paper leaves open is a field here. */
+typedef struct npg_config {
+  int32_t n_levels;               /* L, position-grid levels, 1..16 (Sec. 3.2)     */
+  int32_t res[NPG_MAX_LEVELS];    /* nodes per axis of each level, >= 2            */
+  int32_t feat_p;                 /* F_p, features per position-grid node, 1..4    */
+  int32_t res_n;                  /* R_n, normal grid nodes per axis (paper: 4)    */
+  int32_t feat_n;                 /* F_n, normal grid features (paper: 2), 1..4    */
+  int32_t time_freqs;             /* M Fourier frequencies (Sec. 3.3; paper: 4);   */
+                                  /* 0 selects the scalar code t/(T-1)             */
+  int32_t mlp_hidden;             /* H hidden layers, 1..3                          */
+  int32_t mlp_width;              /* hidden width: 32, 64 or 128                    */
+  int32_t act;                    /* NPG_ACT_RELU or NPG_ACT_LEAKY                  */
+  float leaky_slope;              /* negative slope of LeakyReLU (0.01)             */
+  float alpha_t;                  /* displacement squashing tanh(alpha d), 0.1      */
+  float lr_mlp;                   /* Adam learning rate of the MLP (1e-3)           */
+  float lr_grid[NPG_MAX_LEVELS];  /* per-level grid learning rates                  */
+  float lr_n;                     /* normal-grid learning rate                      */
+  float lam[NPG_MAX_LEVELS];      /* per-level smoothness lambda of (I+lambda L)^-2 */
+  float lam_n;                    /* normal-grid smoothness lambda                  */
+  float beta1, beta2, eps;        /* Adam constants (0.9, 0.999, 1e-8)              */
+  int32_t conf_weight;            /* 1: confidence weight of Sec. 3.5, 0: w = 1     */
+  int32_t t_key;                  /* key frame, 0-based; -1 selects (T-1)/2         */
+  double cg_rtol;                 /* relative residual stop of each CG solve        */
+  int32_t cg_maxit;               /* iteration cap of each CG solve                 */
+  int32_t precond;                /* NPG_PRECOND_CG (iterative) or _DCT (exact)     */
+} npg_config;
+
+typedef struct npg_plan npg_plan;
+
+/* Message describing the calling thread's last non-OK status. */
+const char* npg_last_error(void);
+
+/* Number of floats in the flat parameter vector of a config (host only). */
+npg_status npg_param_count(const npg_config* cfg, int64_t* count_host);
+
+/*
+ * Create a plan for one sequence (Sec. 3 problem statement).
+ *   ref_xyz_dev  [V][3]  reference-mesh vertex positions, inside [-1,1]^3
+ *                        (coordinates outside are clamped by the grid lookup)
+ *   ref_nrm_dev  [V][3]  unit vertex normals
+ *   pts_dev      [sum N_t][3] all frames' points, frame after frame
+ *   frame_off_host [T+1] int64 offsets of each frame into pts, off[0] = 0,
+ *                        strictly increasing (every frame has >= 1 point)
+ *   stream       hipStream_t (as void*) all work of this plan is enqueued on
+ * Copies the inputs (they may be freed after return), validates them (finite
+ * values, sizes), builds the static interpolation and scatter tables, and
+ * allocates all workspace. Parameters start at zero and Adam at step 0.
+ * Synchronizes the stream. Errors: NPG_EINVAL, NPG_ENOMEM, NPG_EHIP.
+ */
+npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* ref_xyz_dev,
+                           const float* ref_nrm_dev, int32_t T, const float* pts_dev,
+                           const int64_t* frame_off_host, void* stream, npg_plan** out);
+
+/* Free every allocation of the plan. Synchronizes the stream. */
+npg_status npg_plan_destroy(npg_plan* plan);
+
+/*
+ * Load the optimizer state: params [P], Adam first/second moments m, v [P]
+ * (either may be NULL: zero) and the count of Adam steps already taken.
+ * Synchronizes.
+ */
+npg_status npg_set_state(npg_plan* plan, const float* params_dev, const float* m_dev,
+                         const float* v_dev, int64_t adam_steps);
+
+/* Copy the optimizer state out (any pointer may be NULL). Synchronizes. */
+npg_status npg_get_state(npg_plan* plan, float* params_dev, float* m_dev, float* v_dev,
+                         int64_t* adam_steps_host);
+
+/*
+ * One full optimization step on the plan's own state (all stages below in
+ * order, then the Adam update with step count adam_steps + 1).
+ *   epoch, n_epochs  0-based epoch e and e_max of the confidence catch-up
+ *                    delta = 1 - sqrt(e / e_max) (Sec. 3.5)
+ *   loss_dev   [1] float64 (may be NULL): L_def of this step's forward pass
+ *   cd_dev     [T] float64 (may be NULL): per-frame Chamfer distances
+ * Returns NPG_ENOTCONV (after completing the step) if a CG solve hit its cap.
+ * With the CG preconditioner the call synchronizes every 16 iterations to test
+ * convergence.
+ */
+npg_status npg_step(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* loss_dev,
+                    double* cd_dev);
+
+/* Deformed vertices of every frame with the plan's parameters, [T][V][3]. */
+npg_status npg_deform(npg_plan* plan, float* xhat_dev);
+
+/* ---- stage entry points (stateless with respect to parameters) ---------- */
+
+/* Sec. 3.2. z_dev [V][F_n+F_p] = (z_n(n_i), (1/L) sum_l z_p^l(x_i)). */
+npg_status npg_encode_fwd(npg_plan* plan, const float* params_dev, float* z_dev);
+
+/*
+ * Sec. 3.3-3.4. For every frame t and vertex i: y = (z_i, gamma(t)),
+ * o = MLP(y), x^ = Exp(o[0:3]) x_i + tanh(alpha o[3:6]).
+ *   xhat_dev [T][V][4] (fourth component written as 0).
+ */
+npg_status npg_decode_fwd(npg_plan* plan, const float* params_dev, const float* z_dev,
+                          float* xhat_dev);
+
+/*
+ * Sec. 3.5. Per frame: a_i = argmin_j |x^_i - p_j|^2 and b_j = argmin_i, with
+ * the lowest index on exact ties (distances in float32, direct form
+ * (x-p).(x-p) with a fixed operation order), and
+ * cd_t = mean_i da_i + mean_j db_j summed in float64.
+ *   a_dev [T][V] int32 (index within frame t), da_dev [T][V] float32,
+ *   b_dev [sum N_t] int32 (vertex index), db_dev [sum N_t] float32,
+ *   cd_dev [T] float64.
+ */
+npg_status npg_chamfer_fwd(npg_plan* plan, const float* xhat_dev, int32_t* a_dev,
+                           float* da_dev, int32_t* b_dev, float* db_dev, double* cd_dev);
+
+/*
+ * Sec. 3.5. Confidence weights w_t (product of omega(tau)^delta between the
+ * key frame and t) and L_def = (1/T) sum_t w_t cd_t, all float64 on device.
+ *   w_dev [T], loss_dev [1].
+ */
+npg_status npg_loss(npg_plan* plan, const double* cd_dev, int32_t epoch, int32_t n_epochs,
+                    double* w_dev, double* loss_dev);
+
+/*
+ * Gradient of L_def w.r.t. x^ with assignments and weights held fixed:
+ * gx_i,t = (w_t/T)[(2/V)(x^_i - p_a_i) + (2/N_t) sum_{j: b_j = i}(x^_i - p_j)].
+ *   gxhat_dev [T][V][4] (fourth component 0).
+ */
+npg_status npg_chamfer_bwd(npg_plan* plan, const float* xhat_dev, const int32_t* a_dev,
+                           const int32_t* b_dev, const double* w_dev, float* gxhat_dev);
+
+/*
+ * Backward of decode: recomputes the MLP forward per tile (activations are
+ * never stored), back-propagates gxhat through the transform and the MLP.
+ *   grad_dev [P]: the MLP block of the flat gradient is overwritten (grid
+ *                 blocks untouched); gz_dev [V][F_n+F_p] = sum over frames of
+ *                 the decoder-input gradient's z part.
+ */
+npg_status npg_decode_bwd(npg_plan* plan, const float* params_dev, const float* z_dev,
+                          const float* gxhat_dev, float* grad_dev, float* gz_dev);
+
+/*
+ * Backward of encode: grid blocks of grad_dev [P] are overwritten with the
+ * dense gradient (zero at nodes no vertex touches); deterministic segmented
+ * reduction over a node-sorted table, no atomics.
+ */
+npg_status npg_encode_bwd(npg_plan* plan, const float* gz_dev, float* grad_dev);
+
+/*
+ * Sec. 3.5 "Preconditioning": every grid block of grad_dev [P] is replaced
+ * in place by (I + lambda L)^-2 g per feature channel, L the 6-neighbour
+ * lattice Laplacian with free boundary (degree minus adjacency). MLP block
+ * untouched. With NPG_PRECOND_CG: two conjugate-gradient solves from zero
+ * with float64 inner products, synchronizing every 16 iterations;
+ * iters_host [2*(L+1)] (may be NULL) receives the iteration counts.
+ */
+npg_status npg_precond(npg_plan* plan, float* grad_dev, int32_t* iters_host);
+
+/*
+ * Adam (bias-corrected, step count adam_step >= 1) over the flat vector with
+ * per-block learning rates (levels, normal grid, MLP).
+ */
+npg_status npg_adam(npg_plan* plan, float* params_dev, const float* grad_dev, float* m_dev,
+                    float* v_dev, int64_t adam_step);
+
+/* Kernel time of the last npg_step per stage in milliseconds (host, [8]):
+ * encode, decode, chamfer+loss, chamfer_bwd, decode_bwd, encode_bwd,
+ * precond, adam. Valid after the stream has finished the step. */
+npg_status npg_stage_times(npg_plan* plan, float* ms_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEUPIG_H */

@@ -1,0 +1,316 @@
+"""Python binding of libneupig.so (the MI355X Neu-PiG optimization-step library).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels. Tensors must be contiguous torch tensors on the plan's GPU; their
+device pointers and the current HIP stream are passed through the C ABI
+declared in include/neupig.h. If the library is missing this module fails
+loudly: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libneupig.so")
+
+NPG_MAX_LEVELS = 16
+NPG_OK, NPG_EINVAL, NPG_ENOMEM, NPG_EHIP, NPG_ENOTCONV, NPG_ENONFINITE = range(6)
+NPG_ACT_RELU, NPG_ACT_LEAKY = 0, 1
+NPG_PRECOND_CG, NPG_PRECOND_DCT = 0, 1
+STAGES = ("encode", "decode", "chamfer+loss", "chamfer_bwd", "decode_bwd", "encode_bwd", "precond", "adam")
+
+
+class NpgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"neupig status {status}: {msg}")
+        self.status = status
+
+
+class npg_config(ctypes.Structure):
+    _fields_ = [
+        ("n_levels", ctypes.c_int32), ("res", ctypes.c_int32 * NPG_MAX_LEVELS),
+        ("feat_p", ctypes.c_int32), ("res_n", ctypes.c_int32), ("feat_n", ctypes.c_int32),
+        ("time_freqs", ctypes.c_int32), ("mlp_hidden", ctypes.c_int32), ("mlp_width", ctypes.c_int32),
+        ("act", ctypes.c_int32), ("leaky_slope", ctypes.c_float), ("alpha_t", ctypes.c_float),
+        ("lr_mlp", ctypes.c_float), ("lr_grid", ctypes.c_float * NPG_MAX_LEVELS), ("lr_n", ctypes.c_float),
+        ("lam", ctypes.c_float * NPG_MAX_LEVELS), ("lam_n", ctypes.c_float),
+        ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+        ("conf_weight", ctypes.c_int32), ("t_key", ctypes.c_int32),
+        ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precond", ctypes.c_int32),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "npg_last_error": ([], ctypes.c_char_p),
+    "npg_param_count": ([ctypes.POINTER(npg_config), ctypes.POINTER(_I64)], ctypes.c_int),
+    "npg_plan_create": ([ctypes.POINTER(npg_config), _I64, _P, _P, _I32, _P, ctypes.POINTER(_I64), _P,
+                         ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_plan_destroy": ([_P], ctypes.c_int),
+    "npg_set_state": ([_P, _P, _P, _P, _I64], ctypes.c_int),
+    "npg_get_state": ([_P, _P, _P, _P, ctypes.POINTER(_I64)], ctypes.c_int),
+    "npg_step": ([_P, _I32, _I32, _P, _P], ctypes.c_int),
+    "npg_deform": ([_P, _P], ctypes.c_int),
+    "npg_encode_fwd": ([_P, _P, _P], ctypes.c_int),
+    "npg_decode_fwd": ([_P, _P, _P, _P], ctypes.c_int),
+    "npg_chamfer_fwd": ([_P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "npg_loss": ([_P, _P, _I32, _I32, _P, _P], ctypes.c_int),
+    "npg_chamfer_bwd": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "npg_decode_bwd": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "npg_encode_bwd": ([_P, _P, _P], ctypes.c_int),
+    "npg_precond": ([_P, _P, ctypes.POINTER(_I32)], ctypes.c_int),
+    "npg_adam": ([_P, _P, _P, _P, _P, _I64], ctypes.c_int),
+    "npg_stage_times": ([_P, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libneupig.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2602_22212_amd.build.build() "
+                               "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != NPG_OK:
+        raise NpgError(status, lib().npg_last_error().decode())
+    return status
+
+
+def make_config(cfg):
+    """Marshal a hyper-parameter dict (see synth.configs) into npg_config."""
+    c = npg_config()
+    levels = list(cfg["levels"])
+    c.n_levels = len(levels)
+    for l, r in enumerate(levels):
+        c.res[l] = int(r)
+        c.lr_grid[l] = float(cfg["lr_grid"][l])
+        c.lam[l] = float(cfg["lam"][l])
+    c.feat_p, c.res_n, c.feat_n = int(cfg["feat_p"]), int(cfg["res_n"]), int(cfg["feat_n"])
+    c.time_freqs = int(cfg["time_freqs"])
+    c.mlp_hidden, c.mlp_width = int(cfg["mlp_hidden"]), int(cfg["mlp_width"])
+    c.act = NPG_ACT_RELU if cfg["act"] == "relu" else NPG_ACT_LEAKY
+    c.leaky_slope, c.alpha_t = float(cfg["leaky_slope"]), float(cfg["alpha_t"])
+    c.lr_mlp, c.lr_n, c.lam_n = float(cfg["lr_mlp"]), float(cfg["lr_n"]), float(cfg["lam_n"])
+    c.beta1, c.beta2, c.eps = float(cfg["beta1"]), float(cfg["beta2"]), float(cfg["eps"])
+    c.conf_weight = int(cfg["conf_weight"])
+    c.t_key = -1 if cfg.get("t_key") is None else int(cfg["t_key"])
+    c.cg_rtol, c.cg_maxit = float(cfg["cg_rtol"]), int(cfg["cg_maxit"])
+    c.precond = NPG_PRECOND_DCT if cfg.get("precond", "cg") == "dct" else NPG_PRECOND_CG
+    return c
+
+
+def param_count(cfg):
+    n = _I64()
+    _check(lib().npg_param_count(ctypes.byref(make_config(cfg)), ctypes.byref(n)))
+    return n.value
+
+
+def param_layout(cfg):
+    """(name, offset, shape) of every block of the flat parameter vector
+    (layout stated in include/neupig.h)."""
+    out, off = [], 0
+    F, Fn, Rn = cfg["feat_p"], cfg["feat_n"], cfg["res_n"]
+    for l, R in enumerate(cfg["levels"]):
+        out.append((f"grid_p{l}", off, (R ** 3, F)))
+        off += R ** 3 * F
+    out.append(("grid_n", off, (Rn ** 3, Fn)))
+    off += Rn ** 3 * Fn
+    M = cfg["time_freqs"]
+    dims = [Fn + F + (2 * M if M > 0 else 1)] + [cfg["mlp_width"]] * cfg["mlp_hidden"] + [6]
+    for k in range(len(dims) - 1):
+        out.append((f"W{k}", off, (dims[k + 1], dims[k])))
+        off += dims[k + 1] * dims[k]
+        out.append((f"b{k}", off, (dims[k + 1],)))
+        off += dims[k + 1]
+    return out, off
+
+
+def pack_params(cfg, p):
+    """Structured parameters (grid_p list, grid_n, mlp [(W, b)]) -> flat float32."""
+    parts = [np.asarray(g, np.float32).ravel() for g in p["grid_p"]]
+    parts.append(np.asarray(p["grid_n"], np.float32).ravel())
+    for W, b in p["mlp"]:
+        parts += [np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()]
+    return np.concatenate(parts)
+
+
+def unpack_params(cfg, flat):
+    flat = np.asarray(flat)
+    lay, _ = param_layout(cfg)
+    d = {name: flat[o:o + int(np.prod(s))].reshape(s) for name, o, s in lay}
+    L = len(cfg["levels"])
+    H = cfg["mlp_hidden"]
+    return dict(grid_p=[d[f"grid_p{l}"] for l in range(L)], grid_n=d["grid_n"],
+                mlp=[(d[f"W{k}"], d[f"b{k}"]) for k in range(H + 1)])
+
+
+def _ptr(t, dtype=None, n=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One sequence's plan (npg_plan): static tables, optimizer state and
+    workspace live on the GPU; methods mirror the C entry points."""
+
+    def __init__(self, cfg, xyz, nrm, pts, frame_off, stream=None):
+        import torch
+        self.cfg = dict(cfg)
+        self._c = make_config(cfg)
+        self.V = int(xyz.shape[0])
+        self.T = int(len(frame_off) - 1)
+        off = np.ascontiguousarray(np.asarray(frame_off, dtype=np.int64))
+        self.frame_off = off
+        self.Ntot = int(off[-1])
+        self.n_params = param_count(cfg)
+        f32 = torch.float32
+        px = _ptr(xyz, f32, 3 * self.V, "xyz")
+        pn = _ptr(nrm, f32, 3 * self.V, "nrm")
+        pp = _ptr(pts, f32, 3 * self.Ntot, "pts")
+        self.device = xyz.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _P()
+        _check(lib().npg_plan_create(ctypes.byref(self._c), self.V, px, pn, self.T, pp,
+                                     off.ctypes.data_as(ctypes.POINTER(_I64)),
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.Fz = cfg["feat_n"] + cfg["feat_p"]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().npg_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state --------------------------------------------------------------
+    def set_state(self, params, m=None, v=None, adam_steps=0):
+        import torch
+        f = torch.float32
+        _check(lib().npg_set_state(self._h, _ptr(params, f, self.n_params, "params"),
+                                   _ptr(m, f, self.n_params, "m"), _ptr(v, f, self.n_params, "v"),
+                                   int(adam_steps)))
+
+    def get_state(self):
+        import torch
+        p = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        m, v = torch.empty_like(p), torch.empty_like(p)
+        k = _I64()
+        _check(lib().npg_get_state(self._h, _ptr(p), _ptr(m), _ptr(v), ctypes.byref(k)))
+        return p, m, v, k.value
+
+    def step(self, epoch, n_epochs, loss=None, cd=None):
+        import torch
+        st = lib().npg_step(self._h, int(epoch), int(n_epochs), _ptr(loss, torch.float64, 1, "loss"),
+                            _ptr(cd, torch.float64, self.T, "cd"))
+        if st == NPG_ENOTCONV:
+            return st
+        return _check(st)
+
+    def deform(self, out):
+        import torch
+        _check(lib().npg_deform(self._h, _ptr(out, torch.float32, 3 * self.T * self.V, "out")))
+
+    def stage_times(self):
+        buf = (ctypes.c_float * 8)()
+        _check(lib().npg_stage_times(self._h, buf))
+        return dict(zip(STAGES, list(buf)))
+
+    # -- stages ---------------------------------------------------------------
+    def encode_fwd(self, params, z):
+        import torch
+        f = torch.float32
+        _check(lib().npg_encode_fwd(self._h, _ptr(params, f, self.n_params, "params"),
+                                    _ptr(z, f, self.V * self.Fz, "z")))
+
+    def decode_fwd(self, params, z, xhat):
+        import torch
+        f = torch.float32
+        _check(lib().npg_decode_fwd(self._h, _ptr(params, f, self.n_params, "params"),
+                                    _ptr(z, f, self.V * self.Fz, "z"), _ptr(xhat, f, 4 * self.T * self.V, "xhat")))
+
+    def chamfer_fwd(self, xhat, a, da, b, db, cd):
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_chamfer_fwd(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
+                                     _ptr(a, torch.int32, TV, "a"), _ptr(da, torch.float32, TV, "da"),
+                                     _ptr(b, torch.int32, self.Ntot, "b"), _ptr(db, torch.float32, self.Ntot, "db"),
+                                     _ptr(cd, torch.float64, self.T, "cd")))
+
+    def loss(self, cd, epoch, n_epochs, w, loss):
+        import torch
+        d = torch.float64
+        _check(lib().npg_loss(self._h, _ptr(cd, d, self.T, "cd"), int(epoch), int(n_epochs),
+                              _ptr(w, d, self.T, "w"), _ptr(loss, d, 1, "loss")))
+
+    def chamfer_bwd(self, xhat, a, b, w, gxhat):
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_chamfer_bwd(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
+                                     _ptr(a, torch.int32, TV, "a"), _ptr(b, torch.int32, self.Ntot, "b"),
+                                     _ptr(w, torch.float64, self.T, "w"), _ptr(gxhat, torch.float32, 4 * TV, "gxhat")))
+
+    def decode_bwd(self, params, z, gxhat, grad, gz):
+        import torch
+        f = torch.float32
+        _check(lib().npg_decode_bwd(self._h, _ptr(params, f, self.n_params, "params"),
+                                    _ptr(z, f, self.V * self.Fz, "z"),
+                                    _ptr(gxhat, f, 4 * self.T * self.V, "gxhat"),
+                                    _ptr(grad, f, self.n_params, "grad"), _ptr(gz, f, self.V * self.Fz, "gz")))
+
+    def encode_bwd(self, gz, grad):
+        import torch
+        f = torch.float32
+        _check(lib().npg_encode_bwd(self._h, _ptr(gz, f, self.V * self.Fz, "gz"),
+                                    _ptr(grad, f, self.n_params, "grad")))
+
+    def precond(self, grad):
+        import torch
+        it = (_I32 * (2 * (len(self.cfg["levels"]) + 1)))()
+        st = lib().npg_precond(self._h, _ptr(grad, torch.float32, self.n_params, "grad"), it)
+        if st not in (NPG_OK, NPG_ENOTCONV):
+            _check(st)
+        return list(it), st
+
+    def adam(self, params, grad, m, v, adam_step):
+        import torch
+        f = torch.float32
+        n = self.n_params
+        _check(lib().npg_adam(self._h, _ptr(params, f, n, "params"), _ptr(grad, f, n, "grad"),
+                              _ptr(m, f, n, "m"), _ptr(v, f, n, "v"), int(adam_step)))
+
+
+def plan_from_workload(cfg, data, device="cuda:0"):
+    """Upload a synth workload dict and create a Plan."""
+    import torch
+    xyz = torch.from_numpy(np.ascontiguousarray(data["xyz"], np.float32)).to(device)
+    nrm = torch.from_numpy(np.ascontiguousarray(data["nrm"], np.float32)).to(device)
+    pts = torch.from_numpy(np.ascontiguousarray(data["pts"], np.float32)).to(device)
+    return Plan(cfg, xyz, nrm, pts, data["frame_off"])

@@ -1,0 +1,276 @@
+// Bidirectional nearest-neighbour Chamfer distance per frame, the confidence
+// weighted deformation loss (Sec. 3.5), and the loss gradient w.r.t. the
+// deformed vertices.
+//
+// Distances are float32 in the direct form (x-p).(x-p) with one fixed
+// operation order (dist2 below), used everywhere a distance is compared, so
+// the argmin recovered in a second pass is the one the first pass saw.
+// Ties resolve to the lowest index in both directions.
+//
+// Main pass, per (frame, block of 256*K vertices): each thread keeps K
+// vertices in registers and streams the frame's points through LDS tiles.
+// The inner loop tracks values only: the running row minimum per vertex and,
+// per point, the minimum over the thread's K vertices, reduced across the
+// wave and then across the block with an LDS atomic min (exact and order
+// independent on the non-negative float bit patterns). The best tile of each
+// vertex is remembered and re-scanned afterwards to recover the lowest index.
+// Column minima of each vertex block are written out; a second pass takes
+// the minimum over blocks and re-scans the first block attaining it.
+#include "internal.h"
+
+namespace {
+
+constexpr int kK = 8;      // vertices per thread
+constexpr int kPT = 256;   // points per LDS tile
+constexpr int kVB = 256 * kK;
+
+__device__ __forceinline__ float dist2(float4 x, float4 p) {
+  float dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
+  return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_chamfer_main(const float4* __restrict__ xhat, const float4* __restrict__ pts,
+                                                      const int64_t* __restrict__ off, int64_t V, int nvb,
+                                                      int64_t Nmax, int32_t* __restrict__ a, float* __restrict__ da,
+                                                      unsigned* __restrict__ colpart) {
+  __shared__ float4 sp[kPT];
+  __shared__ unsigned cm[kPT];
+  const int t = blockIdx.y, vb = blockIdx.x;
+  const int64_t p0 = off[t];
+  const int Nt = (int)(off[t + 1] - p0);
+  const int lane = threadIdx.x & 63;
+  float4 x[kK];
+  float best[kK];
+  int btile[kK];
+#pragma unroll
+  for (int k = 0; k < kK; ++k) {
+    int64_t i = (int64_t)vb * kVB + threadIdx.x + 256 * k;
+    x[k] = i < V ? xhat[(int64_t)t * V + i] : make_float4(1e18f, 1e18f, 1e18f, 0.f);
+    best[k] = INFINITY;
+    btile[k] = 0;
+  }
+  const int ntile = (Nt + kPT - 1) / kPT;
+  for (int tile = 0; tile < ntile; ++tile) {
+    const int cnt = min(kPT, Nt - tile * kPT);
+    for (int j = threadIdx.x; j < kPT; j += 256) {
+      sp[j] = j < cnt ? pts[p0 + (int64_t)tile * kPT + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      cm[j] = 0x7f800000u;  // +inf
+    }
+    __syncthreads();
+    float tmin[kK];
+#pragma unroll
+    for (int k = 0; k < kK; ++k) tmin[k] = INFINITY;
+    for (int j = 0; j < cnt; ++j) {
+      const float4 p = sp[j];
+      float m = INFINITY;
+#pragma unroll
+      for (int k = 0; k < kK; ++k) {
+        float d = dist2(x[k], p);
+        tmin[k] = fminf(tmin[k], d);
+        m = fminf(m, d);
+      }
+      m = wave_min(m);
+      if (lane == 0) atomicMin(&cm[j], __float_as_uint(m));
+    }
+#pragma unroll
+    for (int k = 0; k < kK; ++k)
+      if (tmin[k] < best[k]) {
+        best[k] = tmin[k];
+        btile[k] = tile;
+      }
+    __syncthreads();
+    unsigned* dst = colpart + ((int64_t)t * nvb + vb) * Nmax + (int64_t)tile * kPT;
+    for (int j = threadIdx.x; j < cnt; j += 256) dst[j] = cm[j];
+    __syncthreads();
+  }
+  // recover the lowest index attaining the row minimum inside its best tile
+#pragma unroll
+  for (int k = 0; k < kK; ++k) {
+    int64_t i = (int64_t)vb * kVB + threadIdx.x + 256 * k;
+    if (i >= V) continue;
+    const int j0 = btile[k] * kPT;
+    const int cnt = min(kPT, Nt - j0);
+    int arg = j0;
+    for (int j = 0; j < cnt; ++j)
+      if (dist2(x[k], pts[p0 + j0 + j]) == best[k]) {
+        arg = j0 + j;
+        break;
+      }
+    a[(int64_t)t * V + i] = arg;
+    da[(int64_t)t * V + i] = best[k];
+  }
+}
+
+// One thread per point: minimum over vertex blocks, then the lowest vertex of
+// the first block attaining it.
+__global__ void k_chamfer_cols(const float4* __restrict__ xhat, const float4* __restrict__ pts,
+                               const int64_t* __restrict__ off, const int* __restrict__ pt_frame, int64_t Ntot,
+                               int64_t V, int nvb, int64_t Nmax, const unsigned* __restrict__ colpart,
+                               int32_t* __restrict__ b, float* __restrict__ db) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= Ntot) return;
+  const int t = pt_frame[g];
+  const int64_t j = g - off[t];
+  unsigned m = 0xffffffffu;
+  int vbest = 0;
+  for (int vb = 0; vb < nvb; ++vb) {
+    unsigned u = colpart[((int64_t)t * nvb + vb) * Nmax + j];
+    if (u < m) {
+      m = u;
+      vbest = vb;
+    }
+  }
+  const float dm = __uint_as_float(m);
+  const float4 p = pts[g];
+  const int64_t i0 = (int64_t)vbest * kVB;
+  const int64_t i1 = min(V, i0 + kVB);
+  int64_t arg = i0;
+  for (int64_t i = i0; i < i1; ++i)
+    if (dist2(xhat[(int64_t)t * V + i], p) == dm) {
+      arg = i;
+      break;
+    }
+  b[g] = (int32_t)arg;
+  db[g] = dm;
+}
+
+// cd_t = mean_i da + mean_j db in float64, fixed-order block reduction.
+__global__ void k_frame_sums(const float* __restrict__ da, const float* __restrict__ db,
+                             const int64_t* __restrict__ off, int64_t V, double* __restrict__ cd) {
+  __shared__ double red[2][256];
+  const int t = blockIdx.x;
+  double sa = 0.0, sb = 0.0;
+  for (int64_t i = threadIdx.x; i < V; i += 256) sa += (double)da[(int64_t)t * V + i];
+  const int64_t p0 = off[t], p1 = off[t + 1];
+  for (int64_t j = p0 + threadIdx.x; j < p1; j += 256) sb += (double)db[j];
+  red[0][threadIdx.x] = sa;
+  red[1][threadIdx.x] = sb;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + st];
+      red[1][threadIdx.x] += red[1][threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cd[t] = red[0][0] / (double)V + red[1][0] / (double)(p1 - p0);
+}
+
+// Sec. 3.5: omega(tau) = 1/(1 + max(0, cd_tau - cd_key)), w_t = product of
+// omega^delta over the frames between t_key and t (inclusive), delta =
+// 1 - sqrt(e/e_max); L_def = (1/T) sum_t w_t cd_t.
+__global__ void k_loss(const double* __restrict__ cd, int T, int t_key, int conf, double delta,
+                       double* __restrict__ w, double* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double ck = cd[t_key];
+  if (!conf) {
+    for (int t = 0; t < T; ++t) w[t] = 1.0;
+  } else {
+    w[t_key] = 1.0;
+    double run = 1.0;
+    for (int t = t_key + 1; t < T; ++t) {
+      run *= pow(1.0 / (1.0 + fmax(0.0, cd[t] - ck)), delta);
+      w[t] = run;
+    }
+    run = 1.0;
+    for (int t = t_key - 1; t >= 0; --t) {
+      run *= pow(1.0 / (1.0 + fmax(0.0, cd[t] - ck)), delta);
+      w[t] = run;
+    }
+  }
+  double s = 0.0;
+  for (int t = 0; t < T; ++t) s += w[t] * cd[t];
+  loss[0] = s / (double)T;
+}
+
+__global__ void k_zero_ll(long long* __restrict__ p, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Point -> its nearest vertex: accumulate x^_b - p in 2^-32 fixed point with
+// 64-bit integer atomics (exact, hence order independent).
+__global__ void k_chamfer_bwd_points(const float4* __restrict__ xhat, const float4* __restrict__ pts,
+                                     const int* __restrict__ pt_frame, const int32_t* __restrict__ b, int64_t Ntot,
+                                     int64_t V, long long* __restrict__ acc, int* __restrict__ flag) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= Ntot) return;
+  const int t = pt_frame[g];
+  const int64_t i = b[g];
+  const float4 x = xhat[(int64_t)t * V + i];
+  const float4 p = pts[g];
+  float d[3] = {x.x - p.x, x.y - p.y, x.z - p.z};
+  long long* dst = acc + ((int64_t)t * V + i) * 3;
+  for (int k = 0; k < 3; ++k) {
+    double v = (double)d[k] * 4294967296.0;
+    if (!(fabs(v) < 9.0e15)) {
+      atomicOr(flag, 1);
+      v = 0.0;
+    }
+    atomicAdd(reinterpret_cast<unsigned long long*>(dst + k), (unsigned long long)__double2ll_rn(v));
+  }
+}
+
+__global__ void k_chamfer_bwd_verts(const float4* __restrict__ xhat, const float4* __restrict__ pts,
+                                    const int64_t* __restrict__ off, const int32_t* __restrict__ a,
+                                    const double* __restrict__ w, const long long* __restrict__ acc, int64_t V,
+                                    int T, float4* __restrict__ gx) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)T * V) return;
+  const int t = (int)(e / V);
+  const float4 x = xhat[e];
+  const float4 p = pts[off[t] + a[e]];
+  const float s = (float)(w[t] / (double)T);
+  const float cv = 2.0f / (float)V;
+  const float cn = (float)(2.0 / (double)(off[t + 1] - off[t]));
+  const long long* ac = acc + e * 3;
+  const float inv = 1.0f / 4294967296.0f;
+  float4 r;
+  r.x = s * (cv * (x.x - p.x) + cn * ((float)ac[0] * inv));
+  r.y = s * (cv * (x.y - p.y) + cn * ((float)ac[1] * inv));
+  r.z = s * (cv * (x.z - p.z) + cn * ((float)ac[2] * inv));
+  r.w = 0.f;
+  gx[e] = r;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int npg_chamfer_vblock() { return kVB; }
+
+hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b,
+                                  float* db, double* cd) {
+  hipLaunchKernelGGL(k_chamfer_main, dim3(P->nvb, P->T), dim3(256), 0, P->stream, xhat, P->pts, P->d_off, P->V,
+                     P->nvb, P->Nmax, a, da, reinterpret_cast<unsigned*>(P->colpart));
+  hipLaunchKernelGGL(k_chamfer_cols, dim3(nblk(P->Ntot, 256)), dim3(256), 0, P->stream, xhat, P->pts, P->d_off,
+                     P->pt_frame, P->Ntot, P->V, P->nvb, P->Nmax, reinterpret_cast<const unsigned*>(P->colpart), b,
+                     db);
+  hipLaunchKernelGGL(k_frame_sums, dim3(P->T), dim3(256), 0, P->stream, da, db, P->d_off, P->V, cd);
+  return hipGetLastError();
+}
+
+hipError_t npg_launch_loss(const npg_plan* P, const double* cd, int epoch, int n_epochs, double* w,
+                           double* loss) {
+  double delta = 1.0 - sqrt((double)epoch / (double)n_epochs);
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, P->stream, cd, P->T, P->t_key, P->cfg.conf_weight, delta, w,
+                     loss);
+  return hipGetLastError();
+}
+
+hipError_t npg_launch_chamfer_bwd(const npg_plan* P, const float4* xhat, const int32_t* a, const int32_t* b,
+                                  const double* w, float4* gxhat) {
+  const int64_t n = (int64_t)P->T * P->V;
+  hipLaunchKernelGGL(k_zero_ll, dim3(nblk(3 * n, 256)), dim3(256), 0, P->stream, P->acc, 3 * n);
+  hipLaunchKernelGGL(k_chamfer_bwd_points, dim3(nblk(P->Ntot, 256)), dim3(256), 0, P->stream, xhat, P->pts,
+                     P->pt_frame, b, P->Ntot, P->V, P->acc, P->d_flag);
+  hipLaunchKernelGGL(k_chamfer_bwd_verts, dim3(nblk(n, 256)), dim3(256), 0, P->stream, xhat, P->pts, P->d_off, a,
+                     w, P->acc, P->V, P->T, gxhat);
+  return hipGetLastError();
+}

@@ -1,0 +1,149 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/neupig.h"
+
+#define NPG_MAX_SYS (NPG_MAX_LEVELS + 1)
+
+// One grid "system": a position level or the normal grid.
+struct NpgGrid {
+  int R;            // nodes per axis
+  int F;            // features per node
+  int64_t nodes;    // R^3
+  int64_t poff;     // offset (floats) into the flat parameter vector
+  int64_t noff;     // offset (nodes) into the concatenated node space
+  float lam;        // smoothness of the preconditioner
+  float lr;         // Adam learning rate
+  float scale;      // 1/L for position levels, 1 for the normal grid
+};
+
+struct NpgCG {  // conjugate-gradient workspace
+  float *x, *r, *p, *q;        // [n_grid_params] each, grid layout
+  double* part;                // [n_blocks][2][4] per-block partial dots
+  double* st;                  // [n_sys][4][8] per-system/channel scalars
+  int* active;                 // [n_sys] any channel still iterating
+  int* any_active;             // [1]
+  int* blk_sys;                // [n_blocks] system of each block
+  int64_t* blk_start;          // [n_blocks] first node of each block
+  int* sys_blk0;               // [n_sys+1]
+  int n_blocks;
+};
+
+struct npg_plan {
+  npg_config cfg;
+  hipStream_t stream;
+  int device;
+  int n_cu;
+  int64_t V;
+  int T;
+  int64_t Ntot;
+  std::vector<int64_t> off_h;
+  int n_sys;           // L + 1
+  int L;
+  NpgGrid g[NPG_MAX_SYS];
+  int64_t n_grid_params, n_nodes, mlp_off, n_params;
+  int Fz, Din, W, H, M;
+  int t_key;
+  // static device data
+  float4 *xyz, *nrm, *pts;
+  int64_t* d_off;
+  int* pt_frame;
+  NpgGrid* d_g;
+  // encode-backward table (node-sorted)
+  int64_t n_entries;
+  int32_t* e_vert;     // [E] vertex of each entry
+  float* e_w;          // [E] trilinear weight
+  int64_t n_seg;
+  int32_t* seg_key;    // [U] global node of each segment
+  int32_t* seg_chunk0; // [U+1] first chunk of each segment
+  int64_t n_chunk;
+  int32_t* chunk_start;  // [C+1] first entry of each chunk
+  float* chunk_sum;      // [C][4]
+  int8_t* chunk_sys;     // [C] grid system of each chunk
+  // owned optimizer state
+  float *params, *m, *v, *grad;
+  int64_t adam_k;
+  // intermediates
+  float *z, *gz;
+  float4 *xhat, *gxhat;
+  int32_t *a, *b;
+  float *da, *db;
+  double *cd, *w, *loss;
+  // chamfer workspace
+  int nvb;                 // vertex blocks per frame
+  float* colpart;          // [T][nvb][Nmax]
+  int64_t Nmax;
+  long long* acc;          // [T][V][3] fixed-point accumulators
+  // MLP workspace
+  float *mlpA, *mlpB;      // [V][W], [T][W]
+  float* wpack;            // repacked / transposed hidden and output weights
+  float* gam;              // [T][Din-Fz] time code
+  float *Gv, *Gt, *Gt_part, *gW_part;
+  int n_vblk_mlp;
+  int64_t gw_part_len;
+  // CG
+  NpgCG cg;
+  int* d_flag;             // non-finite flag
+  hipEvent_t ev[10];
+  float stage_ms[8];
+  bool timing;
+};
+
+// error helpers (plan.hip)
+npg_status npg_fail(npg_status s, const std::string& msg);
+#define NPG_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return npg_fail(NPG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- launchers --------------------------------------------------------------
+// setup.hip
+hipError_t npg_launch_pack(const float* src, float4* dst, int64_t n, hipStream_t s);
+hipError_t npg_launch_point_frames(const int64_t* off, int T, int* pt_frame, int64_t N, hipStream_t s);
+hipError_t npg_launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
+npg_status npg_build_scatter_table(npg_plan* P);
+// encode.hip
+hipError_t npg_launch_encode_fwd(const npg_plan* P, const float* params, float* z);
+hipError_t npg_launch_encode_bwd(const npg_plan* P, const float* gz, float* grad);
+// mlp.hip
+hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat);
+hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const float* z,
+                                 const float4* gxhat, float* grad, float* gz);
+// chamfer.hip
+hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t* a, float* da,
+                                  int32_t* b, float* db, double* cd);
+hipError_t npg_launch_loss(const npg_plan* P, const double* cd, int epoch, int n_epochs, double* w,
+                           double* loss);
+hipError_t npg_launch_chamfer_bwd(const npg_plan* P, const float4* xhat, const int32_t* a,
+                                  const int32_t* b, const double* w, float4* gxhat);
+// precond.hip
+npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters);
+// adam.hip
+hipError_t npg_launch_adam(const npg_plan* P, float* params, const float* grad, float* m, float* v,
+                           int64_t k, int* flag);
+
+// ---- device helpers shared by the kernels ----------------------------------
+// Cell of a coordinate in a grid of R nodes per axis spanning [-1,1] (corner
+// nodes on +-1): clamp to the box, u = (x+1)/2 (R-1), i0 = min(floor(u), R-2),
+// fraction u - i0. NaN maps to the first cell.
+__device__ __forceinline__ void npg_cell(float x, int R, int& i0, float& f) {
+  float c = fminf(fmaxf(x, -1.0f), 1.0f);
+  float u = (c + 1.0f) * 0.5f * (float)(R - 1);
+  int i = (int)floorf(u);
+  i = i < 0 ? 0 : (i > R - 2 ? R - 2 : i);
+  i0 = i;
+  f = u - (float)i;
+}
+
+__device__ __forceinline__ float npg_corner_w(int c, float fx, float fy, float fz) {
+  float wx = (c & 1) ? fx : 1.0f - fx;
+  float wy = (c & 2) ? fy : 1.0f - fy;
+  float wz = (c & 4) ? fz : 1.0f - fz;
+  return wx * wy * wz;
+}

@@ -1,0 +1,720 @@
+// Time-modulated MLP decode (Sec. 3.3), exponential-map transform and apply
+// (Sec. 3.4, supplementary rotation study), and their backward.
+//
+// Layout. A sample is a (frame t, vertex i) pair, s = t*V + i. Activations
+// are kept transposed in registers as 16x16 tiles of the MFMA
+// v_mfma_f32_16x16x4_f32 result layout: lane (q = lane/16, c = lane%16)
+// register r holds feature 16*mt + 4q + r of sample c. That layout is exactly
+// the B operand the next layer needs when the K index of k-step r is
+// 16*kt + 4q + r, so the chain of layers never leaves registers; the A
+// operand of every MFMA is a float4 read of 4 consecutive weights of one row.
+//
+// First layer. W1 y + b1 with y = (z_i, gamma_t) splits into
+// A_i = W1z z_i + b1 ([V][W]) and B_t = W1g gamma_t ([T][W]), computed once
+// per call, so the per-sample first layer is one add.
+//
+// Backward. Activations are recomputed per tile (never stored), so memory is
+// O(V + T) per call. Weight gradients contract over samples, which needs the
+// sample index in the MFMA K position: each layer's (gradient, input) tiles
+// of the work-group's 64 samples are staged through LDS, and each of the 4
+// waves accumulates a fixed quarter of the weight-gradient tiles in
+// registers over all frames. Per-work-group partials are summed in a fixed
+// order afterwards, so every result is bitwise reproducible.
+#include "internal.h"
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
+
+struct ActP {
+  int relu;
+  float slope;
+};
+
+__device__ __forceinline__ float actf(float x, ActP a) { return x > 0.f ? x : (a.relu ? 0.f : a.slope * x); }
+// derivative from the activation's output (same sign as its input)
+__device__ __forceinline__ float actd(float h, ActP a) { return h > 0.f ? 1.f : (a.relu ? 0.f : a.slope); }
+
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float comp(const float4& v, int r) {
+  return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
+}
+
+// Workspace layout of the repacked weights (floats, every block 16-B aligned):
+//   for hidden layer l = 1..H-1:  Wh[l] [W][W] (row = out), WhT[l] [W][W]
+//   (row = in), bh[l] [W]; then WoP [16][W] (output rows, 6..15 zero),
+//   WoT [W][16] (transposed, columns 6..15 zero), bo [16].
+struct WPack {
+  int64_t wh, wht, bh, wop, wot, bo, total;
+  __host__ __device__ WPack(int W, int H) {
+    int64_t hsz = (int64_t)W * W;
+    wh = 0;
+    wht = wh + (H - 1) * hsz;
+    bh = wht + (H - 1) * hsz;
+    wop = bh + (int64_t)(H - 1) * W;
+    wot = wop + 16 * (int64_t)W;
+    bo = wot + 16 * (int64_t)W;
+    total = bo + 16;
+  }
+};
+
+// Offsets (floats) inside the flat MLP block.
+__host__ __device__ inline int64_t mlp_layer_off(int l, int W, int Din) {
+  if (l == 0) return 0;
+  return (int64_t)W * Din + W + (int64_t)(l - 1) * ((int64_t)W * W + W);
+}
+
+__global__ void k_prep_weights(const float* __restrict__ mlp, int W, int H, int Din, float* __restrict__ wp) {
+  WPack P(W, H);
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= P.total) return;
+  float val = 0.f;
+  if (e < P.wht) {
+    int64_t l = e / ((int64_t)W * W) + 1, k = e % ((int64_t)W * W);
+    val = mlp[mlp_layer_off((int)l, W, Din) + k];
+  } else if (e < P.bh) {
+    int64_t k = e - P.wht;
+    int64_t l = k / ((int64_t)W * W) + 1, kk = k % ((int64_t)W * W);
+    int64_t in = kk / W, out = kk % W;  // WhT[in][out] = Wh[out][in]
+    val = mlp[mlp_layer_off((int)l, W, Din) + out * W + in];
+  } else if (e < P.wop) {
+    int64_t k = e - P.bh;
+    int64_t l = k / W + 1, o = k % W;
+    val = mlp[mlp_layer_off((int)l, W, Din) + (int64_t)W * W + o];
+  } else if (e < P.wot) {
+    int64_t k = e - P.wop;
+    int64_t row = k / W, col = k % W;
+    if (row < 6) val = mlp[mlp_layer_off(H, W, Din) + row * W + col];
+  } else if (e < P.bo) {
+    int64_t k = e - P.wot;
+    int64_t in = k / 16, o = k % 16;
+    if (o < 6) val = mlp[mlp_layer_off(H, W, Din) + o * W + in];
+  } else {
+    int64_t o = e - P.bo;
+    if (o < 6) val = mlp[mlp_layer_off(H, W, Din) + 6 * (int64_t)W + o];
+  }
+  wp[e] = val;
+}
+
+// A[i][o] = b1[o] + sum_k W1[o][k] z[i][k] (k < Fz)
+__global__ void k_prep_A(const float* __restrict__ mlp, const float* __restrict__ z, int64_t V, int W, int Din,
+                         int Fz, float* __restrict__ A) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= V * W) return;
+  int64_t i = e / W;
+  int o = (int)(e % W);
+  const float* w1 = mlp + (int64_t)o * Din;
+  float acc = mlp[(int64_t)W * Din + o];
+  for (int k = 0; k < Fz; ++k) acc = fmaf(w1[k], z[i * Fz + k], acc);
+  A[e] = acc;
+}
+
+// B[t][o] = sum_k W1[o][Fz + k] gamma_t[k]
+__global__ void k_prep_B(const float* __restrict__ mlp, const float* __restrict__ gam, int T, int W, int Din,
+                         int Fz, float* __restrict__ B) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)T * W) return;
+  int64_t t = e / W;
+  int o = (int)(e % W);
+  const int Dt = Din - Fz;
+  const float* w1 = mlp + (int64_t)o * Din + Fz;
+  float acc = 0.f;
+  for (int k = 0; k < Dt; ++k) acc = fmaf(w1[k], gam[t * Dt + k], acc);
+  B[e] = acc;
+}
+
+// ---- exponential map (Rodrigues) in float32 --------------------------------
+// A = sin(th)/th, B = (1-cos th)/th^2 = 2 sin^2(th/2)/th^2, C = (th - sin th)/th^3.
+// The half-angle form of B and a Taylor series of C below th = 0.5 avoid the
+// cancellation of the textbook forms in float32.
+__device__ __forceinline__ void rod_coef(float th2, float& A, float& B, float& C) {
+  float th = sqrtf(th2);
+  if (th < 1e-4f) {
+    A = 1.f - th2 * (1.f / 6.f);
+    B = 0.5f - th2 * (1.f / 24.f);
+  } else {
+    A = sinf(th) / th;
+    float h = 0.5f * th;
+    float sh = sinf(h) / h;
+    B = 0.5f * sh * sh;
+  }
+  if (th < 0.5f) {
+    C = (1.f / 6.f) - th2 * ((1.f / 120.f) - th2 * ((1.f / 5040.f) - th2 * ((1.f / 362880.f) - th2 * (1.f / 39916800.f))));
+  } else {
+    C = (th - sinf(th)) / (th2 * th);
+  }
+}
+
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+  return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// x^ = R(w) x + tanh(alpha d)
+__device__ __forceinline__ float4 apply_transform(const float* o, float4 xr, float alpha) {
+  float3 w = make_float3(o[0], o[1], o[2]);
+  float A, B, C;
+  rod_coef(w.x * w.x + w.y * w.y + w.z * w.z, A, B, C);
+  float3 x = make_float3(xr.x, xr.y, xr.z);
+  float3 wx = cross3(w, x);
+  float3 wwx = cross3(w, wx);
+  return make_float4(x.x + A * wx.x + B * wwx.x + tanhf(alpha * o[3]),
+                     x.y + A * wx.y + B * wwx.y + tanhf(alpha * o[4]),
+                     x.z + A * wx.z + B * wwx.z + tanhf(alpha * o[5]), 0.f);
+}
+
+// Gradient of g . x^ w.r.t. o = (w, d): with u = R^T g and c = x cross u,
+// d/dw = J_r(w)^T c = c + B (w x c) + C (w x (w x c)); d/dd = alpha (1 - d^2) g.
+__device__ __forceinline__ void transform_grad(const float* o, float4 xr, float4 gr, float alpha, float* go) {
+  float3 w = make_float3(o[0], o[1], o[2]);
+  float A, B, C;
+  rod_coef(w.x * w.x + w.y * w.y + w.z * w.z, A, B, C);
+  float3 g = make_float3(gr.x, gr.y, gr.z);
+  float3 wg = cross3(w, g);
+  float3 wwg = cross3(w, wg);
+  float3 u = make_float3(g.x - A * wg.x + B * wwg.x, g.y - A * wg.y + B * wwg.y, g.z - A * wg.z + B * wwg.z);
+  float3 c = cross3(make_float3(xr.x, xr.y, xr.z), u);
+  float3 wc = cross3(w, c);
+  float3 wwc = cross3(w, wc);
+  go[0] = c.x + B * wc.x + C * wwc.x;
+  go[1] = c.y + B * wc.y + C * wwc.y;
+  go[2] = c.z + B * wc.z + C * wwc.z;
+  for (int k = 0; k < 3; ++k) {
+    float dh = tanhf(alpha * o[3 + k]);
+    float gk = k == 0 ? g.x : (k == 1 ? g.y : g.z);
+    go[3 + k] = alpha * (1.f - dh * dh) * gk;
+  }
+}
+
+// out[mt] += sum_k Wrow(16mt + c, k) * in[k] over all k tiles; wl(mt, kt)
+// returns the float4 of row 16mt + c at columns 16kt + 4q .. +3.
+template <int NT, typename WL>
+__device__ __forceinline__ void dense(const v4f (&in)[NT], v4f (&out)[NT], WL wl) {
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    float4 w[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) w[mt] = wl(mt, kt);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) out[mt] = mfma(comp(w[mt], r), in[kt][r], out[mt]);
+    // keep the next k-tile's operand loads from being hoisted above this one
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// 16-row output layer (rows 6..15 zero): o = Wo h + bo.
+template <int NT, typename WL>
+__device__ __forceinline__ v4f dense_out(const v4f (&in)[NT], v4f init, WL wl) {
+  v4f a0 = init, a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    float4 w = wl(kt);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (kt & 1) a1 = mfma(comp(w, r), in[kt][r], a1);
+      else a0 = mfma(comp(w, r), in[kt][r], a0);
+    }
+  }
+  return a0 + a1;
+}
+
+// Forward activations of one 16-sample tile: h[l] for the H hidden layers.
+template <int W, int H, typename WH, typename BH>
+__device__ __forceinline__ void mlp_hidden(v4f (&h)[H][W / 16], const float* __restrict__ A,
+                                           const float* __restrict__ B, int64_t i, int64_t t, int q, ActP ap,
+                                           WH wh, BH bh) {
+  constexpr int NT = W / 16;
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
+    float4 b = *reinterpret_cast<const float4*>(B + t * W + 16 * mt + 4 * q);
+    h[0][mt] = v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)};
+  }
+#pragma unroll
+  for (int l = 1; l < H; ++l) {
+    v4f o[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      float4 b = bh(l, mt);
+      o[mt] = v4f{b.x, b.y, b.z, b.w};
+    }
+    dense<NT>(h[l - 1], o, [&](int mt, int kt) { return wh(l, mt, kt); });
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+      h[l][mt] = v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward: 8 waves per work-group share the hidden and output weights in LDS;
+// each wave decodes 16-sample tiles in a grid-stride loop.
+// ---------------------------------------------------------------------------
+template <int W, int H>
+__global__ __launch_bounds__(512) void k_decode_fwd(const float* __restrict__ wp, const float* __restrict__ A,
+                                                    const float* __restrict__ B, const float4* __restrict__ xyz,
+                                                    float4* __restrict__ xhat, int64_t V, int T, ActP ap,
+                                                    float alpha) {
+  constexpr int NT = W / 16;
+  constexpr int LD = W + 4;  // padded LDS row
+  extern __shared__ float lds[];
+  float* sW = lds;                           // [H-1][W][LD]
+  float* sWo = sW + (H - 1) * W * LD;        // [16][LD]
+  float* sB = sWo + 16 * LD;                 // [H-1][W] + [16]
+  const WPack P(W, H);
+  for (int e = threadIdx.x; e < (H - 1) * W * W; e += blockDim.x) {
+    int l = e / (W * W), k = e % (W * W);
+    sW[(l * W + k / W) * LD + k % W] = wp[P.wh + e];
+  }
+  for (int e = threadIdx.x; e < 16 * W; e += blockDim.x) sWo[(e / W) * LD + e % W] = wp[P.wop + e];
+  for (int e = threadIdx.x; e < (H - 1) * W; e += blockDim.x) sB[e] = wp[P.bh + e];
+  for (int e = threadIdx.x; e < 16; e += blockDim.x) sB[(H - 1) * W + e] = wp[P.bo + e];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int nw = blockDim.x >> 6;
+  const int64_t S = V * (int64_t)T;
+  const int64_t ntiles = (S + 15) / 16;
+  auto wh = [&](int l, int mt, int kt) {
+    return *reinterpret_cast<const float4*>(sW + ((l - 1) * W + 16 * mt + c) * LD + 16 * kt + 4 * q);
+  };
+  auto bh = [&](int l, int mt) { return *reinterpret_cast<const float4*>(sB + (l - 1) * W + 16 * mt + 4 * q); };
+  auto wo = [&](int kt) { return *reinterpret_cast<const float4*>(sWo + c * LD + 16 * kt + 4 * q); };
+  float4 bo4 = *reinterpret_cast<const float4*>(sB + (H - 1) * W + 4 * q);
+  const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
+
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+    // opaque zero: keeps the LDS weight reads inside the loop (not hoisted)
+    int z0 = 0;
+    asm volatile("" : "+s"(z0));
+    const float* sWl = sW + z0;
+    const float* sWol = sWo + z0;
+    auto whl = [&](int l, int mt, int kt) {
+      return *reinterpret_cast<const float4*>(sWl + ((l - 1) * W + 16 * mt + c) * LD + 16 * kt + 4 * q);
+    };
+    auto wol = [&](int kt) { return *reinterpret_cast<const float4*>(sWol + c * LD + 16 * kt + 4 * q); };
+    int64_t s = tile * 16 + c;
+    const bool valid = s < S;
+    if (!valid) s = S - 1;
+    const int64_t t = s / V, i = s - t * V;
+    v4f h[H][NT];
+    mlp_hidden<W, H>(h, A, B, i, t, q, ap, whl, bh);
+    v4f o = dense_out<NT>(h[H - 1], boi, wol);
+    float o4 = __shfl(o[0], (lane + 16) & 63);
+    float o5 = __shfl(o[1], (lane + 16) & 63);
+    if (q == 0 && valid) {
+      float ov[6] = {o[0], o[1], o[2], o[3], o4, o5};
+      xhat[s] = apply_transform(ov, xyz[i], alpha);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: one work-group = 4 waves = 64 vertices, looping over all frames.
+// ---------------------------------------------------------------------------
+constexpr int kSP = 68;  // staged samples per row (64 + pad)
+
+// LDS of the backward (floats): sH [H][W][kSP] recomputed activations of the
+// work-group's 64 samples, sG [W][kSP] staged gradient rows, sGb bias
+// gradients [H-1][W] + [16], sGt [4][W] per-wave frame sums.
+template <int W, int H>
+constexpr size_t bwd_lds_floats() {
+  return (size_t)H * W * kSP + (size_t)W * kSP + (H - 1) * W + 16 + 4 * W;
+}
+
+template <int W, int H>
+__global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp, const float* __restrict__ A,
+                                                    const float* __restrict__ B, const float4* __restrict__ xyz,
+                                                    const float4* __restrict__ gxhat, int64_t V, int T, ActP ap,
+                                                    float alpha, float* __restrict__ Gv,
+                                                    float* __restrict__ Gt_part, float* __restrict__ gW_part) {
+  constexpr int NT = W / 16;
+  constexpr int NTT = (NT * NT + 3) / 4;  // owned hidden weight-gradient tiles per wave
+  constexpr int NTO = (NT + 3) / 4;       // owned output weight-gradient tiles per wave
+  extern __shared__ float lds[];
+  float* sH = lds;                        // [H][W][kSP]
+  float* sG = sH + H * W * kSP;           // [W][kSP]
+  float* sGb = sG + W * kSP;              // [H-1][W] + [16]
+  float* sGt = sGb + (H - 1) * W + 16;    // [4][W]
+  const WPack P(W, H);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int64_t vb = blockIdx.x;
+  const int64_t i_raw = vb * 64 + wave * 16 + c;
+  const bool vvalid = i_raw < V;
+  const int64_t i = vvalid ? i_raw : V - 1;
+  const int sp = wave * 16 + c;
+
+  for (int e = threadIdx.x; e < (H - 1) * W + 16; e += 256) sGb[e] = 0.f;
+
+  float4 bo4 = *reinterpret_cast<const float4*>(wp + P.bo + 4 * q);
+  const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
+  const float4 xi = xyz[i];
+
+  v4f accW[H > 1 ? H - 1 : 1][NTT];
+  v4f accO[NTO];
+  v4f gv[NT];
+#pragma unroll
+  for (int l = 0; l < (H > 1 ? H - 1 : 1); ++l)
+#pragma unroll
+    for (int k = 0; k < NTT; ++k) accW[l][k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < NTO; ++k) accO[k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < NT; ++k) gv[k] = v4f{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+
+  // this lane's element (feature 16*mt + 4q + r, own sample) of a staged row block
+  auto at = [&](float* base, int mt, int r) -> float& { return base[(16 * mt + 4 * q + r) * kSP + sp]; };
+  // acc += sum over the 64 staged samples of sG[16mt + m][s] * hs[16kt + n][s]
+  auto wgrad_tile = [&](const float* hs, int mt, int kt, v4f acc) {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      float4 a = *reinterpret_cast<const float4*>(sG + (16 * mt + c) * kSP + 16 * q + 4 * jj);
+      float4 b = *reinterpret_cast<const float4*>(hs + (16 * kt + c) * kSP + 16 * q + 4 * jj);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc = mfma(comp(a, r), comp(b, r), acc);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    return acc;
+  };
+  // bias gradient rows: thread tid sums staged gradient row tid over the 64 samples
+  auto bias_rows = [&](int rows, float* dst) {
+    if ((int)threadIdx.x < rows) {
+      const float* src = sG + threadIdx.x * kSP;
+      float s0 = 0.f;
+      for (int j = 0; j < 64; j += 4) {
+        float4 v = *reinterpret_cast<const float4*>(src + j);
+        s0 += (v.x + v.y) + (v.z + v.w);
+      }
+      dst[threadIdx.x] += s0;
+    }
+  };
+
+  for (int t = 0; t < T; ++t) {
+    // Opaque copies of the weight pointers: keeps the compiler from hoisting
+    // every (loop-invariant) weight load of the frame loop into registers.
+    const float* wpl = wp;
+    asm volatile("" : "+s"(wpl));
+    const float* Wh = wpl + P.wh;
+    const float* WhT = wpl + P.wht;
+    // ---- recompute the forward pass; activations go to LDS ---------------
+    v4f h[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
+      float4 b = *reinterpret_cast<const float4*>(B + (int64_t)t * W + 16 * mt + 4 * q);
+      h[mt] = v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) at(sH, mt, r) = h[mt][r];
+    }
+#pragma unroll
+    for (int l = 1; l < H; ++l) {
+      v4f o[NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        float4 b = *reinterpret_cast<const float4*>(wpl + P.bh + (l - 1) * W + 16 * mt + 4 * q);
+        o[mt] = v4f{b.x, b.y, b.z, b.w};
+      }
+      dense<NT>(h, o, [&](int mt, int kt) {
+        return *reinterpret_cast<const float4*>(Wh + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
+      });
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        h[mt] = v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) at(sH + l * W * kSP, mt, r) = h[mt][r];
+      }
+    }
+    v4f o = dense_out<NT>(h, boi, [&](int kt) {
+      return *reinterpret_cast<const float4*>(wpl + P.wop + c * W + 16 * kt + 4 * q);
+    });
+
+    // ---- transform backward: every lane evaluates its sample c -----------
+    float o4 = __shfl(o[0], (lane + 16) & 63);
+    float o5 = __shfl(o[1], (lane + 16) & 63);
+    float ov[6] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
+                   __shfl(o5, c)};
+    float4 gx = vvalid ? gxhat[(int64_t)t * V + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float go[6];
+    transform_grad(ov, xi, gx, alpha, go);
+    if (!vvalid)
+      for (int k = 0; k < 6; ++k) go[k] = 0.f;
+    const v4f got = q == 0 ? v4f{go[0], go[1], go[2], go[3]}
+                           : (q == 1 ? v4f{go[4], go[5], 0.f, 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
+
+    // ---- output layer: weight gradient and back-propagation ---------------
+#pragma unroll
+    for (int r = 0; r < 4; ++r) at(sG, 0, r) = got[r];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NTO; ++k) {
+      int kt = wave + 4 * k;
+      if (kt < NT) accO[k] = wgrad_tile(sH + (H - 1) * W * kSP, 0, kt, accO[k]);
+    }
+    bias_rows(16, sGb + (H - 1) * W);
+    v4f gp[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      float4 w = *reinterpret_cast<const float4*>(wpl + P.wot + (16 * mt + c) * 16 + 4 * q);
+      v4f a = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a = mfma(comp(w, r), got[r], a);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gp[mt][r] = a[r] * actd(at(sH + (H - 1) * W * kSP, mt, r), ap);
+    }
+    __syncthreads();
+
+    // ---- hidden layers, last to first --------------------------------------
+#pragma unroll
+    for (int l = H - 1; l >= 1; --l) {
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) at(sG, mt, r) = gp[mt][r];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NTT; ++k) {
+        int tau = wave + 4 * k;
+        if (tau < NT * NT) accW[l - 1][k] = wgrad_tile(sH + (l - 1) * W * kSP, tau / NT, tau % NT, accW[l - 1][k]);
+      }
+      bias_rows(W, sGb + (l - 1) * W);
+      v4f gh[NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) gh[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+      dense<NT>(gp, gh, [&](int mt, int kt) {
+        return *reinterpret_cast<const float4*>(WhT + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
+      });
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gp[mt][r] = gh[mt][r] * actd(at(sH + (l - 1) * W * kSP, mt, r), ap);
+      __syncthreads();
+    }
+
+    // ---- first layer: per-vertex (Gv) and per-frame (Gt) sums -------------
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        gv[mt][r] += gp[mt][r];
+        float v = gp[mt][r];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if (c == 0) sGt[wave * W + 16 * mt + 4 * q + r] = v;
+      }
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+      float s0 = ((sGt[threadIdx.x] + sGt[W + threadIdx.x]) + sGt[2 * W + threadIdx.x]) + sGt[3 * W + threadIdx.x];
+      Gt_part[((int64_t)t * gridDim.x + vb) * W + threadIdx.x] = s0;
+    }
+  }
+  __syncthreads();
+
+  if (vvalid) {
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Gv[i_raw * W + 16 * mt + 4 * q + r] = gv[mt][r];
+  }
+  // per-work-group weight-gradient partials, flat MLP layout of layers 1..H
+  const int64_t len = (int64_t)(H - 1) * ((int64_t)W * W + W) + 6 * (int64_t)W + 6;
+  float* dst = gW_part + vb * len;
+#pragma unroll
+  for (int l = 1; l < H; ++l) {
+    float* dl = dst + (int64_t)(l - 1) * ((int64_t)W * W + W);
+#pragma unroll
+    for (int k = 0; k < NTT; ++k) {
+      int tau = wave + 4 * k;
+      if (tau < NT * NT) {
+        int mt = tau / NT, kt = tau % NT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dl[(16 * mt + 4 * q + r) * W + 16 * kt + c] = accW[l - 1][k][r];
+      }
+    }
+    for (int e = threadIdx.x; e < W; e += 256) dl[(int64_t)W * W + e] = sGb[(l - 1) * W + e];
+  }
+  float* dout = dst + (int64_t)(H - 1) * ((int64_t)W * W + W);
+#pragma unroll
+  for (int k = 0; k < NTO; ++k) {
+    int kt = wave + 4 * k;
+    if (kt < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * q + r < 6) dout[(4 * q + r) * W + 16 * kt + c] = accO[k][r];
+    }
+  }
+  if (threadIdx.x < 6) dout[6 * W + threadIdx.x] = sGb[(H - 1) * W + threadIdx.x];
+}
+
+// Sum the per-work-group partials in work-group order.
+__global__ void k_sum_parts(const float* __restrict__ part, int64_t len, int nparts, float* __restrict__ dst) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  float s = 0.f;
+  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * len + e];
+  dst[e] = s;
+}
+
+// First layer: gW1 z-part = sum_i Gv[i] z_i^T, gamma part = sum_t Gt[t] gamma_t^T,
+// gb1 = sum_t Gt[t]. One block per output unit, fixed-order tree reductions.
+__global__ void k_first_layer(const float* __restrict__ Gv, const float* __restrict__ Gt,
+                              const float* __restrict__ z, const float* __restrict__ gam, int64_t V, int T, int W,
+                              int Din, int Fz, float* __restrict__ g1) {
+  __shared__ float red[256][9];
+  const int o = blockIdx.x;
+  const int Dt = Din - Fz;
+  float acc[9];
+  for (int k = 0; k < 9; ++k) acc[k] = 0.f;
+  for (int64_t i = threadIdx.x; i < V; i += 256) {
+    float gv = Gv[i * W + o];
+    for (int k = 0; k < Fz; ++k) acc[k] = fmaf(gv, z[i * Fz + k], acc[k]);
+  }
+  for (int k = 0; k < 9; ++k) red[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 9; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < Fz; ++k) g1[(int64_t)o * Din + k] = red[0][k];
+    float gb = 0.f;
+    float gg[16];
+    for (int k = 0; k < Dt; ++k) gg[k] = 0.f;
+    for (int t = 0; t < T; ++t) {
+      float v = Gt[(int64_t)t * W + o];
+      gb += v;
+      for (int k = 0; k < Dt; ++k) gg[k] = fmaf(v, gam[(int64_t)t * Dt + k], gg[k]);
+    }
+    for (int k = 0; k < Dt; ++k) g1[(int64_t)o * Din + Fz + k] = gg[k];
+    g1[(int64_t)W * Din + o] = gb;
+  }
+}
+
+// Gt[t][o] = sum over work-groups of Gt_part[t][wg][o]
+__global__ void k_gt_reduce(const float* __restrict__ part, int T, int nwg, int W, float* __restrict__ Gt) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)T * W) return;
+  int64_t t = e / W, o = e % W;
+  float s = 0.f;
+  for (int p = 0; p < nwg; ++p) s += part[(t * nwg + p) * W + o];
+  Gt[e] = s;
+}
+
+// gz[i][k] = sum_o W1[o][k] Gv[i][o], k < Fz
+__global__ void k_gz(const float* __restrict__ mlp, const float* __restrict__ Gv, int64_t V, int W, int Din,
+                     int Fz, float* __restrict__ gz) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  float acc[8];
+  for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+  for (int o = 0; o < W; ++o) {
+    float gv = Gv[i * W + o];
+    for (int k = 0; k < Fz; ++k) acc[k] = fmaf(mlp[(int64_t)o * Din + k], gv, acc[k]);
+  }
+  for (int k = 0; k < Fz; ++k) gz[i * Fz + k] = acc[k];
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int W, int H>
+size_t fwd_lds() {
+  return sizeof(float) * ((size_t)(H - 1) * W * (W + 4) + 16 * (W + 4) + (H - 1) * W + 16);
+}
+template <int W, int H>
+size_t bwd_lds() {
+  return sizeof(float) * bwd_lds_floats<W, H>();
+}
+
+template <int W, int H>
+hipError_t launch_fwd(const npg_plan* P, float4* xhat, ActP ap) {
+  size_t lds = fwd_lds<W, H>();
+  hipError_t e = hipFuncSetAttribute((const void*)k_decode_fwd<W, H>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_decode_fwd<W, H>), dim3(P->n_cu), dim3(512), lds, P->stream, P->wpack, P->mlpA,
+                     P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t);
+  return hipGetLastError();
+}
+
+template <int W, int H>
+hipError_t launch_bwd(const npg_plan* P, const float4* gxhat, ActP ap) {
+  size_t lds = bwd_lds<W, H>();
+  hipError_t e = hipFuncSetAttribute((const void*)k_decode_bwd<W, H>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_decode_bwd<W, H>), dim3(P->n_vblk_mlp), dim3(256), lds, P->stream, P->wpack, P->mlpA,
+                     P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t, P->Gv, P->Gt_part, P->gW_part);
+  return hipGetLastError();
+}
+
+hipError_t prep(const npg_plan* P, const float* params, const float* z) {
+  const float* mlp = params + P->mlp_off;
+  const WPack wpk(P->W, P->H);
+  hipLaunchKernelGGL(k_prep_weights, dim3(nblk(wpk.total, 256)), dim3(256), 0, P->stream, mlp, P->W, P->H,
+                     P->Din, P->wpack);
+  hipLaunchKernelGGL(k_prep_A, dim3(nblk(P->V * P->W, 256)), dim3(256), 0, P->stream, mlp, z, P->V, P->W,
+                     P->Din, P->Fz, P->mlpA);
+  hipLaunchKernelGGL(k_prep_B, dim3(nblk((int64_t)P->T * P->W, 256)), dim3(256), 0, P->stream, mlp, P->gam,
+                     P->T, P->W, P->Din, P->Fz, P->mlpB);
+  return hipGetLastError();
+}
+
+#define NPG_DISPATCH(FN, ...)                                        \
+  switch (P->W * 10 + P->H) {                                        \
+    case 321: return FN<32, 1>(__VA_ARGS__);                         \
+    case 322: return FN<32, 2>(__VA_ARGS__);                         \
+    case 323: return FN<32, 3>(__VA_ARGS__);                         \
+    case 641: return FN<64, 1>(__VA_ARGS__);                         \
+    case 642: return FN<64, 2>(__VA_ARGS__);                         \
+    case 643: return FN<64, 3>(__VA_ARGS__);                         \
+    case 1281: return FN<128, 1>(__VA_ARGS__);                       \
+    case 1282: return FN<128, 2>(__VA_ARGS__);                       \
+    case 1283: return FN<128, 3>(__VA_ARGS__);                       \
+    default: return hipErrorInvalidValue;                            \
+  }
+
+}  // namespace
+
+int64_t npg_wpack_len(int W, int H) { return WPack(W, H).total; }
+int64_t npg_gw_part_len(int W, int H) { return (int64_t)(H - 1) * ((int64_t)W * W + W) + 6 * (int64_t)W + 6; }
+size_t npg_decode_fwd_lds(int W, int H) { return sizeof(float) * ((size_t)(H - 1) * W * (W + 4) + 16 * (W + 4) + (H - 1) * W + 16); }
+
+hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat) {
+  hipError_t e = prep(P, params, z);
+  if (e != hipSuccess) return e;
+  ActP ap{P->cfg.act == NPG_ACT_RELU, P->cfg.leaky_slope};
+  NPG_DISPATCH(launch_fwd, P, xhat, ap);
+}
+
+static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const float* z, float* grad, float* gz) {
+  const float* mlp = params + P->mlp_off;
+  float* gmlp = grad + P->mlp_off;
+  const int64_t l0 = (int64_t)P->W * P->Din + P->W;
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(P->gw_part_len, 256)), dim3(256), 0, P->stream, P->gW_part,
+                     P->gw_part_len, P->n_vblk_mlp, gmlp + l0);
+  hipLaunchKernelGGL(k_gt_reduce, dim3(nblk((int64_t)P->T * P->W, 256)), dim3(256), 0, P->stream, P->Gt_part,
+                     P->T, P->n_vblk_mlp, P->W, P->Gt);
+  hipLaunchKernelGGL(k_first_layer, dim3(P->W), dim3(256), 0, P->stream, P->Gv, P->Gt, z, P->gam, P->V, P->T,
+                     P->W, P->Din, P->Fz, gmlp);
+  hipLaunchKernelGGL(k_gz, dim3(nblk(P->V, 128)), dim3(128), 0, P->stream, mlp, P->Gv, P->V, P->W, P->Din,
+                     P->Fz, gz);
+  return hipGetLastError();
+}
+
+hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const float* z, const float4* gxhat,
+                                 float* grad, float* gz) {
+  hipError_t e = prep(P, params, z);
+  if (e != hipSuccess) return e;
+  ActP ap{P->cfg.act == NPG_ACT_RELU, P->cfg.leaky_slope};
+  e = [&]() -> hipError_t { NPG_DISPATCH(launch_bwd, P, gxhat, ap); }();
+  if (e != hipSuccess) return e;
+  return decode_bwd_tail(P, params, z, grad, gz);
+}

@@ -1,0 +1,420 @@
+// C ABI of the library: plan creation (validation, packing, static tables,
+// workspace), state import/export, the full step and the stage entry points.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "internal.h"
+
+// launchers defined in the other translation units
+int64_t npg_wpack_len(int W, int H);
+int64_t npg_gw_part_len(int W, int H);
+int npg_chamfer_vblock();
+npg_status npg_cg_setup(npg_plan* P);
+void npg_cg_free(npg_plan* P);
+
+namespace {
+thread_local std::string g_err;
+
+__global__ void k_gamma(int T, int M, float* __restrict__ gam) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double tt = T > 1 ? (double)t / (double)(T - 1) : 0.0;
+  if (M == 0) {
+    gam[t] = (float)tt;
+    return;
+  }
+  double nu = 1.0;
+  for (int j = 0; j < M; ++j) {
+    gam[(int64_t)t * 2 * M + 2 * j] = (float)sin(M_PI * nu * tt);
+    gam[(int64_t)t * 2 * M + 2 * j + 1] = (float)cos(M_PI * nu * tt);
+    nu *= 2.0;
+  }
+}
+
+__global__ void k_unpack_xyz(const float4* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) {
+    float4 v = src[i];
+    dst[3 * i] = v.x;
+    dst[3 * i + 1] = v.y;
+    dst[3 * i + 2] = v.z;
+  }
+}
+
+template <typename T>
+npg_status dalloc(T** p, int64_t count) {
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, (size_t)count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return npg_fail(NPG_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  return NPG_OK;
+}
+
+#define TRY(x)                      \
+  do {                              \
+    npg_status s_ = (x);            \
+    if (s_ != NPG_OK) return s_;    \
+  } while (0)
+
+#define CHECK_ARG(cond, msg) \
+  do {                       \
+    if (!(cond)) return npg_fail(NPG_EINVAL, msg); \
+  } while (0)
+
+npg_status validate_cfg(const npg_config* c) {
+  CHECK_ARG(c, "config is NULL");
+  CHECK_ARG(c->n_levels >= 1 && c->n_levels <= NPG_MAX_LEVELS, "n_levels must be in 1..16");
+  for (int l = 0; l < c->n_levels; ++l) {
+    CHECK_ARG(c->res[l] >= 2 && c->res[l] <= 1024, "every level needs 2..1024 nodes per axis");
+    CHECK_ARG(isfinite(c->lam[l]) && c->lam[l] >= 0.f, "lambda must be finite and >= 0");
+    CHECK_ARG(isfinite(c->lr_grid[l]), "grid learning rates must be finite");
+  }
+  CHECK_ARG(c->feat_p >= 1 && c->feat_p <= 4, "feat_p must be in 1..4");
+  CHECK_ARG(c->feat_n >= 1 && c->feat_n <= 4, "feat_n must be in 1..4");
+  CHECK_ARG(c->res_n >= 2 && c->res_n <= 1024, "res_n must be in 2..1024");
+  CHECK_ARG(c->time_freqs >= 0 && c->time_freqs <= 8, "time_freqs must be in 0..8");
+  CHECK_ARG(c->mlp_hidden >= 1 && c->mlp_hidden <= 3, "mlp_hidden must be in 1..3");
+  CHECK_ARG(c->mlp_width == 32 || c->mlp_width == 64 || c->mlp_width == 128, "mlp_width must be 32, 64 or 128");
+  CHECK_ARG(c->act == NPG_ACT_RELU || c->act == NPG_ACT_LEAKY, "act must be NPG_ACT_RELU or NPG_ACT_LEAKY");
+  CHECK_ARG(isfinite(c->leaky_slope) && c->leaky_slope > 0.f, "leaky_slope must be > 0");
+  CHECK_ARG(isfinite(c->alpha_t), "alpha_t must be finite");
+  CHECK_ARG(c->beta1 >= 0.f && c->beta1 < 1.f && c->beta2 >= 0.f && c->beta2 < 1.f, "Adam betas must be in [0,1)");
+  CHECK_ARG(c->eps > 0.f, "eps must be > 0");
+  CHECK_ARG(c->cg_maxit >= 1 && c->cg_rtol > 0.0, "cg_maxit >= 1 and cg_rtol > 0 are required");
+  CHECK_ARG(c->precond == NPG_PRECOND_CG, "only NPG_PRECOND_CG is available in this build");
+  return NPG_OK;
+}
+
+}  // namespace
+
+npg_status npg_fail(npg_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+extern "C" {
+
+const char* npg_last_error(void) { return g_err.c_str(); }
+
+npg_status npg_param_count(const npg_config* cfg, int64_t* count) {
+  TRY(validate_cfg(cfg));
+  CHECK_ARG(count, "count_host is NULL");
+  int64_t n = 0;
+  for (int l = 0; l < cfg->n_levels; ++l) n += (int64_t)cfg->res[l] * cfg->res[l] * cfg->res[l] * cfg->feat_p;
+  n += (int64_t)cfg->res_n * cfg->res_n * cfg->res_n * cfg->feat_n;
+  const int W = cfg->mlp_width, H = cfg->mlp_hidden;
+  const int Din = cfg->feat_n + cfg->feat_p + (cfg->time_freqs > 0 ? 2 * cfg->time_freqs : 1);
+  n += (int64_t)W * Din + W + (int64_t)(H - 1) * ((int64_t)W * W + W) + 6 * (int64_t)W + 6;
+  *count = n;
+  return NPG_OK;
+}
+
+npg_status npg_plan_destroy(npg_plan* P) {
+  if (!P) return NPG_OK;
+  hipStreamSynchronize(P->stream);
+  void* bufs[] = {P->xyz, P->nrm, P->pts, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
+                  P->seg_chunk0, P->chunk_start, P->chunk_sum, P->chunk_sys, P->params, P->m, P->v, P->grad,
+                  P->z, P->gz, P->xhat, P->gxhat, P->a, P->b, P->da, P->db, P->cd, P->w, P->loss, P->colpart,
+                  P->acc, P->mlpA, P->mlpB, P->wpack, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->gam, P->d_flag};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  npg_cg_free(P);
+  for (auto& e : P->ev)
+    if (e) hipEventDestroy(e);
+  delete P;
+  return NPG_OK;
+}
+
+npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, const float* nrm, int32_t T,
+                           const float* pts, const int64_t* off, void* stream, npg_plan** out) {
+  CHECK_ARG(out, "out is NULL");
+  *out = nullptr;
+  TRY(validate_cfg(cfg));
+  CHECK_ARG(V >= 1 && V < ((int64_t)1 << 31) / 16, "V must be in 1..2^27");
+  CHECK_ARG(T >= 1, "T must be >= 1");
+  CHECK_ARG(xyz && nrm && pts && off, "input pointers must be non-NULL");
+  CHECK_ARG(off[0] == 0, "frame_off[0] must be 0");
+  int64_t Nmax = 0;
+  for (int t = 0; t < T; ++t) {
+    CHECK_ARG(off[t + 1] > off[t], "every frame needs at least one point (frame_off strictly increasing)");
+    Nmax = std::max(Nmax, off[t + 1] - off[t]);
+  }
+  CHECK_ARG(off[T] < ((int64_t)1 << 31), "total point count must be < 2^31");
+  CHECK_ARG(cfg->t_key >= -1 && cfg->t_key < T, "t_key must be -1 or a frame index");
+
+  npg_plan* P = new npg_plan();  // value-initialised: every pointer starts NULL
+  P->off_h.assign(off, off + T + 1);
+  P->cfg = *cfg;
+  P->stream = (hipStream_t)stream;
+  P->V = V;
+  P->T = T;
+  P->Ntot = off[T];
+  P->Nmax = Nmax;
+  P->L = cfg->n_levels;
+  P->n_sys = P->L + 1;
+  P->t_key = cfg->t_key >= 0 ? cfg->t_key : (T - 1) / 2;
+  auto fail = [&](npg_status s) {
+    std::string keep = g_err;
+    npg_plan_destroy(P);
+    g_err = keep;
+    return s;
+  };
+#define TRYP(x)                        \
+  do {                                 \
+    npg_status s_ = (x);               \
+    if (s_ != NPG_OK) return fail(s_); \
+  } while (0)
+#define HIPP(x)                                                                                  \
+  do {                                                                                           \
+    hipError_t e_ = (x);                                                                         \
+    if (e_ != hipSuccess) return fail(npg_fail(NPG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+
+  HIPP(hipGetDevice(&P->device));
+  int ncu = 0;
+  HIPP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device));
+  P->n_cu = ncu > 0 ? ncu : 256;
+
+  // grid systems: position levels then the normal grid
+  int64_t poff = 0, noff = 0;
+  for (int s = 0; s < P->n_sys; ++s) {
+    NpgGrid& g = P->g[s];
+    const bool pos = s < P->L;
+    g.R = pos ? cfg->res[s] : cfg->res_n;
+    g.F = pos ? cfg->feat_p : cfg->feat_n;
+    g.nodes = (int64_t)g.R * g.R * g.R;
+    g.poff = poff;
+    g.noff = noff;
+    g.lam = pos ? cfg->lam[s] : cfg->lam_n;
+    g.lr = pos ? cfg->lr_grid[s] : cfg->lr_n;
+    g.scale = pos ? 1.0f / (float)P->L : 1.0f;
+    poff += g.nodes * g.F;
+    noff += g.nodes;
+  }
+  P->n_grid_params = poff;
+  P->n_nodes = noff;
+  P->mlp_off = poff;
+  TRYP(npg_param_count(cfg, &P->n_params));
+  if (noff >= ((int64_t)1 << 31)) return fail(npg_fail(NPG_EINVAL, "grids too large (2^31 nodes)"));
+  P->W = cfg->mlp_width;
+  P->H = cfg->mlp_hidden;
+  P->M = cfg->time_freqs;
+  P->Fz = cfg->feat_n + cfg->feat_p;
+  P->Din = P->Fz + (P->M > 0 ? 2 * P->M : 1);
+
+  // inputs
+  TRYP(dalloc(&P->xyz, V));
+  TRYP(dalloc(&P->nrm, V));
+  TRYP(dalloc(&P->pts, P->Ntot));
+  TRYP(dalloc(&P->d_off, T + 1));
+  TRYP(dalloc(&P->pt_frame, P->Ntot));
+  TRYP(dalloc(&P->d_g, P->n_sys));
+  TRYP(dalloc(&P->d_flag, 4));
+  HIPP(hipMemcpy(P->d_off, off, (T + 1) * 8, hipMemcpyHostToDevice));
+  HIPP(hipMemcpy(P->d_g, P->g, sizeof(NpgGrid) * P->n_sys, hipMemcpyHostToDevice));
+  HIPP(hipMemsetAsync(P->d_flag, 0, 16, P->stream));
+  HIPP(npg_launch_check_finite(xyz, 3 * V, P->d_flag, P->stream));
+  HIPP(npg_launch_check_finite(nrm, 3 * V, P->d_flag, P->stream));
+  HIPP(npg_launch_check_finite(pts, 3 * P->Ntot, P->d_flag, P->stream));
+  int bad = 0;
+  HIPP(hipMemcpyAsync(&bad, P->d_flag, 4, hipMemcpyDeviceToHost, P->stream));
+  HIPP(hipStreamSynchronize(P->stream));
+  if (bad) return fail(npg_fail(NPG_EINVAL, "non-finite value in ref_xyz, ref_nrm or pts"));
+  HIPP(npg_launch_pack(xyz, P->xyz, V, P->stream));
+  HIPP(npg_launch_pack(nrm, P->nrm, V, P->stream));
+  HIPP(npg_launch_pack(pts, P->pts, P->Ntot, P->stream));
+  HIPP(npg_launch_point_frames(P->d_off, T, P->pt_frame, P->Ntot, P->stream));
+  const int Dt = P->Din - P->Fz;
+  TRYP(dalloc(&P->gam, (int64_t)T * Dt));
+  hipLaunchKernelGGL(k_gamma, dim3((T + 127) / 128), dim3(128), 0, P->stream, T, P->M, P->gam);
+  HIPP(hipGetLastError());
+
+  TRYP(npg_build_scatter_table(P));
+
+  // optimizer state and intermediates
+  const int64_t NP = P->n_params;
+  TRYP(dalloc(&P->params, NP));
+  TRYP(dalloc(&P->m, NP));
+  TRYP(dalloc(&P->v, NP));
+  TRYP(dalloc(&P->grad, NP));
+  HIPP(hipMemsetAsync(P->params, 0, NP * 4, P->stream));
+  HIPP(hipMemsetAsync(P->m, 0, NP * 4, P->stream));
+  HIPP(hipMemsetAsync(P->v, 0, NP * 4, P->stream));
+  TRYP(dalloc(&P->z, V * P->Fz));
+  TRYP(dalloc(&P->gz, V * P->Fz));
+  const int64_t TV = (int64_t)T * V;
+  TRYP(dalloc(&P->xhat, TV));
+  TRYP(dalloc(&P->gxhat, TV));
+  TRYP(dalloc(&P->a, TV));
+  TRYP(dalloc(&P->da, TV));
+  TRYP(dalloc(&P->b, P->Ntot));
+  TRYP(dalloc(&P->db, P->Ntot));
+  TRYP(dalloc(&P->cd, T));
+  TRYP(dalloc(&P->w, T));
+  TRYP(dalloc(&P->loss, 1));
+  const int VB = npg_chamfer_vblock();
+  P->nvb = (int)((V + VB - 1) / VB);
+  TRYP(dalloc(&P->colpart, (int64_t)T * P->nvb * Nmax));
+  TRYP(dalloc(&P->acc, 3 * TV));
+  TRYP(dalloc(&P->mlpA, V * P->W));
+  TRYP(dalloc(&P->mlpB, (int64_t)T * P->W));
+  TRYP(dalloc(&P->wpack, npg_wpack_len(P->W, P->H)));
+  P->n_vblk_mlp = (int)((V + 63) / 64);
+  P->gw_part_len = npg_gw_part_len(P->W, P->H);
+  TRYP(dalloc(&P->Gv, V * P->W));
+  TRYP(dalloc(&P->Gt, (int64_t)T * P->W));
+  TRYP(dalloc(&P->Gt_part, (int64_t)T * P->n_vblk_mlp * P->W));
+  TRYP(dalloc(&P->gW_part, (int64_t)P->n_vblk_mlp * P->gw_part_len));
+  TRYP(npg_cg_setup(P));
+  for (auto& e : P->ev) HIPP(hipEventCreate(&e));
+  P->adam_k = 0;
+  HIPP(hipStreamSynchronize(P->stream));
+  *out = P;
+  return NPG_OK;
+#undef TRYP
+#undef HIPP
+}
+
+npg_status npg_set_state(npg_plan* P, const float* params, const float* m, const float* v, int64_t k) {
+  CHECK_ARG(P && params, "plan and params_dev must be non-NULL");
+  CHECK_ARG(k >= 0, "adam_steps must be >= 0");
+  const size_t nb = (size_t)P->n_params * 4;
+  NPG_HIP(hipMemcpyAsync(P->params, params, nb, hipMemcpyDeviceToDevice, P->stream));
+  if (m) NPG_HIP(hipMemcpyAsync(P->m, m, nb, hipMemcpyDeviceToDevice, P->stream));
+  else NPG_HIP(hipMemsetAsync(P->m, 0, nb, P->stream));
+  if (v) NPG_HIP(hipMemcpyAsync(P->v, v, nb, hipMemcpyDeviceToDevice, P->stream));
+  else NPG_HIP(hipMemsetAsync(P->v, 0, nb, P->stream));
+  P->adam_k = k;
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  return NPG_OK;
+}
+
+npg_status npg_get_state(npg_plan* P, float* params, float* m, float* v, int64_t* k) {
+  CHECK_ARG(P, "plan is NULL");
+  const size_t nb = (size_t)P->n_params * 4;
+  if (params) NPG_HIP(hipMemcpyAsync(params, P->params, nb, hipMemcpyDeviceToDevice, P->stream));
+  if (m) NPG_HIP(hipMemcpyAsync(m, P->m, nb, hipMemcpyDeviceToDevice, P->stream));
+  if (v) NPG_HIP(hipMemcpyAsync(v, P->v, nb, hipMemcpyDeviceToDevice, P->stream));
+  if (k) *k = P->adam_k;
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  return NPG_OK;
+}
+
+npg_status npg_encode_fwd(npg_plan* P, const float* params, float* z) {
+  CHECK_ARG(P && params && z, "NULL argument");
+  NPG_HIP(npg_launch_encode_fwd(P, params, z));
+  return NPG_OK;
+}
+
+npg_status npg_decode_fwd(npg_plan* P, const float* params, const float* z, float* xhat) {
+  CHECK_ARG(P && params && z && xhat, "NULL argument");
+  NPG_HIP(npg_launch_decode_fwd(P, params, z, reinterpret_cast<float4*>(xhat)));
+  return NPG_OK;
+}
+
+npg_status npg_chamfer_fwd(npg_plan* P, const float* xhat, int32_t* a, float* da, int32_t* b, float* db,
+                           double* cd) {
+  CHECK_ARG(P && xhat && a && da && b && db && cd, "NULL argument");
+  NPG_HIP(npg_launch_chamfer_fwd(P, reinterpret_cast<const float4*>(xhat), a, da, b, db, cd));
+  return NPG_OK;
+}
+
+npg_status npg_loss(npg_plan* P, const double* cd, int32_t epoch, int32_t n_epochs, double* w, double* loss) {
+  CHECK_ARG(P && cd && w && loss, "NULL argument");
+  CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
+  NPG_HIP(npg_launch_loss(P, cd, epoch, n_epochs, w, loss));
+  return NPG_OK;
+}
+
+npg_status npg_chamfer_bwd(npg_plan* P, const float* xhat, const int32_t* a, const int32_t* b, const double* w,
+                           float* gxhat) {
+  CHECK_ARG(P && xhat && a && b && w && gxhat, "NULL argument");
+  NPG_HIP(npg_launch_chamfer_bwd(P, reinterpret_cast<const float4*>(xhat), a, b, w,
+                                 reinterpret_cast<float4*>(gxhat)));
+  return NPG_OK;
+}
+
+npg_status npg_decode_bwd(npg_plan* P, const float* params, const float* z, const float* gxhat, float* grad,
+                          float* gz) {
+  CHECK_ARG(P && params && z && gxhat && grad && gz, "NULL argument");
+  NPG_HIP(npg_launch_decode_bwd(P, params, z, reinterpret_cast<const float4*>(gxhat), grad, gz));
+  return NPG_OK;
+}
+
+npg_status npg_encode_bwd(npg_plan* P, const float* gz, float* grad) {
+  CHECK_ARG(P && gz && grad, "NULL argument");
+  NPG_HIP(npg_launch_encode_bwd(P, gz, grad));
+  return NPG_OK;
+}
+
+npg_status npg_precond(npg_plan* P, float* grad, int32_t* iters) {
+  CHECK_ARG(P && grad, "NULL argument");
+  return npg_run_precond_cg(P, grad, iters);
+}
+
+npg_status npg_adam(npg_plan* P, float* params, const float* grad, float* m, float* v, int64_t k) {
+  CHECK_ARG(P && params && grad && m && v, "NULL argument");
+  CHECK_ARG(k >= 1, "adam_step must be >= 1");
+  NPG_HIP(npg_launch_adam(P, params, grad, m, v, k, P->d_flag));
+  return NPG_OK;
+}
+
+npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_out, double* cd_out) {
+  CHECK_ARG(P, "plan is NULL");
+  CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
+  hipStream_t s = P->stream;
+  NPG_HIP(hipEventRecord(P->ev[0], s));
+  NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
+  NPG_HIP(hipEventRecord(P->ev[1], s));
+  NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+  NPG_HIP(hipEventRecord(P->ev[2], s));
+  NPG_HIP(npg_launch_chamfer_fwd(P, P->xhat, P->a, P->da, P->b, P->db, P->cd));
+  NPG_HIP(npg_launch_loss(P, P->cd, epoch, n_epochs, P->w, P->loss));
+  NPG_HIP(hipEventRecord(P->ev[3], s));
+  NPG_HIP(npg_launch_chamfer_bwd(P, P->xhat, P->a, P->b, P->w, P->gxhat));
+  NPG_HIP(hipEventRecord(P->ev[4], s));
+  NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz));
+  NPG_HIP(hipEventRecord(P->ev[5], s));
+  NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
+  NPG_HIP(hipEventRecord(P->ev[6], s));
+  npg_status pst = npg_run_precond_cg(P, P->grad, nullptr);
+  if (pst != NPG_OK && pst != NPG_ENOTCONV) return pst;
+  NPG_HIP(hipEventRecord(P->ev[7], s));
+  P->adam_k += 1;
+  NPG_HIP(npg_launch_adam(P, P->params, P->grad, P->m, P->v, P->adam_k, P->d_flag));
+  NPG_HIP(hipEventRecord(P->ev[8], s));
+  if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
+  if (cd_out) NPG_HIP(hipMemcpyAsync(cd_out, P->cd, 8 * (size_t)P->T, hipMemcpyDeviceToDevice, s));
+  int flag = 0;
+  NPG_HIP(hipMemcpyAsync(&flag, P->d_flag, 4, hipMemcpyDeviceToHost, s));
+  NPG_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    NPG_HIP(hipMemsetAsync(P->d_flag, 0, 4, s));
+    return npg_fail(NPG_ENONFINITE, "a non-finite value was produced during the step");
+  }
+  if (pst == NPG_ENOTCONV) return npg_fail(NPG_ENOTCONV, "a CG solve reached cg_maxit");
+  return NPG_OK;
+}
+
+npg_status npg_stage_times(npg_plan* P, float* ms) {
+  CHECK_ARG(P && ms, "NULL argument");
+  for (int k = 0; k < 8; ++k) NPG_HIP(hipEventElapsedTime(ms + k, P->ev[k], P->ev[k + 1]));
+  return NPG_OK;
+}
+
+npg_status npg_deform(npg_plan* P, float* out) {
+  CHECK_ARG(P && out, "NULL argument");
+  NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
+  NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+  const int64_t n = (int64_t)P->T * P->V;
+  hipLaunchKernelGGL(k_unpack_xyz, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P->stream, P->xhat, out, n);
+  NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
+
+}  // extern "C"

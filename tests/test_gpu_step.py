@@ -1,0 +1,186 @@
+"""Full-step parity (npg_step) against the oracle, determinism, edge cases and
+the headline-size workload on sampled outputs (needs a GPU)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import block_rel, flat_params, gpu_plan, nn_check, rel, to_np
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _touched_nodes(cfg, data):
+    """Nodes read by the grid lookup of some reference vertex (per grid)."""
+    X = data["xyz"].astype(np.float64)
+    Nr = data["nrm"].astype(np.float64)
+    out = []
+    for R in list(cfg["levels"]) + [cfg["res_n"]]:
+        Q = X if len(out) < len(cfg["levels"]) else Nr
+        nodes = set()
+        for node, _ in O.neupig._corners(Q, R):
+            nodes.update(node.tolist())
+        out.append(np.array(sorted(nodes)))
+    return out
+
+
+def test_teacher_forced_steps_on_icosphere():
+    """Each step starts both sides from the oracle's state (Adam moments
+    included). Loss, per-frame Chamfer distances and the updated MLP and
+    touched grid nodes must match; nodes no vertex reads never influence the
+    loss and are only checked against Adam's step bound."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_c1()
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    touched = _touched_nodes(cfg, data)
+    P = O.to64(synth.init_params(cfg))
+    m, v = O.zeros_like_params(P), O.zeros_like_params(P)
+    E = cfg["n_steps"]
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    cd = torch.empty(cfg["T"], dtype=torch.float64, device="cuda")
+    for e in range(5):
+        plan.set_state(flat_params(cfg, P), flat_params(cfg, m), flat_params(cfg, v), e)
+        st = plan.step(e, E, loss, cd)
+        assert st == npg.NPG_OK
+        pg, mg, vg, k = plan.get_state()
+        assert k == e + 1
+        Pn, mn, vn, d = O.step(P, m, v, e + 1, data, cfg, e, E)
+        assert abs(loss.item() - d["ls"]["loss"]) <= TOL * d["ls"]["loss"]
+        assert rel(to_np(cd), d["ls"]["cd"]) < TOL
+        got = npg.unpack_params(cfg, to_np(pg))
+        for k_, ((W, b), (Wr, br)) in enumerate(zip(got["mlp"], Pn["mlp"])):
+            assert rel(W, Wr) < TOL and rel(b, br) < TOL, (e, k_, rel(W, Wr), rel(b, br))
+        grids_g = got["grid_p"] + [got["grid_n"]]
+        grids_o = Pn["grid_p"] + [Pn["grid_n"]]
+        lrs = list(cfg["lr_grid"]) + [cfg["lr_n"]]
+        for l, (g, r, tn, lr, g0) in enumerate(zip(grids_g, grids_o, touched, lrs, P["grid_p"] + [P["grid_n"]])):
+            assert rel(g[tn], r[tn]) < TOL, (e, l, rel(g[tn], r[tn]))
+            # Adam moves any entry by at most lr / (1 - beta1) per step
+            assert np.all(np.abs(g - g0) <= lr / (1 - cfg["beta1"]) * 1.001 + 1e-6)
+        P, m, v = Pn, mn, vn
+    plan.close()
+
+
+def test_step_is_bitwise_deterministic():
+    import torch
+    cfg = synth.config_c1()
+    data = synth.make_workload(cfg)
+    flat = flat_params(cfg, synth.random_state(cfg, 3))
+    outs = []
+    for _ in range(2):
+        plan = gpu_plan(cfg, data)
+        plan.set_state(flat, adam_steps=0)
+        for e in range(2):
+            plan.step(e, 10)
+        outs.append(plan.get_state()[0])
+        plan.close()
+    assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("V,T,N", [(1, 1, [1]), (65, 1, [3]), (130, 3, [1, 2, 400]), (2049, 2, [257, 5])])
+def test_edge_sizes_single_step(V, T, N):
+    """Degenerate and ragged sizes: one vertex, one frame, one-point frames,
+    vertex counts one past a block boundary."""
+    import torch
+    cfg = synth.config_small(mlp_width=32, V=V, T=T, N=N, t_key=0, levels=[2, 3], feat_p=3, seed=V + T)
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    P = O.to64(synth.random_state(cfg, 1))
+    plan.set_state(flat_params(cfg, P), adam_steps=0)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    cd = torch.empty(T, dtype=torch.float64, device="cuda")
+    plan.step(0, 3, loss, cd)
+    _, _, _, d = O.step(P, O.zeros_like_params(P), O.zeros_like_params(P), 1, data, cfg, 0, 3)
+    assert rel(to_np(cd), d["ls"]["cd"]) < TOL
+    assert abs(loss.item() - d["ls"]["loss"]) <= TOL * abs(d["ls"]["loss"])
+    xh = torch.empty(T * V * 3, device="cuda")
+    plan.deform(xh)
+    plan.close()
+
+
+def test_nonfinite_inputs_are_rejected():
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_small(mlp_width=32)
+    data = synth.make_workload(cfg)
+    data["pts"][3, 1] = np.nan
+    with pytest.raises(npg.NpgError) as e:
+        gpu_plan(cfg, data)
+    assert e.value.status == npg.NPG_EINVAL
+
+
+def test_cg_cap_is_reported():
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_small(mlp_width=32, cg_maxit=1, cg_rtol=1e-12, levels=[6, 9])
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    plan.set_state(flat_params(cfg, synth.random_state(cfg, 2)), adam_steps=0)
+    assert plan.step(0, 3) == npg.NPG_ENOTCONV
+    plan.close()
+
+
+def test_headline_workload_sampled():
+    """Human workload at full size (30k vertices, 100 frames, 10k points per
+    frame, 8 levels 16..256, width 128) in the launch configuration the
+    benchmark times: sampled vertices/points and sampled frames checked
+    against the oracle evaluated one by one."""
+    import time
+
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_c2()
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    T, V = data["T"], len(data["xyz"])
+    P = O.to64(synth.random_state(cfg, 9, grid_std=0.05))
+    flat = flat_params(cfg, P)
+    z = torch.empty(V * plan.Fz, device="cuda")
+    xh = torch.empty(T * V * 4, device="cuda")
+    plan.encode_fwd(flat, z)
+    plan.decode_fwd(flat, z, xh)
+    rng = np.random.default_rng(0)
+    vs = rng.choice(V, 64, replace=False)
+    ts = np.array([0, 37, 99])
+    X = data["xyz"].astype(np.float64)[vs]
+    Nr = data["nrm"].astype(np.float64)[vs]
+    zr = O.encode(P, X, Nr, cfg["levels"], cfg["res_n"])
+    assert rel(to_np(z).reshape(V, -1)[vs], zr) < TOL
+    gam = O.time_code(T, cfg["time_freqs"])[ts]
+    o, _, _ = O.mlp_forward(P["mlp"], O.decoder_input(zr, gam), cfg["act"], cfg["leaky_slope"])
+    xr, _, _ = O.transform(o, np.tile(X, (len(ts), 1)), cfg["alpha_t"])
+    xg = to_np(xh).reshape(T, V, 4)[ts][:, vs, :3].reshape(-1, 3)
+    assert rel(xg, xr) < TOL
+    # Chamfer on two full frames (float64 brute force on the GPU's float32 inputs)
+    N = plan.Ntot
+    a = torch.empty(T * V, dtype=torch.int32, device="cuda")
+    da = torch.empty(T * V, device="cuda")
+    b = torch.empty(N, dtype=torch.int32, device="cuda")
+    db = torch.empty(N, device="cuda")
+    cd = torch.empty(T, dtype=torch.float64, device="cuda")
+    plan.chamfer_fwd(xh, a, da, b, db, cd)
+    off = data["frame_off"]
+    xha = to_np(xh).reshape(T, V, 4)[..., :3]
+    for t in (0, 99):
+        Pt = data["pts"][off[t]:off[t + 1]]
+        t0 = time.time()
+        ties = nn_check(xha[t], Pt, to_np(a).reshape(T, V)[t], to_np(b)[off[t]:off[t + 1]])
+        cdo = O.chamfer(xha[t].astype(np.float64), Pt.astype(np.float64))[4]
+        assert abs(to_np(cd)[t] - cdo) <= TOL * cdo
+        print(f"frame {t}: ties {ties}, oracle {time.time() - t0:.1f}s")
+    # a full step runs and lowers the loss from the paper's identity start
+    plan.set_state(flat_params(cfg, synth.init_params(cfg)), adam_steps=0)
+    l0 = torch.empty(1, dtype=torch.float64, device="cuda")
+    l1 = torch.empty(1, dtype=torch.float64, device="cuda")
+    plan.step(0, 500, l0)
+    for e in range(1, 4):
+        plan.step(e, 500, l1)
+    assert l1.item() < l0.item()
+    plan.close()
