@@ -237,6 +237,22 @@ npg_status npg_adam(npg_plan* plan, float* params_dev, const float* grad_dev, fl
  * precond, adam. Valid after the stream has finished the step. */
 npg_status npg_stage_times(npg_plan* plan, float* ms_host);
 
+/*
+ * Profiling of the preconditioner's CG iteration (the k_cg_dir_ap +
+ * k_cg_update kernel pair): with enable != 0, npg_step records HIP events
+ * around both kernels of every iteration on the plan's stream and resolves
+ * them after the step (one extra stream synchronisation per step). Enabling
+ * resets the accumulators.
+ */
+npg_status npg_profile(npg_plan* plan, int32_t enable);
+
+/* Accumulated since npg_profile(plan, 1): summed kernel time of the CG
+ * iteration pairs (ms), number of iterations, and their algorithmic bytes
+ * (6 float32 vector passes -- x, r, p each read and written -- over every
+ * active grid's R^3 F unknowns per iteration). */
+npg_status npg_profile_read(npg_plan* plan, double* cg_ms_host, int64_t* cg_iters_host,
+                            double* cg_bytes_host);
+
 #ifdef __cplusplus
 }
 #endif

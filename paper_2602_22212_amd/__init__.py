@@ -64,6 +64,8 @@ _SIGS = {
     "npg_precond": ([_P, _P, ctypes.POINTER(_I32)], ctypes.c_int),
     "npg_adam": ([_P, _P, _P, _P, _P, _I64], ctypes.c_int),
     "npg_stage_times": ([_P, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "npg_profile": ([_P, _I32], ctypes.c_int),
+    "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
 }
 
 
@@ -242,6 +244,14 @@ class Plan:
         buf = (ctypes.c_float * 8)()
         _check(lib().npg_stage_times(self._h, buf))
         return dict(zip(STAGES, list(buf)))
+
+    def profile(self, enable=True):
+        _check(lib().npg_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        ms, it, by = _D(), _I64(), _D()
+        _check(lib().npg_profile_read(self._h, ctypes.byref(ms), ctypes.byref(it), ctypes.byref(by)))
+        return dict(cg_ms=ms.value, cg_iters=it.value, cg_bytes=by.value)
 
     # -- stages ---------------------------------------------------------------
     def encode_fwd(self, params, z):

@@ -22,8 +22,8 @@ struct NpgGrid {
 };
 
 struct NpgCG {  // conjugate-gradient workspace
-  float *x, *r, *p, *q;        // [n_grid_params] each, grid layout
-  double* part;                // [n_blocks][2][4] per-block partial dots
+  float *x, *r, *p, *q;        // [n_grid_params] each, grid layout (p, q: ping-pong directions)
+  double* part;                // [n_blocks][4 waves][4 channels] partial dots
   double* st;                  // [n_sys][4][8] per-system/channel scalars
   int* active;                 // [n_sys] any channel still iterating
   int* any_active;             // [1]
@@ -90,7 +90,15 @@ struct npg_plan {
   int* d_flag;             // non-finite flag
   hipEvent_t ev[10];
   float stage_ms[8];
-  bool timing;
+  // optional per-launch timing of the CG iteration kernels (profiling only)
+  int prof_cg;
+  std::vector<hipEvent_t> prof_ev;  // 4 per CG iteration
+  int prof_n;                       // events recorded in the current step
+  double prof_cg_ms;                // accumulated kernel time of resolved steps
+  int64_t prof_cg_launches;         // accumulated CG iterations (kernel pairs)
+  double prof_cg_bytes;             // accumulated algorithmic bytes
+  double cg_alg_bytes;              // algorithmic bytes of the last preconditioner call
+  int64_t cg_iters_sum;             // sum over grids and solves of the iteration counts
 };
 
 // error helpers (plan.hip)

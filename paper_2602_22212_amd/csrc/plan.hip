@@ -126,6 +126,8 @@ npg_status npg_plan_destroy(npg_plan* P) {
   npg_cg_free(P);
   for (auto& e : P->ev)
     if (e) hipEventDestroy(e);
+  for (auto& e : P->prof_ev)
+    if (e) hipEventDestroy(e);
   delete P;
   return NPG_OK;
 }
@@ -388,6 +390,19 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
   P->adam_k += 1;
   NPG_HIP(npg_launch_adam(P, P->params, P->grad, P->m, P->v, P->adam_k, P->d_flag));
   NPG_HIP(hipEventRecord(P->ev[8], s));
+  if (P->prof_cg) {
+    // resolve this step's CG kernel timings (the stream is drained below)
+    NPG_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k + 3 < P->prof_n; k += 4) {
+      float a = 0.f, b = 0.f;
+      NPG_HIP(hipEventElapsedTime(&a, P->prof_ev[k], P->prof_ev[k + 1]));
+      NPG_HIP(hipEventElapsedTime(&b, P->prof_ev[k + 2], P->prof_ev[k + 3]));
+      P->prof_cg_ms += (double)a + (double)b;
+    }
+    P->prof_cg_launches += P->prof_n / 4;
+    P->prof_cg_bytes += P->cg_alg_bytes;
+    P->prof_n = 0;
+  }
   if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
   if (cd_out) NPG_HIP(hipMemcpyAsync(cd_out, P->cd, 8 * (size_t)P->T, hipMemcpyDeviceToDevice, s));
   int flag = 0;
@@ -398,6 +413,28 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
     return npg_fail(NPG_ENONFINITE, "a non-finite value was produced during the step");
   }
   if (pst == NPG_ENOTCONV) return npg_fail(NPG_ENOTCONV, "a CG solve reached cg_maxit");
+  return NPG_OK;
+}
+
+npg_status npg_profile(npg_plan* P, int32_t enable) {
+  CHECK_ARG(P, "plan is NULL");
+  if (enable && P->prof_ev.empty()) {
+    P->prof_ev.resize(4 * 2 * (size_t)P->cfg.cg_maxit + 8, nullptr);
+    for (auto& e : P->prof_ev) NPG_HIP(hipEventCreate(&e));
+  }
+  P->prof_cg = enable ? 1 : 0;
+  P->prof_n = 0;
+  P->prof_cg_ms = 0.0;
+  P->prof_cg_launches = 0;
+  P->prof_cg_bytes = 0.0;
+  return NPG_OK;
+}
+
+npg_status npg_profile_read(npg_plan* P, double* cg_ms, int64_t* cg_iters, double* cg_bytes) {
+  CHECK_ARG(P && cg_ms && cg_iters && cg_bytes, "NULL argument");
+  *cg_ms = P->prof_cg_ms;
+  *cg_iters = P->prof_cg_launches;
+  *cg_bytes = P->prof_cg_bytes;
   return NPG_OK;
 }
 
