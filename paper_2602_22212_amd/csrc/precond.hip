@@ -18,10 +18,11 @@
 // differences keep the float32 rounding proportional to |A p|, not to
 // (1 + 12 lam)|p|.
 //
-// Work-groups are mapped XCD-aware: consecutive work-group ids go round-robin
-// to the 8 XCDs, so the logical chunk of id b is (b % 8) * per_xcd + b / 8
-// and each XCD streams one contiguous slab of nodes; the +-R^2 neighbour
-// planes are then read from the same XCD's L2.
+// Large grids (R >= 100) are walked in z-columns (registers carry the z
+// neighbours); small grids in contiguous node chunks. Work-groups are
+// dispatched largest grid first.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace {
@@ -29,7 +30,6 @@ namespace {
 constexpr int kB = 256;       // threads per work-group
 constexpr int kPer = 8;       // nodes per thread
 constexpr int kChunk = kB * kPer;
-constexpr int kXcd = 8;
 
 // per (system, channel) scalars: 0 rr, 1 bb, 2 pq, 3 alpha, 4 beta, 5 active, 6 iterations
 constexpr int kS = 8;
@@ -81,11 +81,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Logical work-group of this launch (XCD-aware), or -1 past the end.
+// Logical work-group of this launch: the block table in reverse, so the
+// largest grids (last in the table) are dispatched first and the hardware's
+// round-robin spreads them evenly over the XCDs.
 __device__ __forceinline__ int logical_block(int nb) {
-  const int per = (nb + kXcd - 1) / kXcd;
-  const int lb = (int)(blockIdx.x % kXcd) * per + (int)(blockIdx.x / kXcd);
-  return lb < nb ? lb : -1;
+  const int lb = nb - 1 - (int)blockIdx.x;
+  return lb >= 0 ? lb : -1;
 }
 
 // Block partials of F channels, part[blk*4 + c]: wave sums, then the 4
@@ -248,6 +249,143 @@ __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
   store_partials<F>(acc, part, blk);
 }
 
+// ---- z-column walks for large grids -----------------------------------------
+// A work-group owns a kTX x kTY block of (x, y) columns and the z range
+// [z0, z1); each thread walks one column. The operand of the planes z-1, z
+// and z+1 stays in registers, so every vector is streamed from HBM about once
+// per kernel; the four in-plane neighbours are re-read from L1/L2 (they are
+// the neighbouring lanes' and rows' own loads). No LDS and no barriers.
+constexpr int kZmR = 100;  // grids with R >= kZmR, F = 4 and 16-byte alignment
+constexpr int kTX = 64, kTY = 4, kZS = 32;
+
+__device__ __forceinline__ bool use_zm(const NpgGrid& g) { return g.R >= kZmR && g.F == 4 && (g.poff % 4) == 0; }
+
+struct Tile {
+  int x0, y0, z0, z1;
+};
+__device__ __forceinline__ Tile unpack_tile(int64_t v) {
+  return Tile{(int)(v & 0xffff), (int)((v >> 16) & 0xffff), (int)((v >> 32) & 0xffff), (int)((v >> 48) & 0xffff)};
+}
+inline int64_t pack_tile(int x0, int y0, int z0, int z1) {
+  return (int64_t)x0 | ((int64_t)y0 << 16) | ((int64_t)z0 << 32) | ((int64_t)z1 << 48);
+}
+
+__device__ __forceinline__ float4 f4fma(float4 a, const float (&s)[4], float4 b) {  // a*s + b per channel
+  return make_float4(fmaf(s[0], a.x, b.x), fmaf(s[1], a.y, b.y), fmaf(s[2], a.z, b.z), fmaf(s[3], a.w, b.w));
+}
+__device__ __forceinline__ void f4lap(float4& acc, const float4& c, const float4& n) {
+  acc.x += c.x - n.x;
+  acc.y += c.y - n.y;
+  acc.z += c.z - n.z;
+  acc.w += c.w - n.w;
+}
+
+// LOAD(node) yields the stencil operand at a node; BODY(node, lap, cur)
+// consumes the operand and its Laplacian at every node of the column.
+template <typename LOAD, typename BODY>
+__device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LOAD load, BODY body) {
+  const int R = g.R;
+  const int64_t R2 = (int64_t)R * R;
+  const int x = t.x0 + (int)(threadIdx.x & (kTX - 1));
+  const int y = t.y0 + (int)(threadIdx.x / kTX);
+  if (x >= R || y >= R) return;
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  int64_t n = (int64_t)t.z0 * R2 + (int64_t)y * R + x;
+  float4 cur = load(n);
+  float4 prev = t.z0 > 0 ? load(n - R2) : zero;
+  for (int z = t.z0; z < t.z1; ++z, n += R2) {
+    const float4 nxt = z + 1 < R ? load(n + R2) : zero;
+    float4 lap = zero;
+    if (x > 0) f4lap(lap, cur, load(n - 1));
+    if (x < R - 1) f4lap(lap, cur, load(n + 1));
+    if (y > 0) f4lap(lap, cur, load(n - R));
+    if (y < R - 1) f4lap(lap, cur, load(n + R));
+    if (z > 0) f4lap(lap, cur, prev);
+    if (z < R - 1) f4lap(lap, cur, nxt);
+    body(n, lap, cur);
+    prev = cur;
+    cur = nxt;
+  }
+}
+
+__device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* x, float* r, float* p, double* part,
+                        int blk) {
+  const int R = g.R;
+  const int64_t R2 = (int64_t)R * R;
+  const int xx = t.x0 + (int)(threadIdx.x & (kTX - 1));
+  const int yy = t.y0 + (int)(threadIdx.x / kTX);
+  const float4* B = reinterpret_cast<const float4*>(b + g.poff);
+  float4* X = reinterpret_cast<float4*>(x + g.poff);
+  float4* Rr = reinterpret_cast<float4*>(r + g.poff);
+  float4* Pp = reinterpret_cast<float4*>(p + g.poff);
+  double acc[4] = {0, 0, 0, 0};
+  if (xx < R && yy < R)
+    for (int z = t.z0; z < t.z1; ++z) {
+      const int64_t n = (int64_t)z * R2 + (int64_t)yy * R + xx;
+      const float4 v = B[n];
+      X[n] = make_float4(0.f, 0.f, 0.f, 0.f);
+      Rr[n] = v;
+      Pp[n] = v;
+      acc[0] += (double)v.x * v.x;
+      acc[1] += (double)v.y * v.y;
+      acc[2] += (double)v.z * v.z;
+      acc[3] += (double)v.w * v.w;
+    }
+  store_partials<4>(acc, part, blk);
+}
+
+__device__ void zm_dir_ap(const NpgGrid& g, const Tile& t, const double* st, int s, const float* r,
+                          const float* p_old, float* p_new, double* part, int blk) {
+  float be[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) be[c] = (float)st[(s * 4 + c) * kS + 4];
+  const float lam = g.lam;
+  const float4* Rr = reinterpret_cast<const float4*>(r + g.poff);
+  const float4* Po = reinterpret_cast<const float4*>(p_old + g.poff);
+  float4* Pn = reinterpret_cast<float4*>(p_new + g.poff);
+  double acc[4] = {0, 0, 0, 0};
+  zm_walk(g, t, [&](int64_t n) { return f4fma(Po[n], be, Rr[n]); },
+          [&](int64_t n, const float4& lap, const float4& pn) {
+            acc[0] += (double)pn.x * (double)fmaf(lam, lap.x, pn.x);
+            acc[1] += (double)pn.y * (double)fmaf(lam, lap.y, pn.y);
+            acc[2] += (double)pn.z * (double)fmaf(lam, lap.z, pn.z);
+            acc[3] += (double)pn.w * (double)fmaf(lam, lap.w, pn.w);
+            Pn[n] = pn;
+          });
+  store_partials<4>(acc, part, blk);
+}
+
+__device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, float* x, float* r,
+                          const float* p, double* part, int blk) {
+  float al[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) al[c] = (float)st[(s * 4 + c) * kS + 3];
+  const float lam = g.lam;
+  const float4* Pp = reinterpret_cast<const float4*>(p + g.poff);
+  float4* X = reinterpret_cast<float4*>(x + g.poff);
+  float4* Rr = reinterpret_cast<float4*>(r + g.poff);
+  double acc[4] = {0, 0, 0, 0};
+  zm_walk(g, t, [&](int64_t n) { return Pp[n]; },
+          [&](int64_t n, const float4& lap, const float4& pc) {
+            float4 xv = X[n], rv = Rr[n];
+            xv.x = fmaf(al[0], pc.x, xv.x);
+            xv.y = fmaf(al[1], pc.y, xv.y);
+            xv.z = fmaf(al[2], pc.z, xv.z);
+            xv.w = fmaf(al[3], pc.w, xv.w);
+            rv.x = fmaf(-al[0], fmaf(lam, lap.x, pc.x), rv.x);
+            rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
+            rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
+            rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
+            X[n] = xv;
+            Rr[n] = rv;
+            acc[0] += (double)rv.x * rv.x;
+            acc[1] += (double)rv.y * rv.y;
+            acc[2] += (double)rv.z * rv.z;
+            acc[3] += (double)rv.w * rv.w;
+          });
+  store_partials<4>(acc, part, blk);
+}
+
 #define NPG_F_SWITCH(g, CALL)                                               \
   switch ((g).F * 2 + (int)(((g).poff % (g).F) == 0)) {                     \
     case 9: { constexpr int FF = 4; CALL; } break;                          \
@@ -267,6 +405,10 @@ __global__ __launch_bounds__(kB) void k_cg_init(const NpgGrid* __restrict__ G, i
   if (blk < 0) return;
   const int s = blk_sys[blk];
   const NpgGrid g = G[s];
+  if (use_zm(g)) {
+    zm_init(g, unpack_tile(blk_start[blk]), b, x, r, p, part, blk);
+    return;
+  }
   NPG_F_SWITCH(g, (init_body<FF>(g, blk_start[blk], b, x, r, p, part, blk)));
 }
 
@@ -284,6 +426,10 @@ __global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G,
   const int s = blk_sys[blk];
   if (!active[s]) return;
   const NpgGrid g = G[s];
+  if (use_zm(g)) {
+    zm_dir_ap(g, unpack_tile(blk_start[blk]), st, s, r, p_old, p_new, part, blk);
+    return;
+  }
   NPG_F_SWITCH(g, (dir_ap_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, r, p_old, p_new, part, blk)));
 }
 
@@ -297,6 +443,10 @@ __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G,
   const int s = blk_sys[blk];
   if (!active[s]) return;
   const NpgGrid g = G[s];
+  if (use_zm(g)) {
+    zm_update(g, unpack_tile(blk_start[blk]), st, s, x, r, p, part, blk);
+    return;
+  }
   NPG_F_SWITCH(g, (update_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, x, r, p, part, blk)));
 }
 
@@ -365,7 +515,7 @@ __global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, i
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-inline unsigned xcd_grid(int nb) { return (unsigned)(((nb + kXcd - 1) / kXcd) * kXcd); }
+inline unsigned xcd_grid(int nb) { return (unsigned)nb; }
 
 }  // namespace
 
@@ -376,9 +526,21 @@ npg_status npg_cg_setup(npg_plan* P) {
   std::vector<int> s0(P->n_sys + 1);
   for (int s = 0; s < P->n_sys; ++s) {
     s0[s] = (int)bsys.size();
-    for (int64_t n = 0; n < P->g[s].nodes; n += kChunk) {
-      bsys.push_back(s);
-      bstart.push_back(n);
+    const NpgGrid& g = P->g[s];
+    if (g.R >= kZmR && g.F == 4 && g.poff % 4 == 0) {
+      // z-marching tiles, z ranges interleaved so concurrently running
+      // work-groups share planes
+      for (int z0 = 0; z0 < g.R; z0 += kZS)
+        for (int y0 = 0; y0 < g.R; y0 += kTY)
+          for (int x0 = 0; x0 < g.R; x0 += kTX) {
+            bsys.push_back(s);
+            bstart.push_back(pack_tile(x0, y0, z0, std::min(g.R, z0 + kZS)));
+          }
+    } else {
+      for (int64_t n = 0; n < g.nodes; n += kChunk) {
+        bsys.push_back(s);
+        bstart.push_back(n);
+      }
     }
   }
   s0[P->n_sys] = (int)bsys.size();

@@ -296,3 +296,32 @@ def test_adam_matches_oracle(case):
         assert rel(to_np(T_[0])[sl], rt) < TOL and rel(to_np(T_[2])[sl], rm) < TOL
         assert rel(to_np(T_[3])[sl], rv) < TOL
     assert L >= 1
+
+
+@pytest.mark.parametrize("levels", [[100, 129, 20], [256]])
+def test_preconditioner_large_grids(levels):
+    """Grids of >= 100 nodes per axis run the z-marching CG kernels; 129 gives
+    partial tiles in x, y and z. Sparse vertex-gradient input as in a step,
+    plus a dense random component."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_small(levels=levels, feat_p=4, mlp_width=32, V=3000, T=1, N=10, t_key=0, seed=33)
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    rng = np.random.default_rng(12)
+    gz = torch.from_numpy(rng.normal(size=(plan.V * plan.Fz)).astype(np.float32)).cuda()
+    grad = torch.zeros(plan.n_params, dtype=torch.float32, device="cuda")
+    plan.encode_bwd(gz, grad)
+    n_grid = dict((name, o) for name, o, _ in npg.param_layout(cfg)[0])["W0"]
+    grad[:n_grid] += 1e-3 * torch.randn(n_grid, device="cuda")
+    g_in = npg.unpack_params(cfg, to_np(grad))
+    its, st = plan.precond(grad)
+    assert st == npg.NPG_OK, its
+    got = npg.unpack_params(cfg, to_np(grad))
+    errs = [rel(g, O.precond_dct(gi.astype(np.float64), R, lam))
+            for g, gi, R, lam in zip(got["grid_p"], g_in["grid_p"], cfg["levels"], cfg["lam"])]
+    errs.append(rel(got["grid_n"], O.precond_dct(g_in["grid_n"].astype(np.float64), cfg["res_n"], cfg["lam_n"])))
+    print("precond rel errors:", ["%.2e" % e for e in errs], "iterations:", its)
+    assert max(errs) < TOL
+    plan.close()
