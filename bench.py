@@ -96,44 +96,53 @@ def cpu_baseline(cfg, data, P0, frames):
                 stage_seconds={k: round(v, 3) for k, v in t.items()}, seconds_per_step=per_step)
 
 
+def run_form(cfg, data, P0, steps, warmup, profile):
+    """Time `steps` full optimization steps of one preconditioner form."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    plan = npg.plan_from_workload(cfg, data)
+    plan.set_state(torch.from_numpy(npg.pack_params(cfg, P0)).cuda(), adam_steps=0)
+    E = cfg["n_steps"]
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    for e in range(warmup):
+        plan.step(e, E, loss)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile(True)
+    stage_sum = {k: 0.0 for k in npg.STAGES}
+    t_total = 0.0
+    statuses = []
+    for k in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        statuses.append(plan.step(warmup + k, E, loss))
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+        for name, ms in plan.stage_times().items():
+            stage_sum[name] += ms
+    prof = plan.profile_read() if profile else None
+    plan.close()
+    return dict(value=steps / t_total, ms_per_step=1e3 * t_total / steps,
+                stage_ms={k: round(v / steps, 3) for k, v in stage_sum.items()},
+                status=sorted(set(int(s) for s in statuses)), prof=prof, loss=loss.item())
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the method is single-GPU; sharding is described, "
               f"not built): --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
-    import torch
-
-    import paper_2602_22212_amd as npg
     import synth
 
     cfg = synth.config_c2()
     data = synth.make_workload(cfg)
     T, V = data["T"], len(data["xyz"])
-    plan = npg.plan_from_workload(cfg, data)
     P0 = synth.random_state(cfg, 9, grid_std=0.05)
-    plan.set_state(torch.from_numpy(npg.pack_params(cfg, P0)).cuda(), adam_steps=0)
-    E = cfg["n_steps"]
-    loss = torch.empty(1, dtype=torch.float64, device="cuda")
-    for e in range(args.warmup):
-        plan.step(e, E, loss)
-    torch.cuda.synchronize()
-    plan.profile(True)
-    stage_sum = {k: 0.0 for k in npg.STAGES}
-    t_total = 0.0
-    statuses = []
-    for k in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        statuses.append(plan.step(args.warmup + k, E, loss))
-        torch.cuda.synchronize()
-        t_total += time.perf_counter() - t0
-        for name, ms in plan.stage_times().items():
-            stage_sum[name] += ms
-    prof = plan.profile_read()
-    plan.profile(False)
-    ms_per_step = 1e3 * t_total / args.steps
+    cg = run_form(dict(cfg, precond="cg"), data, P0, args.steps, args.warmup, profile=True)
+    dct = run_form(dict(cfg, precond="dct"), data, P0, args.steps, args.warmup, profile=False)
+    prof = cg["prof"]
     cg_iter_ms = prof["cg_ms"] / max(prof["cg_iters"], 1)
     achieved = (prof["cg_bytes"] / 1e9) / (prof["cg_ms"] / 1e3) if prof["cg_ms"] > 0 else 0.0
     traffic = traffic_from_profile()
@@ -146,12 +155,12 @@ def main():
                     alg_bytes_per_iteration=round(prof["cg_bytes"] / max(prof["cg_iters"], 1)))
     out = {
         "metric": "optimization steps/sec (fwd+bwd+precond) at 100 frames; fraction of FP32/MFMA peak",
-        "value": round(args.steps / t_total, 4),
+        "value": round(cg["value"], 4),
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(cg["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -161,13 +170,15 @@ def main():
                    "mlp": f"{cfg['feat_n'] + cfg['feat_p'] + 2 * cfg['time_freqs']}->{cfg['mlp_width']}x"
                           f"{cfg['mlp_hidden']}->6", "precond": "cg", "cg_rtol": cfg["cg_rtol"],
                    "parallelism": "single-gpu"},
-        "stage_ms": {k: round(v / args.steps, 3) for k, v in stage_sum.items()},
+        "stage_ms": cg["stage_ms"],
         "cg_iterations_per_step": round(prof["cg_iters"] / args.steps, 1),
-        "step_status": sorted(set(int(s) for s in statuses)),
+        "step_status": cg["status"],
         "roofline": roofline,
+        "precond_dct": {"value": round(dct["value"], 4), "unit": "steps/s",
+                        "ms_per_step": round(dct["ms_per_step"], 3), "stage_ms": dct["stage_ms"],
+                        "note": "same step with the exact DCT form of (I + lambda L)^-2"},
         "cpu_baseline": None,
     }
-    plan.close()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg, data, P0, args.cpu_frames)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

@@ -7,76 +7,108 @@
 // the argmin recovered in a second pass is the one the first pass saw.
 // Ties resolve to the lowest index in both directions.
 //
-// Main pass, per (frame, block of 256*K vertices): each thread keeps K
-// vertices in registers and streams the frame's points through LDS tiles.
-// The inner loop tracks values only: the running row minimum per vertex and,
-// per point, the minimum over the thread's K vertices, reduced across the
-// wave and then across the block with an LDS atomic min (exact and order
-// independent on the non-negative float bit patterns). The best tile of each
-// vertex is remembered and re-scanned afterwards to recover the lowest index.
-// Column minima of each vertex block are written out; a second pass takes
-// the minimum over blocks and re-scans the first block attaining it.
+// Main pass, per (frame, block of kT*kK vertices): each thread keeps kK
+// vertices in registers and streams the frame's points through LDS tiles, two
+// points per iteration. The inner loop tracks values only (min3 updates): the
+// running row minimum per vertex and, per point, the minimum over the
+// thread's vertices. That column value is reduced across the wave with DPP,
+// the lowest lane attaining it is found with a ballot, and an LDS 64-bit
+// atomic min over (distance bits, first vertex of that lane) combines the
+// waves (exact and order independent). The best tile of each vertex is
+// re-scanned afterwards to recover its lowest row index; a second pass takes
+// the smallest column record over vertex blocks and re-scans its kK
+// vertices.
 #include "internal.h"
 
 namespace {
 
-constexpr int kK = 8;      // vertices per thread
+constexpr int kK = 16;     // vertices per thread
+constexpr int kT = 128;    // threads per work-group
 constexpr int kPT = 256;   // points per LDS tile
-constexpr int kVB = 256 * kK;
+constexpr int kVB = kT * kK;
 
 __device__ __forceinline__ float dist2(float4 x, float4 p) {
   float dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
   return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
 }
 
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+__device__ __forceinline__ float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
+
+// Minimum over the 64 lanes with DPP moves; lane 63 ends with the result.
+// Within rows of 16: quad xor 1, quad xor 2, half-row mirror, row mirror;
+// then row 15 -> rows 1, 3 and row 31 -> rows 2, 3 broadcasts.
+__device__ __forceinline__ float wave_min_to_lane63(float v) {
+  const int inf = __float_as_int(INFINITY);
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0xB1, 0xF, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x4E, 0xF, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x141, 0xF, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x140, 0xF, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x142, 0xA, 0xF, false)));
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x143, 0xC, 0xF, false)));
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_chamfer_main(const float4* __restrict__ xhat, const float4* __restrict__ pts,
-                                                      const int64_t* __restrict__ off, int64_t V, int nvb,
-                                                      int64_t Nmax, int32_t* __restrict__ a, float* __restrict__ da,
-                                                      unsigned* __restrict__ colpart) {
-  __shared__ float4 sp[kPT];
-  __shared__ unsigned cm[kPT];
+// Column record of one point: (distance bits << 32) | first vertex of the
+// lowest lane attaining the wave minimum; an LDS 64-bit atomic min keeps the
+// smallest distance and, among equal ones, the lowest vertex range.
+__device__ __forceinline__ void column_record(float m, unsigned long long* slot, uint32_t lane_v0) {
+  const float wm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_min_to_lane63(m)), 63));
+  const unsigned long long hit = __ballot(m == wm);
+  const int first = __builtin_ctzll(hit);
+  if ((int)(threadIdx.x & 63) == first)
+    atomicMin(slot, ((unsigned long long)__float_as_uint(wm) << 32) | (unsigned long long)lane_v0);
+}
+
+// Vertices of a lane are contiguous: thread th of block vb owns
+// vb*kVB + th*kK + k, k < kK, so the lowest lane attaining a column minimum
+// holds the lowest vertex index attaining it.
+__global__ __launch_bounds__(kT) void k_chamfer_main(const float4* __restrict__ xhat, const float4* __restrict__ pts,
+                                                     const int64_t* __restrict__ off, int64_t V, int nvb,
+                                                     int64_t Nmax, int32_t* __restrict__ a, float* __restrict__ da,
+                                                     unsigned long long* __restrict__ colpart) {
+  __shared__ float4 sp[kPT + 2];
+  __shared__ unsigned long long cm[kPT];
   const int t = blockIdx.y, vb = blockIdx.x;
   const int64_t p0 = off[t];
   const int Nt = (int)(off[t + 1] - p0);
-  const int lane = threadIdx.x & 63;
+  const int64_t vbase = (int64_t)vb * kVB + (int64_t)threadIdx.x * kK;
   float4 x[kK];
   float best[kK];
   int btile[kK];
 #pragma unroll
   for (int k = 0; k < kK; ++k) {
-    int64_t i = (int64_t)vb * kVB + threadIdx.x + 256 * k;
+    const int64_t i = vbase + k;
     x[k] = i < V ? xhat[(int64_t)t * V + i] : make_float4(1e18f, 1e18f, 1e18f, 0.f);
     best[k] = INFINITY;
     btile[k] = 0;
   }
+  const uint32_t lane_v0 = (uint32_t)vbase;
   const int ntile = (Nt + kPT - 1) / kPT;
   for (int tile = 0; tile < ntile; ++tile) {
     const int cnt = min(kPT, Nt - tile * kPT);
-    for (int j = threadIdx.x; j < kPT; j += 256) {
-      sp[j] = j < cnt ? pts[p0 + (int64_t)tile * kPT + j] : make_float4(0.f, 0.f, 0.f, 0.f);
-      cm[j] = 0x7f800000u;  // +inf
+    for (int j = threadIdx.x; j < kPT + 2; j += kT) {
+      // padding points sit far away: they never win a row minimum
+      sp[j] = j < cnt ? pts[p0 + (int64_t)tile * kPT + j] : make_float4(3e18f, 3e18f, 3e18f, 0.f);
+      if (j < kPT) cm[j] = ~0ull;
     }
     __syncthreads();
     float tmin[kK];
 #pragma unroll
     for (int k = 0; k < kK; ++k) tmin[k] = INFINITY;
-    for (int j = 0; j < cnt; ++j) {
-      const float4 p = sp[j];
-      float m = INFINITY;
+    for (int j = 0; j < cnt; j += 2) {
+      const float4 q0 = sp[j], q1 = sp[j + 1];
+      float m0 = INFINITY, m1 = INFINITY;
 #pragma unroll
-      for (int k = 0; k < kK; ++k) {
-        float d = dist2(x[k], p);
-        tmin[k] = fminf(tmin[k], d);
-        m = fminf(m, d);
+      for (int k = 0; k < kK; k += 2) {
+        const float d00 = dist2(x[k], q0), d01 = dist2(x[k], q1);
+        const float d10 = dist2(x[k + 1], q0), d11 = dist2(x[k + 1], q1);
+        tmin[k] = min3f(tmin[k], d00, d01);
+        tmin[k + 1] = min3f(tmin[k + 1], d10, d11);
+        m0 = min3f(m0, d00, d10);
+        m1 = min3f(m1, d01, d11);
       }
-      m = wave_min(m);
-      if (lane == 0) atomicMin(&cm[j], __float_as_uint(m));
+      column_record(m0, &cm[j], lane_v0);
+      if (j + 1 < cnt) column_record(m1, &cm[j + 1], lane_v0);
     }
 #pragma unroll
     for (int k = 0; k < kK; ++k)
@@ -85,14 +117,14 @@ __global__ __launch_bounds__(256) void k_chamfer_main(const float4* __restrict__
         btile[k] = tile;
       }
     __syncthreads();
-    unsigned* dst = colpart + ((int64_t)t * nvb + vb) * Nmax + (int64_t)tile * kPT;
-    for (int j = threadIdx.x; j < cnt; j += 256) dst[j] = cm[j];
+    unsigned long long* dst = colpart + ((int64_t)t * nvb + vb) * Nmax + (int64_t)tile * kPT;
+    for (int j = threadIdx.x; j < cnt; j += kT) dst[j] = cm[j];
     __syncthreads();
   }
   // recover the lowest index attaining the row minimum inside its best tile
 #pragma unroll
   for (int k = 0; k < kK; ++k) {
-    int64_t i = (int64_t)vb * kVB + threadIdx.x + 256 * k;
+    const int64_t i = vbase + k;
     if (i >= V) continue;
     const int j0 = btile[k] * kPT;
     const int cnt = min(kPT, Nt - j0);
@@ -107,35 +139,33 @@ __global__ __launch_bounds__(256) void k_chamfer_main(const float4* __restrict__
   }
 }
 
-// One thread per point: minimum over vertex blocks, then the lowest vertex of
-// the first block attaining it.
+// One thread per point: the smallest record over the vertex blocks names the
+// lowest lane range attaining the minimum; its kK vertices are re-scanned.
 __global__ void k_chamfer_cols(const float4* __restrict__ xhat, const float4* __restrict__ pts,
                                const int64_t* __restrict__ off, const int* __restrict__ pt_frame, int64_t Ntot,
-                               int64_t V, int nvb, int64_t Nmax, const unsigned* __restrict__ colpart,
+                               int64_t V, int nvb, int64_t Nmax, const unsigned long long* __restrict__ colpart,
                                int32_t* __restrict__ b, float* __restrict__ db) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= Ntot) return;
   const int t = pt_frame[g];
   const int64_t j = g - off[t];
-  unsigned m = 0xffffffffu;
-  int vbest = 0;
+  unsigned long long m = ~0ull;
   for (int vb = 0; vb < nvb; ++vb) {
-    unsigned u = colpart[((int64_t)t * nvb + vb) * Nmax + j];
-    if (u < m) {
-      m = u;
-      vbest = vb;
-    }
+    const unsigned long long u = colpart[((int64_t)t * nvb + vb) * Nmax + j];
+    m = u < m ? u : m;
   }
-  const float dm = __uint_as_float(m);
+  const float dm = __uint_as_float((uint32_t)(m >> 32));
+  const int64_t i0 = (int64_t)(uint32_t)(m & 0xffffffffu);
   const float4 p = pts[g];
-  const int64_t i0 = (int64_t)vbest * kVB;
-  const int64_t i1 = min(V, i0 + kVB);
   int64_t arg = i0;
-  for (int64_t i = i0; i < i1; ++i)
-    if (dist2(xhat[(int64_t)t * V + i], p) == dm) {
-      arg = i;
+  for (int k = 0; k < kK && i0 + k < V; ++k)
+    if (dist2(xhat[(int64_t)t * V + i0 + k], p) == dm) {
+      arg = i0 + k;
       break;
     }
+  // only reachable with non-finite vertices (flagged by the step): keep the
+  // index inside [0, V) so no later pass can address past the vertex arrays
+  if (arg >= V) arg = V - 1;
   b[g] = (int32_t)arg;
   db[g] = dm;
 }
@@ -247,11 +277,11 @@ int npg_chamfer_vblock() { return kVB; }
 
 hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b,
                                   float* db, double* cd) {
-  hipLaunchKernelGGL(k_chamfer_main, dim3(P->nvb, P->T), dim3(256), 0, P->stream, xhat, P->pts, P->d_off, P->V,
-                     P->nvb, P->Nmax, a, da, reinterpret_cast<unsigned*>(P->colpart));
+  hipLaunchKernelGGL(k_chamfer_main, dim3(P->nvb, P->T), dim3(kT), 0, P->stream, xhat, P->pts, P->d_off, P->V,
+                     P->nvb, P->Nmax, a, da, reinterpret_cast<unsigned long long*>(P->colpart));
   hipLaunchKernelGGL(k_chamfer_cols, dim3(nblk(P->Ntot, 256)), dim3(256), 0, P->stream, xhat, P->pts, P->d_off,
-                     P->pt_frame, P->Ntot, P->V, P->nvb, P->Nmax, reinterpret_cast<const unsigned*>(P->colpart), b,
-                     db);
+                     P->pt_frame, P->Ntot, P->V, P->nvb, P->Nmax,
+                     reinterpret_cast<const unsigned long long*>(P->colpart), b, db);
   hipLaunchKernelGGL(k_frame_sums, dim3(P->T), dim3(256), 0, P->stream, da, db, P->d_off, P->V, cd);
   return hipGetLastError();
 }

@@ -33,6 +33,8 @@ struct NpgCG {  // conjugate-gradient workspace
   int n_blocks;
 };
 
+struct NpgDct;
+
 struct npg_plan {
   npg_config cfg;
   hipStream_t stream;
@@ -75,7 +77,7 @@ struct npg_plan {
   double *cd, *w, *loss;
   // chamfer workspace
   int nvb;                 // vertex blocks per frame
-  float* colpart;          // [T][nvb][Nmax]
+  float* colpart;          // [T][nvb][Nmax] 64-bit column records (2 floats each)
   int64_t Nmax;
   long long* acc;          // [T][V][3] fixed-point accumulators
   // MLP workspace
@@ -85,8 +87,9 @@ struct npg_plan {
   float *Gv, *Gt, *Gt_part, *gW_part;
   int n_vblk_mlp;
   int64_t gw_part_len;
-  // CG
+  // preconditioner workspaces
   NpgCG cg;
+  NpgDct* dct;
   int* d_flag;             // non-finite flag
   hipEvent_t ev[10];
   float stage_ms[8];
@@ -132,6 +135,10 @@ hipError_t npg_launch_chamfer_bwd(const npg_plan* P, const float4* xhat, const i
                                   const int32_t* b, const double* w, float4* gxhat);
 // precond.hip
 npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters);
+// dct.hip
+npg_status npg_dct_setup(npg_plan* P);
+void npg_dct_free(npg_plan* P);
+npg_status npg_run_precond_dct(npg_plan* P, float* grad);
 // adam.hip
 hipError_t npg_launch_adam(const npg_plan* P, float* params, const float* grad, float* m, float* v,
                            int64_t k, int* flag);

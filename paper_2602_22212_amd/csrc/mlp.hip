@@ -39,6 +39,16 @@ __device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Sum over the 16 lanes of a row with DPP moves (quad xor 1, quad xor 2,
+// half-row mirror, row mirror); every lane of the row ends with the sum.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+  return v;
+}
+
 __device__ __forceinline__ float comp(const float4& v, int r) {
   return r == 0 ? v.x : (r == 1 ? v.y : (r == 2 ? v.z : v.w));
 }
@@ -189,19 +199,26 @@ __device__ __forceinline__ void transform_grad(const float* o, float4 xr, float4
 }
 
 // out[mt] += sum_k Wrow(16mt + c, k) * in[k] over all k tiles; wl(mt, kt)
-// returns the float4 of row 16mt + c at columns 16kt + 4q .. +3.
+// returns the float4 of row 16mt + c at columns 16kt + 4q .. +3. The operands
+// of k-tile kt+1 are requested before the MFMAs of k-tile kt are issued, so
+// their latency hides behind the matrix work.
 template <int NT, typename WL>
 __device__ __forceinline__ void dense(const v4f (&in)[NT], v4f (&out)[NT], WL wl) {
+  float4 w[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) w[0][mt] = wl(mt, 0);
 #pragma unroll
   for (int kt = 0; kt < NT; ++kt) {
-    float4 w[NT];
+    const int cb = kt & 1;
+    if (kt + 1 < NT) {
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) w[mt] = wl(mt, kt);
+      for (int mt = 0; mt < NT; ++mt) w[cb ^ 1][mt] = wl(mt, kt + 1);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int mt = 0; mt < NT; ++mt) out[mt] = mfma(comp(w[mt], r), in[kt][r], out[mt]);
-    // keep the next k-tile's operand loads from being hoisted above this one
+      for (int mt = 0; mt < NT; ++mt) out[mt] = mfma(comp(w[cb][mt], r), in[kt][r], out[mt]);
+    // keep later k-tiles' loads from being hoisted further up
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -371,16 +388,34 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
   // this lane's element (feature 16*mt + 4q + r, own sample) of a staged row block
   auto at = [&](float* base, int mt, int r) -> float& { return base[(16 * mt + 4 * q + r) * kSP + sp]; };
   // acc += sum over the 64 staged samples of sG[16mt + m][s] * hs[16kt + n][s]
-  auto wgrad_tile = [&](const float* hs, int mt, int kt, v4f acc) {
+  auto wgrad_load = [&](const float* hs, int mt, int kt, float4 (&a)[4], float4 (&b)[4]) {
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
-      float4 a = *reinterpret_cast<const float4*>(sG + (16 * mt + c) * kSP + 16 * q + 4 * jj);
-      float4 b = *reinterpret_cast<const float4*>(hs + (16 * kt + c) * kSP + 16 * q + 4 * jj);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc = mfma(comp(a, r), comp(b, r), acc);
+      a[jj] = *reinterpret_cast<const float4*>(sG + (16 * mt + c) * kSP + 16 * q + 4 * jj);
+      b[jj] = *reinterpret_cast<const float4*>(hs + (16 * kt + c) * kSP + 16 * q + 4 * jj);
     }
-    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto wgrad_mma = [&](const float4 (&a)[4], const float4 (&b)[4], v4f acc) {
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc = mfma(comp(a[jj], r), comp(b[jj], r), acc);
     return acc;
+  };
+  // all owned tiles of one layer, operands of tile k+1 fetched before tile k's MFMAs
+  auto wgrad_layer = [&](const float* hs, auto& accs, int ntiles_total, int ncols) {
+    constexpr int NA = sizeof(accs) / sizeof(v4f);
+    float4 a[2][4], b[2][4];
+    if (wave < ntiles_total) wgrad_load(hs, wave / ncols, wave % ncols, a[0], b[0]);
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const int tau = wave + 4 * k;
+      if (tau >= ntiles_total) break;
+      const int nx = tau + 4;
+      if (k + 1 < NA && nx < ntiles_total) wgrad_load(hs, nx / ncols, nx % ncols, a[(k + 1) & 1], b[(k + 1) & 1]);
+      accs[k] = wgrad_mma(a[k & 1], b[k & 1], accs[k]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   };
   // bias gradient rows: thread tid sums staged gradient row tid over the 64 samples
   auto bias_rows = [&](int rows, float* dst) {
@@ -451,11 +486,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
 #pragma unroll
     for (int r = 0; r < 4; ++r) at(sG, 0, r) = got[r];
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NTO; ++k) {
-      int kt = wave + 4 * k;
-      if (kt < NT) accO[k] = wgrad_tile(sH + (H - 1) * W * kSP, 0, kt, accO[k]);
-    }
+    wgrad_layer(sH + (H - 1) * W * kSP, accO, NT, NT);
     bias_rows(16, sGb + (H - 1) * W);
     v4f gp[NT];
 #pragma unroll
@@ -477,11 +508,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
 #pragma unroll
         for (int r = 0; r < 4; ++r) at(sG, mt, r) = gp[mt][r];
       __syncthreads();
-#pragma unroll
-      for (int k = 0; k < NTT; ++k) {
-        int tau = wave + 4 * k;
-        if (tau < NT * NT) accW[l - 1][k] = wgrad_tile(sH + (l - 1) * W * kSP, tau / NT, tau % NT, accW[l - 1][k]);
-      }
+      wgrad_layer(sH + (l - 1) * W * kSP, accW[l - 1], NT * NT, NT);
       bias_rows(W, sGb + (l - 1) * W);
       v4f gh[NT];
 #pragma unroll
@@ -502,11 +529,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         gv[mt][r] += gp[mt][r];
-        float v = gp[mt][r];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
+        const float v = row16_sum(gp[mt][r]);
         if (c == 0) sGt[wave * W + 16 * mt + 4 * q + r] = v;
       }
     __syncthreads();

@@ -86,7 +86,12 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->beta1 >= 0.f && c->beta1 < 1.f && c->beta2 >= 0.f && c->beta2 < 1.f, "Adam betas must be in [0,1)");
   CHECK_ARG(c->eps > 0.f, "eps must be > 0");
   CHECK_ARG(c->cg_maxit >= 1 && c->cg_rtol > 0.0, "cg_maxit >= 1 and cg_rtol > 0 are required");
-  CHECK_ARG(c->precond == NPG_PRECOND_CG, "only NPG_PRECOND_CG is available in this build");
+  CHECK_ARG(c->precond == NPG_PRECOND_CG || c->precond == NPG_PRECOND_DCT, "precond must be CG or DCT");
+  if (c->precond == NPG_PRECOND_DCT) {
+    for (int l = 0; l < c->n_levels; ++l)
+      CHECK_ARG(c->res[l] <= 256, "the DCT preconditioner supports up to 256 nodes per axis");
+    CHECK_ARG(c->res_n <= 256, "the DCT preconditioner supports up to 256 nodes per axis");
+  }
   return NPG_OK;
 }
 
@@ -124,6 +129,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
   for (void* b : bufs)
     if (b) hipFree(b);
   npg_cg_free(P);
+  npg_dct_free(P);
   for (auto& e : P->ev)
     if (e) hipEventDestroy(e);
   for (auto& e : P->prof_ev)
@@ -261,7 +267,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->loss, 1));
   const int VB = npg_chamfer_vblock();
   P->nvb = (int)((V + VB - 1) / VB);
-  TRYP(dalloc(&P->colpart, (int64_t)T * P->nvb * Nmax));
+  TRYP(dalloc(&P->colpart, 2 * (int64_t)T * P->nvb * Nmax));
   TRYP(dalloc(&P->acc, 3 * TV));
   TRYP(dalloc(&P->mlpA, V * P->W));
   TRYP(dalloc(&P->mlpB, (int64_t)T * P->W));
@@ -272,7 +278,8 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->Gt, (int64_t)T * P->W));
   TRYP(dalloc(&P->Gt_part, (int64_t)T * P->n_vblk_mlp * P->W));
   TRYP(dalloc(&P->gW_part, (int64_t)P->n_vblk_mlp * P->gw_part_len));
-  TRYP(npg_cg_setup(P));
+  if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
+  else TRYP(npg_cg_setup(P));
   for (auto& e : P->ev) HIPP(hipEventCreate(&e));
   P->adam_k = 0;
   HIPP(hipStreamSynchronize(P->stream));
@@ -356,6 +363,11 @@ npg_status npg_encode_bwd(npg_plan* P, const float* gz, float* grad) {
 
 npg_status npg_precond(npg_plan* P, float* grad, int32_t* iters) {
   CHECK_ARG(P && grad, "NULL argument");
+  if (P->cfg.precond == NPG_PRECOND_DCT) {
+    if (iters)
+      for (int s = 0; s < 2 * P->n_sys; ++s) iters[s] = 0;
+    return npg_run_precond_dct(P, grad);
+  }
   return npg_run_precond_cg(P, grad, iters);
 }
 
@@ -384,7 +396,8 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
   NPG_HIP(hipEventRecord(P->ev[5], s));
   NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
   NPG_HIP(hipEventRecord(P->ev[6], s));
-  npg_status pst = npg_run_precond_cg(P, P->grad, nullptr);
+  npg_status pst = P->cfg.precond == NPG_PRECOND_DCT ? npg_run_precond_dct(P, P->grad)
+                                                     : npg_run_precond_cg(P, P->grad, nullptr);
   if (pst != NPG_OK && pst != NPG_ENOTCONV) return pst;
   NPG_HIP(hipEventRecord(P->ev[7], s));
   P->adam_k += 1;

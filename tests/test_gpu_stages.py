@@ -298,15 +298,18 @@ def test_adam_matches_oracle(case):
     assert L >= 1
 
 
-@pytest.mark.parametrize("levels", [[100, 129, 20], [256]])
-def test_preconditioner_large_grids(levels):
-    """Grids of >= 100 nodes per axis run the z-marching CG kernels; 129 gives
-    partial tiles in x, y and z. Sparse vertex-gradient input as in a step,
-    plus a dense random component."""
+@pytest.mark.parametrize("method", ["cg", "dct"])
+@pytest.mark.parametrize("levels,feat", [([100, 129, 20], 4), ([256], 4), ([7, 33, 50], 2), ([17, 24], 3)])
+def test_preconditioner_large_grids(levels, feat, method):
+    """Grids of >= 100 nodes per axis run the z-column CG kernels; 129 gives
+    partial tiles in x, y and z; F = 2, 3 and odd sizes exercise the generic
+    paths of both methods. Sparse vertex-gradient input as in a step, plus a
+    dense random component."""
     import torch
 
     import paper_2602_22212_amd as npg
-    cfg = synth.config_small(levels=levels, feat_p=4, mlp_width=32, V=3000, T=1, N=10, t_key=0, seed=33)
+    cfg = synth.config_small(levels=levels, feat_p=feat, mlp_width=32, V=3000, T=1, N=10, t_key=0, seed=33,
+                             precond=method)
     data = synth.make_workload(cfg)
     plan = gpu_plan(cfg, data)
     rng = np.random.default_rng(12)

@@ -25,7 +25,8 @@ def _touched_nodes(cfg, data):
     return out
 
 
-def test_teacher_forced_steps_on_icosphere():
+@pytest.mark.parametrize("method", ["cg", "dct"])
+def test_teacher_forced_steps_on_icosphere(method):
     """Each step starts both sides from the oracle's state (Adam moments
     included). Loss, per-frame Chamfer distances and the updated MLP and
     touched grid nodes must match; nodes no vertex reads never influence the
@@ -33,7 +34,7 @@ def test_teacher_forced_steps_on_icosphere():
     import torch
 
     import paper_2602_22212_amd as npg
-    cfg = synth.config_c1()
+    cfg = dict(synth.config_c1(), precond=method)
     data = synth.make_workload(cfg)
     plan = gpu_plan(cfg, data)
     touched = _touched_nodes(cfg, data)
