@@ -62,30 +62,87 @@ __device__ __forceinline__ int64_t line_stride(int pass, int R, int F) {
   return pass == kX ? F : (pass == kY ? (int64_t)R * F : (int64_t)R * R * F);
 }
 
-// D[k][j] = sum_n A[k][n] T[n][j] for this wave's k-tiles (kt = wave, wave+4, ...)
-// and all 4 j-tiles. T is in LDS as T[j][n] (row stride ld); A rows come
-// from a padded [Rp][Rp] table as float4.
+// D[k][j] = sum_n A[k][n] T[n][j] for this wave's k-tiles (kt = wave,
+// wave+4, ...) and all 4 j-tiles. T is in LDS as T[n][j] (row stride kLD);
+// A rows come from a padded [Rp][Rp] table as float4, fetched one k-group
+// ahead of the matrix instructions that use them.
+constexpr int kLD = kJ + 4;
+
 template <int NKT>
-__device__ __forceinline__ void tile_gemm(const float* __restrict__ A, int Rp, const float* T, int ld, int wave,
-                                          int q, int c, v4f (&acc)[NKT][4]) {
+__device__ __forceinline__ void tile_gemm(const float* __restrict__ A, int Rp, const float* T, int wave, int q,
+                                          int c, v4f (&acc)[NKT][4]) {
 #pragma unroll
   for (int i = 0; i < NKT; ++i)
 #pragma unroll
     for (int jt = 0; jt < 4; ++jt) acc[i][jt] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nkt = Rp / 16;
-  for (int g = 0; g < Rp / 16; ++g) {
-    float4 b[4];
+  const int ng = Rp / 16;
+  float4 a[2][NKT];
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) b[jt] = *reinterpret_cast<const float4*>(T + (16 * jt + c) * ld + 16 * g + 4 * q);
+  for (int i = 0; i < NKT; ++i) {
+    const int kt = wave + 4 * i;
+    a[0][i] = kt < nkt ? *reinterpret_cast<const float4*>(A + (int64_t)(16 * kt + c) * Rp + 4 * q)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int g = 0; g < ng; ++g) {
+    const int cb = g & 1;
+    if (g + 1 < ng) {
 #pragma unroll
-    for (int i = 0; i < NKT; ++i) {
-      const int kt = wave + 4 * i;
-      if (kt >= nkt) break;
-      const float4 a = *reinterpret_cast<const float4*>(A + (int64_t)(16 * kt + c) * Rp + 16 * g + 4 * q);
+      for (int i = 0; i < NKT; ++i) {
+        const int kt = wave + 4 * i;
+        if (kt < nkt)
+          a[cb ^ 1][i] = *reinterpret_cast<const float4*>(A + (int64_t)(16 * kt + c) * Rp + 16 * (g + 1) + 4 * q);
+      }
+    }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+      float b[4];
 #pragma unroll
-        for (int jt = 0; jt < 4; ++jt) acc[i][jt] = mfma(comp(a, r), comp(b[jt], r), acc[i][jt]);
+      for (int jt = 0; jt < 4; ++jt) b[jt] = T[(16 * g + 4 * q + r) * kLD + 16 * jt + c];
+#pragma unroll
+      for (int i = 0; i < NKT; ++i) {
+        if (wave + 4 * i >= nkt) break;
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt) acc[i][jt] = mfma(comp(a[cb][i], r), b[jt], acc[i][jt]);
+      }
+    }
+  }
+}
+
+// Tile fill / write-back. x pass: lines j = (zy, f) -> 64 / F rows zy of F
+// channels, stored as T[x][zl*F + f] (float4 when F = 4); y and z passes:
+// 64 lines contiguous in memory per sample n, T[n][jj].
+__device__ __forceinline__ void tile_io(float* base, float* T, int pass, int R, int Rp, int F, int64_t j0, int njl,
+                                        const int64_t* lb, int64_t stride, bool store) {
+  if (pass == 0 && F == 4 && (j0 & 3) == 0) {
+    const int nzl = njl / 4;  // full rows of 4 channels (the tile never splits a row)
+    for (int e = threadIdx.x; e < 16 * Rp; e += 256) {
+      const int zl = e / Rp, n = e - zl * Rp;
+      float4* tp = reinterpret_cast<float4*>(T + n * kLD + 4 * zl);
+      if (store) {
+        if (zl < nzl && n < R) *reinterpret_cast<float4*>(base + lb[4 * zl] + (int64_t)n * 4) = *tp;
+      } else {
+        *tp = (zl < nzl && n < R) ? *reinterpret_cast<const float4*>(base + lb[4 * zl] + (int64_t)n * 4)
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < kJ * Rp; e += 256) {
+    int jj, n;
+    if (pass == 0) {
+      n = e % Rp;
+      jj = e / Rp;
+    } else {
+      jj = e % kJ;
+      n = e / kJ;
+    }
+    float* tp = T + n * kLD + jj;
+    const bool in = n < R && jj < njl;
+    if (store) {
+      if (in) base[lb[jj] + n * stride] = *tp;
+    } else {
+      *tp = in ? base[lb[jj] + n * stride] : 0.f;
     }
   }
 }
@@ -96,36 +153,25 @@ template <int NKT>
 __global__ __launch_bounds__(256) void k_dct_pass(float* __restrict__ grad, const DctSys* __restrict__ sys,
                                                   const int* __restrict__ blk_sys,
                                                   const int64_t* __restrict__ blk_j0, int pass, int mode) {
-  extern __shared__ float T[];  // [kJ][ld]
+  extern __shared__ float T[];  // [Rp][kLD]
   __shared__ int64_t lb[kJ];
   const int s = blk_sys[blockIdx.x];
   const DctSys S = sys[s];
   float* base = grad + S.poff;
   const int64_t j0 = blk_j0[blockIdx.x];
   const int R = S.R, Rp = S.Rp, F = S.F;
-  const int ld = Rp + 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
   const int njl = (int)min((int64_t)kJ, S.lines - j0);
   const int64_t stride = line_stride(pass, R, F);
   if ((int)threadIdx.x < kJ) lb[threadIdx.x] = line_base(pass, R, F, j0 + threadIdx.x);
   __syncthreads();
-
-  // load the tile: T[jj][n] (n >= R and jj >= njl are zero). The x pass walks
-  // samples fastest (consecutive x are consecutive nodes), the others walk
-  // lines fastest (consecutive lines are consecutive floats).
-  for (int e = threadIdx.x; e < kJ * Rp; e += 256) {
-    int jj, n;
-    if (pass == kX) { n = e % Rp; jj = e / Rp; } else { jj = e % kJ; n = e / kJ; }
-    float v = 0.f;
-    if (n < R && jj < njl) v = base[lb[jj] + n * stride];
-    T[jj * ld + n] = v;
-  }
+  tile_io(base, T, pass, R, Rp, F, j0, njl, lb, stride, false);
   __syncthreads();
 
   v4f acc[NKT][4];
   const int nkt = Rp / 16;
-  tile_gemm<NKT>(mode == 1 ? S.CT : S.C, Rp, T, ld, wave, q, c, acc);
+  tile_gemm<NKT>(mode == 1 ? S.CT : S.C, Rp, T, wave, q, c, acc);
   if (mode == 2) {
     // scale by 1 / (1 + lam (mu_kz + mu_ky + mu_kx))^2; the line index
     // j = (y*R + x)*F + f names the (ky, kx) of the two earlier passes
@@ -159,10 +205,10 @@ __global__ __launch_bounds__(256) void k_dct_pass(float* __restrict__ grad, cons
 #pragma unroll
       for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) T[(16 * jt + c) * ld + 16 * kt + 4 * q + r] = acc[i][jt][r];
+        for (int r = 0; r < 4; ++r) T[(16 * kt + 4 * q + r) * kLD + 16 * jt + c] = acc[i][jt][r];
     }
     __syncthreads();
-    tile_gemm<NKT>(S.CT, Rp, T, ld, wave, q, c, acc);
+    tile_gemm<NKT>(S.CT, Rp, T, wave, q, c, acc);
   }
   __syncthreads();  // every wave has finished reading T
 #pragma unroll
@@ -172,14 +218,10 @@ __global__ __launch_bounds__(256) void k_dct_pass(float* __restrict__ grad, cons
 #pragma unroll
     for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) T[(16 * jt + c) * ld + 16 * kt + 4 * q + r] = acc[i][jt][r];
+      for (int r = 0; r < 4; ++r) T[(16 * kt + 4 * q + r) * kLD + 16 * jt + c] = acc[i][jt][r];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kJ * R; e += 256) {
-    int jj, n;
-    if (pass == kX) { n = e % R; jj = e / R; } else { jj = e % kJ; n = e / kJ; }
-    if (jj < njl) base[lb[jj] + n * stride] = T[jj * ld + n];
-  }
+  tile_io(base, T, pass, R, Rp, F, j0, njl, lb, stride, true);
 }
 
 __global__ void k_dct_tables(int R, int Rp, float* __restrict__ C, float* __restrict__ CT, float* __restrict__ mu) {
@@ -274,7 +316,7 @@ void npg_dct_free(npg_plan* P) {
 template <int NKT>
 static hipError_t launch_pass(const npg_plan* P, float* grad, int pass, int mode) {
   NpgDct* D = P->dct;
-  const size_t lds = (size_t)kJ * (D->max_rp + 4) * sizeof(float);
+  const size_t lds = (size_t)D->max_rp * kLD * sizeof(float);
   hipError_t e = hipFuncSetAttribute((const void*)k_dct_pass<NKT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_dct_pass<NKT>), dim3(D->nblk[pass]), dim3(256), lds, P->stream, grad, D->d_sys[pass],
