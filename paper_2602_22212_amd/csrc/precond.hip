@@ -19,8 +19,8 @@
 // (1 + 12 lam)|p|.
 //
 // Large grids (R >= 100) are walked in z-columns (registers carry the z
-// neighbours); small grids in contiguous node chunks. Work-groups are
-// dispatched largest grid first.
+// neighbours, lane shifts the x neighbours, LDS the y neighbours); small grids
+// in contiguous node chunks. Work-groups are dispatched largest grid first.
 #include <algorithm>
 
 #include "internal.h"
@@ -251,12 +251,19 @@ __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
 
 // ---- z-column walks for large grids -----------------------------------------
 // A work-group owns a kTX x kTY block of (x, y) columns and the z range
-// [z0, z1); each thread walks one column. The operand of the planes z-1, z
-// and z+1 stays in registers, so every vector is streamed from HBM about once
-// per kernel; the four in-plane neighbours are re-read from L1/L2 (they are
-// the neighbouring lanes' and rows' own loads). No LDS and no barriers.
+// [z0, z1); wave w walks row y0 + w, one column per lane. Per plane:
+//   z neighbours   registers (the previous and next plane's operand)
+//   x neighbours   the neighbouring lanes (DPP wave shifts); only lanes 0 and
+//                  kTX-1 load the node beyond the tile
+//   y neighbours   the other waves' rows through a triple-buffered LDS plane;
+//                  the first and last wave also load the halo row beyond the
+//                  tile
+// Loads run one plane ahead of the arithmetic (the next plane's operand two).
+// Missing neighbours (grid boundary) and lanes/rows past the grid edge are
+// clamped to the nearest node inside, whose difference then contributes 0.
 constexpr int kZmR = 100;  // grids with R >= kZmR, F = 4 and 16-byte alignment
-constexpr int kTX = 64, kTY = 4, kZS = 32;
+constexpr int kTX = 64, kTY = 4, kZS = 64;
+static_assert(kTX * kTY == kB, "one wave per tile row");
 
 __device__ __forceinline__ bool use_zm(const NpgGrid& g) { return g.R >= kZmR && g.F == 4 && (g.poff % 4) == 0; }
 
@@ -280,31 +287,98 @@ __device__ __forceinline__ void f4lap(float4& acc, const float4& c, const float4
   acc.w += c.w - n.w;
 }
 
-// LOAD(node) yields the stencil operand at a node; BODY(node, lap, cur)
-// consumes the operand and its Laplacian at every node of the column.
-template <typename LOAD, typename BODY>
-__device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LOAD load, BODY body) {
+// Wave-wide lane shifts by one (DPP wave_shr:1 / wave_shl:1). The lane
+// without a source (0, resp. 63) keeps its own `edge` value.
+__device__ __forceinline__ float dpp_from_left(float edge, float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_from_right(float edge, float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float4 from_left(const float4& edge, const float4& v) {
+  return make_float4(dpp_from_left(edge.x, v.x), dpp_from_left(edge.y, v.y), dpp_from_left(edge.z, v.z),
+                     dpp_from_left(edge.w, v.w));
+}
+__device__ __forceinline__ float4 from_right(const float4& edge, const float4& v) {
+  return make_float4(dpp_from_right(edge.x, v.x), dpp_from_right(edge.y, v.y), dpp_from_right(edge.z, v.z),
+                     dpp_from_right(edge.w, v.w));
+}
+
+struct Raw1 {
+  float4 a;
+};
+struct Raw2 {
+  float4 a, b;
+};
+struct NoExtra {};
+
+// Raw loads of one plane: the lane's node, the node beyond the tile (lanes 0
+// and kTX-1 only), the halo row (first and last wave only) and the extra
+// per-node data the body needs.
+template <typename RAW, typename EX>
+struct ZPlane {
+  RAW c, e, h;
+  EX ex;
+};
+
+// LD(node) loads the raw stencil operand, OP(raw) forms it, LDC(node) loads
+// the body's extra data; BODY(node, lap, operand, extra) runs at every node
+// of the grid inside the tile. Every thread of the work-group must call this
+// (it synchronises the work-group once per plane).
+template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY>
+__device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body) {
+  __shared__ float4 sh[3][kTY + 2][kTX];
   const int R = g.R;
   const int64_t R2 = (int64_t)R * R;
-  const int x = t.x0 + (int)(threadIdx.x & (kTX - 1));
-  const int y = t.y0 + (int)(threadIdx.x / kTX);
-  if (x >= R || y >= R) return;
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-  int64_t n = (int64_t)t.z0 * R2 + (int64_t)y * R + x;
-  float4 cur = load(n);
-  float4 prev = t.z0 > 0 ? load(n - R2) : zero;
+  const int lane = threadIdx.x & (kTX - 1), w = threadIdx.x / kTX;
+  const int x = t.x0 + lane, y = t.y0 + w;
+  const int xe = min(x, R - 1), ye = min(y, R - 1);
+  const bool inside = x < R && y < R;
+  const int oxm = xe > 0 ? -1 : 0, oxp = xe < R - 1 ? 1 : 0;
+  const bool edge_lane = lane == 0 || lane == kTX - 1;
+  const int64_t de = lane == 0 ? oxm : oxp;
+  const bool halo = w == 0 || w == kTY - 1;
+  const int hy = w == 0 ? max(t.y0 - 1, 0) : min(t.y0 + kTY, R - 1);
+  const int hrow = w == 0 ? 0 : kTY + 1;
+  const int64_t dh = (int64_t)(hy - ye) * R;
+  auto load_plane = [&](int64_t m, ZPlane<RAW, EX>& P) {
+    P.c = ld(m);
+    P.ex = ldc(m);
+    if (edge_lane) P.e = ld(m + de);
+    if (halo) P.h = ld(m + dh);
+  };
+  int64_t n = (int64_t)t.z0 * R2 + (int64_t)ye * R + xe;
+  ZPlane<RAW, EX> A = {}, B = {};
+  load_plane(n, A);
+  float4 cur = op(A.c), edge = op(A.e);
+  EX ex = A.ex;
+  sh[t.z0 % 3][w + 1][lane] = cur;
+  if (halo) sh[t.z0 % 3][hrow][lane] = op(A.h);
+  float4 prev = t.z0 > 0 ? op(ld(n - R2)) : cur;
+  load_plane(t.z0 + 1 < R ? n + R2 : n, A);
   for (int z = t.z0; z < t.z1; ++z, n += R2) {
-    const float4 nxt = z + 1 < R ? load(n + R2) : zero;
-    float4 lap = zero;
-    if (x > 0) f4lap(lap, cur, load(n - 1));
-    if (x < R - 1) f4lap(lap, cur, load(n + 1));
-    if (y > 0) f4lap(lap, cur, load(n - R));
-    if (y < R - 1) f4lap(lap, cur, load(n + R));
-    if (z > 0) f4lap(lap, cur, prev);
-    if (z < R - 1) f4lap(lap, cur, nxt);
-    body(n, lap, cur);
+    const int64_t n1 = z + 1 < R ? n + R2 : n;
+    load_plane(z + 2 < R ? n1 + R2 : n1, B);
+    // plane z+1 (clamped to z at the top face, where it then adds 0)
+    const float4 nxt = op(A.c), nedge = op(A.e);
+    sh[(z + 1) % 3][w + 1][lane] = nxt;
+    if (halo) sh[(z + 1) % 3][hrow][lane] = op(A.h);
+    __syncthreads();
+    float4 lap = make_float4(0.f, 0.f, 0.f, 0.f);
+    f4lap(lap, cur, from_left(edge, cur));
+    f4lap(lap, cur, from_right(edge, cur));
+    f4lap(lap, cur, sh[z % 3][w][lane]);
+    f4lap(lap, cur, sh[z % 3][w + 2][lane]);
+    f4lap(lap, cur, prev);
+    f4lap(lap, cur, nxt);
+    if (inside) body(n, lap, cur, ex);
     prev = cur;
     cur = nxt;
+    edge = nedge;
+    ex = A.ex;
+    A = B;
   }
 }
 
@@ -344,14 +418,16 @@ __device__ void zm_dir_ap(const NpgGrid& g, const Tile& t, const double* st, int
   const float4* Po = reinterpret_cast<const float4*>(p_old + g.poff);
   float4* Pn = reinterpret_cast<float4*>(p_new + g.poff);
   double acc[4] = {0, 0, 0, 0};
-  zm_walk(g, t, [&](int64_t n) { return f4fma(Po[n], be, Rr[n]); },
-          [&](int64_t n, const float4& lap, const float4& pn) {
-            acc[0] += (double)pn.x * (double)fmaf(lam, lap.x, pn.x);
-            acc[1] += (double)pn.y * (double)fmaf(lam, lap.y, pn.y);
-            acc[2] += (double)pn.z * (double)fmaf(lam, lap.z, pn.z);
-            acc[3] += (double)pn.w * (double)fmaf(lam, lap.w, pn.w);
-            Pn[n] = pn;
-          });
+  zm_walk<Raw2, NoExtra>(
+      g, t, [&](int64_t n) { return Raw2{Po[n], Rr[n]}; }, [&](int64_t) { return NoExtra{}; },
+      [&](const Raw2& v) { return f4fma(v.a, be, v.b); },
+      [&](int64_t n, const float4& lap, const float4& pn, const NoExtra&) {
+        acc[0] += (double)pn.x * (double)fmaf(lam, lap.x, pn.x);
+        acc[1] += (double)pn.y * (double)fmaf(lam, lap.y, pn.y);
+        acc[2] += (double)pn.z * (double)fmaf(lam, lap.z, pn.z);
+        acc[3] += (double)pn.w * (double)fmaf(lam, lap.w, pn.w);
+        Pn[n] = pn;
+      });
   store_partials<4>(acc, part, blk);
 }
 
@@ -365,24 +441,26 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
   float4* X = reinterpret_cast<float4*>(x + g.poff);
   float4* Rr = reinterpret_cast<float4*>(r + g.poff);
   double acc[4] = {0, 0, 0, 0};
-  zm_walk(g, t, [&](int64_t n) { return Pp[n]; },
-          [&](int64_t n, const float4& lap, const float4& pc) {
-            float4 xv = X[n], rv = Rr[n];
-            xv.x = fmaf(al[0], pc.x, xv.x);
-            xv.y = fmaf(al[1], pc.y, xv.y);
-            xv.z = fmaf(al[2], pc.z, xv.z);
-            xv.w = fmaf(al[3], pc.w, xv.w);
-            rv.x = fmaf(-al[0], fmaf(lam, lap.x, pc.x), rv.x);
-            rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
-            rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
-            rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
-            X[n] = xv;
-            Rr[n] = rv;
-            acc[0] += (double)rv.x * rv.x;
-            acc[1] += (double)rv.y * rv.y;
-            acc[2] += (double)rv.z * rv.z;
-            acc[3] += (double)rv.w * rv.w;
-          });
+  zm_walk<Raw1, Raw2>(
+      g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw2{X[n], Rr[n]}; },
+      [&](const Raw1& v) { return v.a; },
+      [&](int64_t n, const float4& lap, const float4& pc, const Raw2& e) {
+        float4 xv = e.a, rv = e.b;
+        xv.x = fmaf(al[0], pc.x, xv.x);
+        xv.y = fmaf(al[1], pc.y, xv.y);
+        xv.z = fmaf(al[2], pc.z, xv.z);
+        xv.w = fmaf(al[3], pc.w, xv.w);
+        rv.x = fmaf(-al[0], fmaf(lam, lap.x, pc.x), rv.x);
+        rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
+        rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
+        rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
+        X[n] = xv;
+        Rr[n] = rv;
+        acc[0] += (double)rv.x * rv.x;
+        acc[1] += (double)rv.y * rv.y;
+        acc[2] += (double)rv.z * rv.z;
+        acc[3] += (double)rv.w * rv.w;
+      });
   store_partials<4>(acc, part, blk);
 }
 
