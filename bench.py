@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,22 +35,28 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
+    ap.add_argument("--forms", default="cg,dct", help="preconditioner forms to time (cg is the headline)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="finish with one plain 1 GiB device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
 
 
 def traffic_from_profile():
-    """HBM bytes per CG iteration from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "cg_iteration_human_pmc.json")
+    """HBM bytes per CG iteration (k_cg_dir_ap + k_cg_update) from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source (its `precond.hip sha256` line names the source)."""
+    path = os.path.join(ROOT, "profiles", "cg_iteration_human_pmc.md")
     src = os.path.join(ROOT, "paper_2602_22212_amd", "csrc", "precond.hip")
     try:
-        prof = json.load(open(path))
+        text = open(path).read()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if prof.get("precond_src_sha") != sha:
-            return None
-        return prof.get("hbm_bytes_per_iteration")
-    except (OSError, ValueError):
+    except OSError:
         return None
+    m_sha = re.search(r"precond\.hip sha256: ([0-9a-f]{16})", text)
+    m_val = re.search(r"hbm_bytes_per_iteration: ([0-9]+)", text)
+    if not m_sha or not m_val or m_sha.group(1) != sha:
+        return None
+    return int(m_val.group(1))
 
 
 def cpu_baseline(cfg, data, P0, frames):
@@ -140,16 +147,22 @@ def main():
     data = synth.make_workload(cfg)
     T, V = data["T"], len(data["xyz"])
     P0 = synth.random_state(cfg, 9, grid_std=0.05)
+    forms = set(args.forms.split(","))
+    if "cg" not in forms:
+        print("the headline form is cg: --forms must include it", file=sys.stderr)
+        sys.exit(2)
     cg = run_form(dict(cfg, precond="cg"), data, P0, args.steps, args.warmup, profile=True)
-    dct = run_form(dict(cfg, precond="dct"), data, P0, args.steps, args.warmup, profile=False)
+    dct = run_form(dict(cfg, precond="dct"), data, P0, args.steps, args.warmup, profile=False) if "dct" in forms else None
     prof = cg["prof"]
     cg_iter_ms = prof["cg_ms"] / max(prof["cg_iters"], 1)
     achieved = (prof["cg_bytes"] / 1e9) / (prof["cg_ms"] / 1e3) if prof["cg_ms"] > 0 else 0.0
     traffic = traffic_from_profile()
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=(None if traffic is None else
-                             round(traffic * prof["cg_iters"] / max(prof["cg_bytes"], 1), 4)),
+                    traffic=traffic,
+                    traffic_unit="HBM bytes per CG iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    traffic_over_algorithmic=(None if traffic is None else round(
+                        traffic * prof["cg_iters"] / max(prof["cg_bytes"], 1), 4)),
                     kernel="CG iteration (k_cg_dir_ap + k_cg_update)",
                     avg_ms_per_iteration=round(cg_iter_ms, 4),
                     alg_bytes_per_iteration=round(prof["cg_bytes"] / max(prof["cg_iters"], 1)))
@@ -174,9 +187,9 @@ def main():
         "cg_iterations_per_step": round(prof["cg_iters"] / args.steps, 1),
         "step_status": cg["status"],
         "roofline": roofline,
-        "precond_dct": {"value": round(dct["value"], 4), "unit": "steps/s",
-                        "ms_per_step": round(dct["ms_per_step"], 3), "stage_ms": dct["stage_ms"],
-                        "note": "same step with the exact DCT form of (I + lambda L)^-2"},
+        "precond_dct": None if dct is None else {
+            "value": round(dct["value"], 4), "unit": "steps/s", "ms_per_step": round(dct["ms_per_step"], 3),
+            "stage_ms": dct["stage_ms"], "note": "same step with the exact DCT form of (I + lambda L)^-2"},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -184,6 +197,12 @@ def main():
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["stage_seconds"] = cb["stage_seconds"]
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -81,11 +81,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Logical work-group of this launch: the block table in reverse, so the
-// largest grids (last in the table) are dispatched first and the hardware's
-// round-robin spreads them evenly over the XCDs.
+// Logical work-group of this launch. Work-groups go to the 8 XCDs in turn
+// (launch index mod 8); every XCD takes kXG consecutive logical blocks in a
+// row, so tiles that are y-neighbours (and share halo rows) run on the same
+// XCD and meet in its L2. The block table is walked in reverse, so the
+// largest grids (last in the table) are dispatched first. Launches are padded
+// to a multiple of 8 kXG work-groups; the padding returns at once.
+constexpr int kXCD = 8, kXG = 16;
 __device__ __forceinline__ int logical_block(int nb) {
-  const int lb = nb - 1 - (int)blockIdx.x;
+  const int b = (int)blockIdx.x;
+  const int round = b / kXCD;
+  const int fwd = (round / kXG) * (kXCD * kXG) + (b % kXCD) * kXG + round % kXG;
+  const int lb = nb - 1 - fwd;
   return lb >= 0 ? lb : -1;
 }
 
@@ -593,7 +600,7 @@ __global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, i
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-inline unsigned xcd_grid(int nb) { return (unsigned)nb; }
+inline unsigned xcd_grid(int nb) { return (unsigned)((nb + kXCD * kXG - 1) / (kXCD * kXG) * (kXCD * kXG)); }
 
 }  // namespace
 
