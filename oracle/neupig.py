@@ -9,6 +9,7 @@ Section references are to the paper (Neu-PiG, arXiv 2602.22212):
   Sec. 3.5 optimization objectives (preconditioned update, deformation loss,
            confidence weight, implementation details)
   Supp. "Rotation Modeling" / Table 11: exponential-map rotation head.
+  Sec. 3.4 "Rotation Component": quaternion rotation head (rot_head "quat").
 
 Parameter structure (float64 numpy):
   params = dict(grid_p=[G_l of shape [R_l^3, F] per level],
@@ -26,7 +27,7 @@ __all__ = [
     "transform", "transform_backward", "chamfer", "confidence", "forward",
     "backward", "laplacian_apply", "precond_dct", "precond_cg", "precondition",
     "adam", "step", "to64", "zeros_like_params", "flatten_params", "losses",
-    "chamfer_backward",
+    "chamfer_backward", "quat_matrix", "quat_normalize", "n_outputs",
 ]
 
 
@@ -202,15 +203,15 @@ def rodrigues(omega):
     return I + A[..., None, None] * K + B[..., None, None] * (K @ K)
 
 
-def transform(o, X, alpha):
+def _transform_expmap(o, X, alpha):
     """o [..., 6] = (omega, d); X [..., 3] -> x^ = R(omega) X + tanh(alpha d)."""
     R = rodrigues(o[..., :3])
     dh = np.tanh(alpha * o[..., 3:])
     return np.einsum("...ab,...b->...a", R, X) + dh, R, dh
 
 
-def transform_backward(g, o, X, R, dh, alpha):
-    """Derivative of transform w.r.t. o. For the rotation part,
+def _transform_expmap_backward(g, o, X, R, dh, alpha):
+    """Derivative of the exp-map transform w.r.t. o. For the rotation part,
     d(R x) = -R [x]_x J_r(omega) d omega (right Jacobian of SO(3)), so the
     gradient is J_r^T (x cross (R^T g))."""
     omega = o[..., :3]
@@ -223,6 +224,75 @@ def transform_backward(g, o, X, R, dh, alpha):
     gw = np.einsum("...ba,...b->...a", Jr, c)          # J_r^T c
     gd = alpha * (1.0 - dh ** 2) * g
     return np.concatenate([gw, gd], axis=-1)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.4 quaternion head (the paper's default): the network's first four
+# outputs (q_w, q_x, q_y, q_z) become the unit quaternion
+# u = (1 + q_w, q_x, q_y, q_z) / |(1 + q_w, q_x, q_y, q_z)| (zero output gives
+# the identity), R(u) is the rotation matrix of u, d^ = tanh(alpha d) from the
+# last three outputs, x^ = R(u) x + d^.
+# --------------------------------------------------------------------------
+def quat_normalize(q):
+    """q [..., 4] raw outputs -> (u [..., 4] unit quaternion (w, x, y, z), norm)."""
+    a = np.array(q, dtype=np.float64, copy=True)
+    a[..., 0] += 1.0
+    n = np.linalg.norm(a, axis=-1)
+    return a / n[..., None], n
+
+
+def quat_matrix(u):
+    """Rotation matrix of the unit quaternion u = (w, x, y, z), entry by entry."""
+    w, x, y, z = u[..., 0], u[..., 1], u[..., 2], u[..., 3]
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def _quat_matrix_partials(u):
+    """d quat_matrix / d (w, x, y, z) [..., 4, 3, 3]: the entry-wise partial
+    derivatives of the polynomial matrix above."""
+    w, x, y, z = u[..., 0], u[..., 1], u[..., 2], u[..., 3]
+    o = np.zeros_like(w)
+    m = lambda *rows: 2.0 * np.stack([np.stack(r, -1) for r in rows], -2)
+    dw = m((o, -z, y), (z, o, -x), (-y, x, o))
+    dx = m((o, y, z), (y, -2 * x, -w), (z, w, -2 * x))
+    dy = m((-2 * y, x, w), (x, o, z), (-w, z, -2 * y))
+    dz = m((-2 * z, -w, x), (w, -2 * z, y), (x, y, o))
+    return np.stack([dw, dx, dy, dz], -3)
+
+
+def _transform_quat(o, X, alpha):
+    u, _ = quat_normalize(o[..., :4])
+    R = quat_matrix(u)
+    dh = np.tanh(alpha * o[..., 4:7])
+    return np.einsum("...ab,...b->...a", R, X) + dh, R, dh
+
+
+def _transform_quat_backward(g, o, X, R, dh, alpha):
+    """Chain rule through the normalisation: with u = a/|a|, du/da =
+    (I - u u^T)/|a|; d(g . R(u) x)/du_k = g^T (dR/du_k) x."""
+    u, n = quat_normalize(o[..., :4])
+    gu = np.einsum("...a,...kab,...b->...k", g, _quat_matrix_partials(u), X)
+    gq = (gu - u * (u * gu).sum(-1, keepdims=True)) / n[..., None]
+    gd = alpha * (1.0 - dh ** 2) * g
+    return np.concatenate([gq, gd], axis=-1)
+
+
+def n_outputs(head):
+    """Network outputs of each rotation head: exp map (omega, d) or quaternion (q, d)."""
+    return {"expmap": 6, "quat": 7}[head]
+
+
+def transform(o, X, alpha, head="expmap"):
+    """x^ = R X + tanh(alpha d) for either rotation head; returns (x^, R, d^)."""
+    return (_transform_quat if head == "quat" else _transform_expmap)(o, X, alpha)
+
+
+def transform_backward(g, o, X, R, dh, alpha, head="expmap"):
+    """d (g . x^) / d o for either rotation head."""
+    return (_transform_quat_backward if head == "quat" else _transform_expmap_backward)(g, o, X, R, dh, alpha)
 
 
 # --------------------------------------------------------------------------
@@ -277,7 +347,7 @@ def forward(params, data, cfg):
     Y = decoder_input(z, gamma)
     o, pres, ins = mlp_forward(params["mlp"], Y, cfg["act"], cfg["leaky_slope"])
     Xt = np.tile(X, (T, 1))
-    xh, R, dh = transform(o, Xt, cfg["alpha_t"])
+    xh, R, dh = transform(o, Xt, cfg["alpha_t"], cfg.get("rot_head", "expmap"))
     return dict(z=z, gamma=gamma, Y=Y, o=o, pres=pres, ins=ins, R=R, dh=dh,
                 xhat=xh.reshape(T, V, 3), Xt=Xt)
 
@@ -318,7 +388,8 @@ def backward(params, data, cfg, fw, ls):
     Nrm = np.asarray(data["nrm"], np.float64)
     T, V, _ = fw["xhat"].shape
     gx = chamfer_backward(fw["xhat"], P, data["frame_off"], ls["a"], ls["b"], ls["w"])
-    go = transform_backward(gx.reshape(T * V, 3), fw["o"], fw["Xt"], fw["R"], fw["dh"], cfg["alpha_t"])
+    go = transform_backward(gx.reshape(T * V, 3), fw["o"], fw["Xt"], fw["R"], fw["dh"], cfg["alpha_t"],
+                            cfg.get("rot_head", "expmap"))
     gmlp, gY = mlp_backward(params["mlp"], go, fw["pres"], fw["ins"], cfg["act"], cfg["leaky_slope"])
     Fz = cfg["feat_n"] + cfg["feat_p"]
     gz = gY[:, :Fz].reshape(T, V, Fz).sum(0)

@@ -26,6 +26,7 @@ def _base(**kw):
         mlp_hidden=2, mlp_width=64, # hidden layers and their width
         act="relu", leaky_slope=0.01,
         alpha_t=0.1,                # displacement squashing tanh(alpha d)
+        rot_head="expmap",          # "expmap" (6 outputs) or "quat" (7 outputs)
         lr_mlp=1e-3,
         lr_grid=None, lr_n=0.005,
         lam=None, lam_n=0.4,

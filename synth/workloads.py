@@ -180,6 +180,12 @@ def _small_workload(cfg, rng):
     return dict(xyz=X, nrm=Nrm, pts_list=pts, truth=None, edges=None)
 
 
+def _out_dim(cfg):
+    """Network outputs: rotation parameters (3 for the exp map, 4 for the
+    quaternion head) plus the 3 displacement components."""
+    return 7 if cfg.get("rot_head", "expmap") == "quat" else 6
+
+
 def _in_dim(cfg):
     M = cfg["time_freqs"]
     return cfg["feat_n"] + cfg["feat_p"] + (2 * M if M > 0 else 1)
@@ -198,7 +204,7 @@ def init_params(cfg, seed=None):
     gp = [(rng.normal(scale=std, size=(R ** 3, F)) if std > 0 else np.zeros((R ** 3, F)))
           .astype(np.float32) for R in cfg["levels"]]
     gn = (rng.normal(scale=std, size=(Rn ** 3, Fn)) if std > 0 else np.zeros((Rn ** 3, Fn))).astype(np.float32)
-    dims = [_in_dim(cfg)] + [cfg["mlp_width"]] * cfg["mlp_hidden"] + [6]
+    dims = [_in_dim(cfg)] + [cfg["mlp_width"]] * cfg["mlp_hidden"] + [_out_dim(cfg)]
     mlp = []
     for k in range(len(dims) - 1):
         fi, fo = dims[k], dims[k + 1]

@@ -41,9 +41,9 @@ def _perturb(p, flat_delta):
     return out
 
 
-@pytest.mark.parametrize("act,M", [("leaky", 2), ("relu", 0)])
-def test_full_loss_gradient_matches_central_differences(act, M):
-    cfg = synth.config_small(act=act, time_freqs=M, N=[50, 41, 47])
+@pytest.mark.parametrize("act,M,head", [("leaky", 2, "expmap"), ("relu", 0, "expmap"), ("leaky", 2, "quat")])
+def test_full_loss_gradient_matches_central_differences(act, M, head):
+    cfg = synth.config_small(act=act, time_freqs=M, N=[50, 41, 47], rot_head=head)
     data = synth.make_workload(cfg)
     p = O.to64(synth.random_state(cfg, 3))
     fw = O.forward(p, data, cfg)

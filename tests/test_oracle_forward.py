@@ -154,6 +154,63 @@ def test_transform_backward_matches_finite_differences():
     np.testing.assert_allclose(go0[:, :3], np.cross(X, g), atol=1e-15)
 
 
+def test_quaternion_head_matches_scipy_and_is_a_rotation():
+    # Sec. 3.4: u = (1 + q_w, q_x, q_y, q_z) / norm; R(u) against scipy's
+    # quaternion -> matrix (scalar-last convention there).
+    rng = np.random.default_rng(4)
+    q = rng.normal(scale=0.6, size=(200, 4))
+    u, n = O.quat_normalize(q)
+    np.testing.assert_allclose(np.linalg.norm(u, axis=1), 1.0, atol=1e-15)
+    R = O.quat_matrix(u)
+    Rs = Rotation.from_quat(np.c_[u[:, 1:], u[:, 0]]).as_matrix()
+    np.testing.assert_allclose(R, Rs, atol=1e-14)
+    np.testing.assert_allclose(R @ np.swapaxes(R, 1, 2), np.broadcast_to(np.eye(3), R.shape), atol=1e-14)
+    np.testing.assert_allclose(np.linalg.det(R), 1.0, atol=1e-14)
+    # zero output is the identity; scaling (1 + q_w, q_v) leaves R unchanged
+    np.testing.assert_array_equal(O.quat_matrix(O.quat_normalize(np.zeros((1, 4)))[0])[0], np.eye(3))
+    a = q.copy()
+    a[:, 0] += 1.0
+    q2 = 2.5 * a
+    q2[:, 0] -= 1.0
+    np.testing.assert_allclose(O.quat_matrix(O.quat_normalize(q2)[0]), R, atol=1e-14)
+
+
+def test_quaternion_head_agrees_with_the_exp_map_head():
+    # the unit quaternion (cos(th/2), sin(th/2) k) and the rotation vector th k
+    # are the same rotation, so both heads give the same deformed points
+    rng = np.random.default_rng(5)
+    w = rng.normal(scale=0.8, size=(100, 3))
+    th = np.linalg.norm(w, axis=1, keepdims=True)
+    q = np.c_[np.cos(th / 2) - 1.0, np.sin(th / 2) * w / th]
+    d = rng.normal(size=(100, 3))
+    X = rng.uniform(-1, 1, size=(100, 3))
+    xq = O.transform(np.c_[q, d], X, 0.1, "quat")[0]
+    xe = O.transform(np.c_[w, d], X, 0.1, "expmap")[0]
+    np.testing.assert_allclose(xq, xe, atol=1e-14)
+
+
+def test_quaternion_backward_matches_finite_differences():
+    rng = np.random.default_rng(6)
+    o = rng.normal(scale=0.5, size=(40, 7))
+    X = rng.uniform(-1, 1, size=(40, 3))
+    g = rng.normal(size=(40, 3))
+    xh, R, dh = O.transform(o, X, 0.1, "quat")
+    go = O.transform_backward(g, o, X, R, dh, 0.1, "quat")
+    h = 1e-6
+    fd = np.zeros_like(o)
+    for k in range(7):
+        e = np.zeros(7)
+        e[k] = h
+        fp = (O.transform(o + e, X, 0.1, "quat")[0] * g).sum(1)
+        fm = (O.transform(o - e, X, 0.1, "quat")[0] * g).sum(1)
+        fd[:, k] = (fp - fm) / (2 * h)
+    np.testing.assert_allclose(go, fd, rtol=1e-6, atol=1e-8)
+    # R depends only on the direction of (1 + q_w, q_v): no radial gradient
+    a = o[:, :4].copy()
+    a[:, 0] += 1.0
+    np.testing.assert_allclose((go[:, :4] * a).sum(1), 0.0, atol=1e-13)
+
+
 def test_identity_start_is_exact():
     # Sec. 3.1: zero last layer => o = 0 => R = I, d^ = 0, x^ = x exactly.
     cfg = synth.config_c1()
