@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,dct", help="preconditioner forms to time (cg is the headline)")
+    ap.add_argument("--forms", default="cg,dct,quat",
+                    help="forms to time: cg (headline), dct (exact DCT preconditioner), "
+                         "quat (quaternion rotation head, DCT preconditioner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with one plain 1 GiB device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
@@ -153,6 +155,10 @@ def main():
         sys.exit(2)
     cg = run_form(dict(cfg, precond="cg"), data, P0, args.steps, args.warmup, profile=True)
     dct = run_form(dict(cfg, precond="dct"), data, P0, args.steps, args.warmup, profile=False) if "dct" in forms else None
+    quat = None
+    if "quat" in forms:
+        cq = dict(cfg, precond="dct", rot_head="quat")
+        quat = run_form(cq, data, synth.random_state(cq, 9, grid_std=0.05), args.steps, args.warmup, profile=False)
     prof = cg["prof"]
     cg_iter_ms = prof["cg_ms"] / max(prof["cg_iters"], 1)
     achieved = (prof["cg_bytes"] / 1e9) / (prof["cg_ms"] / 1e3) if prof["cg_ms"] > 0 else 0.0
@@ -190,6 +196,10 @@ def main():
         "precond_dct": None if dct is None else {
             "value": round(dct["value"], 4), "unit": "steps/s", "ms_per_step": round(dct["ms_per_step"], 3),
             "stage_ms": dct["stage_ms"], "note": "same step with the exact DCT form of (I + lambda L)^-2"},
+        "rot_quat": None if quat is None else {
+            "value": round(quat["value"], 4), "unit": "steps/s", "ms_per_step": round(quat["ms_per_step"], 3),
+            "stage_ms": quat["stage_ms"],
+            "note": "quaternion rotation head (7 outputs, Sec. 3.4) with the DCT preconditioner; compare precond_dct"},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

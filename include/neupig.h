@@ -46,7 +46,8 @@
  *   W_k:      [out][in] row-major, then b_k [out]. Layer 1 maps the decoder
  *             input y = (z_n, z_p, gamma(t)) (Sec. 3.3, in this order) of
  *             width F_n + F_p + (2M or 1) to the hidden width; H hidden
- *             layers; the last layer maps to 6 outputs (omega, d).
+ *             layers; the last layer maps to 6 outputs (omega, d) with the
+ *             exp-map head or 7 (q, d) with the quaternion head.
  * The same layout is used for gradients and the two Adam moment vectors.
  */
 #ifndef NEUPIG_H
@@ -71,6 +72,10 @@ typedef enum {
 
 enum { NPG_ACT_RELU = 0, NPG_ACT_LEAKY = 1 };
 enum { NPG_PRECOND_CG = 0, NPG_PRECOND_DCT = 1 };
+/* Rotation head (Sec. 3.4): the exponential map of the supplementary rotation
+ * study (6 network outputs: omega, d) or the unit quaternion
+ * (1 + q_w, q_x, q_y, q_z)/norm of the main text (7 outputs: q, d). */
+enum { NPG_ROT_EXPMAP = 0, NPG_ROT_QUAT = 1 };
 
 /* Hyper-parameters. Every reading the paper leaves open is a field here. */
 typedef struct npg_config {
@@ -97,6 +102,7 @@ typedef struct npg_config {
   double cg_rtol;                 /* relative residual stop of each CG solve        */
   int32_t cg_maxit;               /* iteration cap of each CG solve                 */
   int32_t precond;                /* NPG_PRECOND_CG (iterative) or _DCT (exact)     */
+  int32_t rot_head;               /* NPG_ROT_EXPMAP or NPG_ROT_QUAT                 */
 } npg_config;
 
 typedef struct npg_plan npg_plan;

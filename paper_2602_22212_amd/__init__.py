@@ -18,6 +18,7 @@ NPG_MAX_LEVELS = 16
 NPG_OK, NPG_EINVAL, NPG_ENOMEM, NPG_EHIP, NPG_ENOTCONV, NPG_ENONFINITE = range(6)
 NPG_ACT_RELU, NPG_ACT_LEAKY = 0, 1
 NPG_PRECOND_CG, NPG_PRECOND_DCT = 0, 1
+NPG_ROT_EXPMAP, NPG_ROT_QUAT = 0, 1
 STAGES = ("encode", "decode", "chamfer+loss", "chamfer_bwd", "decode_bwd", "encode_bwd", "precond", "adam")
 
 
@@ -38,6 +39,7 @@ class npg_config(ctypes.Structure):
         ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
         ("conf_weight", ctypes.c_int32), ("t_key", ctypes.c_int32),
         ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precond", ctypes.c_int32),
+        ("rot_head", ctypes.c_int32),
     ]
 
 
@@ -111,6 +113,10 @@ def make_config(cfg):
     c.t_key = -1 if cfg.get("t_key") is None else int(cfg["t_key"])
     c.cg_rtol, c.cg_maxit = float(cfg["cg_rtol"]), int(cfg["cg_maxit"])
     c.precond = NPG_PRECOND_DCT if cfg.get("precond", "cg") == "dct" else NPG_PRECOND_CG
+    head = cfg.get("rot_head", "expmap")
+    if head not in ("expmap", "quat"):
+        raise ValueError(f"rot_head must be 'expmap' or 'quat', not {head!r}")
+    c.rot_head = NPG_ROT_QUAT if head == "quat" else NPG_ROT_EXPMAP
     return c
 
 
@@ -131,7 +137,8 @@ def param_layout(cfg):
     out.append(("grid_n", off, (Rn ** 3, Fn)))
     off += Rn ** 3 * Fn
     M = cfg["time_freqs"]
-    dims = [Fn + F + (2 * M if M > 0 else 1)] + [cfg["mlp_width"]] * cfg["mlp_hidden"] + [6]
+    n_out = 7 if cfg.get("rot_head", "expmap") == "quat" else 6
+    dims = [Fn + F + (2 * M if M > 0 else 1)] + [cfg["mlp_width"]] * cfg["mlp_hidden"] + [n_out]
     for k in range(len(dims) - 1):
         out.append((f"W{k}", off, (dims[k + 1], dims[k])))
         off += dims[k + 1] * dims[k]

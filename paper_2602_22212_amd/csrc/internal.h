@@ -49,6 +49,7 @@ struct npg_plan {
   NpgGrid g[NPG_MAX_SYS];
   int64_t n_grid_params, n_nodes, mlp_off, n_params;
   int Fz, Din, W, H, M;
+  int n_out;  // network outputs: 6 (exp map) or 7 (quaternion)
   int t_key;
   // static device data
   float4 *xyz, *nrm, *pts;

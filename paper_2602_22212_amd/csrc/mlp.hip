@@ -55,8 +55,8 @@ __device__ __forceinline__ float comp(const float4& v, int r) {
 
 // Workspace layout of the repacked weights (floats, every block 16-B aligned):
 //   for hidden layer l = 1..H-1:  Wh[l] [W][W] (row = out), WhT[l] [W][W]
-//   (row = in), bh[l] [W]; then WoP [16][W] (output rows, 6..15 zero),
-//   WoT [W][16] (transposed, columns 6..15 zero), bo [16].
+//   (row = in), bh[l] [W]; then WoP [16][W] (output rows; rows n_out..15
+//   zero), WoT [W][16] (transposed, columns n_out..15 zero), bo [16].
 struct WPack {
   int64_t wh, wht, bh, wop, wot, bo, total;
   __host__ __device__ WPack(int W, int H) {
@@ -77,7 +77,8 @@ __host__ __device__ inline int64_t mlp_layer_off(int l, int W, int Din) {
   return (int64_t)W * Din + W + (int64_t)(l - 1) * ((int64_t)W * W + W);
 }
 
-__global__ void k_prep_weights(const float* __restrict__ mlp, int W, int H, int Din, float* __restrict__ wp) {
+__global__ void k_prep_weights(const float* __restrict__ mlp, int W, int H, int Din, int n_out,
+                               float* __restrict__ wp) {
   WPack P(W, H);
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= P.total) return;
@@ -97,14 +98,14 @@ __global__ void k_prep_weights(const float* __restrict__ mlp, int W, int H, int 
   } else if (e < P.wot) {
     int64_t k = e - P.wop;
     int64_t row = k / W, col = k % W;
-    if (row < 6) val = mlp[mlp_layer_off(H, W, Din) + row * W + col];
+    if (row < n_out) val = mlp[mlp_layer_off(H, W, Din) + row * W + col];
   } else if (e < P.bo) {
     int64_t k = e - P.wot;
     int64_t in = k / 16, o = k % 16;
-    if (o < 6) val = mlp[mlp_layer_off(H, W, Din) + o * W + in];
+    if (o < n_out) val = mlp[mlp_layer_off(H, W, Din) + o * W + in];
   } else {
     int64_t o = e - P.bo;
-    if (o < 6) val = mlp[mlp_layer_off(H, W, Din) + 6 * (int64_t)W + o];
+    if (o < n_out) val = mlp[mlp_layer_off(H, W, Din) + n_out * (int64_t)W + o];
   }
   wp[e] = val;
 }
@@ -198,6 +199,52 @@ __device__ __forceinline__ void transform_grad(const float* o, float4 xr, float4
   }
 }
 
+// ---- quaternion head (Sec. 3.4) ----------------------------------------------
+// u = (w, v) = (1 + o0, o1, o2, o3) / norm; for a unit quaternion
+// R(u) x = x + 2w (v x x) + 2 v x (v x x); d^ = tanh(alpha o[4..6]).
+__device__ __forceinline__ float4 apply_quat(const float* o, float4 xr, float alpha) {
+  const float a0 = 1.f + o[0];
+  const float inv = 1.f / sqrtf(a0 * a0 + o[1] * o[1] + o[2] * o[2] + o[3] * o[3]);
+  const float w = a0 * inv;
+  const float3 v = make_float3(o[1] * inv, o[2] * inv, o[3] * inv);
+  const float3 x = make_float3(xr.x, xr.y, xr.z);
+  const float3 t = cross3(v, x);
+  const float3 vt = cross3(v, t);
+  return make_float4(x.x + 2.f * (w * t.x + vt.x) + tanhf(alpha * o[4]),
+                     x.y + 2.f * (w * t.y + vt.y) + tanhf(alpha * o[5]),
+                     x.z + 2.f * (w * t.z + vt.z) + tanhf(alpha * o[6]), 0.f);
+}
+
+// Gradient of g . x^ w.r.t. the 7 outputs. With the form above,
+// d/dw = 2 g.(v x x), d/dv = 2w (x x g) + 2 [g (v.x) + x (g.v) - 2 v (g.x)];
+// the normalisation maps a gradient gu on u to (gu - u (u.gu)) / norm.
+__device__ __forceinline__ void quat_grad(const float* o, float4 xr, float4 gr, float alpha, float* go) {
+  const float a0 = 1.f + o[0];
+  const float inv = 1.f / sqrtf(a0 * a0 + o[1] * o[1] + o[2] * o[2] + o[3] * o[3]);
+  const float w = a0 * inv;
+  const float3 v = make_float3(o[1] * inv, o[2] * inv, o[3] * inv);
+  const float3 x = make_float3(xr.x, xr.y, xr.z);
+  const float3 g = make_float3(gr.x, gr.y, gr.z);
+  const float3 vx = cross3(v, x), xg = cross3(x, g);
+  const float vdx = v.x * x.x + v.y * x.y + v.z * x.z;
+  const float gdv = g.x * v.x + g.y * v.y + g.z * v.z;
+  const float gdx = g.x * x.x + g.y * x.y + g.z * x.z;
+  const float gw = 2.f * (g.x * vx.x + g.y * vx.y + g.z * vx.z);
+  const float g1 = 2.f * (w * xg.x + g.x * vdx + x.x * gdv - 2.f * v.x * gdx);
+  const float g2 = 2.f * (w * xg.y + g.y * vdx + x.y * gdv - 2.f * v.y * gdx);
+  const float g3 = 2.f * (w * xg.z + g.z * vdx + x.z * gdv - 2.f * v.z * gdx);
+  const float ug = w * gw + v.x * g1 + v.y * g2 + v.z * g3;
+  go[0] = (gw - w * ug) * inv;
+  go[1] = (g1 - v.x * ug) * inv;
+  go[2] = (g2 - v.y * ug) * inv;
+  go[3] = (g3 - v.z * ug) * inv;
+  for (int k = 0; k < 3; ++k) {
+    float dh = tanhf(alpha * o[4 + k]);
+    float gk = k == 0 ? g.x : (k == 1 ? g.y : g.z);
+    go[4 + k] = alpha * (1.f - dh * dh) * gk;
+  }
+}
+
 // out[mt] += sum_k Wrow(16mt + c, k) * in[k] over all k tiles; wl(mt, kt)
 // returns the float4 of row 16mt + c at columns 16kt + 4q .. +3. The operands
 // of k-tile kt+1 are requested before the MFMAs of k-tile kt are issued, so
@@ -223,7 +270,7 @@ __device__ __forceinline__ void dense(const v4f (&in)[NT], v4f (&out)[NT], WL wl
   }
 }
 
-// 16-row output layer (rows 6..15 zero): o = Wo h + bo.
+// 16-row output layer (rows n_out..15 zero): o = Wo h + bo.
 template <int NT, typename WL>
 __device__ __forceinline__ v4f dense_out(const v4f (&in)[NT], v4f init, WL wl) {
   v4f a0 = init, a1 = {0.f, 0.f, 0.f, 0.f};
@@ -274,7 +321,7 @@ template <int W, int H>
 __global__ __launch_bounds__(512) void k_decode_fwd(const float* __restrict__ wp, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float4* __restrict__ xyz,
                                                     float4* __restrict__ xhat, int64_t V, int T, ActP ap,
-                                                    float alpha) {
+                                                    float alpha, int quat) {
   constexpr int NT = W / 16;
   constexpr int LD = W + 4;  // padded LDS row
   extern __shared__ float lds[];
@@ -323,9 +370,10 @@ __global__ __launch_bounds__(512) void k_decode_fwd(const float* __restrict__ wp
     v4f o = dense_out<NT>(h[H - 1], boi, wol);
     float o4 = __shfl(o[0], (lane + 16) & 63);
     float o5 = __shfl(o[1], (lane + 16) & 63);
+    float o6 = __shfl(o[2], (lane + 16) & 63);
     if (q == 0 && valid) {
-      float ov[6] = {o[0], o[1], o[2], o[3], o4, o5};
-      xhat[s] = apply_transform(ov, xyz[i], alpha);
+      float ov[7] = {o[0], o[1], o[2], o[3], o4, o5, o6};
+      xhat[s] = quat ? apply_quat(ov, xyz[i], alpha) : apply_transform(ov, xyz[i], alpha);
     }
   }
 }
@@ -347,7 +395,7 @@ template <int W, int H>
 __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float4* __restrict__ xyz,
                                                     const float4* __restrict__ gxhat, int64_t V, int T, ActP ap,
-                                                    float alpha, float* __restrict__ Gv,
+                                                    float alpha, int quat, float* __restrict__ Gv,
                                                     float* __restrict__ Gt_part, float* __restrict__ gW_part) {
   constexpr int NT = W / 16;
   constexpr int NTT = (NT * NT + 3) / 4;  // owned hidden weight-gradient tiles per wave
@@ -472,15 +520,18 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
     // ---- transform backward: every lane evaluates its sample c -----------
     float o4 = __shfl(o[0], (lane + 16) & 63);
     float o5 = __shfl(o[1], (lane + 16) & 63);
-    float ov[6] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
-                   __shfl(o5, c)};
+    float o6 = __shfl(o[2], (lane + 16) & 63);
+    float ov[7] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
+                   __shfl(o5, c), __shfl(o6, c)};
     float4 gx = vvalid ? gxhat[(int64_t)t * V + i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    float go[6];
-    transform_grad(ov, xi, gx, alpha, go);
+    float go[7];
+    go[6] = 0.f;
+    if (quat) quat_grad(ov, xi, gx, alpha, go);
+    else transform_grad(ov, xi, gx, alpha, go);
     if (!vvalid)
-      for (int k = 0; k < 6; ++k) go[k] = 0.f;
+      for (int k = 0; k < 7; ++k) go[k] = 0.f;
     const v4f got = q == 0 ? v4f{go[0], go[1], go[2], go[3]}
-                           : (q == 1 ? v4f{go[4], go[5], 0.f, 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
+                           : (q == 1 ? v4f{go[4], go[5], go[6], 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
 
     // ---- output layer: weight gradient and back-propagation ---------------
 #pragma unroll
@@ -547,7 +598,8 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
       for (int r = 0; r < 4; ++r) Gv[i_raw * W + 16 * mt + 4 * q + r] = gv[mt][r];
   }
   // per-work-group weight-gradient partials, flat MLP layout of layers 1..H
-  const int64_t len = (int64_t)(H - 1) * ((int64_t)W * W + W) + 6 * (int64_t)W + 6;
+  const int n_out = quat ? 7 : 6;
+  const int64_t len = (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
   float* dst = gW_part + vb * len;
 #pragma unroll
   for (int l = 1; l < H; ++l) {
@@ -570,10 +622,10 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
     if (kt < NT) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (4 * q + r < 6) dout[(4 * q + r) * W + 16 * kt + c] = accO[k][r];
+        if (4 * q + r < n_out) dout[(4 * q + r) * W + 16 * kt + c] = accO[k][r];
     }
   }
-  if (threadIdx.x < 6) dout[6 * W + threadIdx.x] = sGb[(H - 1) * W + threadIdx.x];
+  if ((int)threadIdx.x < n_out) dout[n_out * W + threadIdx.x] = sGb[(H - 1) * W + threadIdx.x];
 }
 
 // Sum the per-work-group partials in work-group order.
@@ -663,7 +715,7 @@ hipError_t launch_fwd(const npg_plan* P, float4* xhat, ActP ap) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_decode_fwd<W, H>), dim3(P->n_cu), dim3(512), lds, P->stream, P->wpack, P->mlpA,
-                     P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t);
+                     P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7));
   return hipGetLastError();
 }
 
@@ -674,7 +726,8 @@ hipError_t launch_bwd(const npg_plan* P, const float4* gxhat, ActP ap) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_decode_bwd<W, H>), dim3(P->n_vblk_mlp), dim3(256), lds, P->stream, P->wpack, P->mlpA,
-                     P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t, P->Gv, P->Gt_part, P->gW_part);
+                     P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->Gv,
+                     P->Gt_part, P->gW_part);
   return hipGetLastError();
 }
 
@@ -682,7 +735,7 @@ hipError_t prep(const npg_plan* P, const float* params, const float* z) {
   const float* mlp = params + P->mlp_off;
   const WPack wpk(P->W, P->H);
   hipLaunchKernelGGL(k_prep_weights, dim3(nblk(wpk.total, 256)), dim3(256), 0, P->stream, mlp, P->W, P->H,
-                     P->Din, P->wpack);
+                     P->Din, P->n_out, P->wpack);
   hipLaunchKernelGGL(k_prep_A, dim3(nblk(P->V * P->W, 256)), dim3(256), 0, P->stream, mlp, z, P->V, P->W,
                      P->Din, P->Fz, P->mlpA);
   hipLaunchKernelGGL(k_prep_B, dim3(nblk((int64_t)P->T * P->W, 256)), dim3(256), 0, P->stream, mlp, P->gam,
@@ -707,7 +760,9 @@ hipError_t prep(const npg_plan* P, const float* params, const float* z) {
 }  // namespace
 
 int64_t npg_wpack_len(int W, int H) { return WPack(W, H).total; }
-int64_t npg_gw_part_len(int W, int H) { return (int64_t)(H - 1) * ((int64_t)W * W + W) + 6 * (int64_t)W + 6; }
+int64_t npg_gw_part_len(int W, int H, int n_out) {
+  return (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
+}
 size_t npg_decode_fwd_lds(int W, int H) { return sizeof(float) * ((size_t)(H - 1) * W * (W + 4) + 16 * (W + 4) + (H - 1) * W + 16); }
 
 hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat) {

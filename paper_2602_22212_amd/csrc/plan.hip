@@ -10,7 +10,7 @@
 
 // launchers defined in the other translation units
 int64_t npg_wpack_len(int W, int H);
-int64_t npg_gw_part_len(int W, int H);
+int64_t npg_gw_part_len(int W, int H, int n_out);
 int npg_chamfer_vblock();
 npg_status npg_cg_setup(npg_plan* P);
 void npg_cg_free(npg_plan* P);
@@ -87,6 +87,7 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->eps > 0.f, "eps must be > 0");
   CHECK_ARG(c->cg_maxit >= 1 && c->cg_rtol > 0.0, "cg_maxit >= 1 and cg_rtol > 0 are required");
   CHECK_ARG(c->precond == NPG_PRECOND_CG || c->precond == NPG_PRECOND_DCT, "precond must be CG or DCT");
+  CHECK_ARG(c->rot_head == NPG_ROT_EXPMAP || c->rot_head == NPG_ROT_QUAT, "rot_head must be EXPMAP or QUAT");
   if (c->precond == NPG_PRECOND_DCT) {
     for (int l = 0; l < c->n_levels; ++l)
       CHECK_ARG(c->res[l] <= 256, "the DCT preconditioner supports up to 256 nodes per axis");
@@ -114,7 +115,8 @@ npg_status npg_param_count(const npg_config* cfg, int64_t* count) {
   n += (int64_t)cfg->res_n * cfg->res_n * cfg->res_n * cfg->feat_n;
   const int W = cfg->mlp_width, H = cfg->mlp_hidden;
   const int Din = cfg->feat_n + cfg->feat_p + (cfg->time_freqs > 0 ? 2 * cfg->time_freqs : 1);
-  n += (int64_t)W * Din + W + (int64_t)(H - 1) * ((int64_t)W * W + W) + 6 * (int64_t)W + 6;
+  const int n_out = cfg->rot_head == NPG_ROT_QUAT ? 7 : 6;
+  n += (int64_t)W * Din + W + (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
   *count = n;
   return NPG_OK;
 }
@@ -214,6 +216,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   P->M = cfg->time_freqs;
   P->Fz = cfg->feat_n + cfg->feat_p;
   P->Din = P->Fz + (P->M > 0 ? 2 * P->M : 1);
+  P->n_out = cfg->rot_head == NPG_ROT_QUAT ? 7 : 6;
 
   // inputs
   TRYP(dalloc(&P->xyz, V));
@@ -273,7 +276,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->mlpB, (int64_t)T * P->W));
   TRYP(dalloc(&P->wpack, npg_wpack_len(P->W, P->H)));
   P->n_vblk_mlp = (int)((V + 63) / 64);
-  P->gw_part_len = npg_gw_part_len(P->W, P->H);
+  P->gw_part_len = npg_gw_part_len(P->W, P->H, P->n_out);
   TRYP(dalloc(&P->Gv, V * P->W));
   TRYP(dalloc(&P->Gt, (int64_t)T * P->W));
   TRYP(dalloc(&P->Gt_part, (int64_t)T * P->n_vblk_mlp * P->W));

@@ -29,7 +29,12 @@ def _c1():
     return synth.config_c1()
 
 
-CONFIGS = {"c1": _c1, "mid": _mid}
+def _mid_quat():
+    # the same model with the quaternion rotation head of Sec. 3.4 (7 outputs)
+    return dict(_mid(), name="mid_quat", rot_head="quat")
+
+
+CONFIGS = {"c1": _c1, "mid": _mid, "mid_quat": _mid_quat}
 
 
 @pytest.fixture(scope="module", params=list(CONFIGS))
@@ -174,7 +179,8 @@ def test_loss_and_chamfer_backward(case):
 def _oracle_decode_bwd(case, gx):
     cfg, fw = case["cfg"], case["fw"]
     T, V = case["T"], case["V"]
-    go = O.transform_backward(gx.reshape(T * V, 3), fw["o"], fw["Xt"], fw["R"], fw["dh"], cfg["alpha_t"])
+    go = O.transform_backward(gx.reshape(T * V, 3), fw["o"], fw["Xt"], fw["R"], fw["dh"], cfg["alpha_t"],
+                              cfg.get("rot_head", "expmap"))
     gmlp, gY = O.mlp_backward(case["P"]["mlp"], go, fw["pres"], fw["ins"], cfg["act"], cfg["leaky_slope"])
     Fz = cfg["feat_n"] + cfg["feat_p"]
     return gmlp, gY[:, :Fz].reshape(T, V, Fz).sum(0)

@@ -25,8 +25,8 @@ def _touched_nodes(cfg, data):
     return out
 
 
-@pytest.mark.parametrize("method", ["cg", "dct"])
-def test_teacher_forced_steps_on_icosphere(method):
+@pytest.mark.parametrize("method,head", [("cg", "expmap"), ("dct", "expmap"), ("cg", "quat")])
+def test_teacher_forced_steps_on_icosphere(method, head):
     """Each step starts both sides from the oracle's state (Adam moments
     included). Loss, per-frame Chamfer distances and the updated MLP and
     touched grid nodes must match; nodes no vertex reads never influence the
@@ -34,7 +34,7 @@ def test_teacher_forced_steps_on_icosphere(method):
     import torch
 
     import paper_2602_22212_amd as npg
-    cfg = dict(synth.config_c1(), precond=method)
+    cfg = dict(synth.config_c1(), precond=method, rot_head=head)
     data = synth.make_workload(cfg)
     plan = gpu_plan(cfg, data)
     touched = _touched_nodes(cfg, data)
