@@ -27,7 +27,7 @@ __all__ = [
     "transform", "transform_backward", "chamfer", "confidence", "forward",
     "backward", "laplacian_apply", "precond_dct", "precond_cg", "precondition",
     "adam", "step", "to64", "zeros_like_params", "flatten_params", "losses",
-    "chamfer_backward", "quat_matrix", "quat_normalize", "n_outputs",
+    "chamfer_backward", "quat_matrix", "quat_normalize", "n_outputs", "iso_loss", "iso_backward", "iso_signs",
 ]
 
 
@@ -335,6 +335,48 @@ def confidence(cd, t_key, epoch, n_epochs, enabled=True):
     return w
 
 
+# --------------------------------------------------------------------------
+# Sec. 3.5 "Isometry Loss": mean over frames and mesh edges of
+# | |x^_i,t - x^_j,t| - sg(|x^_i,key - x^_j,key|) |, the key-frame lengths taken
+# from the current deformed key frame under a stop-gradient. The total
+# objective is L_def + w_iso L_iso. Subgradients: sign(0) = 0 (so the key
+# frame's own terms contribute no gradient); a zero-length edge contributes 0.
+# --------------------------------------------------------------------------
+def _edge_lengths(xhat, edges):
+    d = xhat[:, edges[:, 0]] - xhat[:, edges[:, 1]]          # [T, E, 3]
+    return d, np.sqrt((d * d).sum(-1))
+
+
+def iso_loss(xhat, edges, t_key):
+    """xhat [T, V, 3], edges [E, 2] -> L_iso (float)."""
+    T, E = xhat.shape[0], len(edges)
+    _, ell = _edge_lengths(xhat, edges)
+    return float(np.abs(ell - ell[t_key][None]).sum() / (T * E))
+
+
+def iso_signs(xhat, edges, t_key):
+    """sign(|e_t| - |e_key|) per frame and edge [T, E]: the subgradient
+    decisions of the L1 isometry term."""
+    _, ell = _edge_lengths(xhat, edges)
+    return np.sign(ell - ell[t_key][None])
+
+
+def iso_backward(xhat, edges, t_key, sign=None):
+    """d L_iso / d x^ [T, V, 3] with the key-frame lengths held fixed. `sign`
+    ([T, E], values -1/0/+1) replaces the float64 decisions of iso_signs, so a
+    caller can evaluate the gradient with decisions taken in another
+    precision."""
+    T, E = xhat.shape[0], len(edges)
+    d, ell = _edge_lengths(xhat, edges)
+    s = iso_signs(xhat, edges, t_key) if sign is None else np.asarray(sign, np.float64)
+    coef = np.where(ell > 0, s / np.where(ell > 0, ell, 1.0), 0.0) / (T * E)
+    g = np.zeros_like(xhat)
+    tt = np.repeat(np.arange(T), E)
+    np.add.at(g, (tt, np.tile(edges[:, 0], T)), (coef[..., None] * d).reshape(-1, 3))
+    np.add.at(g, (tt, np.tile(edges[:, 1], T)), -(coef[..., None] * d).reshape(-1, 3))
+    return g
+
+
 def forward(params, data, cfg):
     """Forward pass over all frames. data: xyz [V,3], nrm [V,3], pts [sum N,3],
     frame_off [T+1]."""
@@ -361,8 +403,12 @@ def losses(fw, data, cfg, epoch, n_epochs):
     t_key = cfg["t_key"] if cfg["t_key"] is not None else (T - 1) // 2
     w = confidence(cd, t_key, epoch, n_epochs, bool(cfg["conf_weight"]))
     loss = float(np.mean(w * cd))
+    iso = 0.0
+    if cfg.get("w_iso", 0.0) > 0:
+        iso = iso_loss(fw["xhat"], np.asarray(data["edges"]), t_key)
+        loss += cfg["w_iso"] * iso
     return dict(a=[r[0] for r in res], b=[r[1] for r in res], da=[r[2] for r in res],
-                db=[r[3] for r in res], cd=cd, w=w, loss=loss)
+                db=[r[3] for r in res], cd=cd, w=w, loss=loss, iso=iso, t_key=t_key)
 
 
 def chamfer_backward(xhat, P, off, a, b, w):
@@ -380,14 +426,16 @@ def chamfer_backward(xhat, P, off, a, b, w):
     return g
 
 
-def backward(params, data, cfg, fw, ls):
+def backward(params, data, cfg, fw, ls, iso_sign=None):
     """Gradient of the loss w.r.t. every parameter block (Sec. 3.5 objective,
-    derivative written out stage by stage)."""
+    derivative written out stage by stage); iso_sign as in iso_backward."""
     P = np.asarray(data["pts"], np.float64)
     X = np.asarray(data["xyz"], np.float64)
     Nrm = np.asarray(data["nrm"], np.float64)
     T, V, _ = fw["xhat"].shape
     gx = chamfer_backward(fw["xhat"], P, data["frame_off"], ls["a"], ls["b"], ls["w"])
+    if cfg.get("w_iso", 0.0) > 0:
+        gx = gx + cfg["w_iso"] * iso_backward(fw["xhat"], np.asarray(data["edges"]), ls["t_key"], iso_sign)
     go = transform_backward(gx.reshape(T * V, 3), fw["o"], fw["Xt"], fw["R"], fw["dh"], cfg["alpha_t"],
                             cfg.get("rot_head", "expmap"))
     gmlp, gY = mlp_backward(params["mlp"], go, fw["pres"], fw["ins"], cfg["act"], cfg["leaky_slope"])
@@ -490,13 +538,13 @@ def _lr_blocks(cfg):
     return dict(grid_p=list(cfg["lr_grid"]), grid_n=cfg["lr_n"], mlp=cfg["lr_mlp"])
 
 
-def step(params, m, v, k, data, cfg, epoch, n_epochs, precond="dct"):
+def step(params, m, v, k, data, cfg, epoch, n_epochs, precond="dct", iso_sign=None):
     """One full optimization step (forward, loss, backward, preconditioning,
-    Adam). k is the 1-based Adam step count of this update. Returns
-    (params, m, v, diagnostics)."""
+    Adam). k is the 1-based Adam step count of this update; iso_sign as in
+    iso_backward. Returns (params, m, v, diagnostics)."""
     fw = forward(params, data, cfg)
     ls = losses(fw, data, cfg, epoch, n_epochs)
-    grads, aux = backward(params, data, cfg, fw, ls)
+    grads, aux = backward(params, data, cfg, fw, ls, iso_sign)
     pg = precondition(grads, cfg, precond)
     b1, b2, eps = cfg["beta1"], cfg["beta2"], cfg["eps"]
     lrs = _lr_blocks(cfg)

@@ -123,7 +123,22 @@ def _figure_workload(cfg, rng, kind):
             Q += w[sel, k:k + 1] * (np.einsum("nab,nb->na", Rg[t, jk], P) + tg[t, jk])
         Q = (Q - c) * s + rng.normal(scale=0.002 * diag, size=Q.shape)
         pts.append(Q)
-    return dict(xyz=(X - c) * s, nrm=Nrm, pts_list=pts, truth=None, edges=None)
+    return dict(xyz=(X - c) * s, nrm=Nrm, pts_list=pts, truth=None, edges=knn_edges((X - c) * s))
+
+
+def knn_edges(X, k=6):
+    """Undirected edge list [E, 2] (i < j, sorted, unique) of the symmetrised
+    k-nearest-neighbour graph of the points X: the connectivity used for
+    reference vertex sets that come without faces."""
+    from scipy.spatial import cKDTree
+    V = len(X)
+    k = min(k, V - 1)
+    if k < 1:
+        return np.zeros((0, 2), np.int64)
+    _, nb = cKDTree(X).query(X, k + 1)
+    e = np.stack([np.repeat(np.arange(V), k), nb[:, 1:].ravel()], 1)
+    e.sort(axis=1)
+    return np.unique(e, axis=0).astype(np.int64)
 
 
 def _seg(P, a, b):
@@ -138,7 +153,9 @@ def make_workload(cfg, T=None):
     """Build the seeded workload of a config.
 
     Returns a dict with float32 arrays xyz [V,3], nrm [V,3], pts [sum N_t,3],
-    int64 frame_off [T+1] and the config's frame count T. ``T`` truncates
+    int64 frame_off [T+1], int64 mesh edges [E,2] (icosphere faces' edges, else
+    a symmetrised 6-nearest-neighbour graph of the vertices) and the config's
+    frame count T. ``T`` truncates
     the sequence to its first T frames (same seed, same frames).
     """
     rng = np.random.default_rng(cfg["seed"])
@@ -177,7 +194,7 @@ def _small_workload(cfg, rng):
     for t in range(T):
         P = rng.uniform(-0.9, 0.9, size=(Ns[t], 3))
         pts.append(P)
-    return dict(xyz=X, nrm=Nrm, pts_list=pts, truth=None, edges=None)
+    return dict(xyz=X, nrm=Nrm, pts_list=pts, truth=None, edges=knn_edges(X))
 
 
 def _out_dim(cfg):

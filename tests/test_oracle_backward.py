@@ -7,9 +7,10 @@ import oracle as O
 import synth
 
 
-def _loss_fixed_w(p, data, cfg, w, ref):
-    """Loss with the confidence weights frozen (stop-gradient of Sec. 3.5);
-    also returns whether the NN assignments equal the reference ones."""
+def _loss_fixed_w(p, data, cfg, w, ref, key_len=None):
+    """Loss with the confidence weights frozen (stop-gradient of Sec. 3.5) and,
+    with an isometry term, the key-frame edge lengths frozen too; also returns
+    whether the NN assignments equal the reference ones."""
     fw = O.forward(p, data, cfg)
     P = np.asarray(data["pts"], np.float64)
     off = data["frame_off"]
@@ -19,7 +20,12 @@ def _loss_fixed_w(p, data, cfg, w, ref):
         a, b, _, _, cd = O.chamfer(fw["xhat"][t], P[off[t]:off[t + 1]])
         same &= np.array_equal(a, ref["a"][t]) and np.array_equal(b, ref["b"][t])
         tot += w[t] * cd
-    return tot / T, same
+    tot /= T
+    if key_len is not None:
+        e = np.asarray(data["edges"])
+        ell = np.linalg.norm(fw["xhat"][:, e[:, 0]] - fw["xhat"][:, e[:, 1]], axis=-1)
+        tot += cfg["w_iso"] * np.abs(ell - key_len[None]).mean()
+    return tot, same
 
 
 def _perturb(p, flat_delta):
@@ -41,13 +47,18 @@ def _perturb(p, flat_delta):
     return out
 
 
-@pytest.mark.parametrize("act,M,head", [("leaky", 2, "expmap"), ("relu", 0, "expmap"), ("leaky", 2, "quat")])
-def test_full_loss_gradient_matches_central_differences(act, M, head):
-    cfg = synth.config_small(act=act, time_freqs=M, N=[50, 41, 47], rot_head=head)
+@pytest.mark.parametrize("act,M,head,w_iso", [("leaky", 2, "expmap", 0.0), ("relu", 0, "expmap", 0.0),
+                                              ("leaky", 2, "quat", 0.0), ("leaky", 2, "expmap", 100.0)])
+def test_full_loss_gradient_matches_central_differences(act, M, head, w_iso):
+    cfg = synth.config_small(act=act, time_freqs=M, N=[50, 41, 47], rot_head=head, w_iso=w_iso)
     data = synth.make_workload(cfg)
     p = O.to64(synth.random_state(cfg, 3))
     fw = O.forward(p, data, cfg)
     ls = O.losses(fw, data, cfg, 1, 3)
+    key_len = None
+    if w_iso > 0:
+        e = data["edges"]
+        key_len = np.linalg.norm(fw["xhat"][ls["t_key"], e[:, 0]] - fw["xhat"][ls["t_key"], e[:, 1]], axis=-1)
     grads, _ = O.backward(p, data, cfg, fw, ls)
     g = O.flatten_params(grads)
     n = g.size
@@ -60,8 +71,8 @@ def test_full_loss_gradient_matches_central_differences(act, M, head):
     for k in idx:
         e = np.zeros(n)
         e[k] = h
-        fp, s1 = _loss_fixed_w(_perturb(p, e), data, cfg, ls["w"], ls)
-        fm, s2 = _loss_fixed_w(_perturb(p, -e), data, cfg, ls["w"], ls)
+        fp, s1 = _loss_fixed_w(_perturb(p, e), data, cfg, ls["w"], ls, key_len)
+        fm, s2 = _loss_fixed_w(_perturb(p, -e), data, cfg, ls["w"], ls, key_len)
         if not (s1 and s2):
             continue
         fd = (fp - fm) / (2 * h)
@@ -71,8 +82,8 @@ def test_full_loss_gradient_matches_central_differences(act, M, head):
     # directional derivative along a random direction
     d = rng.normal(size=n)
     d /= np.linalg.norm(d)
-    fp, s1 = _loss_fixed_w(_perturb(p, h * d), data, cfg, ls["w"], ls)
-    fm, s2 = _loss_fixed_w(_perturb(p, -h * d), data, cfg, ls["w"], ls)
+    fp, s1 = _loss_fixed_w(_perturb(p, h * d), data, cfg, ls["w"], ls, key_len)
+    fm, s2 = _loss_fixed_w(_perturb(p, -h * d), data, cfg, ls["w"], ls, key_len)
     assert s1 and s2
     assert abs((fp - fm) / (2 * h) - g @ d) < 1e-7 * max(1, abs(g @ d))
 
@@ -246,3 +257,49 @@ def test_step_reduces_loss_on_sphere():
         p, m, v, d = O.step(p, m, v, e + 1, data, cfg, e, cfg["n_steps"])
         losses.append(float(np.mean(d["ls"]["cd"])))
     assert np.all(np.diff(losses) < 0)
+
+
+def test_isometry_loss_hand_worked_example():
+    # two edges (0,1), (1,2); key frame 0 has lengths 1 and 1, frame 1 has
+    # lengths 2 and 0.5: L = (|2-1| + |0.5-1|)/(T |E|) = 1.5/4. Frame 1's
+    # gradient: edge (0,1) pulls with sign +1 along (x0-x1)/2, edge (1,2) with
+    # sign -1 along (x1-x2)/0.5, each scaled by 1/(T |E|) = 1/4.
+    x = np.array([[[0, 0, 0], [1, 0, 0], [1, 1, 0]],
+                  [[0, 0, 0], [2, 0, 0], [2, 0.5, 0]]], np.float64)
+    e = np.array([[0, 1], [1, 2]])
+    assert O.iso_loss(x, e, 0) == 0.375
+    g = O.iso_backward(x, e, 0)
+    np.testing.assert_array_equal(g[0], 0.0)  # key frame: sign(0) = 0
+    np.testing.assert_allclose(g[1], [[-0.25, 0, 0], [0.25, 0.25, 0], [0, -0.25, 0]], atol=1e-15)
+    # with frame 1 as the key frame the roles swap
+    assert O.iso_loss(x, e, 1) == 0.375
+
+
+def test_isometry_loss_rigid_motions_and_finite_differences():
+    from scipy.spatial.transform import Rotation
+    X, _, E = synth.meshes.icosphere(2)
+    rng = np.random.default_rng(2)
+    T, t_key = 4, 1
+    Rs = Rotation.random(T, random_state=3).as_matrix()
+    rigid = np.stack([X @ Rs[t].T + rng.normal(size=3) for t in range(T)])
+    assert O.iso_loss(rigid, E, t_key) < 1e-15
+    # identical frames: every length difference is exactly 0, so is the gradient
+    same = np.stack([X] * T)
+    assert O.iso_loss(same, E, t_key) == 0.0
+    assert np.all(O.iso_backward(same, E, t_key) == 0.0)
+    # explicit decisions reproduce the float64 ones
+    xs0 = rigid + rng.normal(scale=0.05, size=rigid.shape)
+    np.testing.assert_array_equal(O.iso_backward(xs0, E, t_key, O.iso_signs(xs0, E, t_key)),
+                                  O.iso_backward(xs0, E, t_key))
+    # generic frames: gradient of every frame except the key frame against
+    # central differences (the key-frame lengths are a stop-gradient, so only
+    # perturbations of the other frames leave them fixed)
+    xs = rigid + rng.normal(scale=0.05, size=rigid.shape)
+    g = O.iso_backward(xs, E, t_key)
+    h = 1e-7
+    for t, i, c in zip(rng.choice([0, 2, 3], 40), rng.integers(0, len(X), 40), rng.integers(0, 3, 40)):
+        d = np.zeros_like(xs)
+        d[t, i, c] = h
+        fd = (O.iso_loss(xs + d, E, t_key) - O.iso_loss(xs - d, E, t_key)) / (2 * h)
+        assert abs(fd - g[t, i, c]) < 1e-7 * max(1e-3, abs(g[t, i, c])), (t, i, c, fd, g[t, i, c])
+    assert np.all(g[t_key] == 0)
