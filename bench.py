@@ -35,9 +35,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,dct,quat",
+    ap.add_argument("--forms", default="cg,dct,quat,iso",
                     help="forms to time: cg (headline), dct (exact DCT preconditioner), "
-                         "quat (quaternion rotation head, DCT preconditioner)")
+                         "quat (quaternion rotation head, DCT preconditioner), "
+                         "iso (isometry loss w_iso = 100 on a 6-NN edge graph, DCT preconditioner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with one plain 1 GiB device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
@@ -159,6 +160,9 @@ def main():
     if "quat" in forms:
         cq = dict(cfg, precond="dct", rot_head="quat")
         quat = run_form(cq, data, synth.random_state(cq, 9, grid_std=0.05), args.steps, args.warmup, profile=False)
+    iso = None
+    if "iso" in forms:
+        iso = run_form(dict(cfg, precond="dct", w_iso=100.0), data, P0, args.steps, args.warmup, profile=False)
     prof = cg["prof"]
     cg_iter_ms = prof["cg_ms"] / max(prof["cg_iters"], 1)
     achieved = (prof["cg_bytes"] / 1e9) / (prof["cg_ms"] / 1e3) if prof["cg_ms"] > 0 else 0.0
@@ -200,6 +204,10 @@ def main():
             "value": round(quat["value"], 4), "unit": "steps/s", "ms_per_step": round(quat["ms_per_step"], 3),
             "stage_ms": quat["stage_ms"],
             "note": "quaternion rotation head (7 outputs, Sec. 3.4) with the DCT preconditioner; compare precond_dct"},
+        "isometry": None if iso is None else {
+            "value": round(iso["value"], 4), "unit": "steps/s", "ms_per_step": round(iso["ms_per_step"], 3),
+            "stage_ms": iso["stage_ms"], "edges": int(len(data["edges"])),
+            "note": "objective L_def + 100 L_iso (Sec. 3.5) with the DCT preconditioner; compare precond_dct"},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

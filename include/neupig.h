@@ -103,6 +103,8 @@ typedef struct npg_config {
   int32_t cg_maxit;               /* iteration cap of each CG solve                 */
   int32_t precond;                /* NPG_PRECOND_CG (iterative) or _DCT (exact)     */
   int32_t rot_head;               /* NPG_ROT_EXPMAP or NPG_ROT_QUAT                 */
+  float w_iso;                    /* isometry-loss weight of Sec. 3.5 (paper: 100); */
+                                  /* 0 disables the term, > 0 needs the mesh edges  */
 } npg_config;
 
 typedef struct npg_plan npg_plan;
@@ -151,7 +153,8 @@ npg_status npg_get_state(npg_plan* plan, float* params_dev, float* m_dev, float*
  * order, then the Adam update with step count adam_steps + 1).
  *   epoch, n_epochs  0-based epoch e and e_max of the confidence catch-up
  *                    delta = 1 - sqrt(e / e_max) (Sec. 3.5)
- *   loss_dev   [1] float64 (may be NULL): L_def of this step's forward pass
+ *   loss_dev   [1] float64 (may be NULL): L_def + w_iso L_iso of this step's
+ *              forward pass
  *   cd_dev     [T] float64 (may be NULL): per-frame Chamfer distances
  * Returns NPG_ENOTCONV (after completing the step) if a CG solve hit its cap.
  * With the CG preconditioner the call synchronizes every 16 iterations to test
@@ -159,6 +162,15 @@ npg_status npg_get_state(npg_plan* plan, float* params_dev, float* m_dev, float*
  */
 npg_status npg_step(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* loss_dev,
                     double* cd_dev);
+
+/*
+ * Mesh edges of the reference surface for the isometry loss (Sec. 3.5):
+ * edges_host [n_edges][2] int32 vertex pairs (host memory, read during the
+ * call; 1 <= n_edges < 2^30, endpoints in [0, V), i != j; a repeated edge
+ * counts twice). Replaces earlier edges. Synchronizes. NPG_EINVAL on a bad
+ * edge, leaving the previous edges in place.
+ */
+npg_status npg_plan_set_edges(npg_plan* plan, int64_t n_edges, const int32_t* edges_host);
 
 /* Deformed vertices of every frame with the plan's parameters, [T][V][3]. */
 npg_status npg_deform(npg_plan* plan, float* xhat_dev);
@@ -232,15 +244,30 @@ npg_status npg_encode_bwd(npg_plan* plan, const float* gz_dev, float* grad_dev);
 npg_status npg_precond(npg_plan* plan, float* grad_dev, int32_t* iters_host);
 
 /*
+ * Sec. 3.5 "Isometry Loss" on deformed vertices xhat_dev [T][V][4] (as from
+ * npg_decode_fwd): iso_dev [1] float64 receives
+ *   L_iso = (1/(T E)) sum_t sum_(i,j) | |x^_i,t - x^_j,t| - |x^_i,key - x^_j,key| |
+ * (key frame t_key of the config; its lengths are a stop-gradient);
+ * gxhat_dev [T][V][4] (may be NULL) is incremented by w_iso dL_iso/dx^
+ * (w column untouched); sign_dev [T][E] int8 (may be NULL) receives the
+ * subgradient decision sign(|e_t| - |e_key|) of every frame and edge, in
+ * the order of npg_plan_set_edges. Lengths and decisions are evaluated in
+ * float64 from the float32 vertices; sign(0) = 0. NPG_EINVAL without edges.
+ */
+npg_status npg_iso(npg_plan* plan, const float* xhat_dev, float* gxhat_dev, double* iso_dev,
+                   int8_t* sign_dev);
+
+/*
  * Adam (bias-corrected, step count adam_step >= 1) over the flat vector with
  * per-block learning rates (levels, normal grid, MLP).
  */
 npg_status npg_adam(npg_plan* plan, float* params_dev, const float* grad_dev, float* m_dev,
                     float* v_dev, int64_t adam_step);
 
-/* Kernel time of the last npg_step per stage in milliseconds (host, [8]):
- * encode, decode, chamfer+loss, chamfer_bwd, decode_bwd, encode_bwd,
- * precond, adam. Valid after the stream has finished the step. */
+/* Kernel time of the last npg_step per stage in milliseconds (host, [9]):
+ * encode, decode, chamfer+loss, chamfer_bwd, iso (0 without the isometry
+ * term), decode_bwd, encode_bwd, precond, adam. Valid after the stream has
+ * finished the step. */
 npg_status npg_stage_times(npg_plan* plan, float* ms_host);
 
 /*

@@ -19,7 +19,7 @@ NPG_OK, NPG_EINVAL, NPG_ENOMEM, NPG_EHIP, NPG_ENOTCONV, NPG_ENONFINITE = range(6
 NPG_ACT_RELU, NPG_ACT_LEAKY = 0, 1
 NPG_PRECOND_CG, NPG_PRECOND_DCT = 0, 1
 NPG_ROT_EXPMAP, NPG_ROT_QUAT = 0, 1
-STAGES = ("encode", "decode", "chamfer+loss", "chamfer_bwd", "decode_bwd", "encode_bwd", "precond", "adam")
+STAGES = ("encode", "decode", "chamfer+loss", "chamfer_bwd", "iso", "decode_bwd", "encode_bwd", "precond", "adam")
 
 
 class NpgError(RuntimeError):
@@ -39,7 +39,7 @@ class npg_config(ctypes.Structure):
         ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
         ("conf_weight", ctypes.c_int32), ("t_key", ctypes.c_int32),
         ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precond", ctypes.c_int32),
-        ("rot_head", ctypes.c_int32),
+        ("rot_head", ctypes.c_int32), ("w_iso", ctypes.c_float),
     ]
 
 
@@ -66,6 +66,8 @@ _SIGS = {
     "npg_precond": ([_P, _P, ctypes.POINTER(_I32)], ctypes.c_int),
     "npg_adam": ([_P, _P, _P, _P, _P, _I64], ctypes.c_int),
     "npg_stage_times": ([_P, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "npg_plan_set_edges": ([_P, _I64, ctypes.POINTER(_I32)], ctypes.c_int),
+    "npg_iso": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "npg_profile": ([_P, _I32], ctypes.c_int),
     "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
 }
@@ -117,6 +119,7 @@ def make_config(cfg):
     if head not in ("expmap", "quat"):
         raise ValueError(f"rot_head must be 'expmap' or 'quat', not {head!r}")
     c.rot_head = NPG_ROT_QUAT if head == "quat" else NPG_ROT_EXPMAP
+    c.w_iso = float(cfg.get("w_iso", 0.0))
     return c
 
 
@@ -243,12 +246,27 @@ class Plan:
             return st
         return _check(st)
 
+    def set_edges(self, edges):
+        """Mesh edges [E, 2] (host array) for the isometry loss."""
+        e = np.ascontiguousarray(edges, np.int32)
+        if e.ndim != 2 or e.shape[1] != 2:
+            raise ValueError("edges must have shape [E, 2]")
+        _check(lib().npg_plan_set_edges(self._h, len(e), e.ctypes.data_as(ctypes.POINTER(_I32))))
+        self.n_edges = len(e)
+
+    def iso(self, xhat, iso, gxhat=None, sign=None):
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_iso(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
+                             _ptr(gxhat, torch.float32, 4 * TV, "gxhat"), _ptr(iso, torch.float64, 1, "iso"),
+                             _ptr(sign, torch.int8, self.T * getattr(self, "n_edges", 0), "sign")))
+
     def deform(self, out):
         import torch
         _check(lib().npg_deform(self._h, _ptr(out, torch.float32, 3 * self.T * self.V, "out")))
 
     def stage_times(self):
-        buf = (ctypes.c_float * 8)()
+        buf = (ctypes.c_float * len(STAGES))()
         _check(lib().npg_stage_times(self._h, buf))
         return dict(zip(STAGES, list(buf)))
 
@@ -330,4 +348,7 @@ def plan_from_workload(cfg, data, device="cuda:0"):
     xyz = torch.from_numpy(np.ascontiguousarray(data["xyz"], np.float32)).to(device)
     nrm = torch.from_numpy(np.ascontiguousarray(data["nrm"], np.float32)).to(device)
     pts = torch.from_numpy(np.ascontiguousarray(data["pts"], np.float32)).to(device)
-    return Plan(cfg, xyz, nrm, pts, data["frame_off"])
+    plan = Plan(cfg, xyz, nrm, pts, data["frame_off"])
+    if cfg.get("w_iso", 0.0) > 0:
+        plan.set_edges(data["edges"])
+    return plan

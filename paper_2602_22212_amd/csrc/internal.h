@@ -91,6 +91,15 @@ struct npg_plan {
   // preconditioner workspaces
   NpgCG cg;
   NpgDct* dct;
+  // isometry term: vertex -> incident-edge table (row [V+1]; per entry the
+  // other endpoint and the edge id with the ownership bit 31), loss partials
+  int64_t n_edges;
+  int* iso_row;
+  int* iso_nbr;
+  uint32_t* iso_eid;
+  double* iso_part;
+  double* iso_val;
+  int n_iso_blk;
   int* d_flag;             // non-finite flag
   hipEvent_t ev[10];
   float stage_ms[8];
@@ -139,6 +148,10 @@ npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters);
 // dct.hip
 npg_status npg_dct_setup(npg_plan* P);
 void npg_dct_free(npg_plan* P);
+npg_status npg_iso_set_edges(npg_plan* P, int64_t E, const int32_t* edges_host);
+void npg_iso_free(npg_plan* P);
+hipError_t npg_launch_iso(const npg_plan* P, const float4* xhat, float4* gxhat, double* iso, int8_t* sign,
+                          double* loss);
 npg_status npg_run_precond_dct(npg_plan* P, float* grad);
 // adam.hip
 hipError_t npg_launch_adam(const npg_plan* P, float* params, const float* grad, float* m, float* v,

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 
 #include "internal.h"
@@ -88,6 +89,7 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->cg_maxit >= 1 && c->cg_rtol > 0.0, "cg_maxit >= 1 and cg_rtol > 0 are required");
   CHECK_ARG(c->precond == NPG_PRECOND_CG || c->precond == NPG_PRECOND_DCT, "precond must be CG or DCT");
   CHECK_ARG(c->rot_head == NPG_ROT_EXPMAP || c->rot_head == NPG_ROT_QUAT, "rot_head must be EXPMAP or QUAT");
+  CHECK_ARG(c->w_iso >= 0.f && std::isfinite(c->w_iso), "w_iso must be finite and >= 0");
   if (c->precond == NPG_PRECOND_DCT) {
     for (int l = 0; l < c->n_levels; ++l)
       CHECK_ARG(c->res[l] <= 256, "the DCT preconditioner supports up to 256 nodes per axis");
@@ -132,6 +134,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
     if (b) hipFree(b);
   npg_cg_free(P);
   npg_dct_free(P);
+  npg_iso_free(P);
   for (auto& e : P->ev)
     if (e) hipEventDestroy(e);
   for (auto& e : P->prof_ev)
@@ -384,6 +387,7 @@ npg_status npg_adam(npg_plan* P, float* params, const float* grad, float* m, flo
 npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_out, double* cd_out) {
   CHECK_ARG(P, "plan is NULL");
   CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
+  CHECK_ARG(P->cfg.w_iso == 0.f || P->n_edges > 0, "w_iso > 0 needs the mesh edges (npg_plan_set_edges)");
   hipStream_t s = P->stream;
   NPG_HIP(hipEventRecord(P->ev[0], s));
   NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
@@ -395,17 +399,19 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
   NPG_HIP(hipEventRecord(P->ev[3], s));
   NPG_HIP(npg_launch_chamfer_bwd(P, P->xhat, P->a, P->b, P->w, P->gxhat));
   NPG_HIP(hipEventRecord(P->ev[4], s));
-  NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz));
+  if (P->cfg.w_iso > 0.f) NPG_HIP(npg_launch_iso(P, P->xhat, P->gxhat, P->iso_val, nullptr, P->loss));
   NPG_HIP(hipEventRecord(P->ev[5], s));
-  NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
+  NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz));
   NPG_HIP(hipEventRecord(P->ev[6], s));
+  NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
+  NPG_HIP(hipEventRecord(P->ev[7], s));
   npg_status pst = P->cfg.precond == NPG_PRECOND_DCT ? npg_run_precond_dct(P, P->grad)
                                                      : npg_run_precond_cg(P, P->grad, nullptr);
   if (pst != NPG_OK && pst != NPG_ENOTCONV) return pst;
-  NPG_HIP(hipEventRecord(P->ev[7], s));
+  NPG_HIP(hipEventRecord(P->ev[8], s));
   P->adam_k += 1;
   NPG_HIP(npg_launch_adam(P, P->params, P->grad, P->m, P->v, P->adam_k, P->d_flag));
-  NPG_HIP(hipEventRecord(P->ev[8], s));
+  NPG_HIP(hipEventRecord(P->ev[9], s));
   if (P->prof_cg) {
     // resolve this step's CG kernel timings (the stream is drained below)
     NPG_HIP(hipStreamSynchronize(s));
@@ -456,7 +462,21 @@ npg_status npg_profile_read(npg_plan* P, double* cg_ms, int64_t* cg_iters, doubl
 
 npg_status npg_stage_times(npg_plan* P, float* ms) {
   CHECK_ARG(P && ms, "NULL argument");
-  for (int k = 0; k < 8; ++k) NPG_HIP(hipEventElapsedTime(ms + k, P->ev[k], P->ev[k + 1]));
+  for (int k = 0; k < 9; ++k) NPG_HIP(hipEventElapsedTime(ms + k, P->ev[k], P->ev[k + 1]));
+  return NPG_OK;
+}
+
+npg_status npg_plan_set_edges(npg_plan* P, int64_t n_edges, const int32_t* edges_host) {
+  CHECK_ARG(P && edges_host, "plan and edges_host must be non-NULL");
+  CHECK_ARG(n_edges >= 1 && n_edges < (int64_t)1 << 30, "need 1 <= n_edges < 2^30");
+  return npg_iso_set_edges(P, n_edges, edges_host);
+}
+
+npg_status npg_iso(npg_plan* P, const float* xhat_dev, float* gxhat_dev, double* iso_dev, int8_t* sign_dev) {
+  CHECK_ARG(P && xhat_dev && iso_dev, "plan, xhat_dev and iso_dev must be non-NULL");
+  CHECK_ARG(P->n_edges > 0, "no mesh edges (npg_plan_set_edges)");
+  NPG_HIP(npg_launch_iso(P, reinterpret_cast<const float4*>(xhat_dev), reinterpret_cast<float4*>(gxhat_dev),
+                         iso_dev, sign_dev, nullptr));
   return NPG_OK;
 }
 

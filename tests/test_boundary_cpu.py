@@ -80,6 +80,7 @@ def test_param_count_matches_layout(name, head):
     (dict(time_freqs=9), "time_freqs"),
     (dict(eps=0.0), "eps"),
     (dict(cg_maxit=0), "cg_maxit"),
+    (dict(w_iso=-1.0), "w_iso"),
 ])
 def test_invalid_configs_are_rejected(bad, msg):
     _lib()

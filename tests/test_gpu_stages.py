@@ -204,6 +204,40 @@ def test_decode_backward(case):
     assert rel(to_np(gz).reshape(V, -1), gz_ref) < TOL
 
 
+def test_isometry_stage(case):
+    """Sec. 3.5 isometry term on the GPU's deformed vertices: the loss value,
+    the subgradient decisions (against float64 decisions on the same float32
+    vertices; a difference is allowed only at a length tie within 1e-12
+    relative) and the gradient evaluated with the kernel's decisions."""
+    import torch
+    cfg = dict(case["cfg"], w_iso=100.0)
+    data, T, V = case["data"], case["T"], case["V"]
+    plan = gpu_plan(cfg, data)
+    E = data["edges"]
+    t_key = cfg["t_key"] if cfg["t_key"] is not None else (T - 1) // 2
+    gx = torch.zeros(T * V * 4, dtype=torch.float32, device="cuda")
+    iso = torch.empty(1, dtype=torch.float64, device="cuda")
+    sign = torch.empty(T * len(E), dtype=torch.int8, device="cuda")
+    plan.iso(case["xhat"], iso, gx, sign)
+    xh = to_np(case["xhat"]).reshape(T, V, 4)[..., :3].astype(np.float64)
+    ref = O.iso_loss(xh, E, t_key)
+    assert abs(iso.item() - ref) <= 1e-10 * ref
+    sg = to_np(sign).reshape(T, len(E)).astype(np.float64)
+    so = O.iso_signs(xh, E, t_key)
+    ell = np.linalg.norm(xh[:, E[:, 0]] - xh[:, E[:, 1]], axis=-1)
+    diff = sg != so
+    assert np.all(np.abs(ell - ell[t_key][None])[diff] <= 1e-12 * ell[diff]), diff.sum()
+    assert np.all(sg[t_key] == 0)
+    g = to_np(gx).reshape(T, V, 4)
+    gref = cfg["w_iso"] * O.iso_backward(xh, E, t_key, sg)
+    for t in range(T):
+        if t != t_key:
+            assert rel(g[t, :, :3], gref[t]) < TOL, t
+    assert np.all(g[t_key] == 0) and np.all(g[..., 3] == 0)
+    print("decision differences:", int(diff.sum()), "of", diff.size)
+    plan.close()
+
+
 def test_encode_backward(case):
     import torch
     plan, V, cfg, data = case["plan"], case["V"], case["cfg"], case["data"]

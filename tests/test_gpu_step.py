@@ -66,6 +66,81 @@ def test_teacher_forced_steps_on_icosphere(method, head):
     plan.close()
 
 
+def test_teacher_forced_steps_with_isometry():
+    """Full objective L_def + 100 L_iso (Sec. 3.5) on the icosphere. The L1
+    term's subgradient decisions are taken in the kernel's precision: the
+    GPU's decisions for the step are read through the stage entry point (same
+    kernels, same state, bitwise the same deformed vertices as inside the
+    step), checked against the oracle's own float64 decisions (a difference
+    only where the oracle's length difference is below 1e-5 relative), and
+    handed to the oracle step."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = dict(synth.config_c1(), precond="dct", w_iso=100.0)
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    E = data["edges"]
+    T, V = data["T"], len(data["xyz"])
+    t_key = (T - 1) // 2 if cfg["t_key"] is None else cfg["t_key"]
+    touched = _touched_nodes(cfg, data)
+    P = O.to64(synth.random_state(cfg, 4, grid_std=0.05))
+    m, v = O.zeros_like_params(P), O.zeros_like_params(P)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    cd = torch.empty(T, dtype=torch.float64, device="cuda")
+    z = torch.empty(V * plan.Fz, device="cuda")
+    xh = torch.empty(T * V * 4, device="cuda")
+    iso = torch.empty(1, dtype=torch.float64, device="cuda")
+    sign = torch.empty(T * len(E), dtype=torch.int8, device="cuda")
+    ndiff = 0
+    for e in range(3):
+        flat = flat_params(cfg, P)
+        plan.encode_fwd(flat, z)
+        plan.decode_fwd(flat, z, xh)
+        plan.iso(xh, iso, None, sign)
+        sg = to_np(sign).reshape(T, len(E)).astype(np.float64)
+        fw = O.forward(P, data, cfg)
+        so = O.iso_signs(fw["xhat"], E, t_key)
+        ell = np.linalg.norm(fw["xhat"][:, E[:, 0]] - fw["xhat"][:, E[:, 1]], axis=-1)
+        diff = sg != so
+        assert np.all(np.abs(ell - ell[t_key][None])[diff] <= 1e-5 * ell[diff]), diff.sum()
+        ndiff += int(diff.sum())
+        plan.set_state(flat, flat_params(cfg, m), flat_params(cfg, v), e)
+        assert plan.step(e, cfg["n_steps"], loss, cd) == npg.NPG_OK
+        Pn, mn, vn, d = O.step(P, m, v, e + 1, data, cfg, e, cfg["n_steps"], precond="dct", iso_sign=sg)
+        assert d["ls"]["iso"] > 0
+        assert abs(loss.item() - d["ls"]["loss"]) <= TOL * d["ls"]["loss"]
+        assert rel(to_np(cd), d["ls"]["cd"]) < TOL
+        got = npg.unpack_params(cfg, to_np(plan.get_state()[0]))
+        for k_, ((W, b), (Wr, br)) in enumerate(zip(got["mlp"], Pn["mlp"])):
+            assert rel(W, Wr) < TOL and rel(b, br) < TOL, (e, k_, rel(W, Wr), rel(b, br))
+        for l, (g, r, tn) in enumerate(zip(got["grid_p"] + [got["grid_n"]], Pn["grid_p"] + [Pn["grid_n"]], touched)):
+            assert rel(g[tn], r[tn]) < TOL, (e, l, rel(g[tn], r[tn]))
+        P, m, v = Pn, mn, vn
+    print("decisions that differ from the oracle's float64 ones:", ndiff)
+    plan.close()
+
+
+def test_isometry_needs_edges_and_valid_edges():
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_small(mlp_width=32, w_iso=100.0)
+    data = synth.make_workload(cfg)
+    plan = npg.Plan(cfg, *[torch.from_numpy(np.ascontiguousarray(data[k], np.float32)).cuda()
+                           for k in ("xyz", "nrm", "pts")], data["frame_off"])
+    with pytest.raises(npg.NpgError) as e:
+        plan.step(0, 3)
+    assert e.value.status == npg.NPG_EINVAL
+    for bad in ([[0, 0]], [[0, len(data["xyz"])]], [[-1, 2]]):
+        with pytest.raises(npg.NpgError) as e:
+            plan.set_edges(np.array(bad))
+        assert e.value.status == npg.NPG_EINVAL
+    plan.set_edges(data["edges"])
+    assert plan.step(0, 3) == npg.NPG_OK
+    plan.close()
+
+
 def test_step_is_bitwise_deterministic():
     import torch
     cfg = synth.config_c1()
