@@ -260,3 +260,106 @@ def test_headline_workload_sampled():
         plan.step(e, 500, l1)
     assert l1.item() < l0.item()
     plan.close()
+
+
+def test_long_quadruped_sequence_sampled():
+    """Quadruped workload: 50 000 vertices, 1000 frames, ragged ~7 600 points
+    per frame. Sampled decode outputs and one full frame's Chamfer against
+    the oracle; the decode backward on a 20-frame subset (the loss gradient
+    is a sum over frames, so feeding the GPU an upstream gradient that is
+    zero outside the subset gives exactly the subset's contribution); a full
+    step that runs and lowers the loss from the identity start."""
+    import time
+
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_c3()
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    T, V = data["T"], len(data["xyz"])
+    assert T == 1000 and V == 50000
+    P = O.to64(synth.random_state(cfg, 13, grid_std=0.05))
+    flat = flat_params(cfg, P)
+    z = torch.empty(V * plan.Fz, device="cuda")
+    xh = torch.empty(T * V * 4, device="cuda")
+    plan.encode_fwd(flat, z)
+    plan.decode_fwd(flat, z, xh)
+    rng = np.random.default_rng(1)
+    X = data["xyz"].astype(np.float64)
+    Nr = data["nrm"].astype(np.float64)
+    vs = rng.choice(V, 64, replace=False)
+    zr = O.encode(P, X[vs], Nr[vs], cfg["levels"], cfg["res_n"])
+    assert rel(to_np(z).reshape(V, -1)[vs], zr) < TOL
+    ts = np.array([0, 1, 499, 998, 999])
+    gam = O.time_code(T, cfg["time_freqs"])[ts]
+    o, _, _ = O.mlp_forward(P["mlp"], O.decoder_input(zr, gam), cfg["act"], cfg["leaky_slope"])
+    xr, _, _ = O.transform(o, np.tile(X[vs], (len(ts), 1)), cfg["alpha_t"])
+    xg = to_np(xh).reshape(T, V, 4)[ts][:, vs, :3].reshape(-1, 3)
+    assert rel(xg, xr) < TOL
+    # Chamfer of one full frame against float64 brute force on the GPU's vertices
+    N = plan.Ntot
+    a = torch.empty(T * V, dtype=torch.int32, device="cuda")
+    da = torch.empty(T * V, device="cuda")
+    b = torch.empty(N, dtype=torch.int32, device="cuda")
+    db = torch.empty(N, device="cuda")
+    cd = torch.empty(T, dtype=torch.float64, device="cuda")
+    t0 = time.time()
+    plan.chamfer_fwd(xh, a, da, b, db, cd)
+    torch.cuda.synchronize()
+    print(f"Chamfer of 1000 frames: {time.time() - t0:.2f} s")
+    off = data["frame_off"]
+    xha = to_np(xh).reshape(T, V, 4)[..., :3]
+    t = 731
+    Pt = data["pts"][off[t]:off[t + 1]]
+    ties = nn_check(xha[t], Pt, to_np(a).reshape(T, V)[t], to_np(b)[off[t]:off[t + 1]])
+    cdo = O.chamfer(xha[t].astype(np.float64), Pt.astype(np.float64))[4]
+    assert abs(to_np(cd)[t] - cdo) <= TOL * cdo
+    print("frame", t, "points", len(Pt), "near-ties", ties)
+    # decode backward restricted to 20 frames. The activation derivative is a
+    # decision taken in floating point (pre-activation > 0); samples with a
+    # hidden pre-activation within 1e-4 of the kink get a zero upstream
+    # gradient on both sides, so every remaining decision is the same in
+    # float32 and float64 (their float32 error is far below 1e-4).
+    sub = np.sort(rng.choice(T, 20, replace=False))
+    zall = O.encode(P, X, Nr, cfg["levels"], cfg["res_n"])
+    gam = O.time_code(T, cfg["time_freqs"])[sub]
+    Y = O.decoder_input(zall, gam)
+    o, pres, ins = O.mlp_forward(P["mlp"], Y, cfg["act"], cfg["leaky_slope"])
+    kink = np.zeros(len(Y), bool)
+    for pre in pres:
+        kink |= (np.abs(pre) < 1e-4).any(1)
+    print(f"samples at an activation kink: {kink.mean():.3%}")
+    gsub = rng.normal(size=(20 * V, 3))
+    gsub[kink] = 0.0
+    gsub = gsub.astype(np.float32)
+    gx = np.zeros((T, V, 4), np.float32)
+    gx[sub, :, :3] = gsub.reshape(20, V, 3)
+    grad = torch.zeros(plan.n_params, device="cuda")
+    gz = torch.empty(V * plan.Fz, device="cuda")
+    plan.decode_bwd(flat, z, torch.from_numpy(gx.ravel()).cuda(), grad, gz)
+    Xt = np.tile(X, (len(sub), 1))
+    _, R, dh = O.transform(o, Xt, cfg["alpha_t"])
+    go = O.transform_backward(gsub.astype(np.float64), o, Xt, R, dh, cfg["alpha_t"])
+    gmlp, gY = O.mlp_backward(P["mlp"], go, pres, ins, cfg["act"], cfg["leaky_slope"])
+    got = npg.unpack_params(cfg, to_np(grad))
+    Fz = cfg["feat_n"] + cfg["feat_p"]
+    errs = [(rel(gW, rW), rel(gb, rb)) for (gW, gb), (rW, rb) in zip(got["mlp"], gmlp)]
+    W1, W1r = got["mlp"][0][0], gmlp[0][0]
+    errs.append(("W1 z-part", rel(W1[:, :Fz], W1r[:, :Fz]), "W1 time-part", rel(W1[:, Fz:], W1r[:, Fz:])))
+    errs.append(("gz", rel(to_np(gz).reshape(V, -1), gY[:, :Fz].reshape(len(sub), V, Fz).sum(0))))
+    print("decode backward errors on the 20-frame subset:", errs)
+    for k, (eW, eb) in enumerate(errs[:len(gmlp)]):
+        assert eW < TOL and eb < TOL, (k, eW, eb)
+    assert errs[-1][1] < TOL
+    # full steps from the identity start
+    plan.set_state(flat_params(cfg, synth.init_params(cfg)), adam_steps=0)
+    l0 = torch.empty(1, dtype=torch.float64, device="cuda")
+    l1 = torch.empty(1, dtype=torch.float64, device="cuda")
+    t0 = time.time()
+    assert plan.step(0, 500, l0) == npg.NPG_OK
+    for e in range(1, 3):
+        assert plan.step(e, 500, l1) == npg.NPG_OK
+    print(f"3 steps: {time.time() - t0:.2f} s, loss {l0.item():.4e} -> {l1.item():.4e}")
+    assert l1.item() < l0.item()
+    plan.close()
