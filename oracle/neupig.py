@@ -10,6 +10,8 @@ Section references are to the paper (Neu-PiG, arXiv 2602.22212):
            confidence weight, implementation details)
   Supp. "Rotation Modeling" / Table 11: exponential-map rotation head.
   Sec. 3.4 "Rotation Component": quaternion rotation head (rot_head "quat").
+  Sec. 4 "Evaluation Metrics": CD, NC, F-score, correspondence error (the
+           paper names them only; the definitions below are readings).
 
 Parameter structure (float64 numpy):
   params = dict(grid_p=[G_l of shape [R_l^3, F] per level],
@@ -28,6 +30,7 @@ __all__ = [
     "backward", "laplacian_apply", "precond_dct", "precond_cg", "precondition",
     "adam", "step", "to64", "zeros_like_params", "flatten_params", "losses",
     "chamfer_backward", "quat_matrix", "quat_normalize", "n_outputs", "iso_loss", "iso_backward", "iso_signs",
+    "deformed_normals", "metrics",
 ]
 
 
@@ -565,3 +568,36 @@ def step(params, m, v, k, data, cfg, epoch, n_epochs, precond="dct", iso_sign=No
         nv["mlp"].append((vW2, vb2))
     diag = dict(fw=fw, ls=ls, grads=grads, pgrads=pg, aux=aux)
     return np_, nm, nv, diag
+
+
+# --------------------------------------------------------------------------
+# Sec. 4 "Evaluation Metrics" on ground truth (readings; the paper gives the
+# names only). Predicted normals are the reference normals turned by each
+# vertex's predicted rotation. Per frame t, with nearest neighbours a (from
+# the prediction into the truth) and b (from the truth into the prediction):
+#   CD   = mean_i |x^_i - g_a_i|^2 + mean_j |g_j - x^_b_j|^2
+#   NC   = (mean_i |n^_i . m_a_i| + mean_j |m_j . n^_b_j|) / 2
+#   F    = 2 P R / (P + R), P = share of i with |x^_i - g_a_i| < tau,
+#          R = share of j with |g_j - x^_b_j| < tau (0 when P + R = 0)
+#   Corr = mean_i |x^_i - g_i| (each vertex against its own true position)
+# --------------------------------------------------------------------------
+def deformed_normals(fw, Nrm):
+    """R_i,t n_i for every frame and vertex [T, V, 3] from a forward pass."""
+    T, V, _ = fw["xhat"].shape
+    n = np.einsum("sab,sb->sa", fw["R"], np.tile(np.asarray(Nrm, np.float64), (T, 1)))
+    return n.reshape(T, V, 3)
+
+
+def metrics(xhat, nhat, gt, gt_n, tau):
+    """Per-frame (CD, NC, F, Corr) [T, 4] of predicted vertices/normals
+    against true vertices/normals [T, V, 3] (same vertex order)."""
+    out = []
+    for t in range(len(xhat)):
+        a, b, da, db, cd = chamfer(xhat[t], gt[t])
+        nc = 0.5 * (np.abs((nhat[t] * gt_n[t][a]).sum(1)).mean() + np.abs((gt_n[t] * nhat[t][b]).sum(1)).mean())
+        prec = (da < tau * tau).mean()
+        rec = (db < tau * tau).mean()
+        f = 2 * prec * rec / (prec + rec) if prec + rec > 0 else 0.0
+        corr = np.linalg.norm(xhat[t] - gt[t], axis=1).mean()
+        out.append((cd, nc, f, corr))
+    return np.array(out)

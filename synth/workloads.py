@@ -46,7 +46,7 @@ def _rot_axis_angle_quat(axis, ang):
 def _sphere_workload(cfg, rng):
     V_, _, E = icosphere(4)
     T, N = cfg["T"], cfg["N"]
-    pts, truth = [], []
+    pts, truth, truth_n = [], [], []
     for t in range(T):
         ang = np.deg2rad(rng.uniform(0, 30))
         axis = rng.normal(size=3)
@@ -60,14 +60,25 @@ def _sphere_workload(cfg, rng):
             Y = Y * (1.0 + 0.1 * np.sin(2 * np.pi * Y[:, 2:3] + phi))
             return Y @ Rm.T + d
 
+        def warp_normal(Y, Nn):
+            # normals map by the inverse transpose of the bend's Jacobian
+            # J = f I + y (df/dy_z) e_z^T, then rotate
+            f = 1.0 + 0.1 * np.sin(2 * np.pi * Y[:, 2] + phi)
+            df = 0.1 * 2 * np.pi * np.cos(2 * np.pi * Y[:, 2] + phi)
+            J = f[:, None, None] * np.eye(3) + np.einsum("va,b->vab", Y * df[:, None], np.array([0.0, 0.0, 1.0]))
+            n = np.linalg.solve(np.swapaxes(J, 1, 2), Nn[..., None])[..., 0]
+            n /= np.linalg.norm(n, axis=1, keepdims=True)
+            return n @ Rm.T
+
         S = rng.normal(size=(N, 3))
         S /= np.linalg.norm(S, axis=1, keepdims=True)
         pts.append(warp(S))
         truth.append(warp(V_))
-    return dict(xyz=V_, nrm=V_.copy(), pts_list=pts, truth=np.stack(truth), edges=E)
+        truth_n.append(warp_normal(V_, V_))
+    return dict(xyz=V_, nrm=V_.copy(), pts_list=pts, truth=np.stack(truth), truth_nrm=np.stack(truth_n), edges=E)
 
 
-def _figure_workload(cfg, rng, kind):
+def _figure_workload(cfg, rng, kind, want_truth=False):
     J, C = FIGURES[kind]()
     V, T, N = cfg["V"], cfg["T"], cfg["N"]
     X, Nrm, own = capsule_figure(kind, V, rng)
@@ -123,7 +134,26 @@ def _figure_workload(cfg, rng, kind):
             Q += w[sel, k:k + 1] * (np.einsum("nab,nb->na", Rg[t, jk], P) + tg[t, jk])
         Q = (Q - c) * s + rng.normal(scale=0.002 * diag, size=Q.shape)
         pts.append(Q)
-    return dict(xyz=(X - c) * s, nrm=Nrm, pts_list=pts, truth=None, edges=knn_edges((X - c) * s))
+    truth = truth_n = None
+    if want_truth:
+        # the reference vertices skinned like the dense set (no noise): true
+        # positions and normals (weight-blended rotations, renormalised)
+        dX = np.stack([_seg(X, a, b) - r for a, b, r, _ in C], 1)
+        topX = np.argsort(dX, 1)[:, :4]
+        dtX = np.take_along_axis(dX, topX, 1)
+        wX = np.exp(-(dtX - dtX[:, :1]) / 0.02)
+        wX /= wX.sum(1, keepdims=True)
+        jX = cap_joint[topX]
+        truth = np.zeros((T, len(X), 3))
+        truth_n = np.zeros((T, len(X), 3))
+        for t in range(T):
+            for k in range(4):
+                Rk = Rg[t, jX[:, k]]
+                truth[t] += wX[:, k:k + 1] * (np.einsum("nab,nb->na", Rk, X) + tg[t, jX[:, k]])
+                truth_n[t] += wX[:, k:k + 1] * np.einsum("nab,nb->na", Rk, Nrm)
+            truth[t] = (truth[t] - c) * s
+        truth_n /= np.linalg.norm(truth_n, axis=-1, keepdims=True)
+    return dict(xyz=(X - c) * s, nrm=Nrm, pts_list=pts, truth=truth, truth_nrm=truth_n, edges=knn_edges((X - c) * s))
 
 
 def knn_edges(X, k=6):
@@ -149,7 +179,7 @@ def _seg(P, a, b):
     return np.linalg.norm(P - (a + t[:, None] * ab), axis=1)
 
 
-def make_workload(cfg, T=None):
+def make_workload(cfg, T=None, truth=False):
     """Build the seeded workload of a config.
 
     Returns a dict with float32 arrays xyz [V,3], nrm [V,3], pts [sum N_t,3],
@@ -157,20 +187,26 @@ def make_workload(cfg, T=None):
     a symmetrised 6-nearest-neighbour graph of the vertices) and the config's
     frame count T. ``T`` truncates
     the sequence to its first T frames (same seed, same frames).
+    Ground truth (the true per-frame positions and unit normals of the
+    reference vertices, truth [T,V,3] and truth_nrm [T,V,3]) comes with the
+    icosphere workload always and with the capsule figures when ``truth``.
     """
     rng = np.random.default_rng(cfg["seed"])
     name = cfg["name"]
     if name.startswith("c1") or cfg.get("shape") == "sphere":
         w = _sphere_workload(cfg, rng)
     elif name.startswith("c3") or cfg.get("shape") == "quadruped":
-        w = _figure_workload(cfg, rng, "quadruped")
+        w = _figure_workload(cfg, rng, "quadruped", truth)
     elif name.startswith("c2") or cfg.get("shape") == "human":
-        w = _figure_workload(cfg, rng, "human")
+        w = _figure_workload(cfg, rng, "human", truth)
     else:
         w = _small_workload(cfg, rng)
     plist = w.pop("pts_list")
     if T is not None:
         plist = plist[:T]
+        for k in ("truth", "truth_nrm"):
+            if w.get(k) is not None:
+                w[k] = w[k][:T]
     off = np.zeros(len(plist) + 1, np.int64)
     off[1:] = np.cumsum([len(p) for p in plist])
     w["pts"] = np.ascontiguousarray(np.concatenate(plist), dtype=np.float32)
@@ -194,7 +230,7 @@ def _small_workload(cfg, rng):
     for t in range(T):
         P = rng.uniform(-0.9, 0.9, size=(Ns[t], 3))
         pts.append(P)
-    return dict(xyz=X, nrm=Nrm, pts_list=pts, truth=None, edges=knn_edges(X))
+    return dict(xyz=X, nrm=Nrm, pts_list=pts, truth=None, truth_nrm=None, edges=knn_edges(X))
 
 
 def _out_dim(cfg):

@@ -303,3 +303,61 @@ def test_confidence_worked_example_and_invariants():
         assert np.all(np.diff(w[3:]) <= 0) and np.all(np.diff(w[:4]) >= 0)
     np.testing.assert_array_equal(O.confidence(cd, 3, 5, 5), np.ones(9))   # delta = 0
     np.testing.assert_array_equal(O.confidence(cd, 3, 2, 5, enabled=False), np.ones(9))
+
+
+def test_metrics_closed_forms():
+    # Sec. 4 metrics (readings): identity, a small rigid shift, flipped and
+    # perpendicular normals, and a hand-counted F-score
+    X, _, _ = synth.meshes.icosphere(2)
+    N = X.copy()
+    gt, gn = X[None], N[None]
+    m = O.metrics(gt, gn, gt, gn, 0.01)[0]
+    np.testing.assert_allclose(m, [0.0, 1.0, 1.0, 0.0], atol=1e-15)
+    spacing = min(np.linalg.norm(X[i] - X[j]) for i in range(10) for j in range(len(X)) if i != j)
+    d = np.array([0.3, -0.2, 0.1]) * spacing / 10
+    m = O.metrics(gt + d, -gn, gt, gn, np.linalg.norm(d) * 1.01)[0]
+    np.testing.assert_allclose(m, [2 * (d @ d), 1.0, 1.0, np.linalg.norm(d)], rtol=1e-12)
+    assert O.metrics(gt + d, gn, gt, gn, np.linalg.norm(d) * 0.99)[0][2] == 0.0
+    perp = np.cross(gn[0], np.array([0.0, 0.0, 1.0]) + 0.3)
+    perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+    assert O.metrics(gt, perp[None], gt, gn, 0.01)[0][1] < 1e-15
+    # 4 predicted points at distances 0, 0.5, 0.5, 2 from 4 true ones on a line
+    g = np.array([[0, 0, 0], [10, 0, 0], [20, 0, 0], [30, 0, 0]], float)
+    x = g + np.array([[0, 0, 0], [0, 0.5, 0], [0, -0.5, 0], [0, 2, 0]], float)
+    _, _, F, corr = O.metrics(x[None], np.ones((1, 4, 3)), g[None], np.ones((1, 4, 3)), 1.0)[0]
+    assert F == 0.75 and corr == 0.75  # P = R = 3/4; mean distance (0 + .5 + .5 + 2)/4
+
+
+def test_metrics_against_double_loops():
+    rng = np.random.default_rng(9)
+    x = rng.normal(size=(2, 30, 3))
+    g = rng.normal(size=(2, 30, 3))
+    nx = rng.normal(size=(2, 30, 3))
+    ng = rng.normal(size=(2, 30, 3))
+    tau = 0.4
+    m = O.metrics(x, nx, g, ng, tau)
+    for t in range(2):
+        da = [min(((x[t, i] - g[t, j]) ** 2).sum() for j in range(30)) for i in range(30)]
+        ai = [min(range(30), key=lambda j: ((x[t, i] - g[t, j]) ** 2).sum()) for i in range(30)]
+        db = [min(((g[t, j] - x[t, i]) ** 2).sum() for i in range(30)) for j in range(30)]
+        bj = [min(range(30), key=lambda i: ((g[t, j] - x[t, i]) ** 2).sum()) for j in range(30)]
+        nc = 0.5 * (sum(abs(nx[t, i] @ ng[t, ai[i]]) for i in range(30)) / 30
+                    + sum(abs(ng[t, j] @ nx[t, bj[j]]) for j in range(30)) / 30)
+        P = sum(v < tau * tau for v in da) / 30
+        R = sum(v < tau * tau for v in db) / 30
+        np.testing.assert_allclose(m[t], [np.mean(da) + np.mean(db), nc, 2 * P * R / (P + R),
+                                          np.mean(np.linalg.norm(x[t] - g[t], axis=1))], rtol=1e-12)
+
+
+def test_deformed_normals_of_a_known_rotation():
+    # last layer zero with bias omega*: every normal turns by R(omega*) (scipy)
+    cfg = synth.config_small(V=40, T=2, N=40)
+    data = synth.make_workload(cfg)
+    p = O.to64(synth.init_params(cfg))
+    np.testing.assert_array_equal(O.deformed_normals(O.forward(p, data, cfg), data["nrm"])[1],
+                                  data["nrm"].astype(np.float64))
+    wstar = np.array([0.3, -0.2, 0.5])
+    W, b = p["mlp"][-1]
+    p["mlp"][-1] = (np.zeros_like(W), np.concatenate([wstar, np.zeros(3)]))
+    n = O.deformed_normals(O.forward(p, data, cfg), data["nrm"])
+    np.testing.assert_allclose(n[0], data["nrm"] @ Rotation.from_rotvec(wstar).as_matrix().T, atol=1e-14)
