@@ -175,6 +175,34 @@ npg_status npg_plan_set_edges(npg_plan* plan, int64_t n_edges, const int32_t* ed
 /* Deformed vertices of every frame with the plan's parameters, [T][V][3]. */
 npg_status npg_deform(npg_plan* plan, float* xhat_dev);
 
+/*
+ * Inference export (Sec. 3.4 applied with the plan's parameters): deformed
+ * vertices xhat_dev [T][V][4] and, if nhat_dev is not NULL, deformed unit
+ * normals nhat_dev [T][V][4] (reference normal turned by the vertex's
+ * predicted rotation); the 4th component is 0.
+ */
+npg_status npg_predict(npg_plan* plan, float* xhat_dev, float* nhat_dev);
+
+/*
+ * Sec. 4 "Evaluation Metrics" against ground truth. The paper names CD, NC,
+ * F-score and correspondence error only; per frame t these readings are
+ * computed, with nearest neighbours a (prediction -> truth) and b (truth ->
+ * prediction) between the predicted vertices x^_t and the true vertices g_t:
+ *   out[t][0] CD   = mean_i |x^_i - g_a(i)|^2 + mean_j |g_j - x^_b(j)|^2
+ *   out[t][1] NC   = (mean_i |n^_i . m_a(i)| + mean_j |m_j . n^_b(j)|) / 2
+ *   out[t][2] F    = 2PR/(P+R); P, R: shares of squared NN distances < tau^2
+ *                    in each direction (0 when P + R = 0)
+ *   out[t][3] Corr = mean_i |x^_i - g_i| (vertex i against its own truth)
+ * xhat_dev, nhat_dev: predicted vertices/normals [T][V][4] (npg_predict);
+ * gt_dev, gtn_dev: true vertices and unit normals [T][V][4] (4th component
+ * ignored), same vertex order; tau > 0 (the paper's F-0.5% is 0.5% of the
+ * object's scale, chosen by the caller); out_dev [T][4] float64.
+ * Allocates temporary device memory (about T * V * 8 * ceil(V / 2048) bytes)
+ * and synchronizes.
+ */
+npg_status npg_metrics(npg_plan* plan, const float* xhat_dev, const float* nhat_dev, const float* gt_dev,
+                       const float* gtn_dev, float tau, double* out_dev);
+
 /* ---- stage entry points (stateless with respect to parameters) ---------- */
 
 /* Sec. 3.2. z_dev [V][F_n+F_p] = (z_n(n_i), (1/L) sum_l z_p^l(x_i)). */

@@ -68,6 +68,8 @@ _SIGS = {
     "npg_stage_times": ([_P, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "npg_plan_set_edges": ([_P, _I64, ctypes.POINTER(_I32)], ctypes.c_int),
     "npg_iso": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "npg_predict": ([_P, _P, _P], ctypes.c_int),
+    "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_profile": ([_P, _I32], ctypes.c_int),
     "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
 }
@@ -260,6 +262,22 @@ class Plan:
         _check(lib().npg_iso(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
                              _ptr(gxhat, torch.float32, 4 * TV, "gxhat"), _ptr(iso, torch.float64, 1, "iso"),
                              _ptr(sign, torch.int8, self.T * getattr(self, "n_edges", 0), "sign")))
+
+    def predict(self, xhat, nhat=None):
+        """Deformed vertices (and normals) [T][V][4] with the plan's parameters."""
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_predict(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
+                                 _ptr(nhat, torch.float32, 4 * TV, "nhat")))
+
+    def metrics(self, xhat, nhat, gt, gtn, tau, out):
+        """Per-frame (CD, NC, F, Corr) [T][4] float64 against true vertices/normals [T][V][4]."""
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_metrics(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
+                                 _ptr(nhat, torch.float32, 4 * TV, "nhat"), _ptr(gt, torch.float32, 4 * TV, "gt"),
+                                 _ptr(gtn, torch.float32, 4 * TV, "gtn"), float(tau),
+                                 _ptr(out, torch.float64, 4 * self.T, "out")))
 
     def deform(self, out):
         import torch

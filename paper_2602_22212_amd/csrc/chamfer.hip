@@ -275,13 +275,23 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int npg_chamfer_vblock() { return kVB; }
 
+// Both nearest-neighbour directions between the plan's per-frame vertices and
+// any per-frame point set (frame t owns points off[t] .. off[t+1]-1, at most
+// Nmax; colpart holds T * nvb * Nmax 64-bit column records).
+hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pts, const int64_t* off,
+                         const int* pt_frame, int64_t Ntot, int64_t Nmax, void* colpart, int32_t* a, float* da,
+                         int32_t* b, float* db) {
+  hipLaunchKernelGGL(k_chamfer_main, dim3(P->nvb, P->T), dim3(kT), 0, P->stream, xhat, pts, off, P->V, P->nvb,
+                     Nmax, a, da, reinterpret_cast<unsigned long long*>(colpart));
+  hipLaunchKernelGGL(k_chamfer_cols, dim3(nblk(Ntot, 256)), dim3(256), 0, P->stream, xhat, pts, off, pt_frame, Ntot,
+                     P->V, P->nvb, Nmax, reinterpret_cast<const unsigned long long*>(colpart), b, db);
+  return hipGetLastError();
+}
+
 hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b,
                                   float* db, double* cd) {
-  hipLaunchKernelGGL(k_chamfer_main, dim3(P->nvb, P->T), dim3(kT), 0, P->stream, xhat, P->pts, P->d_off, P->V,
-                     P->nvb, P->Nmax, a, da, reinterpret_cast<unsigned long long*>(P->colpart));
-  hipLaunchKernelGGL(k_chamfer_cols, dim3(nblk(P->Ntot, 256)), dim3(256), 0, P->stream, xhat, P->pts, P->d_off,
-                     P->pt_frame, P->Ntot, P->V, P->nvb, P->Nmax,
-                     reinterpret_cast<const unsigned long long*>(P->colpart), b, db);
+  hipError_t e = npg_launch_nn(P, xhat, P->pts, P->d_off, P->pt_frame, P->Ntot, P->Nmax, P->colpart, a, da, b, db);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_frame_sums, dim3(P->T), dim3(256), 0, P->stream, da, db, P->d_off, P->V, cd);
   return hipGetLastError();
 }

@@ -133,7 +133,8 @@ npg_status npg_build_scatter_table(npg_plan* P);
 hipError_t npg_launch_encode_fwd(const npg_plan* P, const float* params, float* z);
 hipError_t npg_launch_encode_bwd(const npg_plan* P, const float* gz, float* grad);
 // mlp.hip
-hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat);
+hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat,
+                                 float4* nhat = nullptr);
 hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const float* z,
                                  const float4* gxhat, float* grad, float* gz);
 // chamfer.hip
@@ -150,6 +151,11 @@ npg_status npg_dct_setup(npg_plan* P);
 void npg_dct_free(npg_plan* P);
 npg_status npg_iso_set_edges(npg_plan* P, int64_t E, const int32_t* edges_host);
 void npg_iso_free(npg_plan* P);
+npg_status npg_run_metrics(npg_plan* P, const float4* xhat, const float4* nhat, const float4* gt, const float4* gtn,
+                           float tau, double* out);
+hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pts, const int64_t* off,
+                         const int* pt_frame, int64_t Ntot, int64_t Nmax, void* colpart, int32_t* a, float* da,
+                         int32_t* b, float* db);
 hipError_t npg_launch_iso(const npg_plan* P, const float4* xhat, float4* gxhat, double* iso, int8_t* sign,
                           double* loss);
 npg_status npg_run_precond_dct(npg_plan* P, float* grad);

@@ -163,6 +163,17 @@ __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
   return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
+// R(w) n for a direction n (the rotation part alone)
+__device__ __forceinline__ float4 rotate_expmap(const float* o, float4 nr) {
+  float3 w = make_float3(o[0], o[1], o[2]);
+  float A, B, C;
+  rod_coef(w.x * w.x + w.y * w.y + w.z * w.z, A, B, C);
+  float3 n = make_float3(nr.x, nr.y, nr.z);
+  float3 wn = cross3(w, n);
+  float3 wwn = cross3(w, wn);
+  return make_float4(n.x + A * wn.x + B * wwn.x, n.y + A * wn.y + B * wwn.y, n.z + A * wn.z + B * wwn.z, 0.f);
+}
+
 // x^ = R(w) x + tanh(alpha d)
 __device__ __forceinline__ float4 apply_transform(const float* o, float4 xr, float alpha) {
   float3 w = make_float3(o[0], o[1], o[2]);
@@ -213,6 +224,18 @@ __device__ __forceinline__ float4 apply_quat(const float* o, float4 xr, float al
   return make_float4(x.x + 2.f * (w * t.x + vt.x) + tanhf(alpha * o[4]),
                      x.y + 2.f * (w * t.y + vt.y) + tanhf(alpha * o[5]),
                      x.z + 2.f * (w * t.z + vt.z) + tanhf(alpha * o[6]), 0.f);
+}
+
+// R(u) n for a direction n (the rotation part alone)
+__device__ __forceinline__ float4 rotate_quat(const float* o, float4 nr) {
+  const float a0 = 1.f + o[0];
+  const float inv = 1.f / sqrtf(a0 * a0 + o[1] * o[1] + o[2] * o[2] + o[3] * o[3]);
+  const float w = a0 * inv;
+  const float3 v = make_float3(o[1] * inv, o[2] * inv, o[3] * inv);
+  const float3 n = make_float3(nr.x, nr.y, nr.z);
+  const float3 t = cross3(v, n);
+  const float3 vt = cross3(v, t);
+  return make_float4(n.x + 2.f * (w * t.x + vt.x), n.y + 2.f * (w * t.y + vt.y), n.z + 2.f * (w * t.z + vt.z), 0.f);
 }
 
 // Gradient of g . x^ w.r.t. the 7 outputs. With the form above,
@@ -321,7 +344,8 @@ template <int W, int H>
 __global__ __launch_bounds__(512) void k_decode_fwd(const float* __restrict__ wp, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float4* __restrict__ xyz,
                                                     float4* __restrict__ xhat, int64_t V, int T, ActP ap,
-                                                    float alpha, int quat) {
+                                                    float alpha, int quat, const float4* __restrict__ nrm,
+                                                    float4* __restrict__ nhat) {
   constexpr int NT = W / 16;
   constexpr int LD = W + 4;  // padded LDS row
   extern __shared__ float lds[];
@@ -374,6 +398,7 @@ __global__ __launch_bounds__(512) void k_decode_fwd(const float* __restrict__ wp
     if (q == 0 && valid) {
       float ov[7] = {o[0], o[1], o[2], o[3], o4, o5, o6};
       xhat[s] = quat ? apply_quat(ov, xyz[i], alpha) : apply_transform(ov, xyz[i], alpha);
+      if (nhat) nhat[s] = quat ? rotate_quat(ov, nrm[i]) : rotate_expmap(ov, nrm[i]);
     }
   }
 }
@@ -709,13 +734,14 @@ size_t bwd_lds() {
 }
 
 template <int W, int H>
-hipError_t launch_fwd(const npg_plan* P, float4* xhat, ActP ap) {
+hipError_t launch_fwd(const npg_plan* P, float4* xhat, ActP ap, float4* nhat) {
   size_t lds = fwd_lds<W, H>();
   hipError_t e = hipFuncSetAttribute((const void*)k_decode_fwd<W, H>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_decode_fwd<W, H>), dim3(P->n_cu), dim3(512), lds, P->stream, P->wpack, P->mlpA,
-                     P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7));
+                     P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->nrm,
+                     nhat);
   return hipGetLastError();
 }
 
@@ -765,11 +791,12 @@ int64_t npg_gw_part_len(int W, int H, int n_out) {
 }
 size_t npg_decode_fwd_lds(int W, int H) { return sizeof(float) * ((size_t)(H - 1) * W * (W + 4) + 16 * (W + 4) + (H - 1) * W + 16); }
 
-hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat) {
+hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat,
+                                 float4* nhat) {
   hipError_t e = prep(P, params, z);
   if (e != hipSuccess) return e;
   ActP ap{P->cfg.act == NPG_ACT_RELU, P->cfg.leaky_slope};
-  NPG_DISPATCH(launch_fwd, P, xhat, ap);
+  NPG_DISPATCH(launch_fwd, P, xhat, ap, nhat);
 }
 
 static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const float* z, float* grad, float* gz) {

@@ -480,6 +480,23 @@ npg_status npg_iso(npg_plan* P, const float* xhat_dev, float* gxhat_dev, double*
   return NPG_OK;
 }
 
+npg_status npg_predict(npg_plan* P, float* xhat_dev, float* nhat_dev) {
+  CHECK_ARG(P && xhat_dev, "plan and xhat_dev must be non-NULL");
+  NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
+  NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, reinterpret_cast<float4*>(xhat_dev),
+                                reinterpret_cast<float4*>(nhat_dev)));
+  return NPG_OK;
+}
+
+npg_status npg_metrics(npg_plan* P, const float* xhat_dev, const float* nhat_dev, const float* gt_dev,
+                       const float* gtn_dev, float tau, double* out_dev) {
+  CHECK_ARG(P && xhat_dev && nhat_dev && gt_dev && gtn_dev && out_dev, "NULL argument");
+  CHECK_ARG(tau > 0.f && std::isfinite(tau), "tau must be finite and > 0");
+  return npg_run_metrics(P, reinterpret_cast<const float4*>(xhat_dev), reinterpret_cast<const float4*>(nhat_dev),
+                         reinterpret_cast<const float4*>(gt_dev), reinterpret_cast<const float4*>(gtn_dev), tau,
+                         out_dev);
+}
+
 npg_status npg_deform(npg_plan* P, float* out) {
   CHECK_ARG(P && out, "NULL argument");
   NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
