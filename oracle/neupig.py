@@ -30,7 +30,7 @@ __all__ = [
     "backward", "laplacian_apply", "precond_dct", "precond_cg", "precondition",
     "adam", "step", "to64", "zeros_like_params", "flatten_params", "losses",
     "chamfer_backward", "quat_matrix", "quat_normalize", "n_outputs", "iso_loss", "iso_backward", "iso_signs",
-    "deformed_normals", "metrics",
+    "deformed_normals", "metrics", "bf16_round",
 ]
 
 
@@ -92,14 +92,34 @@ def trilinear_backward(gout, R, X, F):
     return gG
 
 
-def encode(params, X, Nrm, levels, res_n):
+# --------------------------------------------------------------------------
+# Mixed-precision form (BF16): bfloat16 keeps 8 significant bits (7 stored)
+# of a binary32 number with the same exponent range; rounding is to nearest,
+# ties to even. The BF16 form rounds every MLP matrix operand (the gathered
+# grid features, the decoder input, weights, hidden activations and the
+# back-propagated gradients fed to the matrix products) and accumulates in
+# full precision; biases, the first layer's sums and everything outside the
+# MLP stay unrounded.
+# --------------------------------------------------------------------------
+def bf16_round(x):
+    """Round to the nearest bfloat16 (8-bit significand, ties to even; below
+    the smallest normal 2^-126 the spacing stays 2^-133, as in binary32)."""
+    x = np.asarray(x, np.float64)
+    _, e = np.frexp(x)                      # x = m 2^e, 0.5 <= |m| < 1
+    q = np.maximum(e, -125) - 8             # spacing 2^q of the bfloat16 grid at x
+    return np.ldexp(np.round(np.ldexp(x, -q)), q)
+
+
+def encode(params, X, Nrm, levels, res_n, bf16=False):
     """Sec. 3.2: z_p = (1/L) sum_l trilinear(G_p^l, x); z_n = trilinear(G_n, n).
+    With bf16 the gathered features are rounded to bfloat16.
 
     Returns z = [z_n, z_p] per vertex (normal part first, the decoder's
     input order of Sec. 3.3)."""
     L = len(levels)
-    zp = sum(trilinear(G, R, X) for G, R in zip(params["grid_p"], levels)) / L
-    zn = trilinear(params["grid_n"], res_n, Nrm)
+    rd = bf16_round if bf16 else (lambda a: a)
+    zp = sum(trilinear(rd(G), R, X) for G, R in zip(params["grid_p"], levels)) / L
+    zn = trilinear(rd(params["grid_n"]), res_n, Nrm)
     return np.concatenate([zn, zp], axis=1)
 
 
@@ -146,15 +166,18 @@ def _act_grad(pre, kind, slope):
     return np.where(pre > 0, 1.0, slope)
 
 
-def mlp_forward(mlp, Y, act, slope):
+def mlp_forward(mlp, Y, act, slope, bf16=False):
     """Sec. 3.3 "Network Architecture": hidden Linear+activation layers, then a
     linear output layer. Returns (output, list of pre-activations, list of
-    layer inputs)."""
+    layer inputs). With bf16 every layer input and weight is rounded to
+    bfloat16 (biases are not)."""
+    rd = bf16_round if bf16 else (lambda a: a)
     h = Y
     pres, ins = [], []
     for k, (W, b) in enumerate(mlp):
+        h = rd(h)
         ins.append(h)
-        pre = h @ W.T + b
+        pre = h @ rd(W).T + b
         if k < len(mlp) - 1:
             pres.append(pre)
             h = _act(pre, act, slope)
@@ -163,14 +186,21 @@ def mlp_forward(mlp, Y, act, slope):
     return h, pres, ins
 
 
-def mlp_backward(mlp, go, pres, ins, act, slope):
-    """Reverse-mode derivative of mlp_forward. Returns ([(gW, gb)], gY)."""
+def mlp_backward(mlp, go, pres, ins, act, slope, bf16=False):
+    """Reverse-mode derivative of mlp_forward. Returns ([(gW, gb)], gY).
+    With bf16 the gradient entering each matrix product of layers 2.. is
+    rounded to bfloat16 (weight gradient and back-propagation), as are the
+    weights; bias gradients and the first layer's weight gradient (a sum
+    over samples of the unrounded gradient times the rounded input) and its
+    input gradient use the unrounded gradient."""
+    rd = bf16_round if bf16 else (lambda a: a)
     grads = [None] * len(mlp)
     g = go
     for k in range(len(mlp) - 1, -1, -1):
         W, _ = mlp[k]
-        grads[k] = (g.T @ ins[k], g.sum(0))
-        g = g @ W
+        gm = rd(g) if k > 0 else g
+        grads[k] = (gm.T @ ins[k], g.sum(0))
+        g = gm @ rd(W)
         if k > 0:
             g = g * _act_grad(pres[k - 1], act, slope)
     return grads, g
@@ -387,10 +417,11 @@ def forward(params, data, cfg):
     Nrm = np.asarray(data["nrm"], np.float64)
     T = len(data["frame_off"]) - 1
     V = len(X)
-    z = encode(params, X, Nrm, cfg["levels"], cfg["res_n"])
+    bf16 = cfg.get("precision", "fp32") == "bf16"
+    z = encode(params, X, Nrm, cfg["levels"], cfg["res_n"], bf16)
     gamma = time_code(T, cfg["time_freqs"])
     Y = decoder_input(z, gamma)
-    o, pres, ins = mlp_forward(params["mlp"], Y, cfg["act"], cfg["leaky_slope"])
+    o, pres, ins = mlp_forward(params["mlp"], Y, cfg["act"], cfg["leaky_slope"], bf16)
     Xt = np.tile(X, (T, 1))
     xh, R, dh = transform(o, Xt, cfg["alpha_t"], cfg.get("rot_head", "expmap"))
     return dict(z=z, gamma=gamma, Y=Y, o=o, pres=pres, ins=ins, R=R, dh=dh,
@@ -441,7 +472,8 @@ def backward(params, data, cfg, fw, ls, iso_sign=None):
         gx = gx + cfg["w_iso"] * iso_backward(fw["xhat"], np.asarray(data["edges"]), ls["t_key"], iso_sign)
     go = transform_backward(gx.reshape(T * V, 3), fw["o"], fw["Xt"], fw["R"], fw["dh"], cfg["alpha_t"],
                             cfg.get("rot_head", "expmap"))
-    gmlp, gY = mlp_backward(params["mlp"], go, fw["pres"], fw["ins"], cfg["act"], cfg["leaky_slope"])
+    gmlp, gY = mlp_backward(params["mlp"], go, fw["pres"], fw["ins"], cfg["act"], cfg["leaky_slope"],
+                            cfg.get("precision", "fp32") == "bf16")
     Fz = cfg["feat_n"] + cfg["feat_p"]
     gz = gY[:, :Fz].reshape(T, V, Fz).sum(0)
     gp, gn = encode_backward(gz, X, Nrm, cfg["levels"], cfg["res_n"], cfg["feat_p"], cfg["feat_n"])

@@ -303,3 +303,26 @@ def test_isometry_loss_rigid_motions_and_finite_differences():
         fd = (O.iso_loss(xs + d, E, t_key) - O.iso_loss(xs - d, E, t_key)) / (2 * h)
         assert abs(fd - g[t, i, c]) < 1e-7 * max(1e-3, abs(g[t, i, c])), (t, i, c, fd, g[t, i, c])
     assert np.all(g[t_key] == 0)
+
+
+def test_bf16_backward_rounds_only_the_matrix_operands():
+    # two layers, everything already bfloat16-representable: the BF16
+    # backward equals the plain one exactly; a non-representable upstream
+    # gradient is rounded for layer 2's products and kept for its bias
+    rng = np.random.default_rng(3)
+    W1 = O.bf16_round(rng.normal(size=(4, 3)))
+    W2 = O.bf16_round(rng.normal(size=(2, 4)))
+    mlp = [(W1, np.zeros(4)), (W2, np.zeros(2))]
+    Y = O.bf16_round(rng.normal(size=(5, 3)))
+    o, pres, ins = O.mlp_forward(mlp, Y, "relu", 0.0, bf16=True)
+    go = O.bf16_round(rng.normal(size=(5, 2)))
+    ref, gy = O.mlp_backward(mlp, go, pres, [Y, O.bf16_round(ins[1])], "relu", 0.0)
+    got, gy2 = O.mlp_backward(mlp, go, pres, ins, "relu", 0.0, bf16=True)
+    if np.array_equal(ins[1], O.bf16_round(ins[1])):
+        for (a, b), (c, d) in zip(ref, got):
+            np.testing.assert_array_equal(a, c)
+            np.testing.assert_array_equal(b, d)
+    go2 = rng.normal(size=(5, 2))
+    got2, _ = O.mlp_backward(mlp, go2, pres, ins, "relu", 0.0, bf16=True)
+    np.testing.assert_array_equal(got2[1][0], O.bf16_round(go2).T @ ins[1])
+    np.testing.assert_array_equal(got2[1][1], go2.sum(0))

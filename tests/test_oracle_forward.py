@@ -361,3 +361,40 @@ def test_deformed_normals_of_a_known_rotation():
     p["mlp"][-1] = (np.zeros_like(W), np.concatenate([wstar, np.zeros(3)]))
     n = O.deformed_normals(O.forward(p, data, cfg), data["nrm"])
     np.testing.assert_allclose(n[0], data["nrm"] @ Rotation.from_rotvec(wstar).as_matrix().T, atol=1e-14)
+
+
+def test_bf16_rounding_matches_torch_and_its_definition():
+    # against torch's float32 -> bfloat16 cast (round to nearest even) on
+    # float32 inputs, including ties and both signs
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.normal(size=2000) * 10.0 ** rng.integers(-20, 20, 2000),
+                        [1.0, -1.0, 1.00390625, 1.01171875, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, 0.0, 3.0e38,
+                         1e-40, -5e-39, 1e-38, 2.0 ** -126]])
+    x32 = x.astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(O.bf16_round(x32.astype(np.float64)), ref)
+    # 8 significant bits: relative rounding error <= 2^-8 for normal numbers;
+    # representable values are fixed points
+    y = O.bf16_round(x)
+    nz = np.abs(x) >= 2.0 ** -126
+    assert np.all(np.abs(y[nz] - x[nz]) <= 2.0 ** -8 * np.abs(x[nz]))
+    np.testing.assert_array_equal(O.bf16_round(y), y)
+
+
+def test_bf16_forward_reduces_to_fp32_on_representable_operands():
+    # with grids, decoder input and weights already bfloat16 values and
+    # activations that stay representable, the BF16 form equals the plain one
+    cfg = synth.config_small(act="relu", time_freqs=0)
+    data = synth.make_workload(cfg)
+    p = O.to64(synth.random_state(cfg, 3))
+    p = dict(grid_p=[O.bf16_round(g) for g in p["grid_p"]], grid_n=O.bf16_round(p["grid_n"]),
+             mlp=[(O.bf16_round(W), b) for W, b in p["mlp"]])
+    a = O.forward(p, data, dict(cfg, precision="bf16"))
+    b = O.forward(p, data, cfg)
+    assert np.abs(a["xhat"] - b["xhat"]).max() < 1e-2          # activations were rounded
+    np.testing.assert_array_equal(a["ins"][1], O.bf16_round(a["ins"][1]))
+    # a single linear layer of bf16 values: exact agreement
+    W = O.bf16_round(np.random.default_rng(1).normal(size=(6, 5)))
+    Y = O.bf16_round(np.random.default_rng(2).normal(size=(7, 5)))
+    o1 = O.mlp_forward([(W, np.zeros(6))], Y, "relu", 0.0, bf16=True)[0]
+    np.testing.assert_array_equal(o1, Y @ W.T)
