@@ -35,11 +35,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,dct,quat,iso,metrics",
+    ap.add_argument("--forms", default="cg,dct,quat,iso,metrics,bf16",
                     help="forms to time: cg (headline), dct (exact DCT preconditioner), "
                          "quat (quaternion rotation head, DCT preconditioner), "
                          "iso (isometry loss w_iso = 100 on a 6-NN edge graph, DCT preconditioner), "
-                         "metrics (inference export + evaluation metrics on ground truth)")
+                         "metrics (inference export + evaluation metrics on ground truth), "
+                         "bf16 (BF16 MLP form: CG steps/s and time-to-target against FP32)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with one plain 1 GiB device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
@@ -179,6 +180,45 @@ def run_metrics(cfg, P0, reps=3):
                      "workspace allocation and final synchronisation")}
 
 
+def run_quality(cfg, steps=100):
+    """BF16 against FP32 on the same workload: `steps` steps from the paper's
+    identity start (DCT preconditioner) in each precision, the mean per-frame
+    Chamfer distance after every step (from the step's own float64 sums), and
+    the time each form needs to reach the FP32 form's final value x 1.01."""
+    import numpy as np
+    import torch
+
+    import paper_2602_22212_amd as npg
+    import synth
+    data = synth.make_workload(cfg)
+    out = {}
+    for prec in ("fp32", "bf16"):
+        c = dict(cfg, precond="dct", precision=prec)
+        plan = npg.plan_from_workload(c, data)
+        plan.set_state(torch.from_numpy(npg.pack_params(c, synth.init_params(c))).cuda(), adam_steps=0)
+        cd = torch.empty(data["T"], dtype=torch.float64, device="cuda")
+        curve, t_total = [], 0.0
+        for e in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.step(e, steps, None, cd)
+            torch.cuda.synchronize()
+            t_total += time.perf_counter() - t0
+            curve.append(float(cd.mean().item()))
+        plan.close()
+        out[prec] = dict(curve=curve, ms_per_step=1e3 * t_total / steps)
+    target = out["fp32"]["curve"][-1] * 1.01
+    res = {"steps": steps, "target_cd": target, "note": (
+        "mean per-frame Chamfer distance after each of 100 steps from the identity start, DCT preconditioner; "
+        "target = FP32 final x 1.01; time = steps to first reach it x that form's ms/step")}
+    for prec, r in out.items():
+        hit = next((k + 1 for k, v in enumerate(r["curve"]) if v <= target), None)
+        res[prec] = {"final_cd": r["curve"][-1], "ms_per_step": round(r["ms_per_step"], 3),
+                     "steps_to_target": hit,
+                     "time_to_target_s": None if hit is None else round(hit * r["ms_per_step"] / 1e3, 3)}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -250,8 +290,15 @@ def main():
             "stage_ms": iso["stage_ms"], "edges": int(len(data["edges"])),
             "note": "objective L_def + 100 L_iso (Sec. 3.5) with the DCT preconditioner; compare precond_dct"},
         "evaluation": run_metrics(cfg, P0) if "metrics" in forms else None,
+        "bf16": None,
         "cpu_baseline": None,
     }
+    if "bf16" in forms:
+        b16 = run_form(dict(cfg, precond="cg", precision="bf16"), data, P0, args.steps, args.warmup, profile=False)
+        out["bf16"] = {"value": round(b16["value"], 4), "unit": "steps/s", "ms_per_step": round(b16["ms_per_step"], 3),
+                       "stage_ms": b16["stage_ms"],
+                       "note": "headline step with the MLP's matrix operands in bfloat16 (float32 accumulation)",
+                       "quality": run_quality(cfg)}
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg, data, P0, args.cpu_frames)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

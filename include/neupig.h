@@ -76,6 +76,13 @@ enum { NPG_PRECOND_CG = 0, NPG_PRECOND_DCT = 1 };
  * study (6 network outputs: omega, d) or the unit quaternion
  * (1 + q_w, q_x, q_y, q_z)/norm of the main text (7 outputs: q, d). */
 enum { NPG_ROT_EXPMAP = 0, NPG_ROT_QUAT = 1 };
+/* Arithmetic of the decoder MLP: float32 throughout, or the mixed form with
+ * every MLP matrix operand (decoder input incl. the gathered grid features,
+ * weights, hidden activations, back-propagated gradients) rounded to
+ * bfloat16 on the matrix cores with float32 accumulation; biases, the
+ * transform, the loss, the preconditioner and the float32 master parameters
+ * and Adam state are unchanged. */
+enum { NPG_PREC_FP32 = 0, NPG_PREC_BF16 = 1 };
 
 /* Hyper-parameters. Every reading the paper leaves open is a field here. */
 typedef struct npg_config {
@@ -105,6 +112,7 @@ typedef struct npg_config {
   int32_t rot_head;               /* NPG_ROT_EXPMAP or NPG_ROT_QUAT                 */
   float w_iso;                    /* isometry-loss weight of Sec. 3.5 (paper: 100); */
                                   /* 0 disables the term, > 0 needs the mesh edges  */
+  int32_t precision;              /* NPG_PREC_FP32 or NPG_PREC_BF16                 */
 } npg_config;
 
 typedef struct npg_plan npg_plan;

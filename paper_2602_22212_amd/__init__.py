@@ -19,6 +19,7 @@ NPG_OK, NPG_EINVAL, NPG_ENOMEM, NPG_EHIP, NPG_ENOTCONV, NPG_ENONFINITE = range(6
 NPG_ACT_RELU, NPG_ACT_LEAKY = 0, 1
 NPG_PRECOND_CG, NPG_PRECOND_DCT = 0, 1
 NPG_ROT_EXPMAP, NPG_ROT_QUAT = 0, 1
+NPG_PREC_FP32, NPG_PREC_BF16 = 0, 1
 STAGES = ("encode", "decode", "chamfer+loss", "chamfer_bwd", "iso", "decode_bwd", "encode_bwd", "precond", "adam")
 
 
@@ -39,7 +40,7 @@ class npg_config(ctypes.Structure):
         ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
         ("conf_weight", ctypes.c_int32), ("t_key", ctypes.c_int32),
         ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precond", ctypes.c_int32),
-        ("rot_head", ctypes.c_int32), ("w_iso", ctypes.c_float),
+        ("rot_head", ctypes.c_int32), ("w_iso", ctypes.c_float), ("precision", ctypes.c_int32),
     ]
 
 
@@ -122,6 +123,10 @@ def make_config(cfg):
         raise ValueError(f"rot_head must be 'expmap' or 'quat', not {head!r}")
     c.rot_head = NPG_ROT_QUAT if head == "quat" else NPG_ROT_EXPMAP
     c.w_iso = float(cfg.get("w_iso", 0.0))
+    prec = cfg.get("precision", "fp32")
+    if prec not in ("fp32", "bf16"):
+        raise ValueError(f"precision must be 'fp32' or 'bf16', not {prec!r}")
+    c.precision = NPG_PREC_BF16 if prec == "bf16" else NPG_PREC_FP32
     return c
 
 

@@ -2,7 +2,8 @@
 //
 // Forward: one thread per reference vertex gathers the 8 cell corners of
 // every position level and of the normal grid; the position result is the
-// mean over levels.
+// mean over levels. In the BF16 form each gathered feature is rounded to
+// bfloat16 first (the float32 master grid is unchanged).
 // Backward: the vertex -> node scatter is replaced by a gather over a
 // node-sorted table built once per plan (setup.hip): chunks of at most 32
 // entries are summed in order, then each touched node adds its chunks in
@@ -13,7 +14,7 @@ namespace {
 
 __global__ void k_encode_fwd(const float4* __restrict__ xyz, const float4* __restrict__ nrm,
                              const NpgGrid* __restrict__ g, int L, const float* __restrict__ params,
-                             int64_t V, int Fp, int Fn, float* __restrict__ z) {
+                             int64_t V, int Fp, int Fn, int bf16, float* __restrict__ z) {
   int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= V) return;
   const int Fz = Fn + Fp;
@@ -31,7 +32,10 @@ __global__ void k_encode_fwd(const float4* __restrict__ xyz, const float4* __res
     for (int c = 0; c < 8; ++c) {
       int64_t node = ((int64_t)(iz + (c >> 2)) * R + (iy + ((c >> 1) & 1))) * R + (ix + (c & 1));
       float w = npg_corner_w(c, fx, fy, fz);
-      for (int f = 0; f < Fp; ++f) lv[f] = fmaf(w, G[node * Fp + f], lv[f]);
+      for (int f = 0; f < Fp; ++f) {
+        const float gv = G[node * Fp + f];
+        lv[f] = fmaf(w, bf16 ? npg_bf16_round(gv) : gv, lv[f]);
+      }
     }
     for (int f = 0; f < Fp; ++f) acc[f] += lv[f];
   }
@@ -50,7 +54,10 @@ __global__ void k_encode_fwd(const float4* __restrict__ xyz, const float4* __res
   for (int c = 0; c < 8; ++c) {
     int64_t node = ((int64_t)(iz + (c >> 2)) * R + (iy + ((c >> 1) & 1))) * R + (ix + (c & 1));
     float w = npg_corner_w(c, fx, fy, fz);
-    for (int f = 0; f < Fn; ++f) zn[f] = fmaf(w, G[node * Fn + f], zn[f]);
+    for (int f = 0; f < Fn; ++f) {
+      const float gv = G[node * Fn + f];
+      zn[f] = fmaf(w, bf16 ? npg_bf16_round(gv) : gv, zn[f]);
+    }
   }
   for (int f = 0; f < Fn; ++f) z[v * Fz + f] = zn[f];
 }
@@ -104,7 +111,7 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t npg_launch_encode_fwd(const npg_plan* P, const float* params, float* z) {
   hipLaunchKernelGGL(k_encode_fwd, dim3(nblk(P->V, 128)), dim3(128), 0, P->stream, P->xyz, P->nrm, P->d_g,
-                     P->L, params, P->V, P->cfg.feat_p, P->cfg.feat_n, z);
+                     P->L, params, P->V, P->cfg.feat_p, P->cfg.feat_n, (int)(P->cfg.precision == NPG_PREC_BF16), z);
   return hipGetLastError();
 }
 

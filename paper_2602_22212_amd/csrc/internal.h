@@ -84,6 +84,7 @@ struct npg_plan {
   // MLP workspace
   float *mlpA, *mlpB;      // [V][W], [T][W]
   float* wpack;            // repacked / transposed hidden and output weights
+  uint16_t* wpack16;       // bfloat16 copy of wpack (BF16 form only)
   float* gam;              // [T][Din-Fz] time code
   float *Gv, *Gt, *Gt_part, *gW_part;
   int n_vblk_mlp;
@@ -175,6 +176,15 @@ __device__ __forceinline__ void npg_cell(float x, int R, int& i0, float& f) {
   i0 = i;
   f = u - (float)i;
 }
+
+// bfloat16 (round to nearest, ties to even) of a float32, as its 16 bits and
+// widened back to float32.
+__device__ __forceinline__ uint16_t npg_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float npg_bf16_round(float x) { return __uint_as_float((uint32_t)npg_bf16_bits(x) << 16); }
 
 __device__ __forceinline__ float npg_corner_w(int c, float fx, float fy, float fz) {
   float wx = (c & 1) ? fx : 1.0f - fx;

@@ -110,22 +110,25 @@ __global__ void k_prep_weights(const float* __restrict__ mlp, int W, int H, int 
   wp[e] = val;
 }
 
-// A[i][o] = b1[o] + sum_k W1[o][k] z[i][k] (k < Fz)
+__device__ __forceinline__ float rnd(float x, int bf16) { return bf16 ? npg_bf16_round(x) : x; }
+
+// A[i][o] = b1[o] + sum_k W1[o][k] z[i][k] (k < Fz); in the BF16 form W1 and z
+// are rounded to bfloat16 first (float32 accumulation)
 __global__ void k_prep_A(const float* __restrict__ mlp, const float* __restrict__ z, int64_t V, int W, int Din,
-                         int Fz, float* __restrict__ A) {
+                         int Fz, int bf16, float* __restrict__ A) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= V * W) return;
   int64_t i = e / W;
   int o = (int)(e % W);
   const float* w1 = mlp + (int64_t)o * Din;
   float acc = mlp[(int64_t)W * Din + o];
-  for (int k = 0; k < Fz; ++k) acc = fmaf(w1[k], z[i * Fz + k], acc);
+  for (int k = 0; k < Fz; ++k) acc = fmaf(rnd(w1[k], bf16), rnd(z[i * Fz + k], bf16), acc);
   A[e] = acc;
 }
 
 // B[t][o] = sum_k W1[o][Fz + k] gamma_t[k]
 __global__ void k_prep_B(const float* __restrict__ mlp, const float* __restrict__ gam, int T, int W, int Din,
-                         int Fz, float* __restrict__ B) {
+                         int Fz, int bf16, float* __restrict__ B) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)T * W) return;
   int64_t t = e / W;
@@ -133,7 +136,7 @@ __global__ void k_prep_B(const float* __restrict__ mlp, const float* __restrict_
   const int Dt = Din - Fz;
   const float* w1 = mlp + (int64_t)o * Din + Fz;
   float acc = 0.f;
-  for (int k = 0; k < Dt; ++k) acc = fmaf(w1[k], gam[t * Dt + k], acc);
+  for (int k = 0; k < Dt; ++k) acc = fmaf(rnd(w1[k], bf16), rnd(gam[t * Dt + k], bf16), acc);
   B[e] = acc;
 }
 
@@ -653,6 +656,383 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
   if ((int)threadIdx.x < n_out) dout[n_out * W + threadIdx.x] = sGb[(H - 1) * W + threadIdx.x];
 }
 
+// ===========================================================================
+// BF16 form. Every MLP matrix operand (hidden activations, weights,
+// back-propagated gradients) is rounded to bfloat16 and multiplied on
+// v_mfma_f32_16x16x16_bf16 with float32 accumulation. The 16x16x16 layout
+// keeps the register chaining of the float32 path: lane (q, c) supplies the
+// K indices 4q..4q+3 of its B operand, which are exactly the rows 4q + r of
+// the previous layer's result, and its A operand is 4 consecutive bfloat16
+// weights of one row (one 8-byte read).
+// ===========================================================================
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4s pack_bf16(const v4f& v) {
+  return v4s{(short)npg_bf16_bits(v[0]), (short)npg_bf16_bits(v[1]), (short)npg_bf16_bits(v[2]),
+             (short)npg_bf16_bits(v[3])};
+}
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4s ld4bf(const uint16_t* p) { return *reinterpret_cast<const v4s*>(p); }
+
+// bfloat16 copy of the float32 weight pack (same layout)
+__global__ void k_pack_bf16(const float* __restrict__ src, int64_t n, uint16_t* __restrict__ dst) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = npg_bf16_bits(src[e]);
+}
+
+// out[mt] += W(16mt + c, .) in over all k tiles, one bf16 MFMA per (mt, kt);
+// wl(mt, kt) returns the 4 weights of row 16mt + c at columns 16kt + 4q..+3.
+template <int NT, typename WL>
+__device__ __forceinline__ void dense16(const v4s (&in)[NT], v4f (&out)[NT], WL wl) {
+  v4s w[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) w[0][mt] = wl(mt, 0);
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    const int cb = kt & 1;
+    if (kt + 1 < NT) {
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) w[cb ^ 1][mt] = wl(mt, kt + 1);
+    }
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) out[mt] = mfma16(w[cb][mt], in[kt], out[mt]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int NT, typename WL>
+__device__ __forceinline__ v4f dense_out16(const v4s (&in)[NT], v4f init, WL wl) {
+  v4f a0 = init, a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    if (kt & 1) a1 = mfma16(wl(kt), in[kt], a1);
+    else a0 = mfma16(wl(kt), in[kt], a0);
+  }
+  return a0 + a1;
+}
+
+template <int W, int H>
+__global__ __launch_bounds__(512) void k_decode_fwd16(const uint16_t* __restrict__ wp16,
+                                                      const float* __restrict__ wp, const float* __restrict__ A,
+                                                      const float* __restrict__ B, const float4* __restrict__ xyz,
+                                                      float4* __restrict__ xhat, int64_t V, int T, ActP ap,
+                                                      float alpha, int quat, const float4* __restrict__ nrm,
+                                                      float4* __restrict__ nhat) {
+  constexpr int NT = W / 16;
+  constexpr int LD = W + 8;  // padded LDS row (bf16 elements)
+  extern __shared__ float lds[];
+  float* sB = lds;                                                      // [H-1][W] + [16]
+  uint16_t* sW = reinterpret_cast<uint16_t*>(sB + (H - 1) * W + 16);    // [H-1][W][LD]
+  uint16_t* sWo = sW + (H - 1) * W * LD;                                // [16][LD]
+  const WPack P(W, H);
+  for (int e = threadIdx.x; e < (H - 1) * W * W; e += blockDim.x) {
+    int l = e / (W * W), k = e % (W * W);
+    sW[(l * W + k / W) * LD + k % W] = wp16[P.wh + e];
+  }
+  for (int e = threadIdx.x; e < 16 * W; e += blockDim.x) sWo[(e / W) * LD + e % W] = wp16[P.wop + e];
+  for (int e = threadIdx.x; e < (H - 1) * W; e += blockDim.x) sB[e] = wp[P.bh + e];
+  for (int e = threadIdx.x; e < 16; e += blockDim.x) sB[(H - 1) * W + e] = wp[P.bo + e];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int nw = blockDim.x >> 6;
+  const int64_t S = V * (int64_t)T;
+  const int64_t ntiles = (S + 15) / 16;
+  float4 bo4 = *reinterpret_cast<const float4*>(sB + (H - 1) * W + 4 * q);
+  const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
+
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+    int z0 = 0;
+    asm volatile("" : "+s"(z0));
+    const uint16_t* sWl = sW + z0;
+    const uint16_t* sWol = sWo + z0;
+    int64_t s = tile * 16 + c;
+    const bool valid = s < S;
+    if (!valid) s = S - 1;
+    const int64_t t = s / V, i = s - t * V;
+    v4s hb[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
+      float4 b = *reinterpret_cast<const float4*>(B + t * W + 16 * mt + 4 * q);
+      hb[mt] = pack_bf16(v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)});
+    }
+#pragma unroll
+    for (int l = 1; l < H; ++l) {
+      v4f o[NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        float4 b = *reinterpret_cast<const float4*>(sB + (l - 1) * W + 16 * mt + 4 * q);
+        o[mt] = v4f{b.x, b.y, b.z, b.w};
+      }
+      dense16<NT>(hb, o, [&](int mt, int kt) { return ld4bf(sWl + ((l - 1) * W + 16 * mt + c) * LD + 16 * kt + 4 * q); });
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+        hb[mt] = pack_bf16(v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)});
+    }
+    v4f o = dense_out16<NT>(hb, boi, [&](int kt) { return ld4bf(sWol + c * LD + 16 * kt + 4 * q); });
+    float o4 = __shfl(o[0], (lane + 16) & 63);
+    float o5 = __shfl(o[1], (lane + 16) & 63);
+    float o6 = __shfl(o[2], (lane + 16) & 63);
+    if (q == 0 && valid) {
+      float ov[7] = {o[0], o[1], o[2], o[3], o4, o5, o6};
+      xhat[s] = quat ? apply_quat(ov, xyz[i], alpha) : apply_transform(ov, xyz[i], alpha);
+      if (nhat) nhat[s] = quat ? rotate_quat(ov, nrm[i]) : rotate_expmap(ov, nrm[i]);
+    }
+  }
+}
+
+// Backward, BF16 form: the structure of k_decode_bwd (64 vertices per
+// work-group, all frames, recomputed activations, per-wave weight-gradient
+// tiles over all frames). Staged activations and gradients are bfloat16;
+// bias gradients and the first-layer sums use the float32 gradients.
+constexpr int kSP16 = 72;  // staged samples per row (64 + pad), bf16 elements
+
+template <int W, int H>
+constexpr size_t bwd16_lds_bytes() {
+  return sizeof(float) * ((size_t)W * kSP + (H - 1) * W + 16 + 4 * W) +
+         sizeof(uint16_t) * ((size_t)H * W * kSP16 + (size_t)W * kSP16);
+}
+
+template <int W, int H>
+__global__ __launch_bounds__(256) void k_decode_bwd16(const uint16_t* __restrict__ wp16,
+                                                      const float* __restrict__ wp, const float* __restrict__ A,
+                                                      const float* __restrict__ B, const float4* __restrict__ xyz,
+                                                      const float4* __restrict__ gxhat, int64_t V, int T, ActP ap,
+                                                      float alpha, int quat, float* __restrict__ Gv,
+                                                      float* __restrict__ Gt_part, float* __restrict__ gW_part) {
+  constexpr int NT = W / 16;
+  constexpr int NTT = (NT * NT + 3) / 4;
+  constexpr int NTO = (NT + 3) / 4;
+  extern __shared__ float lds[];
+  float* sG = lds;                                                   // [W][kSP] float32 gradients
+  float* sGb = sG + W * kSP;                                         // [H-1][W] + [16]
+  float* sGt = sGb + (H - 1) * W + 16;                               // [4][W]
+  uint16_t* sH = reinterpret_cast<uint16_t*>(sGt + 4 * W);           // [H][W][kSP16]
+  uint16_t* sG16 = sH + H * W * kSP16;                               // [W][kSP16]
+  const WPack P(W, H);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = lane >> 4, c = lane & 15;
+  const int64_t vb = blockIdx.x;
+  const int64_t i_raw = vb * 64 + wave * 16 + c;
+  const bool vvalid = i_raw < V;
+  const int64_t i = vvalid ? i_raw : V - 1;
+  const int sp = wave * 16 + c;
+
+  for (int e = threadIdx.x; e < (H - 1) * W + 16; e += 256) sGb[e] = 0.f;
+  float4 bo4 = *reinterpret_cast<const float4*>(wp + P.bo + 4 * q);
+  const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
+  const float4 xi = xyz[i];
+
+  v4f accW[H > 1 ? H - 1 : 1][NTT];
+  v4f accO[NTO];
+  v4f gv[NT];
+#pragma unroll
+  for (int l = 0; l < (H > 1 ? H - 1 : 1); ++l)
+#pragma unroll
+    for (int k = 0; k < NTT; ++k) accW[l][k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < NTO; ++k) accO[k] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < NT; ++k) gv[k] = v4f{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+
+  auto at = [&](float* base, int mt, int r) -> float& { return base[(16 * mt + 4 * q + r) * kSP + sp]; };
+  auto at16 = [&](uint16_t* base, int mt, int r) -> uint16_t& { return base[(16 * mt + 4 * q + r) * kSP16 + sp]; };
+  auto hval = [&](int l, int mt, int r) { return __uint_as_float((uint32_t)at16(sH + l * W * kSP16, mt, r) << 16); };
+  // acc += sum over the 64 staged samples of sG16[16mt + m][s] * hs[16kt + n][s]
+  auto wgrad_tile = [&](const uint16_t* hs, int mt, int kt, v4f acc) {
+    v4s a[4], b[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      a[jj] = ld4bf(sG16 + (16 * mt + c) * kSP16 + 16 * jj + 4 * q);
+      b[jj] = ld4bf(hs + (16 * kt + c) * kSP16 + 16 * jj + 4 * q);
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) acc = mfma16(a[jj], b[jj], acc);
+    return acc;
+  };
+  auto bias_rows = [&](int rows, float* dst) {
+    if ((int)threadIdx.x < rows) {
+      const float* src = sG + threadIdx.x * kSP;
+      float s0 = 0.f;
+      for (int j = 0; j < 64; j += 4) {
+        float4 v = *reinterpret_cast<const float4*>(src + j);
+        s0 += (v.x + v.y) + (v.z + v.w);
+      }
+      dst[threadIdx.x] += s0;
+    }
+  };
+  auto stage = [&](const v4f (&g)[NT], int rows_mt) {
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      if (mt >= rows_mt) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        at(sG, mt, r) = g[mt][r];
+        at16(sG16, mt, r) = npg_bf16_bits(g[mt][r]);
+      }
+    }
+  };
+
+  for (int t = 0; t < T; ++t) {
+    const uint16_t* wpl = wp16;
+    asm volatile("" : "+s"(wpl));
+    const float* wpf = wp;
+    asm volatile("" : "+s"(wpf));
+    // ---- recompute the forward pass; bf16 activations go to LDS ------------
+    v4s hb[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
+      float4 b = *reinterpret_cast<const float4*>(B + (int64_t)t * W + 16 * mt + 4 * q);
+      hb[mt] = pack_bf16(v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)});
+#pragma unroll
+      for (int r = 0; r < 4; ++r) at16(sH, mt, r) = (uint16_t)hb[mt][r];
+    }
+#pragma unroll
+    for (int l = 1; l < H; ++l) {
+      v4f o[NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        float4 b = *reinterpret_cast<const float4*>(wpf + P.bh + (l - 1) * W + 16 * mt + 4 * q);
+        o[mt] = v4f{b.x, b.y, b.z, b.w};
+      }
+      dense16<NT>(hb, o, [&](int mt, int kt) {
+        return ld4bf(wpl + P.wh + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
+      });
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        hb[mt] = pack_bf16(v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)});
+#pragma unroll
+        for (int r = 0; r < 4; ++r) at16(sH + l * W * kSP16, mt, r) = (uint16_t)hb[mt][r];
+      }
+    }
+    v4f o = dense_out16<NT>(hb, boi, [&](int kt) { return ld4bf(wpl + P.wop + c * W + 16 * kt + 4 * q); });
+
+    // ---- transform backward (float32) -------------------------------------
+    float o4 = __shfl(o[0], (lane + 16) & 63);
+    float o5 = __shfl(o[1], (lane + 16) & 63);
+    float o6 = __shfl(o[2], (lane + 16) & 63);
+    float ov[7] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
+                   __shfl(o5, c), __shfl(o6, c)};
+    float4 gx = vvalid ? gxhat[(int64_t)t * V + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float go[7];
+    go[6] = 0.f;
+    if (quat) quat_grad(ov, xi, gx, alpha, go);
+    else transform_grad(ov, xi, gx, alpha, go);
+    if (!vvalid)
+      for (int k = 0; k < 7; ++k) go[k] = 0.f;
+    const v4f got = q == 0 ? v4f{go[0], go[1], go[2], go[3]}
+                           : (q == 1 ? v4f{go[4], go[5], go[6], 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
+
+    // ---- output layer --------------------------------------------------------
+    {
+      v4f g1[NT];
+      g1[0] = got;
+      stage(g1, 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NTO; ++k) {
+      const int kt = wave + 4 * k;
+      if (kt < NT) accO[k] = wgrad_tile(sH + (H - 1) * W * kSP16, 0, kt, accO[k]);
+    }
+    bias_rows(16, sGb + (H - 1) * W);
+    const v4s gotb = pack_bf16(got);
+    v4f gp[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      v4f a = {0.f, 0.f, 0.f, 0.f};
+      a = mfma16(ld4bf(wpl + P.wot + (16 * mt + c) * 16 + 4 * q), gotb, a);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gp[mt][r] = a[r] * actd(hval(H - 1, mt, r), ap);
+    }
+    __syncthreads();
+
+    // ---- hidden layers, last to first ---------------------------------------
+#pragma unroll
+    for (int l = H - 1; l >= 1; --l) {
+      stage(gp, NT);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NTT; ++k) {
+        const int tau = wave + 4 * k;
+        if (tau < NT * NT) accW[l - 1][k] = wgrad_tile(sH + (l - 1) * W * kSP16, tau / NT, tau % NT, accW[l - 1][k]);
+      }
+      bias_rows(W, sGb + (l - 1) * W);
+      v4s gpb[NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) gpb[mt] = pack_bf16(gp[mt]);
+      v4f gh[NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) gh[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+      dense16<NT>(gpb, gh, [&](int mt, int kt) {
+        return ld4bf(wpl + P.wht + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
+      });
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gp[mt][r] = gh[mt][r] * actd(hval(l - 1, mt, r), ap);
+      __syncthreads();
+    }
+
+    // ---- first layer: per-vertex (Gv) and per-frame (Gt) sums -------------
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        gv[mt][r] += gp[mt][r];
+        const float v = row16_sum(gp[mt][r]);
+        if (c == 0) sGt[wave * W + 16 * mt + 4 * q + r] = v;
+      }
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+      float s0 = ((sGt[threadIdx.x] + sGt[W + threadIdx.x]) + sGt[2 * W + threadIdx.x]) + sGt[3 * W + threadIdx.x];
+      Gt_part[((int64_t)t * gridDim.x + vb) * W + threadIdx.x] = s0;
+    }
+  }
+  __syncthreads();
+
+  if (vvalid) {
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Gv[i_raw * W + 16 * mt + 4 * q + r] = gv[mt][r];
+  }
+  const int n_out = quat ? 7 : 6;
+  const int64_t len = (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
+  float* dst = gW_part + vb * len;
+#pragma unroll
+  for (int l = 1; l < H; ++l) {
+    float* dl = dst + (int64_t)(l - 1) * ((int64_t)W * W + W);
+#pragma unroll
+    for (int k = 0; k < NTT; ++k) {
+      int tau = wave + 4 * k;
+      if (tau < NT * NT) {
+        int mt = tau / NT, kt = tau % NT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dl[(16 * mt + 4 * q + r) * W + 16 * kt + c] = accW[l - 1][k][r];
+      }
+    }
+    for (int e = threadIdx.x; e < W; e += 256) dl[(int64_t)W * W + e] = sGb[(l - 1) * W + e];
+  }
+  float* dout = dst + (int64_t)(H - 1) * ((int64_t)W * W + W);
+#pragma unroll
+  for (int k = 0; k < NTO; ++k) {
+    int kt = wave + 4 * k;
+    if (kt < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * q + r < n_out) dout[(4 * q + r) * W + 16 * kt + c] = accO[k][r];
+    }
+  }
+  if ((int)threadIdx.x < n_out) dout[n_out * W + threadIdx.x] = sGb[(H - 1) * W + threadIdx.x];
+}
+
 // Sum the per-work-group partials in work-group order.
 __global__ void k_sum_parts(const float* __restrict__ part, int64_t len, int nparts, float* __restrict__ dst) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -666,7 +1046,7 @@ __global__ void k_sum_parts(const float* __restrict__ part, int64_t len, int npa
 // gb1 = sum_t Gt[t]. One block per output unit, fixed-order tree reductions.
 __global__ void k_first_layer(const float* __restrict__ Gv, const float* __restrict__ Gt,
                               const float* __restrict__ z, const float* __restrict__ gam, int64_t V, int T, int W,
-                              int Din, int Fz, float* __restrict__ g1) {
+                              int Din, int Fz, int bf16, float* __restrict__ g1) {
   __shared__ float red[256][9];
   const int o = blockIdx.x;
   const int Dt = Din - Fz;
@@ -674,7 +1054,7 @@ __global__ void k_first_layer(const float* __restrict__ Gv, const float* __restr
   for (int k = 0; k < 9; ++k) acc[k] = 0.f;
   for (int64_t i = threadIdx.x; i < V; i += 256) {
     float gv = Gv[i * W + o];
-    for (int k = 0; k < Fz; ++k) acc[k] = fmaf(gv, z[i * Fz + k], acc[k]);
+    for (int k = 0; k < Fz; ++k) acc[k] = fmaf(gv, rnd(z[i * Fz + k], bf16), acc[k]);
   }
   for (int k = 0; k < 9; ++k) red[threadIdx.x][k] = acc[k];
   __syncthreads();
@@ -691,7 +1071,7 @@ __global__ void k_first_layer(const float* __restrict__ Gv, const float* __restr
     for (int t = 0; t < T; ++t) {
       float v = Gt[(int64_t)t * W + o];
       gb += v;
-      for (int k = 0; k < Dt; ++k) gg[k] = fmaf(v, gam[(int64_t)t * Dt + k], gg[k]);
+      for (int k = 0; k < Dt; ++k) gg[k] = fmaf(v, rnd(gam[(int64_t)t * Dt + k], bf16), gg[k]);
     }
     for (int k = 0; k < Dt; ++k) g1[(int64_t)o * Din + Fz + k] = gg[k];
     g1[(int64_t)W * Din + o] = gb;
@@ -710,14 +1090,14 @@ __global__ void k_gt_reduce(const float* __restrict__ part, int T, int nwg, int 
 
 // gz[i][k] = sum_o W1[o][k] Gv[i][o], k < Fz
 __global__ void k_gz(const float* __restrict__ mlp, const float* __restrict__ Gv, int64_t V, int W, int Din,
-                     int Fz, float* __restrict__ gz) {
+                     int Fz, int bf16, float* __restrict__ gz) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= V) return;
   float acc[8];
   for (int k = 0; k < 8; ++k) acc[k] = 0.f;
   for (int o = 0; o < W; ++o) {
     float gv = Gv[i * W + o];
-    for (int k = 0; k < Fz; ++k) acc[k] = fmaf(mlp[(int64_t)o * Din + k], gv, acc[k]);
+    for (int k = 0; k < Fz; ++k) acc[k] = fmaf(rnd(mlp[(int64_t)o * Din + k], bf16), gv, acc[k]);
   }
   for (int k = 0; k < Fz; ++k) gz[i * Fz + k] = acc[k];
 }
@@ -757,15 +1137,50 @@ hipError_t launch_bwd(const npg_plan* P, const float4* gxhat, ActP ap) {
   return hipGetLastError();
 }
 
+inline int is_bf16(const npg_plan* P) { return P->cfg.precision == NPG_PREC_BF16; }
+
 hipError_t prep(const npg_plan* P, const float* params, const float* z) {
   const float* mlp = params + P->mlp_off;
   const WPack wpk(P->W, P->H);
+  const int bf = is_bf16(P);
   hipLaunchKernelGGL(k_prep_weights, dim3(nblk(wpk.total, 256)), dim3(256), 0, P->stream, mlp, P->W, P->H,
                      P->Din, P->n_out, P->wpack);
+  if (bf)
+    hipLaunchKernelGGL(k_pack_bf16, dim3(nblk(wpk.total, 256)), dim3(256), 0, P->stream, P->wpack, wpk.total,
+                       P->wpack16);
   hipLaunchKernelGGL(k_prep_A, dim3(nblk(P->V * P->W, 256)), dim3(256), 0, P->stream, mlp, z, P->V, P->W,
-                     P->Din, P->Fz, P->mlpA);
+                     P->Din, P->Fz, bf, P->mlpA);
   hipLaunchKernelGGL(k_prep_B, dim3(nblk((int64_t)P->T * P->W, 256)), dim3(256), 0, P->stream, mlp, P->gam,
-                     P->T, P->W, P->Din, P->Fz, P->mlpB);
+                     P->T, P->W, P->Din, P->Fz, bf, P->mlpB);
+  return hipGetLastError();
+}
+
+template <int W, int H>
+size_t fwd16_lds() {
+  return sizeof(float) * ((size_t)(H - 1) * W + 16) + sizeof(uint16_t) * ((size_t)(H - 1) * W * (W + 8) + 16 * (W + 8));
+}
+
+template <int W, int H>
+hipError_t launch_fwd16(const npg_plan* P, float4* xhat, ActP ap, float4* nhat) {
+  size_t lds = fwd16_lds<W, H>();
+  hipError_t e = hipFuncSetAttribute((const void*)k_decode_fwd16<W, H>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_decode_fwd16<W, H>), dim3(2 * P->n_cu), dim3(512), lds, P->stream, P->wpack16, P->wpack,
+                     P->mlpA, P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->nrm,
+                     nhat);
+  return hipGetLastError();
+}
+
+template <int W, int H>
+hipError_t launch_bwd16(const npg_plan* P, const float4* gxhat, ActP ap) {
+  size_t lds = bwd16_lds_bytes<W, H>();
+  hipError_t e = hipFuncSetAttribute((const void*)k_decode_bwd16<W, H>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_decode_bwd16<W, H>), dim3(P->n_vblk_mlp), dim3(256), lds, P->stream, P->wpack16,
+                     P->wpack, P->mlpA, P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t,
+                     (int)(P->n_out == 7), P->Gv, P->Gt_part, P->gW_part);
   return hipGetLastError();
 }
 
@@ -796,6 +1211,9 @@ hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const f
   hipError_t e = prep(P, params, z);
   if (e != hipSuccess) return e;
   ActP ap{P->cfg.act == NPG_ACT_RELU, P->cfg.leaky_slope};
+  if (is_bf16(P)) {
+    NPG_DISPATCH(launch_fwd16, P, xhat, ap, nhat);
+  }
   NPG_DISPATCH(launch_fwd, P, xhat, ap, nhat);
 }
 
@@ -808,9 +1226,9 @@ static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const 
   hipLaunchKernelGGL(k_gt_reduce, dim3(nblk((int64_t)P->T * P->W, 256)), dim3(256), 0, P->stream, P->Gt_part,
                      P->T, P->n_vblk_mlp, P->W, P->Gt);
   hipLaunchKernelGGL(k_first_layer, dim3(P->W), dim3(256), 0, P->stream, P->Gv, P->Gt, z, P->gam, P->V, P->T,
-                     P->W, P->Din, P->Fz, gmlp);
+                     P->W, P->Din, P->Fz, is_bf16(P), gmlp);
   hipLaunchKernelGGL(k_gz, dim3(nblk(P->V, 128)), dim3(128), 0, P->stream, mlp, P->Gv, P->V, P->W, P->Din,
-                     P->Fz, gz);
+                     P->Fz, is_bf16(P), gz);
   return hipGetLastError();
 }
 
@@ -819,7 +1237,8 @@ hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const f
   hipError_t e = prep(P, params, z);
   if (e != hipSuccess) return e;
   ActP ap{P->cfg.act == NPG_ACT_RELU, P->cfg.leaky_slope};
-  e = [&]() -> hipError_t { NPG_DISPATCH(launch_bwd, P, gxhat, ap); }();
+  e = is_bf16(P) ? [&]() -> hipError_t { NPG_DISPATCH(launch_bwd16, P, gxhat, ap); }()
+                 : [&]() -> hipError_t { NPG_DISPATCH(launch_bwd, P, gxhat, ap); }();
   if (e != hipSuccess) return e;
   return decode_bwd_tail(P, params, z, grad, gz);
 }

@@ -90,6 +90,7 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->precond == NPG_PRECOND_CG || c->precond == NPG_PRECOND_DCT, "precond must be CG or DCT");
   CHECK_ARG(c->rot_head == NPG_ROT_EXPMAP || c->rot_head == NPG_ROT_QUAT, "rot_head must be EXPMAP or QUAT");
   CHECK_ARG(c->w_iso >= 0.f && std::isfinite(c->w_iso), "w_iso must be finite and >= 0");
+  CHECK_ARG(c->precision == NPG_PREC_FP32 || c->precision == NPG_PREC_BF16, "precision must be FP32 or BF16");
   if (c->precond == NPG_PRECOND_DCT) {
     for (int l = 0; l < c->n_levels; ++l)
       CHECK_ARG(c->res[l] <= 256, "the DCT preconditioner supports up to 256 nodes per axis");
@@ -129,7 +130,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
   void* bufs[] = {P->xyz, P->nrm, P->pts, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
                   P->seg_chunk0, P->chunk_start, P->chunk_sum, P->chunk_sys, P->params, P->m, P->v, P->grad,
                   P->z, P->gz, P->xhat, P->gxhat, P->a, P->b, P->da, P->db, P->cd, P->w, P->loss, P->colpart,
-                  P->acc, P->mlpA, P->mlpB, P->wpack, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->gam, P->d_flag};
+                  P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->gam, P->d_flag};
   for (void* b : bufs)
     if (b) hipFree(b);
   npg_cg_free(P);
@@ -278,6 +279,8 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->mlpA, V * P->W));
   TRYP(dalloc(&P->mlpB, (int64_t)T * P->W));
   TRYP(dalloc(&P->wpack, npg_wpack_len(P->W, P->H)));
+  if (cfg->precision == NPG_PREC_BF16)
+    HIPP(hipMalloc(&P->wpack16, npg_wpack_len(P->W, P->H) * sizeof(uint16_t)));
   P->n_vblk_mlp = (int)((V + 63) / 64);
   P->gw_part_len = npg_gw_part_len(P->W, P->H, P->n_out);
   TRYP(dalloc(&P->Gv, V * P->W));

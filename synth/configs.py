@@ -28,6 +28,7 @@ def _base(**kw):
         alpha_t=0.1,                # displacement squashing tanh(alpha d)
         rot_head="expmap",          # "expmap" (6 outputs) or "quat" (7 outputs)
         w_iso=0.0,                  # isometry-loss weight (paper: 100); 0 = off
+        precision="fp32",           # "fp32" or "bf16" (MLP matrix operands in bfloat16)
         lr_mlp=1e-3,
         lr_grid=None, lr_n=0.005,
         lam=None, lam_n=0.4,
