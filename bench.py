@@ -35,12 +35,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,dct,quat,iso,metrics,bf16",
+    ap.add_argument("--forms", default="cg,dct,quat,iso,metrics,bf16,batch",
                     help="forms to time: cg (headline), dct (exact DCT preconditioner), "
                          "quat (quaternion rotation head, DCT preconditioner), "
                          "iso (isometry loss w_iso = 100 on a 6-NN edge graph, DCT preconditioner), "
                          "metrics (inference export + evaluation metrics on ground truth), "
-                         "bf16 (BF16 MLP form: CG steps/s and time-to-target against FP32)")
+                         "bf16 (BF16 MLP form: CG steps/s and time-to-target against FP32), "
+                         "batch (16 independent sequences stepped together)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with one plain 1 GiB device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
@@ -219,6 +220,43 @@ def run_quality(cfg, steps=100):
     return res
 
 
+def run_batch(steps=2, warmup=1):
+    """Batched sequences (16 independent sequences, survey config 5): one
+    npg_batch_step advances every sequence by one step, concurrently."""
+    import numpy as np
+    import torch
+
+    import paper_2602_22212_amd as npg
+    import synth
+    cfgs = synth.config_c5()
+    t0 = time.perf_counter()
+    datas = [synth.make_workload(c) for c in cfgs]
+    t_gen = time.perf_counter() - t0
+    batch = npg.Batch(cfgs, datas)
+    for k, (c, p) in enumerate(zip(cfgs, batch.plans)):
+        p.set_state(torch.from_numpy(npg.pack_params(c, synth.random_state(c, 900 + k, grid_std=0.05))).cuda(),
+                    adam_steps=0)
+    for e in range(warmup):
+        batch.step(e, 500)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(steps):
+        batch.step(warmup + e, 500)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    batch.close()
+    pairs = sum(len(d["xyz"]) * int(d["frame_off"][-1]) for d in datas)
+    samples = sum(len(d["xyz"]) * d["T"] for d in datas)
+    return {"value": round(1.0 / dt, 4), "unit": "batch steps/s", "ms_per_step": round(1e3 * dt, 2),
+            "sequences": len(cfgs), "steps": steps, "warmup": warmup,
+            "samples_per_step": samples, "chamfer_pairs_per_direction": pairs,
+            "sequence_shapes": [(len(d["xyz"]), d["T"], int(d["frame_off"][-1])) for d in datas],
+            "note": ("16 sequences (V ~ U[5k,60k], T ~ U[20,400], N_t ~ U[4k,16k] per frame; human and quadruped "
+                     "alternating), each with its own 8-level grids and 14->128x3->6 MLP in the BF16 form, CG "
+                     "preconditioner; one batch step = one step of every sequence, run concurrently on per-"
+                     f"sequence streams; inputs generated in {t_gen:.0f} s and resident before timing")}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -291,6 +329,7 @@ def main():
             "note": "objective L_def + 100 L_iso (Sec. 3.5) with the DCT preconditioner; compare precond_dct"},
         "evaluation": run_metrics(cfg, P0) if "metrics" in forms else None,
         "bf16": None,
+        "batch": None,
         "cpu_baseline": None,
     }
     if "bf16" in forms:
@@ -299,6 +338,8 @@ def main():
                        "stage_ms": b16["stage_ms"],
                        "note": "headline step with the MLP's matrix operands in bfloat16 (float32 accumulation)",
                        "quality": run_quality(cfg)}
+    if "batch" in forms:
+        out["batch"] = run_batch()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg, data, P0, args.cpu_frames)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

@@ -117,6 +117,8 @@ typedef struct npg_config {
 
 typedef struct npg_plan npg_plan;
 
+typedef struct npg_batch npg_batch;
+
 /* Message describing the calling thread's last non-OK status. */
 const char* npg_last_error(void);
 
@@ -210,6 +212,35 @@ npg_status npg_predict(npg_plan* plan, float* xhat_dev, float* nhat_dev);
  */
 npg_status npg_metrics(npg_plan* plan, const float* xhat_dev, const float* nhat_dev, const float* gt_dev,
                        const float* gtn_dev, float tau, double* out_dev);
+
+/*
+ * Batched sequences (survey config 5: many independent sequences at once).
+ * n_seq sequences, each described exactly as for npg_plan_create by the
+ * k-th entry of every array (its own config, so its own grids and MLP; host
+ * arrays of device pointers for xyz/nrm/pts, host frame offsets). The batch
+ * owns one plan and one default-priority HIP stream per sequence; reach a
+ * sequence's plan (state import/export, npg_deform, stages) through
+ * npg_batch_plan. NPG_EINVAL names the first invalid sequence; nothing is
+ * left allocated on failure. Synchronizes.
+ */
+npg_status npg_plan_create_batched(const npg_config* cfg, int32_t n_seq, const int64_t* V, const float* const* xyz_dev,
+                                   const float* const* nrm_dev, const int32_t* T, const float* const* pts_dev,
+                                   const int64_t* const* frame_off_host, npg_batch** out);
+
+/* The plan of sequence k (owned by the batch; do not destroy it). */
+npg_status npg_batch_plan(npg_batch* batch, int32_t k, npg_plan** out);
+
+/*
+ * One optimization step of every sequence (npg_step on each plan), the
+ * sequences running concurrently from host worker threads on their own
+ * streams. loss_dev: NULL or n_seq float64 device pointers (each may be
+ * NULL). Returns the most severe status over the sequences (EHIP/EINVAL >
+ * ENONFINITE > ENOTCONV > OK) with the sequence index in npg_last_error();
+ * every sequence has completed its step when the call returns.
+ */
+npg_status npg_batch_step(npg_batch* batch, int32_t epoch, int32_t n_epochs, double* const* loss_dev);
+
+npg_status npg_batch_destroy(npg_batch* batch);
 
 /* ---- stage entry points (stateless with respect to parameters) ---------- */
 

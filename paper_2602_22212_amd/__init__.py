@@ -70,6 +70,12 @@ _SIGS = {
     "npg_plan_set_edges": ([_P, _I64, ctypes.POINTER(_I32)], ctypes.c_int),
     "npg_iso": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "npg_predict": ([_P, _P, _P], ctypes.c_int),
+    "npg_plan_create_batched": ([ctypes.POINTER(npg_config), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_P),
+                                 ctypes.POINTER(_P), ctypes.POINTER(_I32), ctypes.POINTER(_P),
+                                 ctypes.POINTER(ctypes.POINTER(_I64)), ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_batch_plan": ([_P, _I32, ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_batch_step": ([_P, _I32, _I32, ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_batch_destroy": ([_P], ctypes.c_int),
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_profile": ([_P, _I32], ctypes.c_int),
     "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
@@ -219,9 +225,9 @@ class Plan:
         self.Fz = cfg["feat_n"] + cfg["feat_p"]
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and getattr(self, "_owned", True):
             lib().npg_plan_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -363,6 +369,75 @@ class Plan:
         n = self.n_params
         _check(lib().npg_adam(self._h, _ptr(params, f, n, "params"), _ptr(grad, f, n, "grad"),
                               _ptr(m, f, n, "m"), _ptr(v, f, n, "v"), int(adam_step)))
+
+
+class Batch:
+    """Many independent sequences (npg_batch): one plan and stream per
+    sequence, stepped concurrently by npg_batch_step."""
+
+    def __init__(self, cfgs, datas, device="cuda:0"):
+        import torch
+        n = len(cfgs)
+        if n < 1 or len(datas) != n:
+            raise ValueError("need one workload per config and at least one sequence")
+        self.cfgs = [dict(c) for c in cfgs]
+        self._keep = []
+        confs = (npg_config * n)(*[make_config(c) for c in cfgs])
+        V = (_I64 * n)()
+        T = (_I32 * n)()
+        xyz, nrm, pts = (_P * n)(), (_P * n)(), (_P * n)()
+        offs = (ctypes.POINTER(_I64) * n)()
+        for k, d in enumerate(datas):
+            tx = torch.from_numpy(np.ascontiguousarray(d["xyz"], np.float32)).to(device)
+            tn = torch.from_numpy(np.ascontiguousarray(d["nrm"], np.float32)).to(device)
+            tp = torch.from_numpy(np.ascontiguousarray(d["pts"], np.float32)).to(device)
+            off = np.ascontiguousarray(np.asarray(d["frame_off"], np.int64))
+            self._keep += [tx, tn, tp, off]
+            V[k], T[k] = len(d["xyz"]), len(off) - 1
+            xyz[k], nrm[k], pts[k] = tx.data_ptr(), tn.data_ptr(), tp.data_ptr()
+            offs[k] = off.ctypes.data_as(ctypes.POINTER(_I64))
+        h = _P()
+        _check(lib().npg_plan_create_batched(confs, n, V, xyz, nrm, T, pts, offs, ctypes.byref(h)))
+        self._h = h
+        self.plans = []
+        for k, (c, d) in enumerate(zip(cfgs, datas)):
+            ph = _P()
+            _check(lib().npg_batch_plan(self._h, k, ctypes.byref(ph)))
+            v = Plan.__new__(Plan)
+            v.cfg, v._c, v._owned, v._h = dict(c), make_config(c), False, ph
+            v.V, v.T = int(V[k]), int(T[k])
+            v.frame_off = self._keep[4 * k + 3]
+            v.Ntot = int(v.frame_off[-1])
+            v.n_params = param_count(c)
+            v.device, v.stream = torch.device(device), None
+            v.Fz = c["feat_n"] + c["feat_p"]
+            if c.get("w_iso", 0.0) > 0:
+                v.set_edges(d["edges"])
+            self.plans.append(v)
+
+    def step(self, epoch, n_epochs, losses=None):
+        import torch
+        arr = None
+        if losses is not None:
+            arr = (_P * len(self.plans))(*[None if l is None else _ptr(l, torch.float64, 1, "loss").value
+                                          for l in losses])
+        st = lib().npg_batch_step(self._h, int(epoch), int(n_epochs), arr)
+        if st == NPG_ENOTCONV:
+            return st
+        return _check(st)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            for v in self.plans:
+                v._h = None
+            lib().npg_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def plan_from_workload(cfg, data, device="cuda:0"):

@@ -12,6 +12,6 @@ are not available: sizes follow the paper's scales (17-1000 frames, 2k-20k
 points per frame, sensor noise well inside the stable range of the noise
 ablation, Table 8).
 """
-from .configs import config_c1, config_c2, config_c3, config_small, config_by_name  # noqa: F401
+from .configs import config_c1, config_c2, config_c3, config_c5, config_small, config_by_name  # noqa: F401
 from .meshes import icosphere, capsule_figure  # noqa: F401
 from .workloads import make_workload, init_params, random_state  # noqa: F401

@@ -71,6 +71,25 @@ def config_c3():
                  seed=3, V=50000, T=1000, N=8000, drop=0.05)
 
 
+def config_c5(n_seq=16, seed=5, scale=1.0):
+    """Batched sequences: n_seq independent sequences, each with its own
+    headline-shaped grids and MLP in the BF16 form, human and quadruped
+    alternating; V ~ U[5k, 60k], T ~ U[20, 400] and N_t ~ U[4k, 16k] drawn
+    per frame (`scale` shrinks V, T and N for tests)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_seq):
+        V = max(64, int(rng.integers(5000, 60001) * scale))
+        T = max(2, int(rng.integers(20, 401) * scale))
+        N = [max(16, int(n * scale)) for n in rng.integers(4000, 16001, size=T)]
+        shape = "human" if k % 2 == 0 else "quadruped"
+        out.append(_base(name=f"c5_{k:02d}_{shape}", shape=shape, levels=_geometric_res(16, 256, 8), feat_p=4,
+                         time_freqs=4, mlp_hidden=3, mlp_width=128, act="leaky", t_key=None, n_steps=500,
+                         grid_init_std=0.0, seed=500 + k, V=V, T=T, N=N, precision="bf16"))
+    return out
+
+
 def config_small(**kw):
     """Tiny sizes for finite-difference and multi-tile tests."""
     cfg = _base(name="small", levels=[3, 4, 5], feat_p=2, time_freqs=2,

@@ -80,9 +80,10 @@ def _sphere_workload(cfg, rng):
 
 def _figure_workload(cfg, rng, kind, want_truth=False):
     J, C = FIGURES[kind]()
-    V, T, N = cfg["V"], cfg["T"], cfg["N"]
+    V, T = cfg["V"], cfg["T"]
+    Ns = list(cfg["N"]) if isinstance(cfg["N"], (list, tuple)) else [cfg["N"]] * T
     X, Nrm, own = capsule_figure(kind, V, rng)
-    dense, _, dense_own = capsule_figure(kind, max(200_000, 4 * N), rng)
+    dense, _, dense_own = capsule_figure(kind, max(200_000, 4 * max(Ns)), rng)
     lo, hi = X.min(0), X.max(0)
     c = 0.5 * (lo + hi)
     s = 0.9 / (0.5 * (hi - lo)).max()
@@ -124,6 +125,7 @@ def _figure_workload(cfg, rng, kind, want_truth=False):
     pts = []
     drop = cfg.get("drop", 0.0)
     for t in range(T):
+        N = Ns[t]
         sel = rng.choice(len(dense), size=N, replace=False)
         if drop > 0:
             sel = sel[rng.random(N) >= drop]
