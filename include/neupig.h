@@ -325,6 +325,17 @@ npg_status npg_iso(npg_plan* plan, const float* xhat_dev, float* gxhat_dev, doub
                    int8_t* sign_dev);
 
 /*
+ * Chain rule for reverse-mode callers (torch.autograd Functions built on the
+ * stage entry points above): x_dev[k] *= c * s_dev[0] for 0 <= k < n, the
+ * factor formed in float64 on the device (s_dev: one float64, typically the
+ * upstream gradient of a scalar loss; c: a host constant). x_dev is float64
+ * with is_f64 != 0, else float32; in place, on the plan's stream.
+ * NPG_EINVAL for NULL pointers or n < 0; n = 0 does nothing.
+ */
+npg_status npg_scale(npg_plan* plan, const double* s_dev, double c, void* x_dev, int32_t is_f64,
+                     int64_t n);
+
+/*
  * Adam (bias-corrected, step count adam_step >= 1) over the flat vector with
  * per-block learning rates (levels, normal grid, MLP).
  */

@@ -77,6 +77,7 @@ _SIGS = {
     "npg_batch_step": ([_P, _I32, _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "npg_batch_destroy": ([_P], ctypes.c_int),
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
+    "npg_scale": ([_P, _P, _D, _P, _I32, _I64], ctypes.c_int),
     "npg_profile": ([_P, _I32], ctypes.c_int),
     "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
 }
@@ -369,6 +370,15 @@ class Plan:
         n = self.n_params
         _check(lib().npg_adam(self._h, _ptr(params, f, n, "params"), _ptr(grad, f, n, "grad"),
                               _ptr(m, f, n, "m"), _ptr(v, f, n, "v"), int(adam_step)))
+
+
+    def scale(self, s, x, c=1.0):
+        """x *= c * s[0] on the device (s: one float64; x: float32 or float64)."""
+        import torch
+        if x.dtype not in (torch.float32, torch.float64):
+            raise TypeError("scale: x must be float32 or float64")
+        _check(lib().npg_scale(self._h, _ptr(s, torch.float64, 1, "s"), float(c), _ptr(x, x.dtype, x.numel(), "x"),
+                               int(x.dtype == torch.float64), x.numel()))
 
 
 class Batch:
