@@ -89,6 +89,10 @@ struct npg_plan {
   float *Gv, *Gt, *Gt_part, *gW_part;
   int n_vblk_mlp;
   int64_t gw_part_len;
+  // BF16 backward schedule: 128-vertex blocks x frame chunks, items dealt
+  // round-robin to a persistent grid; per-chunk vertex sums in Gv_part
+  int b16_nvb, b16_nch, b16_grid;
+  float* Gv_part;          // [b16_nch][V][W] (NULL when b16_nch == 1)
   // preconditioner workspaces
   NpgCG cg;
   NpgDct* dct;

@@ -20,6 +20,9 @@
 // waves accumulates a fixed quarter of the weight-gradient tiles in
 // registers over all frames. Per-work-group partials are summed in a fixed
 // order afterwards, so every result is bitwise reproducible.
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -46,6 +49,21 @@ __device__ __forceinline__ float row16_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+  return v;
+}
+
+// row16_sum of the 4 components, one DPP stage for all of them at a time
+template <int CTRL>
+__device__ __forceinline__ void dpp_add4(v4f& v) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    v[r] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[r]), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ v4f row16_sum4(v4f v) {
+  dpp_add4<0xB1>(v);
+  dpp_add4<0x4E>(v);
+  dpp_add4<0x141>(v);
+  dpp_add4<0x140>(v);
   return v;
 }
 
@@ -659,22 +677,52 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
 // ===========================================================================
 // BF16 form. Every MLP matrix operand (hidden activations, weights,
 // back-propagated gradients) is rounded to bfloat16 and multiplied on
-// v_mfma_f32_16x16x16_bf16 with float32 accumulation. The 16x16x16 layout
-// keeps the register chaining of the float32 path: lane (q, c) supplies the
-// K indices 4q..4q+3 of its B operand, which are exactly the rows 4q + r of
-// the previous layer's result, and its A operand is 4 consecutive bfloat16
-// weights of one row (one 8-byte read).
+// v_mfma_f32_16x16x32_bf16 with float32 accumulation. Lane (q, c) supplies 8
+// operand values; its slot j stands for K index 16*(j/4) + 4q + j%4 of the
+// 32-wide K block, so the B operand of K block kb is the register pair
+// (tile 2kb, tile 2kb+1) of a feature-major activation (rows 4q + r of each
+// 16-row tile at lane q) and layers chain without moving data. Weight rows
+// are staged once per work-group into LDS with their columns permuted within
+// every 32-column block to that slot order (one 16-byte read per operand);
+// back-propagation reads the transposed operands from the same rows with the
+// LDS transpose load.
 // ===========================================================================
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2b __attribute__((ext_vector_type(2)));
+typedef __bf16 v4b __attribute__((ext_vector_type(4)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+#define NPG_LDS __attribute__((address_space(3)))
 
+// round to nearest even (the conversion instruction, denormals kept: the same
+// result as npg_bf16_bits)
 __device__ __forceinline__ v4s pack_bf16(const v4f& v) {
-  return v4s{(short)npg_bf16_bits(v[0]), (short)npg_bf16_bits(v[1]), (short)npg_bf16_bits(v[2]),
-             (short)npg_bf16_bits(v[3])};
+  const v2b lo = __builtin_convertvector((v2f{v[0], v[1]}), v2b);
+  const v2b hi = __builtin_convertvector((v2f{v[2], v[3]}), v2b);
+  return __builtin_bit_cast(v4s, __builtin_shufflevector(lo, hi, 0, 1, 2, 3));
 }
+__device__ __forceinline__ float bf16_val(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+// K = 16 product (lane (q, c) supplies K indices 4q..4q+3)
 __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ v4s ld4bf(const uint16_t* p) { return *reinterpret_cast<const v4s*>(p); }
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8b, a), __builtin_bit_cast(v8b, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ v8s cat8(v4s lo, v4s hi) { return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7); }
+__device__ __forceinline__ v8s lds8(const uint16_t* p) { return *reinterpret_cast<const v8s*>(p); }
+// LDS transpose load: every lane reads 4 consecutive bfloat16 at p; within
+// each group of 16 lanes, lane 4a + b receives element b of the reads of
+// lanes a, 4 + a, 8 + a, 12 + a (in that order).
+__device__ __forceinline__ v4s lds_tr(const uint16_t* p) {
+  NPG_LDS uint16_t* l = (NPG_LDS uint16_t*)const_cast<uint16_t*>(p);
+  return __builtin_bit_cast(v4s, __builtin_amdgcn_ds_read_tr16_b64_v4bf16(reinterpret_cast<NPG_LDS v4b*>(l)));
+}
+// LDS position of weight column k within its row (the slot order above)
+__device__ __forceinline__ int kpos(int k) {
+  return (k & ~31) | (((k >> 2) & 3) << 3) | (((k >> 4) & 1) << 2) | (k & 3);
+}
 
 // bfloat16 copy of the float32 weight pack (same layout)
 __global__ void k_pack_bf16(const float* __restrict__ src, int64_t n, uint16_t* __restrict__ dst) {
@@ -682,35 +730,109 @@ __global__ void k_pack_bf16(const float* __restrict__ src, int64_t n, uint16_t* 
   if (e < n) dst[e] = npg_bf16_bits(src[e]);
 }
 
-// out[mt] += W(16mt + c, .) in over all k tiles, one bf16 MFMA per (mt, kt);
-// wl(mt, kt) returns the 4 weights of row 16mt + c at columns 16kt + 4q..+3.
-template <int NT, typename WL>
-__device__ __forceinline__ void dense16(const v4s (&in)[NT], v4f (&out)[NT], WL wl) {
-  v4s w[2][NT];
+// LDS rows of staged bfloat16 weights: row stride LD; for W = 32 and 128 the
+// 16-byte chunks of a row are XOR-swizzled by a function of the row's low 4
+// bits (a bijection whose high 2 bits differ between the 4 rows one 16-lane
+// transpose read touches), so the row reads of the forward pass and the
+// transpose reads of back-propagation both spread over the LDS banks. All
+// row bases passed around are multiples of 16 rows.
+template <int W>
+struct WLds {
+  static constexpr bool kSwz = (W != 64);
+  static constexpr int LD = kSwz ? W : W + 8;
+  __device__ static int swz(int row) {
+    return kSwz ? ((((row & 3) << 2) | ((row >> 2) & 3)) & (W / 8 - 1)) : 0;
+  }
+  // element offset of permuted position p of row `row`
+  __device__ static int at(int row, int p) { return row * LD + ((((p >> 3) ^ swz(row))) << 3) + (p & 7); }
+};
+
+// Stage the hidden matrices (H-1 blocks of W rows, row = output unit) and the
+// 16 output rows into LDS in permuted column order.
+template <int W, int H>
+__device__ void stage_w16(const uint16_t* __restrict__ wp16, uint16_t* sW) {
+  using L = WLds<W>;
+  const WPack P(W, H);
+  for (int e = threadIdx.x; e < (H - 1) * W * W; e += blockDim.x) sW[L::at(e / W, kpos(e % W))] = wp16[P.wh + e];
+  for (int e = threadIdx.x; e < 16 * W; e += blockDim.x) sW[L::at((H - 1) * W + e / W, kpos(e % W))] = wp16[P.wop + e];
+}
+
+// out[mt] += sum_k Wl[16mt + c][k] in[k] over the W inputs (feature-major).
+// With PF the next K block's weights are read while the current one
+// multiplies (NT more operand registers).
+template <int W, bool PF>
+__device__ __forceinline__ void dense32(const v4s (&in)[W / 16], v4f (&out)[W / 16], const uint16_t* sWl, int q,
+                                        int c) {
+  constexpr int NT = W / 16;
+  using L = WLds<W>;
+  const int sc = L::swz(c);  // rows 16mt + c share their low 4 bits
+  auto frag = [&](int mt, int kb) { return lds8(sWl + (16 * mt + c) * L::LD + (((4 * kb + q) ^ sc) << 3)); };
+  v8s w[PF ? 2 : 1][NT];
+  if (PF) {
 #pragma unroll
-  for (int mt = 0; mt < NT; ++mt) w[0][mt] = wl(mt, 0);
+    for (int mt = 0; mt < NT; ++mt) w[0][mt] = frag(mt, 0);
+  }
 #pragma unroll
-  for (int kt = 0; kt < NT; ++kt) {
-    const int cb = kt & 1;
-    if (kt + 1 < NT) {
+  for (int kb = 0; kb < NT / 2; ++kb) {
+    const int cb = PF ? (kb & 1) : 0;
+    if (PF && kb + 1 < NT / 2) {
 #pragma unroll
-      for (int mt = 0; mt < NT; ++mt) w[cb ^ 1][mt] = wl(mt, kt + 1);
+      for (int mt = 0; mt < NT; ++mt) w[cb ^ 1][mt] = frag(mt, kb + 1);
     }
+    if (!PF) {
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) out[mt] = mfma16(w[cb][mt], in[kt], out[mt]);
+      for (int mt = 0; mt < NT; ++mt) w[0][mt] = frag(mt, kb);
+    }
+    const v8s b = cat8(in[2 * kb], in[2 * kb + 1]);
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) out[mt] = mfma32(w[cb][mt], b, out[mt]);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-template <int NT, typename WL>
-__device__ __forceinline__ v4f dense_out16(const v4s (&in)[NT], v4f init, WL wl) {
+// output rows (sWo: the 16 output rows): init + sum_k Wo[c][k] in[k]
+template <int W>
+__device__ __forceinline__ v4f dense_out32(const v4s (&in)[W / 16], v4f init, const uint16_t* sWo, int q, int c) {
+  using L = WLds<W>;
+  const int sc = L::swz(c);
   v4f a0 = init, a1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kt = 0; kt < NT; ++kt) {
-    if (kt & 1) a1 = mfma16(wl(kt), in[kt], a1);
-    else a0 = mfma16(wl(kt), in[kt], a0);
+  for (int kb = 0; kb < W / 32; ++kb) {
+    const v4f r = mfma32(lds8(sWo + c * L::LD + (((4 * kb + q) ^ sc) << 3)), cat8(in[2 * kb], in[2 * kb + 1]),
+                         (kb & 1) ? a1 : a0);
+    if (kb & 1) a1 = r;
+    else a0 = r;
   }
   return a0 + a1;
+}
+
+// Transpose read of 4 weights for back-propagation: lane (q, c) reads row
+// `row` (its low 4 bits = 4q + c/4) at the permuted position of columns
+// 16mt + 4(c%4) .. +3, i.e. chunk 4(mt/2) + c%4, half mt%2.
+template <int W>
+__device__ __forceinline__ v4s wtr(const uint16_t* sWl, int row, int mt, int c) {
+  using L = WLds<W>;
+  return lds_tr(sWl + row * L::LD + (((4 * (mt >> 1) + (c & 3)) ^ L::swz(row)) << 3) + 4 * (mt & 1));
+}
+
+// out[mt] += sum_k Wl[k][16mt + c] g[k]: back-propagation through the rows of
+// Wl with the transposed operands from the LDS transpose read
+template <int W>
+__device__ __forceinline__ void dgrad32(const v4s (&g)[W / 16], v4f (&out)[W / 16], const uint16_t* sWl, int q,
+                                        int c) {
+  constexpr int NT = W / 16;
+  const int rl = 4 * q + (c >> 2);
+#pragma unroll
+  for (int kb = 0; kb < NT / 2; ++kb) {
+    const v8s b = cat8(g[2 * kb], g[2 * kb + 1]);
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      const v4s lo = wtr<W>(sWl, 32 * kb + rl, mt, c);
+      const v4s hi = wtr<W>(sWl, 32 * kb + 16 + rl, mt, c);
+      out[mt] = mfma32(cat8(lo, hi), b, out[mt]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 template <int W, int H>
@@ -721,17 +843,12 @@ __global__ __launch_bounds__(512) void k_decode_fwd16(const uint16_t* __restrict
                                                       float alpha, int quat, const float4* __restrict__ nrm,
                                                       float4* __restrict__ nhat) {
   constexpr int NT = W / 16;
-  constexpr int LD = W + 8;  // padded LDS row (bf16 elements)
-  extern __shared__ float lds[];
-  float* sB = lds;                                                      // [H-1][W] + [16]
-  uint16_t* sW = reinterpret_cast<uint16_t*>(sB + (H - 1) * W + 16);    // [H-1][W][LD]
-  uint16_t* sWo = sW + (H - 1) * W * LD;                                // [16][LD]
+  constexpr int LD = WLds<W>::LD;
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  uint16_t* sW = reinterpret_cast<uint16_t*>(lds);                      // [(H-1)W + 16][LD]
+  float* sB = reinterpret_cast<float*>(sW + ((H - 1) * W + 16) * LD);   // [H-1][W] + [16]
   const WPack P(W, H);
-  for (int e = threadIdx.x; e < (H - 1) * W * W; e += blockDim.x) {
-    int l = e / (W * W), k = e % (W * W);
-    sW[(l * W + k / W) * LD + k % W] = wp16[P.wh + e];
-  }
-  for (int e = threadIdx.x; e < 16 * W; e += blockDim.x) sWo[(e / W) * LD + e % W] = wp16[P.wop + e];
+  stage_w16<W, H>(wp16, sW);
   for (int e = threadIdx.x; e < (H - 1) * W; e += blockDim.x) sB[e] = wp[P.bh + e];
   for (int e = threadIdx.x; e < 16; e += blockDim.x) sB[(H - 1) * W + e] = wp[P.bo + e];
   __syncthreads();
@@ -745,10 +862,6 @@ __global__ __launch_bounds__(512) void k_decode_fwd16(const uint16_t* __restrict
   const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
 
   for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
-    int z0 = 0;
-    asm volatile("" : "+s"(z0));
-    const uint16_t* sWl = sW + z0;
-    const uint16_t* sWol = sWo + z0;
     int64_t s = tile * 16 + c;
     const bool valid = s < S;
     if (!valid) s = S - 1;
@@ -768,12 +881,12 @@ __global__ __launch_bounds__(512) void k_decode_fwd16(const uint16_t* __restrict
         float4 b = *reinterpret_cast<const float4*>(sB + (l - 1) * W + 16 * mt + 4 * q);
         o[mt] = v4f{b.x, b.y, b.z, b.w};
       }
-      dense16<NT>(hb, o, [&](int mt, int kt) { return ld4bf(sWl + ((l - 1) * W + 16 * mt + c) * LD + 16 * kt + 4 * q); });
+      dense32<W, true>(hb, o, sW + (l - 1) * W * LD, q, c);
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt)
         hb[mt] = pack_bf16(v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)});
     }
-    v4f o = dense_out16<NT>(hb, boi, [&](int kt) { return ld4bf(sWol + c * LD + 16 * kt + 4 * q); });
+    v4f o = dense_out32<W>(hb, boi, sW + (H - 1) * W * LD, q, c);
     float o4 = __shfl(o[0], (lane + 16) & 63);
     float o5 = __shfl(o[1], (lane + 16) & 63);
     float o6 = __shfl(o[2], (lane + 16) & 63);
@@ -785,252 +898,298 @@ __global__ __launch_bounds__(512) void k_decode_fwd16(const uint16_t* __restrict
   }
 }
 
-// Backward, BF16 form: the structure of k_decode_bwd (64 vertices per
-// work-group, all frames, recomputed activations, per-wave weight-gradient
-// tiles over all frames). Staged activations and gradients are bfloat16;
-// bias gradients and the first-layer sums use the float32 gradients.
-constexpr int kSP16 = 72;  // staged samples per row (64 + pad), bf16 elements
+// Backward, BF16 form. A persistent work-group of 4 waves (one per SIMD, so
+// each wave has the whole register file) takes work items (block of 64
+// vertices, chunk of consecutive frames) in a fixed round-robin order. Per
+// frame every wave recomputes the forward pass of its 16 vertices,
+// back-propagates in registers, and stages each layer's bfloat16 (gradient,
+// input) of the 64 samples in LDS as [sample][feature] rows (one 8-byte store
+// per tile), from which every wave accumulates a fixed quarter of the
+// weight-gradient tiles (K = samples, operands by the LDS transpose read) in
+// registers over all its items. Bias gradients use the float32 gradients (per-wave row sums
+// in LDS), as do the first-layer sums: per vertex over the chunk's frames
+// (Gv, one slice per chunk) and per frame over the block's vertices
+// (Gt_part). Every partial is reduced later in a fixed order. The
+// first-layer terms of the item (A_i of its vertices, B_t of its frames) are
+// staged in LDS at the start of the item; the next frame's gradient rows are
+// read one frame ahead.
+constexpr int kB16W = 4;            // waves per work-group
+constexpr int kB16S = 16 * kB16W;   // vertices (samples) per frame round
+template <int W>
+constexpr int b16_ls() { return W + 16; }  // staged [sample][feature] row stride (bfloat16)
+constexpr int kB16TC = 16;          // most frames per work item
 
 template <int W, int H>
 constexpr size_t bwd16_lds_bytes() {
-  return sizeof(float) * ((size_t)W * kSP + (H - 1) * W + 16 + 4 * W) +
-         sizeof(uint16_t) * ((size_t)H * W * kSP16 + (size_t)W * kSP16);
+  return sizeof(uint16_t) * ((size_t)((H - 1) * W + 16) * WLds<W>::LD + 2 * (size_t)kB16S * b16_ls<W>()) +
+         sizeof(float) * ((size_t)kB16W * ((H - 1) * W + 16) + (size_t)kB16W * W + (size_t)kB16S * (W + 4) +
+                          (size_t)kB16TC * W);
 }
 
 template <int W, int H>
-__global__ __launch_bounds__(256) void k_decode_bwd16(const uint16_t* __restrict__ wp16,
-                                                      const float* __restrict__ wp, const float* __restrict__ A,
-                                                      const float* __restrict__ B, const float4* __restrict__ xyz,
-                                                      const float4* __restrict__ gxhat, int64_t V, int T, ActP ap,
-                                                      float alpha, int quat, float* __restrict__ Gv,
-                                                      float* __restrict__ Gt_part, float* __restrict__ gW_part) {
+__global__ __launch_bounds__(64 * kB16W) void k_decode_bwd16(
+    const uint16_t* __restrict__ wp16, const float* __restrict__ wp, const float* __restrict__ A,
+    const float* __restrict__ B, const float4* __restrict__ xyz, const float4* __restrict__ gxhat, int64_t V, int T,
+    ActP ap, float alpha, int quat, int nvb, int nch, float* __restrict__ Gv, float* __restrict__ Gt_part,
+    float* __restrict__ gW_part) {
   constexpr int NT = W / 16;
-  constexpr int NTT = (NT * NT + 3) / 4;
-  constexpr int NTO = (NT + 3) / 4;
-  extern __shared__ float lds[];
-  float* sG = lds;                                                   // [W][kSP] float32 gradients
-  float* sGb = sG + W * kSP;                                         // [H-1][W] + [16]
-  float* sGt = sGb + (H - 1) * W + 16;                               // [4][W]
-  uint16_t* sH = reinterpret_cast<uint16_t*>(sGt + 4 * W);           // [H][W][kSP16]
-  uint16_t* sG16 = sH + H * W * kSP16;                               // [W][kSP16]
+  constexpr int LD = WLds<W>::LD;
+  constexpr int LA = W + 4;                            // A-row stride in LDS (floats)
+  constexpr int NTT = (NT * NT + kB16W - 1) / kB16W;   // owned hidden weight-gradient tiles per wave
+  constexpr int NTO = (NT + kB16W - 1) / kB16W;        // owned output weight-gradient tiles per wave
+  constexpr int NB = (H - 1) * W + 16;                 // bias-gradient entries (hidden, then output rows)
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  uint16_t* sW = reinterpret_cast<uint16_t*>(lds);                 // [NB][LD] weights
+  constexpr int LS = b16_ls<W>();
+  uint16_t* sG = sW + NB * LD;                                     // [kB16S][LS] staged gradients
+  uint16_t* sH = sG + kB16S * LS;                                  // [kB16S][LS] staged layer inputs
+  float* sGb = reinterpret_cast<float*>(sH + kB16S * LS);          // [kB16W][NB]
+  float* sGt = sGb + kB16W * NB;                                   // [kB16W][W]
+  float* sA = sGt + kB16W * W;                                     // [kB16S][LA] the item's A rows
+  float* sBt = sA + kB16S * LA;                                    // [kB16TC][W] the item's B rows
   const WPack P(W, H);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
-  const int64_t vb = blockIdx.x;
-  const int64_t i_raw = vb * 64 + wave * 16 + c;
-  const bool vvalid = i_raw < V;
-  const int64_t i = vvalid ? i_raw : V - 1;
   const int sp = wave * 16 + c;
 
-  for (int e = threadIdx.x; e < (H - 1) * W + 16; e += 256) sGb[e] = 0.f;
+  stage_w16<W, H>(wp16, sW);
+  for (int e = threadIdx.x; e < kB16W * NB; e += blockDim.x) sGb[e] = 0.f;
   float4 bo4 = *reinterpret_cast<const float4*>(wp + P.bo + 4 * q);
   const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
-  const float4 xi = xyz[i];
-
   v4f accW[H > 1 ? H - 1 : 1][NTT];
   v4f accO[NTO];
-  v4f gv[NT];
 #pragma unroll
   for (int l = 0; l < (H > 1 ? H - 1 : 1); ++l)
 #pragma unroll
     for (int k = 0; k < NTT; ++k) accW[l][k] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < NTO; ++k) accO[k] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int k = 0; k < NT; ++k) gv[k] = v4f{0.f, 0.f, 0.f, 0.f};
   __syncthreads();
 
-  auto at = [&](float* base, int mt, int r) -> float& { return base[(16 * mt + 4 * q + r) * kSP + sp]; };
-  auto at16 = [&](uint16_t* base, int mt, int r) -> uint16_t& { return base[(16 * mt + 4 * q + r) * kSP16 + sp]; };
-  auto hval = [&](int l, int mt, int r) { return __uint_as_float((uint32_t)at16(sH + l * W * kSP16, mt, r) << 16); };
-  // acc += sum over the 64 staged samples of sG16[16mt + m][s] * hs[16kt + n][s]
-  auto wgrad_tile = [&](const uint16_t* hs, int mt, int kt, v4f acc) {
-    v4s a[4], b[4];
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      a[jj] = ld4bf(sG16 + (16 * mt + c) * kSP16 + 16 * jj + 4 * q);
-      b[jj] = ld4bf(hs + (16 * kt + c) * kSP16 + 16 * jj + 4 * q);
-    }
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) acc = mfma16(a[jj], b[jj], acc);
-    return acc;
-  };
-  auto bias_rows = [&](int rows, float* dst) {
-    if ((int)threadIdx.x < rows) {
-      const float* src = sG + threadIdx.x * kSP;
-      float s0 = 0.f;
-      for (int j = 0; j < 64; j += 4) {
-        float4 v = *reinterpret_cast<const float4*>(src + j);
-        s0 += (v.x + v.y) + (v.z + v.w);
-      }
-      dst[threadIdx.x] += s0;
-    }
-  };
-  auto stage = [&](const v4f (&g)[NT], int rows_mt) {
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      if (mt >= rows_mt) break;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        at(sG, mt, r) = g[mt][r];
-        at16(sG16, mt, r) = npg_bf16_bits(g[mt][r]);
-      }
-    }
+  // this lane's 4 features 16mt + 4q .. +3 of its sample, one 8-byte store
+  auto stage = [&](uint16_t* buf, int mt, v4s v) { *reinterpret_cast<v4s*>(buf + sp * LS + 16 * mt + 4 * q) = v; };
+  // operand of K block ks (samples 32ks ..): row tile t of buf, slot 4h + k of
+  // lane (q, c) = feature 16t + c of sample 32ks + 16h + 4q + k
+  auto kop = [&](const uint16_t* buf, int t, int ks) {
+    const uint16_t* p = buf + (32 * ks + 4 * q + (c >> 2)) * LS + 16 * t + 4 * (c & 3);
+    return cat8(lds_tr(p), lds_tr(p + 16 * LS));
   };
 
-  for (int t = 0; t < T; ++t) {
-    const uint16_t* wpl = wp16;
-    asm volatile("" : "+s"(wpl));
-    const float* wpf = wp;
-    asm volatile("" : "+s"(wpf));
-    // ---- recompute the forward pass; bf16 activations go to LDS ------------
-    v4s hb[NT];
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
-      float4 b = *reinterpret_cast<const float4*>(B + (int64_t)t * W + 16 * mt + 4 * q);
-      hb[mt] = pack_bf16(v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)});
-#pragma unroll
-      for (int r = 0; r < 4; ++r) at16(sH, mt, r) = (uint16_t)hb[mt][r];
-    }
-#pragma unroll
-    for (int l = 1; l < H; ++l) {
-      v4f o[NT];
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt) {
-        float4 b = *reinterpret_cast<const float4*>(wpf + P.bh + (l - 1) * W + 16 * mt + 4 * q);
-        o[mt] = v4f{b.x, b.y, b.z, b.w};
+  const int64_t n_items = (int64_t)nvb * nch;
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int vb = (int)(item % nvb), ch = (int)(item / nvb);
+    const int t0 = (int)((int64_t)T * ch / nch), t1 = (int)((int64_t)T * (ch + 1) / nch);
+    const int64_t i_raw = (int64_t)vb * kB16S + sp;
+    const bool vvalid = i_raw < V;
+    const int64_t i = vvalid ? i_raw : V - 1;
+    const float4 xi = xyz[i];
+    {  // the item's first-layer rows (the previous item's readers have passed a barrier)
+      const int64_t v0 = (int64_t)vb * kB16S;
+      for (int e = threadIdx.x; e < kB16S * W / 4; e += blockDim.x) {
+        const int64_t v = std::min<int64_t>(v0 + (4 * e) / W, V - 1);
+        *reinterpret_cast<float4*>(sA + ((4 * e) / W) * LA + (4 * e) % W) =
+            *reinterpret_cast<const float4*>(A + v * W + (4 * e) % W);
       }
-      dense16<NT>(hb, o, [&](int mt, int kt) {
-        return ld4bf(wpl + P.wh + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
-      });
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt) {
-        hb[mt] = pack_bf16(v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)});
-#pragma unroll
-        for (int r = 0; r < 4; ++r) at16(sH + l * W * kSP16, mt, r) = (uint16_t)hb[mt][r];
-      }
-    }
-    v4f o = dense_out16<NT>(hb, boi, [&](int kt) { return ld4bf(wpl + P.wop + c * W + 16 * kt + 4 * q); });
-
-    // ---- transform backward (float32) -------------------------------------
-    float o4 = __shfl(o[0], (lane + 16) & 63);
-    float o5 = __shfl(o[1], (lane + 16) & 63);
-    float o6 = __shfl(o[2], (lane + 16) & 63);
-    float ov[7] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
-                   __shfl(o5, c), __shfl(o6, c)};
-    float4 gx = vvalid ? gxhat[(int64_t)t * V + i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    float go[7];
-    go[6] = 0.f;
-    if (quat) quat_grad(ov, xi, gx, alpha, go);
-    else transform_grad(ov, xi, gx, alpha, go);
-    if (!vvalid)
-      for (int k = 0; k < 7; ++k) go[k] = 0.f;
-    const v4f got = q == 0 ? v4f{go[0], go[1], go[2], go[3]}
-                           : (q == 1 ? v4f{go[4], go[5], go[6], 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
-
-    // ---- output layer --------------------------------------------------------
-    {
-      v4f g1[NT];
-      g1[0] = got;
-      stage(g1, 1);
+      for (int e = threadIdx.x; e < (t1 - t0) * W / 4; e += blockDim.x)
+        reinterpret_cast<float4*>(sBt)[e] = *reinterpret_cast<const float4*>(B + (int64_t)t0 * W + 4 * e);
     }
     __syncthreads();
+    float4 gxn = vvalid ? gxhat[(int64_t)t0 * V + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    v4f gv[NT];
 #pragma unroll
-    for (int k = 0; k < NTO; ++k) {
-      const int kt = wave + 4 * k;
-      if (kt < NT) accO[k] = wgrad_tile(sH + (H - 1) * W * kSP16, 0, kt, accO[k]);
-    }
-    bias_rows(16, sGb + (H - 1) * W);
-    const v4s gotb = pack_bf16(got);
-    v4f gp[NT];
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      v4f a = {0.f, 0.f, 0.f, 0.f};
-      a = mfma16(ld4bf(wpl + P.wot + (16 * mt + c) * 16 + 4 * q), gotb, a);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gp[mt][r] = a[r] * actd(hval(H - 1, mt, r), ap);
-    }
-    __syncthreads();
+    for (int mt = 0; mt < NT; ++mt) gv[mt] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    // ---- hidden layers, last to first ---------------------------------------
+    // first hidden layer's output of this lane's sample at frame t (from LDS)
+    auto first_layer = [&](int t, v4s (&h0)[NT]) {
 #pragma unroll
-    for (int l = H - 1; l >= 1; --l) {
-      stage(gp, NT);
+      for (int mt = 0; mt < NT; ++mt) {
+        const float4 a = *reinterpret_cast<const float4*>(sA + sp * LA + 16 * mt + 4 * q);
+        const float4 b = *reinterpret_cast<const float4*>(sBt + (t - t0) * W + 16 * mt + 4 * q);
+        h0[mt] = pack_bf16(v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)});
+      }
+    };
+
+    for (int t = t0; t < t1; ++t) {
+      // ---- forward pass, recomputed; bfloat16 inputs of the layers kept
+      // (the first one is read again from LDS when it is needed) -----------
+      v4s h[H][NT];
+      first_layer(t, h[0]);
+      const float4 gx = gxn;
+      if (t + 1 < t1 && vvalid) gxn = gxhat[(int64_t)(t + 1) * V + i];  // next frame's row
+#pragma unroll
+      for (int l = 1; l < H; ++l) {
+        v4f o[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          float4 b = *reinterpret_cast<const float4*>(wp + P.bh + (l - 1) * W + 16 * mt + 4 * q);
+          o[mt] = v4f{b.x, b.y, b.z, b.w};
+        }
+        dense32<W, false>(h[l - 1], o, sW + (l - 1) * W * LD, q, c);
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+          h[l][mt] = pack_bf16(v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)});
+      }
+      const v4f o = dense_out32<W>(h[H - 1], boi, sW + (H - 1) * W * LD, q, c);
+
+      // ---- transform backward (float32) -----------------------------------
+      float o4 = __shfl(o[0], (lane + 16) & 63);
+      float o5 = __shfl(o[1], (lane + 16) & 63);
+      float o6 = __shfl(o[2], (lane + 16) & 63);
+      float ov[7] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
+                     __shfl(o5, c), __shfl(o6, c)};
+      float go[7];
+      go[6] = 0.f;
+      if (quat) quat_grad(ov, xi, gx, alpha, go);
+      else transform_grad(ov, xi, gx, alpha, go);
+      if (!vvalid)
+        for (int k = 0; k < 7; ++k) go[k] = 0.f;
+      const v4f got = q == 0 ? v4f{go[0], go[1], go[2], go[3]}
+                             : (q == 1 ? v4f{go[4], go[5], go[6], 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
+      const v4s gotb = pack_bf16(got);
+
+      // ---- output layer ---------------------------------------------------
+      stage(sG, 0, gotb);
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) stage(sH, mt, h[H - 1][mt]);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < NTT; ++k) {
-        const int tau = wave + 4 * k;
-        if (tau < NT * NT) accW[l - 1][k] = wgrad_tile(sH + (l - 1) * W * kSP16, tau / NT, tau % NT, accW[l - 1][k]);
+      for (int ks = 0; ks < kB16S / 32; ++ks) {
+        const v8s a = kop(sG, 0, ks);
+#pragma unroll
+        for (int k = 0; k < NTO; ++k) {
+          const int kt = wave + kB16W * k;
+          if (kt < NT) accO[k] = mfma32(a, kop(sH, kt, ks), accO[k]);
+        }
       }
-      bias_rows(W, sGb + (l - 1) * W);
-      v4s gpb[NT];
+      {
+        const v4f v = row16_sum4(got);
+        if (c == 0) {
+          float4* p = reinterpret_cast<float4*>(sGb + wave * NB + (H - 1) * W + 4 * q);
+          const float4 u = *p;
+          *p = make_float4(u.x + v[0], u.y + v[1], u.z + v[2], u.w + v[3]);
+        }
+      }
+      v4f gp[NT];
 #pragma unroll
-      for (int mt = 0; mt < NT; ++mt) gpb[mt] = pack_bf16(gp[mt]);
-      v4f gh[NT];
+      for (int mt = 0; mt < NT; ++mt) {
+        const v4f a = mfma16(wtr<W>(sW + (H - 1) * W * LD, 4 * q + (c >> 2), mt, c), gotb, v4f{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-      for (int mt = 0; mt < NT; ++mt) gh[mt] = v4f{0.f, 0.f, 0.f, 0.f};
-      dense16<NT>(gpb, gh, [&](int mt, int kt) {
-        return ld4bf(wpl + P.wht + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
-      });
+        for (int r = 0; r < 4; ++r) gp[mt][r] = a[r] * actd(bf16_val(h[H - 1][mt][r]), ap);
+      }
+      __syncthreads();
+
+      // ---- hidden layers, last to first ----------------------------------
+#pragma unroll
+      for (int l = H - 1; l >= 1; --l) {
+        if (l == 1 && H > 2) first_layer(t, h[0]);
+        v4s gb[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          gb[mt] = pack_bf16(gp[mt]);
+          stage(sG, mt, gb[mt]);
+          stage(sH, mt, h[l - 1][mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          const v4f v = row16_sum4(gp[mt]);
+          if (c == 0) {
+            float4* p = reinterpret_cast<float4*>(sGb + wave * NB + (l - 1) * W + 16 * mt + 4 * q);
+            const float4 u = *p;
+            *p = make_float4(u.x + v[0], u.y + v[1], u.z + v[2], u.w + v[3]);
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kB16S / 32; ++ks) {
+#pragma unroll
+          for (int k = 0; k < NTT; ++k) {
+            const unsigned tau = (unsigned)wave + kB16W * k;
+            if (tau < (unsigned)(NT * NT))
+              accW[l - 1][k] = mfma32(kop(sG, tau / NT, ks), kop(sH, tau % NT, ks), accW[l - 1][k]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        v4f gh[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) gh[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+        dgrad32<W>(gb, gh, sW + (l - 1) * W * LD, q, c);
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gp[mt][r] = gh[mt][r] * actd(bf16_val(h[l - 1][mt][r]), ap);
+        if (l > 1) __syncthreads();
+      }
+
+      // ---- first layer: per-vertex and per-frame sums ---------------------
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        gv[mt] += gp[mt];
+        const v4f v = row16_sum4(gp[mt]);
+        if (c == 0) *reinterpret_cast<float4*>(sGt + wave * W + 16 * mt + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+      }
+      __syncthreads();
+      for (int f = threadIdx.x; f < W; f += blockDim.x) {
+        float s0 = 0.f;
+#pragma unroll
+        for (int w = 0; w < kB16W; ++w) s0 += sGt[w * W + f];
+        Gt_part[((int64_t)t * nvb + vb) * W + f] = s0;
+      }
+    }
+    if (vvalid) {
+      float* dst = Gv + ((int64_t)ch * V + i_raw) * W;
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) gp[mt][r] = gh[mt][r] * actd(hval(l - 1, mt, r), ap);
-      __syncthreads();
-    }
-
-    // ---- first layer: per-vertex (Gv) and per-frame (Gt) sums -------------
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        gv[mt][r] += gp[mt][r];
-        const float v = row16_sum(gp[mt][r]);
-        if (c == 0) sGt[wave * W + 16 * mt + 4 * q + r] = v;
-      }
-    __syncthreads();
-    if ((int)threadIdx.x < W) {
-      float s0 = ((sGt[threadIdx.x] + sGt[W + threadIdx.x]) + sGt[2 * W + threadIdx.x]) + sGt[3 * W + threadIdx.x];
-      Gt_part[((int64_t)t * gridDim.x + vb) * W + threadIdx.x] = s0;
+        *reinterpret_cast<float4*>(dst + 16 * mt + 4 * q) = make_float4(gv[mt][0], gv[mt][1], gv[mt][2], gv[mt][3]);
     }
   }
   __syncthreads();
 
-  if (vvalid) {
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Gv[i_raw * W + 16 * mt + 4 * q + r] = gv[mt][r];
-  }
+  // ---- this work-group's weight-gradient partial --------------------------
   const int n_out = quat ? 7 : 6;
   const int64_t len = (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
-  float* dst = gW_part + vb * len;
+  float* dst = gW_part + (int64_t)blockIdx.x * len;
 #pragma unroll
   for (int l = 1; l < H; ++l) {
     float* dl = dst + (int64_t)(l - 1) * ((int64_t)W * W + W);
 #pragma unroll
     for (int k = 0; k < NTT; ++k) {
-      int tau = wave + 4 * k;
-      if (tau < NT * NT) {
-        int mt = tau / NT, kt = tau % NT;
+      const unsigned tau = (unsigned)wave + kB16W * k;
+      if (tau < (unsigned)(NT * NT)) {
+        const int mt = tau / NT, kt = tau % NT;
 #pragma unroll
         for (int r = 0; r < 4; ++r) dl[(16 * mt + 4 * q + r) * W + 16 * kt + c] = accW[l - 1][k][r];
       }
     }
-    for (int e = threadIdx.x; e < W; e += 256) dl[(int64_t)W * W + e] = sGb[(l - 1) * W + e];
+    for (int e = threadIdx.x; e < W; e += blockDim.x) {
+      float s0 = 0.f;
+      for (int w = 0; w < kB16W; ++w) s0 += sGb[w * NB + (l - 1) * W + e];
+      dl[(int64_t)W * W + e] = s0;
+    }
   }
   float* dout = dst + (int64_t)(H - 1) * ((int64_t)W * W + W);
 #pragma unroll
   for (int k = 0; k < NTO; ++k) {
-    int kt = wave + 4 * k;
+    const int kt = wave + kB16W * k;
     if (kt < NT) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         if (4 * q + r < n_out) dout[(4 * q + r) * W + 16 * kt + c] = accO[k][r];
     }
   }
-  if ((int)threadIdx.x < n_out) dout[n_out * W + threadIdx.x] = sGb[(H - 1) * W + threadIdx.x];
+  if ((int)threadIdx.x < n_out) {
+    float s0 = 0.f;
+    for (int w = 0; w < kB16W; ++w) s0 += sGb[w * NB + (H - 1) * W + threadIdx.x];
+    dout[n_out * W + threadIdx.x] = s0;
+  }
+}
+
+// Gv[i][o] = sum over chunks of Gv_part[chunk][i][o]
+__global__ void k_gv_reduce(const float* __restrict__ part, int64_t n, int nch, float* __restrict__ Gv) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float s = 0.f;
+  for (int k = 0; k < nch; ++k) s += part[(int64_t)k * n + e];
+  Gv[e] = s;
 }
 
 // Sum the per-work-group partials in work-group order.
@@ -1157,7 +1316,7 @@ hipError_t prep(const npg_plan* P, const float* params, const float* z) {
 
 template <int W, int H>
 size_t fwd16_lds() {
-  return sizeof(float) * ((size_t)(H - 1) * W + 16) + sizeof(uint16_t) * ((size_t)(H - 1) * W * (W + 8) + 16 * (W + 8));
+  return sizeof(uint16_t) * ((size_t)((H - 1) * W + 16) * WLds<W>::LD) + sizeof(float) * ((size_t)(H - 1) * W + 16);
 }
 
 template <int W, int H>
@@ -1178,9 +1337,10 @@ hipError_t launch_bwd16(const npg_plan* P, const float4* gxhat, ActP ap) {
   hipError_t e = hipFuncSetAttribute((const void*)k_decode_bwd16<W, H>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode_bwd16<W, H>), dim3(P->n_vblk_mlp), dim3(256), lds, P->stream, P->wpack16,
+  hipLaunchKernelGGL((k_decode_bwd16<W, H>), dim3(P->b16_grid), dim3(64 * kB16W), lds, P->stream, P->wpack16,
                      P->wpack, P->mlpA, P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t,
-                     (int)(P->n_out == 7), P->Gv, P->Gt_part, P->gW_part);
+                     (int)(P->n_out == 7), P->b16_nvb, P->b16_nch, P->b16_nch > 1 ? P->Gv_part : P->Gv,
+                     P->Gt_part, P->gW_part);
   return hipGetLastError();
 }
 
@@ -1204,7 +1364,34 @@ int64_t npg_wpack_len(int W, int H) { return WPack(W, H).total; }
 int64_t npg_gw_part_len(int W, int H, int n_out) {
   return (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
 }
-size_t npg_decode_fwd_lds(int W, int H) { return sizeof(float) * ((size_t)(H - 1) * W * (W + 4) + 16 * (W + 4) + (H - 1) * W + 16); }
+
+// Work items of the BF16 backward: nvb blocks of 64 vertices times nch frame
+// chunks (balanced split of the T frames, at most 16 frames each), dealt
+// round-robin to grid = min(items, n_cu) work-groups. nch minimizes the
+// largest per-group frame count (fewest chunks on a tie).
+void npg_bf16_schedule(int64_t V, int T, int n_cu, int* nvb, int* nch, int* grid) {
+  const int nb = (int)((V + kB16S - 1) / kB16S);
+  int best_n = (T + kB16TC - 1) / kB16TC;
+  int64_t best = -1;
+  const int n_min = (T + kB16TC - 1) / kB16TC;
+  for (int n = n_min; n <= std::min(T, n_min + 63); ++n) {
+    const int64_t items = (int64_t)nb * n;
+    const int G = (int)std::min<int64_t>(items, n_cu);
+    std::vector<int64_t> load(G, 0);
+    for (int64_t it = 0; it < items; ++it) {
+      const int ch = (int)(it / nb);
+      load[it % G] += (int64_t)T * (ch + 1) / n - (int64_t)T * ch / n;
+    }
+    const int64_t mk = *std::max_element(load.begin(), load.end());
+    if (best < 0 || mk < best) {
+      best = mk;
+      best_n = n;
+    }
+  }
+  *nvb = nb;
+  *nch = best_n;
+  *grid = (int)std::min<int64_t>((int64_t)nb * best_n, n_cu);
+}
 
 hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat,
                                  float4* nhat) {
@@ -1221,14 +1408,18 @@ static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const 
   const float* mlp = params + P->mlp_off;
   float* gmlp = grad + P->mlp_off;
   const int64_t l0 = (int64_t)P->W * P->Din + P->W;
+  const bool bf = is_bf16(P);
   hipLaunchKernelGGL(k_sum_parts, dim3(nblk(P->gw_part_len, 256)), dim3(256), 0, P->stream, P->gW_part,
-                     P->gw_part_len, P->n_vblk_mlp, gmlp + l0);
+                     P->gw_part_len, bf ? P->b16_grid : P->n_vblk_mlp, gmlp + l0);
   hipLaunchKernelGGL(k_gt_reduce, dim3(nblk((int64_t)P->T * P->W, 256)), dim3(256), 0, P->stream, P->Gt_part,
-                     P->T, P->n_vblk_mlp, P->W, P->Gt);
+                     P->T, bf ? P->b16_nvb : P->n_vblk_mlp, P->W, P->Gt);
+  if (bf && P->b16_nch > 1)
+    hipLaunchKernelGGL(k_gv_reduce, dim3(nblk(P->V * P->W, 256)), dim3(256), 0, P->stream, P->Gv_part,
+                       P->V * P->W, P->b16_nch, P->Gv);
   hipLaunchKernelGGL(k_first_layer, dim3(P->W), dim3(256), 0, P->stream, P->Gv, P->Gt, z, P->gam, P->V, P->T,
-                     P->W, P->Din, P->Fz, is_bf16(P), gmlp);
+                     P->W, P->Din, P->Fz, (int)bf, gmlp);
   hipLaunchKernelGGL(k_gz, dim3(nblk(P->V, 128)), dim3(128), 0, P->stream, mlp, P->Gv, P->V, P->W, P->Din,
-                     P->Fz, is_bf16(P), gz);
+                     P->Fz, (int)bf, gz);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 // launchers defined in the other translation units
 int64_t npg_wpack_len(int W, int H);
 int64_t npg_gw_part_len(int W, int H, int n_out);
+void npg_bf16_schedule(int64_t V, int T, int n_cu, int* nvb, int* nch, int* grid);
 int npg_chamfer_vblock();
 npg_status npg_cg_setup(npg_plan* P);
 void npg_cg_free(npg_plan* P);
@@ -130,7 +131,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
   void* bufs[] = {P->xyz, P->nrm, P->pts, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
                   P->seg_chunk0, P->chunk_start, P->chunk_sum, P->chunk_sys, P->params, P->m, P->v, P->grad,
                   P->z, P->gz, P->xhat, P->gxhat, P->a, P->b, P->da, P->db, P->cd, P->w, P->loss, P->colpart,
-                  P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->gam, P->d_flag};
+                  P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->gam, P->d_flag};
   for (void* b : bufs)
     if (b) hipFree(b);
   npg_cg_free(P);
@@ -286,7 +287,13 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->Gv, V * P->W));
   TRYP(dalloc(&P->Gt, (int64_t)T * P->W));
   TRYP(dalloc(&P->Gt_part, (int64_t)T * P->n_vblk_mlp * P->W));
-  TRYP(dalloc(&P->gW_part, (int64_t)P->n_vblk_mlp * P->gw_part_len));
+  int64_t n_parts = P->n_vblk_mlp;
+  if (cfg->precision == NPG_PREC_BF16) {
+    npg_bf16_schedule(V, T, P->n_cu, &P->b16_nvb, &P->b16_nch, &P->b16_grid);
+    n_parts = std::max<int64_t>(n_parts, P->b16_grid);
+    if (P->b16_nch > 1) TRYP(dalloc(&P->Gv_part, (int64_t)P->b16_nch * V * P->W));
+  }
+  TRYP(dalloc(&P->gW_part, n_parts * P->gw_part_len));
   if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
   else TRYP(npg_cg_setup(P));
   for (auto& e : P->ev) HIPP(hipEventCreate(&e));
