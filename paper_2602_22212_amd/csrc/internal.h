@@ -93,6 +93,7 @@ struct npg_plan {
   // round-robin to a persistent grid; per-chunk vertex sums in Gv_part
   int b16_nvb, b16_nch, b16_grid;
   float* Gv_part;          // [b16_nch][V][W] (NULL when b16_nch == 1)
+  float* fl_part;          // [ceil(V/256)][W][8] first-layer partial sums
   // preconditioner workspaces
   NpgCG cg;
   NpgDct* dct;

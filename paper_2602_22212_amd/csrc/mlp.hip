@@ -1192,73 +1192,130 @@ __global__ void k_gv_reduce(const float* __restrict__ part, int64_t n, int nch, 
   Gv[e] = s;
 }
 
-// Sum the per-work-group partials in work-group order.
-__global__ void k_sum_parts(const float* __restrict__ part, int64_t len, int nparts, float* __restrict__ dst) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= len) return;
-  float s = 0.f;
-  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * len + e];
-  dst[e] = s;
+// Fixed-order sums of partials: in a block of kRG x kRE threads, thread
+// (g, e) adds the parts p = g, g + kRG, ... of entry e in order, then the kRG
+// group sums are added in g order. Reads are coalesced over e.
+constexpr int kRG = 16;
+constexpr int kRE = 64;
+
+// dst[e] = sum over p of part[p * len + e]
+__global__ __launch_bounds__(kRG * kRE) void k_sum_parts(const float* __restrict__ part, int64_t len, int nparts,
+                                                         float* __restrict__ dst) {
+  __shared__ float red[kRG][kRE + 1];
+  const int el = threadIdx.x % kRE, g = threadIdx.x / kRE;
+  const int64_t e = blockIdx.x * (int64_t)kRE + el;
+  float s0 = 0.f;
+  if (e < len)
+    for (int p = g; p < nparts; p += kRG) s0 += part[(int64_t)p * len + e];
+  red[g][el] = s0;
+  __syncthreads();
+  if (g == 0 && e < len) {
+    float t = 0.f;
+    for (int k = 0; k < kRG; ++k) t += red[k][el];
+    dst[e] = t;
+  }
 }
 
-// First layer: gW1 z-part = sum_i Gv[i] z_i^T, gamma part = sum_t Gt[t] gamma_t^T,
-// gb1 = sum_t Gt[t]. One block per output unit, fixed-order tree reductions.
-__global__ void k_first_layer(const float* __restrict__ Gv, const float* __restrict__ Gt,
-                              const float* __restrict__ z, const float* __restrict__ gam, int64_t V, int T, int W,
-                              int Din, int Fz, int bf16, float* __restrict__ g1) {
+// Gt[t][o] = sum over work-groups p of Gt_part[t][p][o]
+__global__ __launch_bounds__(kRG * kRE) void k_gt_reduce(const float* __restrict__ part, int T, int nwg, int W,
+                                                         float* __restrict__ Gt) {
+  __shared__ float red[kRG][kRE + 1];
+  const int el = threadIdx.x % kRE, g = threadIdx.x / kRE;
+  const int64_t e = blockIdx.x * (int64_t)kRE + el;
+  const bool ok = e < (int64_t)T * W;
+  float s0 = 0.f;
+  if (ok) {
+    const int64_t t = e / W, o = e % W;
+    for (int p = g; p < nwg; p += kRG) s0 += part[(t * nwg + p) * W + o];
+  }
+  red[g][el] = s0;
+  __syncthreads();
+  if (g == 0 && ok) {
+    float t = 0.f;
+    for (int k = 0; k < kRG; ++k) t += red[k][el];
+    Gt[e] = t;
+  }
+}
+
+// First layer, z part, stage 1: per block of kFLV vertices and per output
+// unit o, sum_i Gv[i][o] z_i[k] (k < Fz), in fixed order (vertex sub-streams
+// of the block, then their sums in order). part [block][W][8].
+constexpr int kFLV = 256;
+__global__ __launch_bounds__(256) void k_first_layer_z(const float* __restrict__ Gv, const float* __restrict__ z,
+                                                       int64_t V, int W, int Fz, int bf16,
+                                                       float* __restrict__ part) {
   __shared__ float red[256][9];
-  const int o = blockIdx.x;
-  const int Dt = Din - Fz;
-  float acc[9];
-  for (int k = 0; k < 9; ++k) acc[k] = 0.f;
-  for (int64_t i = threadIdx.x; i < V; i += 256) {
-    float gv = Gv[i * W + o];
+  const int o = threadIdx.x % W, sub = threadIdx.x / W, nsub = 256 / W;
+  const int64_t i0 = (int64_t)blockIdx.x * kFLV;
+  const int64_t i1 = i0 + kFLV < V ? i0 + kFLV : V;
+  float acc[8];
+  for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+  for (int64_t i = i0 + sub; i < i1; i += nsub) {
+    const float gv = Gv[i * W + o];
     for (int k = 0; k < Fz; ++k) acc[k] = fmaf(gv, rnd(z[i * Fz + k], bf16), acc[k]);
   }
-  for (int k = 0; k < 9; ++k) red[threadIdx.x][k] = acc[k];
+  for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  if (sub == 0) {
+    for (int k = 0; k < Fz; ++k) {
+      float t = 0.f;
+      for (int u = 0; u < nsub; ++u) t += red[u * W + o][k];
+      part[((int64_t)blockIdx.x * W + o) * 8 + k] = t;
+    }
+  }
+}
+
+// First layer, stage 2 (one block per output unit o): gW1 z part = sum over
+// blocks of the stage-1 partials; gamma part = sum_t Gt[t][o] gamma_t;
+// gb1[o] = sum_t Gt[t][o]. Fixed-order tree reductions.
+__global__ __launch_bounds__(256) void k_first_layer(const float* __restrict__ part, int nb,
+                                                     const float* __restrict__ Gt, const float* __restrict__ gam,
+                                                     int T, int W, int Din, int Fz, int bf16,
+                                                     float* __restrict__ g1) {
+  constexpr int kN = 8 + 16 + 1;  // z part, gamma part, bias
+  __shared__ float red[256][kN];
+  const int o = blockIdx.x;
+  const int Dt = Din - Fz;
+  float acc[kN];
+  for (int k = 0; k < kN; ++k) acc[k] = 0.f;
+  for (int b = threadIdx.x; b < nb; b += 256)
+    for (int k = 0; k < Fz; ++k) acc[k] += part[((int64_t)b * W + o) * 8 + k];
+  for (int t = threadIdx.x; t < T; t += 256) {
+    const float v = Gt[(int64_t)t * W + o];
+    acc[8 + 16] += v;
+    for (int k = 0; k < Dt; ++k) acc[8 + k] = fmaf(v, rnd(gam[(int64_t)t * Dt + k], bf16), acc[8 + k]);
+  }
+  for (int k = 0; k < kN; ++k) red[threadIdx.x][k] = acc[k];
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
-      for (int k = 0; k < 9; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
+      for (int k = 0; k < kN; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     for (int k = 0; k < Fz; ++k) g1[(int64_t)o * Din + k] = red[0][k];
-    float gb = 0.f;
-    float gg[16];
-    for (int k = 0; k < Dt; ++k) gg[k] = 0.f;
-    for (int t = 0; t < T; ++t) {
-      float v = Gt[(int64_t)t * W + o];
-      gb += v;
-      for (int k = 0; k < Dt; ++k) gg[k] = fmaf(v, rnd(gam[(int64_t)t * Dt + k], bf16), gg[k]);
-    }
-    for (int k = 0; k < Dt; ++k) g1[(int64_t)o * Din + Fz + k] = gg[k];
-    g1[(int64_t)W * Din + o] = gb;
+    for (int k = 0; k < Dt; ++k) g1[(int64_t)o * Din + Fz + k] = red[0][8 + k];
+    g1[(int64_t)W * Din + o] = red[0][8 + 16];
   }
 }
 
-// Gt[t][o] = sum over work-groups of Gt_part[t][wg][o]
-__global__ void k_gt_reduce(const float* __restrict__ part, int T, int nwg, int W, float* __restrict__ Gt) {
-  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)T * W) return;
-  int64_t t = e / W, o = e % W;
-  float s = 0.f;
-  for (int p = 0; p < nwg; ++p) s += part[(t * nwg + p) * W + o];
-  Gt[e] = s;
-}
-
-// gz[i][k] = sum_o W1[o][k] Gv[i][o], k < Fz
-__global__ void k_gz(const float* __restrict__ mlp, const float* __restrict__ Gv, int64_t V, int W, int Din,
-                     int Fz, int bf16, float* __restrict__ gz) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= V) return;
+// gz[i][k] = sum_o W1[o][k] Gv[i][o], k < Fz: one wave per vertex, lanes over
+// o, then a fixed butterfly over the wave
+__global__ __launch_bounds__(256) void k_gz(const float* __restrict__ mlp, const float* __restrict__ Gv, int64_t V,
+                                            int W, int Din, int Fz, int bf16, float* __restrict__ gz) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= V) return;  // uniform over the wave; no barriers below
   float acc[8];
   for (int k = 0; k < 8; ++k) acc[k] = 0.f;
-  for (int o = 0; o < W; ++o) {
-    float gv = Gv[i * W + o];
+  for (int o = lane; o < W; o += 64) {
+    const float gv = Gv[i * W + o];
     for (int k = 0; k < Fz; ++k) acc[k] = fmaf(rnd(mlp[(int64_t)o * Din + k], bf16), gv, acc[k]);
   }
-  for (int k = 0; k < Fz; ++k) gz[i * Fz + k] = acc[k];
+  for (int k = 0; k < 8; ++k)
+    for (int m = 32; m > 0; m >>= 1) acc[k] += __shfl_xor(acc[k], m);
+  if (lane == 0)
+    for (int k = 0; k < Fz; ++k) gz[i * Fz + k] = acc[k];
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -1409,17 +1466,21 @@ static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const 
   float* gmlp = grad + P->mlp_off;
   const int64_t l0 = (int64_t)P->W * P->Din + P->W;
   const bool bf = is_bf16(P);
-  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(P->gw_part_len, 256)), dim3(256), 0, P->stream, P->gW_part,
+  const int64_t TW = (int64_t)P->T * P->W;
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(P->gw_part_len, kRE)), dim3(kRG * kRE), 0, P->stream, P->gW_part,
                      P->gw_part_len, bf ? P->b16_grid : P->n_vblk_mlp, gmlp + l0);
-  hipLaunchKernelGGL(k_gt_reduce, dim3(nblk((int64_t)P->T * P->W, 256)), dim3(256), 0, P->stream, P->Gt_part,
-                     P->T, bf ? P->b16_nvb : P->n_vblk_mlp, P->W, P->Gt);
+  hipLaunchKernelGGL(k_gt_reduce, dim3(nblk(TW, kRE)), dim3(kRG * kRE), 0, P->stream, P->Gt_part, P->T,
+                     bf ? P->b16_nvb : P->n_vblk_mlp, P->W, P->Gt);
   if (bf && P->b16_nch > 1)
     hipLaunchKernelGGL(k_gv_reduce, dim3(nblk(P->V * P->W, 256)), dim3(256), 0, P->stream, P->Gv_part,
                        P->V * P->W, P->b16_nch, P->Gv);
-  hipLaunchKernelGGL(k_first_layer, dim3(P->W), dim3(256), 0, P->stream, P->Gv, P->Gt, z, P->gam, P->V, P->T,
+  const int nb = (int)nblk(P->V, kFLV);
+  hipLaunchKernelGGL(k_first_layer_z, dim3(nb), dim3(256), 0, P->stream, P->Gv, z, P->V, P->W, P->Fz, (int)bf,
+                     P->fl_part);
+  hipLaunchKernelGGL(k_first_layer, dim3(P->W), dim3(256), 0, P->stream, P->fl_part, nb, P->Gt, P->gam, P->T,
                      P->W, P->Din, P->Fz, (int)bf, gmlp);
-  hipLaunchKernelGGL(k_gz, dim3(nblk(P->V, 128)), dim3(128), 0, P->stream, mlp, P->Gv, P->V, P->W, P->Din,
-                     P->Fz, (int)bf, gz);
+  hipLaunchKernelGGL(k_gz, dim3(nblk(P->V, 4)), dim3(256), 0, P->stream, mlp, P->Gv, P->V, P->W, P->Din, P->Fz,
+                     (int)bf, gz);
   return hipGetLastError();
 }
 

@@ -131,7 +131,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
   void* bufs[] = {P->xyz, P->nrm, P->pts, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
                   P->seg_chunk0, P->chunk_start, P->chunk_sum, P->chunk_sys, P->params, P->m, P->v, P->grad,
                   P->z, P->gz, P->xhat, P->gxhat, P->a, P->b, P->da, P->db, P->cd, P->w, P->loss, P->colpart,
-                  P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->gam, P->d_flag};
+                  P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->fl_part, P->gam, P->d_flag};
   for (void* b : bufs)
     if (b) hipFree(b);
   npg_cg_free(P);
@@ -294,6 +294,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
     if (P->b16_nch > 1) TRYP(dalloc(&P->Gv_part, (int64_t)P->b16_nch * V * P->W));
   }
   TRYP(dalloc(&P->gW_part, n_parts * P->gw_part_len));
+  TRYP(dalloc(&P->fl_part, ((V + 255) / 256) * P->W * 8));
   if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
   else TRYP(npg_cg_setup(P));
   for (auto& e : P->ev) HIPP(hipEventCreate(&e));
