@@ -35,28 +35,47 @@ __device__ __forceinline__ float dist2(float4 x, float4 p) {
 __device__ __forceinline__ float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
 
 // Minimum over the 64 lanes with DPP moves; lane 63 ends with the result.
+// Distances are non-negative finite floats (+0 included, never -0), whose
+// bit patterns order like unsigned integers, so the reduction runs on the
+// bits (an integer minimum folds into the DPP move; identity 0xffffffff).
 // Within rows of 16: quad xor 1, quad xor 2, half-row mirror, row mirror;
 // then row 15 -> rows 1, 3 and row 31 -> rows 2, 3 broadcasts.
-__device__ __forceinline__ float wave_min_to_lane63(float v) {
-  const int inf = __float_as_int(INFINITY);
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0xB1, 0xF, 0xF, false)));
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x4E, 0xF, 0xF, false)));
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x141, 0xF, 0xF, false)));
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x140, 0xF, 0xF, false)));
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x142, 0xA, 0xF, false)));
-  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(inf, __float_as_int(v), 0x143, 0xC, 0xF, false)));
-  return v;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t umin_dpp(uint32_t v) {
+  return min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xffffffffu, (int)v, CTRL, ROWS, 0xF, false));
+}
+// two independent reductions stage by stage (no wait between dependent DPP steps)
+__device__ __forceinline__ void wave_min2_to_lane63(uint32_t& a, uint32_t& b) {
+  a = umin_dpp<0xB1, 0xF>(a);
+  b = umin_dpp<0xB1, 0xF>(b);
+  a = umin_dpp<0x4E, 0xF>(a);
+  b = umin_dpp<0x4E, 0xF>(b);
+  a = umin_dpp<0x141, 0xF>(a);
+  b = umin_dpp<0x141, 0xF>(b);
+  a = umin_dpp<0x140, 0xF>(a);
+  b = umin_dpp<0x140, 0xF>(b);
+  a = umin_dpp<0x142, 0xA>(a);
+  b = umin_dpp<0x142, 0xA>(b);
+  a = umin_dpp<0x143, 0xC>(a);
+  b = umin_dpp<0x143, 0xC>(b);
 }
 
-// Column record of one point: (distance bits << 32) | first vertex of the
-// lowest lane attaining the wave minimum; an LDS 64-bit atomic min keeps the
-// smallest distance and, among equal ones, the lowest vertex range.
-__device__ __forceinline__ void column_record(float m, unsigned long long* slot, uint32_t lane_v0) {
-  const float wm = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_min_to_lane63(m)), 63));
-  const unsigned long long hit = __ballot(m == wm);
-  const int first = __builtin_ctzll(hit);
-  if ((int)(threadIdx.x & 63) == first)
-    atomicMin(slot, ((unsigned long long)__float_as_uint(wm) << 32) | (unsigned long long)lane_v0);
+// Column records of two points (the second only when has1): per point
+// (distance bits << 32) | first vertex of the lowest lane attaining the wave
+// minimum; an LDS 64-bit atomic min keeps the smallest distance and, among
+// equal ones, the lowest vertex range.
+__device__ __forceinline__ void column_record2(float m0, float m1, unsigned long long* slot, bool has1,
+                                               uint32_t lane_v0) {
+  const uint32_t b0 = __float_as_uint(m0), b1 = __float_as_uint(m1);
+  uint32_t r0 = b0, r1 = b1;
+  wave_min2_to_lane63(r0, r1);
+  const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)r0, 63);
+  const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)r1, 63);
+  const int lane = (int)(threadIdx.x & 63);
+  const int f0 = __builtin_ctzll(__ballot(b0 == w0));
+  const int f1 = __builtin_ctzll(__ballot(b1 == w1));
+  if (lane == f0) atomicMin(slot, ((unsigned long long)w0 << 32) | (unsigned long long)lane_v0);
+  if (has1 && lane == f1) atomicMin(slot + 1, ((unsigned long long)w1 << 32) | (unsigned long long)lane_v0);
 }
 
 // Vertices of a lane are contiguous: thread th of block vb owns
@@ -107,8 +126,7 @@ __global__ __launch_bounds__(kT) void k_chamfer_main(const float4* __restrict__ 
         m0 = min3f(m0, d00, d10);
         m1 = min3f(m1, d01, d11);
       }
-      column_record(m0, &cm[j], lane_v0);
-      if (j + 1 < cnt) column_record(m1, &cm[j + 1], lane_v0);
+      column_record2(m0, m1, &cm[j], j + 1 < cnt, lane_v0);
     }
 #pragma unroll
     for (int k = 0; k < kK; ++k)
