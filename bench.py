@@ -50,13 +50,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,dct,quat,iso,metrics,bf16,batch",
+    ap.add_argument("--forms", default="cg,dct,quat,iso,metrics,bf16,batch,animal",
                     help="forms to time: cg (headline), dct (exact DCT preconditioner), "
                          "quat (quaternion rotation head, DCT preconditioner), "
                          "iso (isometry loss w_iso = 100 on a 6-NN edge graph, DCT preconditioner), "
                          "metrics (inference export + evaluation metrics on ground truth), "
                          "bf16 (BF16 MLP form: CG steps/s and time-to-target against FP32), "
-                         "batch (16 independent sequences stepped together)")
+                         "batch (16 independent sequences stepped together, BF16 and FP32), "
+                         "animal (quadruped workload: 50000 vertices, 1000 frames, CG)")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the 100-step BF16/FP32 quality comparison (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -184,6 +185,7 @@ def run_form(cfg, data, P0, steps, warmup, profile):
     import paper_2602_22212_amd as npg
     plan = npg.plan_from_workload(cfg, data)
     plan.set_state(torch.from_numpy(npg.pack_params(cfg, P0)).cuda(), adam_steps=0)
+    nn_threads, nn_ms = plan.tune_nn(0)  # autotuned nearest-neighbour work-group size
     E = cfg["n_steps"]
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     for e in range(warmup):
@@ -208,7 +210,8 @@ def run_form(cfg, data, P0, steps, warmup, profile):
     plan.close()
     return dict(value=steps / t_total, ms_per_step=1e3 * t_total / steps,
                 stage_ms={k: round(v / steps, 3) for k, v in stage_sum.items()},
-                status=sorted(set(int(s) for s in statuses)), prof=prof, loss=loss.item())
+                status=sorted(set(int(s) for s in statuses)), prof=prof, loss=loss.item(),
+                nn_tune={"threads": nn_threads, "ms_64_128_256": [round(m, 3) for m in nn_ms]})
 
 
 def run_metrics(cfg, P0, reps=3):
@@ -290,41 +293,104 @@ def run_quality(cfg, steps=100):
     return res
 
 
-def run_batch(steps=2, warmup=1):
-    """Batched sequences (16 independent sequences, survey config 5): one
-    npg_batch_step advances every sequence by one step, concurrently."""
-    import numpy as np
+def _batch_time(cfgs, datas, steps, warmup, state):
     import torch
 
     import paper_2602_22212_amd as npg
+    import synth
+    batch = npg.Batch(cfgs, datas)
+    tuned = []
+    for k, (c, p) in enumerate(zip(cfgs, batch.plans)):
+        P = synth.random_state(c, 900 + k, grid_std=0.05) if state == "random" else synth.init_params(c)
+        p.set_state(torch.from_numpy(npg.pack_params(c, P)).cuda(), adam_steps=0)
+        tuned.append(p.tune_nn(0)[0])
+    for e in range(warmup):
+        batch.step(e, max(steps + warmup, 500))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(steps):
+        batch.step(warmup + e, max(steps + warmup, 500))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    final = [plan_cd(p) for p in batch.plans]
+    batch.close()
+    return dt, final, tuned
+
+
+def plan_cd(plan):
+    """Mean per-frame Chamfer distance at the plan's current parameters
+    (the library's forward stages and float64 frame sums)."""
+    import torch
+    f = dict(device="cuda")
+    params = plan.get_state()[0]
+    z = torch.empty(plan.V * plan.Fz, **f)
+    xh = torch.empty(plan.T * plan.V * 4, **f)
+    plan.encode_fwd(params, z)
+    plan.decode_fwd(params, z, xh)
+    a = torch.empty(plan.T * plan.V, dtype=torch.int32, **f)
+    da = torch.empty(plan.T * plan.V, **f)
+    b = torch.empty(plan.Ntot, dtype=torch.int32, **f)
+    db = torch.empty(plan.Ntot, **f)
+    cd = torch.empty(plan.T, dtype=torch.float64, **f)
+    plan.chamfer_fwd(xh, a, da, b, db, cd)
+    torch.cuda.synchronize()  # the plan's stream may differ from torch's
+    return float(cd.mean().item())
+
+
+def run_batch(steps=2, warmup=1, quality_steps=20):
+    """Batched sequences (16 independent sequences, survey config 5): one
+    npg_batch_step advances every sequence by one step, concurrently; the
+    BF16 form (default of the batch configs) and the FP32 form on the same
+    sequences, and both forms from the identity start for quality_steps
+    steps (DCT preconditioner) to compare their final Chamfer distances."""
+    import numpy as np
+
     import synth
     cfgs = synth.config_c5()
     t0 = time.perf_counter()
     datas = [synth.make_workload(c) for c in cfgs]
     t_gen = time.perf_counter() - t0
-    batch = npg.Batch(cfgs, datas)
-    for k, (c, p) in enumerate(zip(cfgs, batch.plans)):
-        p.set_state(torch.from_numpy(npg.pack_params(c, synth.random_state(c, 900 + k, grid_std=0.05))).cuda(),
-                    adam_steps=0)
-    for e in range(warmup):
-        batch.step(e, 500)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e in range(steps):
-        batch.step(warmup + e, 500)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    batch.close()
+    res = {}
+    for prec in ("bf16", "fp32"):
+        cs = [dict(c, precision=prec) for c in cfgs]
+        dt, _, tuned = _batch_time(cs, datas, steps, warmup, "random")
+        dq, final, _ = _batch_time([dict(c, precond="dct") for c in cs], datas, quality_steps, 0, "init")
+        res[prec] = dict(dt=dt, dq=dq, final=final, tuned=tuned)
     pairs = sum(len(d["xyz"]) * int(d["frame_off"][-1]) for d in datas)
     samples = sum(len(d["xyz"]) * d["T"] for d in datas)
-    return {"value": round(1.0 / dt, 4), "unit": "batch steps/s", "ms_per_step": round(1e3 * dt, 2),
+    b, f = res["bf16"], res["fp32"]
+    ratio = float(np.mean(np.array(b["final"]) / np.array(f["final"])))
+    return {"value": round(1.0 / b["dt"], 4), "unit": "batch steps/s", "ms_per_step": round(1e3 * b["dt"], 2),
+            "fp32": {"value": round(1.0 / f["dt"], 4), "ms_per_step": round(1e3 * f["dt"], 2)},
+            "bf16_over_fp32_steps_per_s": round(f["dt"] / b["dt"], 4),
+            "quality": {"steps": quality_steps, "preconditioner": "dct", "start": "identity (the paper's init)",
+                        "bf16_ms_per_step": round(1e3 * b["dq"], 2), "fp32_ms_per_step": round(1e3 * f["dq"], 2),
+                        "bf16_final_cd_mean": float(np.mean(b["final"])), "fp32_final_cd_mean": float(np.mean(f["final"])),
+                        "mean_ratio_bf16_over_fp32_final_cd": round(ratio, 5),
+                        "note": "mean per-frame Chamfer distance of each sequence after the last step, averaged"},
+            "nn_autotune_threads": res["bf16"]["tuned"],
             "sequences": len(cfgs), "steps": steps, "warmup": warmup,
             "samples_per_step": samples, "chamfer_pairs_per_direction": pairs,
             "sequence_shapes": [(len(d["xyz"]), d["T"], int(d["frame_off"][-1])) for d in datas],
             "note": ("16 sequences (V ~ U[5k,60k], T ~ U[20,400], N_t ~ U[4k,16k] per frame; human and quadruped "
-                     "alternating), each with its own 8-level grids and 14->128x3->6 MLP in the BF16 form, CG "
-                     "preconditioner; one batch step = one step of every sequence, run concurrently on per-"
-                     f"sequence streams; inputs generated in {t_gen:.0f} s and resident before timing")}
+                     "alternating), each with its own 8-level grids and 14->128x3->6 MLP; value: the BF16 form, "
+                     "CG preconditioner, seeded non-degenerate state; one batch step = one step of every "
+                     "sequence, run concurrently on per-sequence streams; inputs generated in "
+                     f"{t_gen:.0f} s and resident before timing")}
+
+
+def run_animal(steps=2, warmup=1):
+    """The quadruped (animal-shaped) workload: 50 000 vertices, 1000 frames,
+    ~7600 points per frame (5 % dropped), CG preconditioner, FP32."""
+    import synth
+    cfg = dict(synth.config_c3(), precond="cg")
+    data = synth.make_workload(cfg)
+    r = run_form(cfg, data, synth.random_state(cfg, 9, grid_std=0.05), steps, warmup, profile=False)
+    return {"value": round(r["value"], 4), "unit": "steps/s", "ms_per_step": round(r["ms_per_step"], 2),
+            "steps": steps, "warmup": warmup, "stage_ms": r["stage_ms"],
+            "stage_roofline": stage_roofline(cfg, data, r["stage_ms"], "f32"),
+            "workload": f"quadruped_v{len(data['xyz'])}_t{data['T']}_n{int(data['frame_off'][-1])}",
+            "note": "13-capsule quadruped, 8-level grids 16..256 x 4, 14->128x3->6 MLP, float32, CG"}
 
 
 def main():
@@ -383,6 +449,7 @@ def main():
                           f"{cfg['mlp_hidden']}->6", "precond": "cg", "cg_rtol": cfg["cg_rtol"],
                    "parallelism": "single-gpu"},
         "stage_ms": cg["stage_ms"],
+        "nn_autotune": cg["nn_tune"],
         "stage_roofline": stage_roofline(cfg, data, cg["stage_ms"], "f32", prof),
         "paper_context": PAPER_CONTEXT,
         "cg_iterations_per_step": round(prof["cg_iters"] / args.steps, 1),
@@ -413,6 +480,8 @@ def main():
                        "quality": None if args.no_quality else run_quality(cfg)}
     if "batch" in forms:
         out["batch"] = run_batch()
+    if "animal" in forms:
+        out["animal"] = run_animal()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(cfg, data, P0, args.cpu_frames)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}

@@ -325,6 +325,20 @@ npg_status npg_iso(npg_plan* plan, const float* xhat_dev, float* gxhat_dev, doub
                    int8_t* sign_dev);
 
 /*
+ * Autotuner of the nearest-neighbour main pass (npg_chamfer_fwd, the
+ * metrics and every step): its work-group size, 64, 128 (the default) or 256
+ * threads of 16 vertices each. threads = 0 times the three candidates on the
+ * plan's current deformed vertices and point sets (one warm-up and two timed
+ * calls each, HIP events on the plan's stream) and keeps the fastest;
+ * threads = 64, 128 or 256 sets it without timing. chosen_host [1] (may be
+ * NULL) receives the work-group size in use; ms_host [3] (may be NULL) the
+ * measured milliseconds per call for 64, 128, 256 (0 when not timed). Indices,
+ * distances and sums do not depend on the choice (bitwise). Synchronizes the
+ * plan's stream. NPG_EINVAL for other values of threads.
+ */
+npg_status npg_tune_nn(npg_plan* plan, int32_t threads, int32_t* chosen_host, float* ms_host);
+
+/*
  * Chain rule for reverse-mode callers (torch.autograd Functions built on the
  * stage entry points above): x_dev[k] *= c * s_dev[0] for 0 <= k < n, the
  * factor formed in float64 on the device (s_dev: one float64, typically the

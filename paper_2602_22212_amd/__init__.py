@@ -78,6 +78,7 @@ _SIGS = {
     "npg_batch_destroy": ([_P], ctypes.c_int),
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_scale": ([_P, _P, _D, _P, _I32, _I64], ctypes.c_int),
+    "npg_tune_nn": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "npg_profile": ([_P, _I32], ctypes.c_int),
     "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
 }
@@ -371,6 +372,14 @@ class Plan:
         _check(lib().npg_adam(self._h, _ptr(params, f, n, "params"), _ptr(grad, f, n, "grad"),
                               _ptr(m, f, n, "m"), _ptr(v, f, n, "v"), int(adam_step)))
 
+
+    def tune_nn(self, threads=0):
+        """Work-group size of the nearest-neighbour pass: 0 = time 64/128/256
+        on the current state and keep the fastest. Returns (chosen, ms [3])."""
+        ch = _I32()
+        ms = (ctypes.c_float * 3)()
+        _check(lib().npg_tune_nn(self._h, int(threads), ctypes.byref(ch), ms))
+        return ch.value, list(ms)
 
     def scale(self, s, x, c=1.0):
         """x *= c * s[0] on the device (s: one float64; x: float32 or float64)."""

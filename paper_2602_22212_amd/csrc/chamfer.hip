@@ -7,7 +7,7 @@
 // the argmin recovered in a second pass is the one the first pass saw.
 // Ties resolve to the lowest index in both directions.
 //
-// Main pass, per (frame, block of kT*kK vertices): each thread keeps kK
+// Main pass, per (frame, block of KT*kK vertices): each thread keeps kK
 // vertices in registers and streams the frame's points through LDS tiles, two
 // points per iteration. The inner loop tracks values only (min3 updates): the
 // running row minimum per vertex and, per point, the minimum over the
@@ -23,9 +23,9 @@
 namespace {
 
 constexpr int kK = 16;     // vertices per thread
-constexpr int kT = 128;    // threads per work-group
 constexpr int kPT = 256;   // points per LDS tile
-constexpr int kVB = kT * kK;
+// work-group size KT of the main pass: 64, 128 (default) or 256 threads, the
+// plan's choice (npg_tune_nn); results do not depend on it
 
 __device__ __forceinline__ float dist2(float4 x, float4 p) {
   float dx = x.x - p.x, dy = x.y - p.y, dz = x.z - p.z;
@@ -79,9 +79,10 @@ __device__ __forceinline__ void column_record2(float m0, float m1, unsigned long
 }
 
 // Vertices of a lane are contiguous: thread th of block vb owns
-// vb*kVB + th*kK + k, k < kK, so the lowest lane attaining a column minimum
+// vb*KT*kK + th*kK + k, k < kK, so the lowest lane attaining a column minimum
 // holds the lowest vertex index attaining it.
-__global__ __launch_bounds__(kT) void k_chamfer_main(const float4* __restrict__ xhat, const float4* __restrict__ pts,
+template <int KT>
+__global__ __launch_bounds__(KT) void k_chamfer_main(const float4* __restrict__ xhat, const float4* __restrict__ pts,
                                                      const int64_t* __restrict__ off, int64_t V, int nvb,
                                                      int64_t Nmax, int32_t* __restrict__ a, float* __restrict__ da,
                                                      unsigned long long* __restrict__ colpart) {
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(kT) void k_chamfer_main(const float4* __restrict__ 
   const int t = blockIdx.y, vb = blockIdx.x;
   const int64_t p0 = off[t];
   const int Nt = (int)(off[t + 1] - p0);
-  const int64_t vbase = (int64_t)vb * kVB + (int64_t)threadIdx.x * kK;
+  const int64_t vbase = (int64_t)vb * (KT * kK) + (int64_t)threadIdx.x * kK;
   float4 x[kK];
   float best[kK];
   int btile[kK];
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(kT) void k_chamfer_main(const float4* __restrict__ 
   const int ntile = (Nt + kPT - 1) / kPT;
   for (int tile = 0; tile < ntile; ++tile) {
     const int cnt = min(kPT, Nt - tile * kPT);
-    for (int j = threadIdx.x; j < kPT + 2; j += kT) {
+    for (int j = threadIdx.x; j < kPT + 2; j += KT) {
       // padding points sit far away: they never win a row minimum
       sp[j] = j < cnt ? pts[p0 + (int64_t)tile * kPT + j] : make_float4(3e18f, 3e18f, 3e18f, 0.f);
       if (j < kPT) cm[j] = ~0ull;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(kT) void k_chamfer_main(const float4* __restrict__ 
       }
     __syncthreads();
     unsigned long long* dst = colpart + ((int64_t)t * nvb + vb) * Nmax + (int64_t)tile * kPT;
-    for (int j = threadIdx.x; j < cnt; j += kT) dst[j] = cm[j];
+    for (int j = threadIdx.x; j < cnt; j += KT) dst[j] = cm[j];
     __syncthreads();
   }
   // recover the lowest index attaining the row minimum inside its best tile
@@ -291,7 +292,7 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-int npg_chamfer_vblock() { return kVB; }
+int npg_chamfer_vblock(int threads) { return threads * kK; }
 
 // Both nearest-neighbour directions between the plan's per-frame vertices and
 // any per-frame point set (frame t owns points off[t] .. off[t+1]-1, at most
@@ -299,8 +300,20 @@ int npg_chamfer_vblock() { return kVB; }
 hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pts, const int64_t* off,
                          const int* pt_frame, int64_t Ntot, int64_t Nmax, void* colpart, int32_t* a, float* da,
                          int32_t* b, float* db) {
-  hipLaunchKernelGGL(k_chamfer_main, dim3(P->nvb, P->T), dim3(kT), 0, P->stream, xhat, pts, off, P->V, P->nvb,
-                     Nmax, a, da, reinterpret_cast<unsigned long long*>(colpart));
+  unsigned long long* cp = reinterpret_cast<unsigned long long*>(colpart);
+  switch (P->nn_threads) {
+    case 64:
+      hipLaunchKernelGGL(k_chamfer_main<64>, dim3(P->nvb, P->T), dim3(64), 0, P->stream, xhat, pts, off, P->V,
+                         P->nvb, Nmax, a, da, cp);
+      break;
+    case 256:
+      hipLaunchKernelGGL(k_chamfer_main<256>, dim3(P->nvb, P->T), dim3(256), 0, P->stream, xhat, pts, off, P->V,
+                         P->nvb, Nmax, a, da, cp);
+      break;
+    default:
+      hipLaunchKernelGGL(k_chamfer_main<128>, dim3(P->nvb, P->T), dim3(128), 0, P->stream, xhat, pts, off, P->V,
+                         P->nvb, Nmax, a, da, cp);
+  }
   hipLaunchKernelGGL(k_chamfer_cols, dim3(nblk(Ntot, 256)), dim3(256), 0, P->stream, xhat, pts, off, pt_frame, Ntot,
                      P->V, P->nvb, Nmax, reinterpret_cast<const unsigned long long*>(colpart), b, db);
   return hipGetLastError();

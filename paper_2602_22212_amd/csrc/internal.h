@@ -77,7 +77,9 @@ struct npg_plan {
   float *da, *db;
   double *cd, *w, *loss;
   // chamfer workspace
-  int nvb;                 // vertex blocks per frame
+  int nvb;                 // vertex blocks per frame of the NN main pass
+  int nn_threads;          // its work-group size (64, 128, 256; npg_tune_nn)
+  int nvb_max;             // vertex blocks at 64 threads (colpart sizing)
   float* colpart;          // [T][nvb][Nmax] 64-bit column records (2 floats each)
   int64_t Nmax;
   long long* acc;          // [T][V][3] fixed-point accumulators

@@ -13,7 +13,7 @@
 int64_t npg_wpack_len(int W, int H);
 int64_t npg_gw_part_len(int W, int H, int n_out);
 void npg_bf16_schedule(int64_t V, int T, int n_cu, int* nvb, int* nch, int* grid);
-int npg_chamfer_vblock();
+int npg_chamfer_vblock(int threads);
 npg_status npg_cg_setup(npg_plan* P);
 void npg_cg_free(npg_plan* P);
 
@@ -273,9 +273,10 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->cd, T));
   TRYP(dalloc(&P->w, T));
   TRYP(dalloc(&P->loss, 1));
-  const int VB = npg_chamfer_vblock();
-  P->nvb = (int)((V + VB - 1) / VB);
-  TRYP(dalloc(&P->colpart, 2 * (int64_t)T * P->nvb * Nmax));
+  P->nn_threads = 128;
+  P->nvb = (int)((V + npg_chamfer_vblock(128) - 1) / npg_chamfer_vblock(128));
+  P->nvb_max = (int)((V + npg_chamfer_vblock(64) - 1) / npg_chamfer_vblock(64));
+  TRYP(dalloc(&P->colpart, 2 * (int64_t)T * P->nvb_max * Nmax));
   TRYP(dalloc(&P->acc, 3 * TV));
   TRYP(dalloc(&P->mlpA, V * P->W));
   TRYP(dalloc(&P->mlpB, (int64_t)T * P->W));
@@ -515,6 +516,51 @@ npg_status npg_deform(npg_plan* P, float* out) {
   const int64_t n = (int64_t)P->T * P->V;
   hipLaunchKernelGGL(k_unpack_xyz, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P->stream, P->xhat, out, n);
   NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
+
+npg_status npg_tune_nn(npg_plan* P, int32_t threads, int32_t* chosen, float* ms) {
+  CHECK_ARG(P, "plan is NULL");
+  CHECK_ARG(threads == 0 || threads == 64 || threads == 128 || threads == 256, "threads must be 0, 64, 128 or 256");
+  auto set = [&](int kt) {
+    P->nn_threads = kt;
+    const int vb = npg_chamfer_vblock(kt);
+    P->nvb = (int)((P->V + vb - 1) / vb);
+  };
+  if (ms)
+    for (int k = 0; k < 3; ++k) ms[k] = 0.f;
+  if (threads != 0) {
+    set(threads);
+  } else {
+    // the current deformed vertices of the plan's parameters
+    NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
+    NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+    const int cand[3] = {64, 128, 256};
+    float best = 0.f;
+    int best_kt = 128;
+    for (int k = 0; k < 3; ++k) {
+      set(cand[k]);
+      NPG_HIP(npg_launch_nn(P, P->xhat, P->pts, P->d_off, P->pt_frame, P->Ntot, P->Nmax, P->colpart, P->a, P->da,
+                            P->b, P->db));  // warm-up
+      NPG_HIP(hipEventRecord(P->ev[0], P->stream));
+      for (int r = 0; r < 2; ++r)
+        NPG_HIP(npg_launch_nn(P, P->xhat, P->pts, P->d_off, P->pt_frame, P->Ntot, P->Nmax, P->colpart, P->a, P->da,
+                              P->b, P->db));
+      NPG_HIP(hipEventRecord(P->ev[1], P->stream));
+      NPG_HIP(hipEventSynchronize(P->ev[1]));
+      float t = 0.f;
+      NPG_HIP(hipEventElapsedTime(&t, P->ev[0], P->ev[1]));
+      t *= 0.5f;
+      if (ms) ms[k] = t;
+      if (k == 0 || t < best) {
+        best = t;
+        best_kt = cand[k];
+      }
+    }
+    set(best_kt);
+  }
+  if (chosen) *chosen = P->nn_threads;
+  NPG_HIP(hipStreamSynchronize(P->stream));
   return NPG_OK;
 }
 
