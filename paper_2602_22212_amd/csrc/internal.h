@@ -91,10 +91,11 @@ struct npg_plan {
   float *Gv, *Gt, *Gt_part, *gW_part;
   int n_vblk_mlp;
   int64_t gw_part_len;
-  // BF16 backward schedule: 128-vertex blocks x frame chunks, items dealt
-  // round-robin to a persistent grid; per-chunk vertex sums in Gv_part
-  int b16_nvb, b16_nch, b16_grid;
-  float* Gv_part;          // [b16_nch][V][W] (NULL when b16_nch == 1)
+  // MLP backward schedule (both precisions): n_vblk_mlp 64-vertex blocks x
+  // mlp_nch frame chunks, items dealt round-robin to mlp_grid persistent
+  // work-groups; per-chunk vertex sums in Gv_part
+  int mlp_nch, mlp_grid;
+  float* Gv_part;          // [mlp_nch][V][W] (NULL when mlp_nch == 1)
   float* fl_part;          // [ceil(V/256)][W][8] first-layer partial sums
   // preconditioner workspaces
   NpgCG cg;

@@ -441,7 +441,7 @@ template <int W, int H>
 __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float4* __restrict__ xyz,
                                                     const float4* __restrict__ gxhat, int64_t V, int T, ActP ap,
-                                                    float alpha, int quat, float* __restrict__ Gv,
+                                                    float alpha, int quat, int nvb, int nch, float* __restrict__ Gv,
                                                     float* __restrict__ Gt_part, float* __restrict__ gW_part) {
   constexpr int NT = W / 16;
   constexpr int NTT = (NT * NT + 3) / 4;  // owned hidden weight-gradient tiles per wave
@@ -454,17 +454,12 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
   const WPack P(W, H);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane >> 4, c = lane & 15;
-  const int64_t vb = blockIdx.x;
-  const int64_t i_raw = vb * 64 + wave * 16 + c;
-  const bool vvalid = i_raw < V;
-  const int64_t i = vvalid ? i_raw : V - 1;
   const int sp = wave * 16 + c;
 
   for (int e = threadIdx.x; e < (H - 1) * W + 16; e += 256) sGb[e] = 0.f;
 
   float4 bo4 = *reinterpret_cast<const float4*>(wp + P.bo + 4 * q);
   const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
-  const float4 xi = xyz[i];
 
   v4f accW[H > 1 ? H - 1 : 1][NTT];
   v4f accO[NTO];
@@ -475,8 +470,6 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
     for (int k = 0; k < NTT; ++k) accW[l][k] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < NTO; ++k) accO[k] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int k = 0; k < NT; ++k) gv[k] = v4f{0.f, 0.f, 0.f, 0.f};
   __syncthreads();
 
   // this lane's element (feature 16*mt + 4q + r, own sample) of a staged row block
@@ -524,129 +517,143 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
     }
   };
 
-  for (int t = 0; t < T; ++t) {
-    // Opaque copies of the weight pointers: keeps the compiler from hoisting
-    // every (loop-invariant) weight load of the frame loop into registers.
-    const float* wpl = wp;
-    asm volatile("" : "+s"(wpl));
-    const float* Wh = wpl + P.wh;
-    const float* WhT = wpl + P.wht;
-    // ---- recompute the forward pass; activations go to LDS ---------------
-    v4f h[NT];
+  // work items (block of 64 vertices, chunk of frames) in a fixed round-robin
+  // order; the weight-gradient accumulators run over all of them
+  const int64_t n_items = (int64_t)nvb * nch;
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int64_t vb = item % nvb;
+    const int ch = (int)(item / nvb);
+    const int t0 = (int)((int64_t)T * ch / nch), t1 = (int)((int64_t)T * (ch + 1) / nch);
+    const int64_t i_raw = vb * 64 + wave * 16 + c;
+    const bool vvalid = i_raw < V;
+    const int64_t i = vvalid ? i_raw : V - 1;
+    const float4 xi = xyz[i];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
-      float4 b = *reinterpret_cast<const float4*>(B + (int64_t)t * W + 16 * mt + 4 * q);
-      h[mt] = v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) at(sH, mt, r) = h[mt][r];
-    }
-#pragma unroll
-    for (int l = 1; l < H; ++l) {
-      v4f o[NT];
+    for (int k = 0; k < NT; ++k) gv[k] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = t0; t < t1; ++t) {
+      // Opaque copies of the weight pointers: keeps the compiler from hoisting
+      // every (loop-invariant) weight load of the frame loop into registers.
+      const float* wpl = wp;
+      asm volatile("" : "+s"(wpl));
+      const float* Wh = wpl + P.wh;
+      const float* WhT = wpl + P.wht;
+      // ---- recompute the forward pass; activations go to LDS ---------------
+      v4f h[NT];
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt) {
-        float4 b = *reinterpret_cast<const float4*>(wpl + P.bh + (l - 1) * W + 16 * mt + 4 * q);
-        o[mt] = v4f{b.x, b.y, b.z, b.w};
+        float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
+        float4 b = *reinterpret_cast<const float4*>(B + (int64_t)t * W + 16 * mt + 4 * q);
+        h[mt] = v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) at(sH, mt, r) = h[mt][r];
       }
-      dense<NT>(h, o, [&](int mt, int kt) {
-        return *reinterpret_cast<const float4*>(Wh + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
+#pragma unroll
+      for (int l = 1; l < H; ++l) {
+        v4f o[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          float4 b = *reinterpret_cast<const float4*>(wpl + P.bh + (l - 1) * W + 16 * mt + 4 * q);
+          o[mt] = v4f{b.x, b.y, b.z, b.w};
+        }
+        dense<NT>(h, o, [&](int mt, int kt) {
+          return *reinterpret_cast<const float4*>(Wh + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
+        });
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          h[mt] = v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) at(sH + l * W * kSP, mt, r) = h[mt][r];
+        }
+      }
+      v4f o = dense_out<NT>(h, boi, [&](int kt) {
+        return *reinterpret_cast<const float4*>(wpl + P.wop + c * W + 16 * kt + 4 * q);
       });
+
+      // ---- transform backward: every lane evaluates its sample c -----------
+      float o4 = __shfl(o[0], (lane + 16) & 63);
+      float o5 = __shfl(o[1], (lane + 16) & 63);
+      float o6 = __shfl(o[2], (lane + 16) & 63);
+      float ov[7] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
+                     __shfl(o5, c), __shfl(o6, c)};
+      float4 gx = vvalid ? gxhat[(int64_t)t * V + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float go[7];
+      go[6] = 0.f;
+      if (quat) quat_grad(ov, xi, gx, alpha, go);
+      else transform_grad(ov, xi, gx, alpha, go);
+      if (!vvalid)
+        for (int k = 0; k < 7; ++k) go[k] = 0.f;
+      const v4f got = q == 0 ? v4f{go[0], go[1], go[2], go[3]}
+                             : (q == 1 ? v4f{go[4], go[5], go[6], 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
+
+      // ---- output layer: weight gradient and back-propagation ---------------
+#pragma unroll
+      for (int r = 0; r < 4; ++r) at(sG, 0, r) = got[r];
+      __syncthreads();
+      wgrad_layer(sH + (H - 1) * W * kSP, accO, NT, NT);
+      bias_rows(16, sGb + (H - 1) * W);
+      v4f gp[NT];
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt) {
-        h[mt] = v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)};
+        float4 w = *reinterpret_cast<const float4*>(wpl + P.wot + (16 * mt + c) * 16 + 4 * q);
+        v4f a = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) at(sH + l * W * kSP, mt, r) = h[mt][r];
+        for (int r = 0; r < 4; ++r) a = mfma(comp(w, r), got[r], a);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gp[mt][r] = a[r] * actd(at(sH + (H - 1) * W * kSP, mt, r), ap);
       }
-    }
-    v4f o = dense_out<NT>(h, boi, [&](int kt) {
-      return *reinterpret_cast<const float4*>(wpl + P.wop + c * W + 16 * kt + 4 * q);
-    });
+      __syncthreads();
 
-    // ---- transform backward: every lane evaluates its sample c -----------
-    float o4 = __shfl(o[0], (lane + 16) & 63);
-    float o5 = __shfl(o[1], (lane + 16) & 63);
-    float o6 = __shfl(o[2], (lane + 16) & 63);
-    float ov[7] = {__shfl(o[0], c), __shfl(o[1], c), __shfl(o[2], c), __shfl(o[3], c), __shfl(o4, c),
-                   __shfl(o5, c), __shfl(o6, c)};
-    float4 gx = vvalid ? gxhat[(int64_t)t * V + i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    float go[7];
-    go[6] = 0.f;
-    if (quat) quat_grad(ov, xi, gx, alpha, go);
-    else transform_grad(ov, xi, gx, alpha, go);
-    if (!vvalid)
-      for (int k = 0; k < 7; ++k) go[k] = 0.f;
-    const v4f got = q == 0 ? v4f{go[0], go[1], go[2], go[3]}
-                           : (q == 1 ? v4f{go[4], go[5], go[6], 0.f} : v4f{0.f, 0.f, 0.f, 0.f});
+      // ---- hidden layers, last to first --------------------------------------
+#pragma unroll
+      for (int l = H - 1; l >= 1; --l) {
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) at(sG, mt, r) = gp[mt][r];
+        __syncthreads();
+        wgrad_layer(sH + (l - 1) * W * kSP, accW[l - 1], NT * NT, NT);
+        bias_rows(W, sGb + (l - 1) * W);
+        v4f gh[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) gh[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+        dense<NT>(gp, gh, [&](int mt, int kt) {
+          return *reinterpret_cast<const float4*>(WhT + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
+        });
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gp[mt][r] = gh[mt][r] * actd(at(sH + (l - 1) * W * kSP, mt, r), ap);
+        __syncthreads();
+      }
 
-    // ---- output layer: weight gradient and back-propagation ---------------
-#pragma unroll
-    for (int r = 0; r < 4; ++r) at(sG, 0, r) = got[r];
-    __syncthreads();
-    wgrad_layer(sH + (H - 1) * W * kSP, accO, NT, NT);
-    bias_rows(16, sGb + (H - 1) * W);
-    v4f gp[NT];
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      float4 w = *reinterpret_cast<const float4*>(wpl + P.wot + (16 * mt + c) * 16 + 4 * q);
-      v4f a = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a = mfma(comp(w, r), got[r], a);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gp[mt][r] = a[r] * actd(at(sH + (H - 1) * W * kSP, mt, r), ap);
-    }
-    __syncthreads();
-
-    // ---- hidden layers, last to first --------------------------------------
-#pragma unroll
-    for (int l = H - 1; l >= 1; --l) {
+      // ---- first layer: per-vertex (Gv) and per-frame (Gt) sums -------------
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) at(sG, mt, r) = gp[mt][r];
+        for (int r = 0; r < 4; ++r) {
+          gv[mt][r] += gp[mt][r];
+          const float v = row16_sum(gp[mt][r]);
+          if (c == 0) sGt[wave * W + 16 * mt + 4 * q + r] = v;
+        }
       __syncthreads();
-      wgrad_layer(sH + (l - 1) * W * kSP, accW[l - 1], NT * NT, NT);
-      bias_rows(W, sGb + (l - 1) * W);
-      v4f gh[NT];
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt) gh[mt] = v4f{0.f, 0.f, 0.f, 0.f};
-      dense<NT>(gp, gh, [&](int mt, int kt) {
-        return *reinterpret_cast<const float4*>(WhT + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
-      });
+      if ((int)threadIdx.x < W) {
+        float s0 = ((sGt[threadIdx.x] + sGt[W + threadIdx.x]) + sGt[2 * W + threadIdx.x]) + sGt[3 * W + threadIdx.x];
+        Gt_part[((int64_t)t * nvb + vb) * W + threadIdx.x] = s0;
+      }
+    }
+    if (vvalid) {  // this chunk's per-vertex sums
+      float* dv = Gv + ((int64_t)ch * V + i_raw) * W;
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) gp[mt][r] = gh[mt][r] * actd(at(sH + (l - 1) * W * kSP, mt, r), ap);
-      __syncthreads();
-    }
-
-    // ---- first layer: per-vertex (Gv) and per-frame (Gt) sums -------------
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        gv[mt][r] += gp[mt][r];
-        const float v = row16_sum(gp[mt][r]);
-        if (c == 0) sGt[wave * W + 16 * mt + 4 * q + r] = v;
-      }
-    __syncthreads();
-    if ((int)threadIdx.x < W) {
-      float s0 = ((sGt[threadIdx.x] + sGt[W + threadIdx.x]) + sGt[2 * W + threadIdx.x]) + sGt[3 * W + threadIdx.x];
-      Gt_part[((int64_t)t * gridDim.x + vb) * W + threadIdx.x] = s0;
+        *reinterpret_cast<float4*>(dv + 16 * mt + 4 * q) = make_float4(gv[mt][0], gv[mt][1], gv[mt][2], gv[mt][3]);
     }
   }
   __syncthreads();
 
-  if (vvalid) {
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Gv[i_raw * W + 16 * mt + 4 * q + r] = gv[mt][r];
-  }
   // per-work-group weight-gradient partials, flat MLP layout of layers 1..H
   const int n_out = quat ? 7 : 6;
   const int64_t len = (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
-  float* dst = gW_part + vb * len;
+  float* dst = gW_part + (int64_t)blockIdx.x * len;
 #pragma unroll
   for (int l = 1; l < H; ++l) {
     float* dl = dst + (int64_t)(l - 1) * ((int64_t)W * W + W);
@@ -1347,9 +1354,9 @@ hipError_t launch_bwd(const npg_plan* P, const float4* gxhat, ActP ap) {
   hipError_t e = hipFuncSetAttribute((const void*)k_decode_bwd<W, H>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode_bwd<W, H>), dim3(P->n_vblk_mlp), dim3(256), lds, P->stream, P->wpack, P->mlpA,
-                     P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->Gv,
-                     P->Gt_part, P->gW_part);
+  hipLaunchKernelGGL((k_decode_bwd<W, H>), dim3(P->mlp_grid), dim3(256), lds, P->stream, P->wpack, P->mlpA,
+                     P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->n_vblk_mlp,
+                     P->mlp_nch, P->mlp_nch > 1 ? P->Gv_part : P->Gv, P->Gt_part, P->gW_part);
   return hipGetLastError();
 }
 
@@ -1394,9 +1401,9 @@ hipError_t launch_bwd16(const npg_plan* P, const float4* gxhat, ActP ap) {
   hipError_t e = hipFuncSetAttribute((const void*)k_decode_bwd16<W, H>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode_bwd16<W, H>), dim3(P->b16_grid), dim3(64 * kB16W), lds, P->stream, P->wpack16,
+  hipLaunchKernelGGL((k_decode_bwd16<W, H>), dim3(P->mlp_grid), dim3(64 * kB16W), lds, P->stream, P->wpack16,
                      P->wpack, P->mlpA, P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t,
-                     (int)(P->n_out == 7), P->b16_nvb, P->b16_nch, P->b16_nch > 1 ? P->Gv_part : P->Gv,
+                     (int)(P->n_out == 7), P->n_vblk_mlp, P->mlp_nch, P->mlp_nch > 1 ? P->Gv_part : P->Gv,
                      P->Gt_part, P->gW_part);
   return hipGetLastError();
 }
@@ -1422,15 +1429,16 @@ int64_t npg_gw_part_len(int W, int H, int n_out) {
   return (int64_t)(H - 1) * ((int64_t)W * W + W) + n_out * (int64_t)W + n_out;
 }
 
-// Work items of the BF16 backward: nvb blocks of 64 vertices times nch frame
-// chunks (balanced split of the T frames, at most 16 frames each), dealt
-// round-robin to grid = min(items, n_cu) work-groups. nch minimizes the
-// largest per-group frame count (fewest chunks on a tie).
-void npg_bf16_schedule(int64_t V, int T, int n_cu, int* nvb, int* nch, int* grid) {
-  const int nb = (int)((V + kB16S - 1) / kB16S);
-  int best_n = (T + kB16TC - 1) / kB16TC;
+// Work items of the MLP backward (both precisions): blocks of 64 vertices
+// times nch frame chunks (balanced split of the T frames, at most tc_max
+// frames each when tc_max > 0), dealt round-robin to grid = min(items, n_cu)
+// persistent work-groups. nch minimizes the largest per-group frame count
+// (fewest chunks on a tie).
+void npg_mlp_schedule(int64_t V, int T, int n_cu, int tc_max, int* nvb, int* nch, int* grid) {
+  const int nb = (int)((V + 63) / 64);
+  const int n_min = tc_max > 0 ? (T + tc_max - 1) / tc_max : 1;
+  int best_n = n_min;
   int64_t best = -1;
-  const int n_min = (T + kB16TC - 1) / kB16TC;
   for (int n = n_min; n <= std::min(T, n_min + 63); ++n) {
     const int64_t items = (int64_t)nb * n;
     const int G = (int)std::min<int64_t>(items, n_cu);
@@ -1449,6 +1457,7 @@ void npg_bf16_schedule(int64_t V, int T, int n_cu, int* nvb, int* nch, int* grid
   *nch = best_n;
   *grid = (int)std::min<int64_t>((int64_t)nb * best_n, n_cu);
 }
+int npg_mlp_bf16_frames() { return kB16TC; }
 
 hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat,
                                  float4* nhat) {
@@ -1468,12 +1477,12 @@ static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const 
   const bool bf = is_bf16(P);
   const int64_t TW = (int64_t)P->T * P->W;
   hipLaunchKernelGGL(k_sum_parts, dim3(nblk(P->gw_part_len, kRE)), dim3(kRG * kRE), 0, P->stream, P->gW_part,
-                     P->gw_part_len, bf ? P->b16_grid : P->n_vblk_mlp, gmlp + l0);
+                     P->gw_part_len, P->mlp_grid, gmlp + l0);
   hipLaunchKernelGGL(k_gt_reduce, dim3(nblk(TW, kRE)), dim3(kRG * kRE), 0, P->stream, P->Gt_part, P->T,
-                     bf ? P->b16_nvb : P->n_vblk_mlp, P->W, P->Gt);
-  if (bf && P->b16_nch > 1)
+                     P->n_vblk_mlp, P->W, P->Gt);
+  if (P->mlp_nch > 1)
     hipLaunchKernelGGL(k_gv_reduce, dim3(nblk(P->V * P->W, 256)), dim3(256), 0, P->stream, P->Gv_part,
-                       P->V * P->W, P->b16_nch, P->Gv);
+                       P->V * P->W, P->mlp_nch, P->Gv);
   const int nb = (int)nblk(P->V, kFLV);
   hipLaunchKernelGGL(k_first_layer_z, dim3(nb), dim3(256), 0, P->stream, P->Gv, z, P->V, P->W, P->Fz, (int)bf,
                      P->fl_part);

@@ -12,7 +12,8 @@
 // launchers defined in the other translation units
 int64_t npg_wpack_len(int W, int H);
 int64_t npg_gw_part_len(int W, int H, int n_out);
-void npg_bf16_schedule(int64_t V, int T, int n_cu, int* nvb, int* nch, int* grid);
+void npg_mlp_schedule(int64_t V, int T, int n_cu, int tc_max, int* nvb, int* nch, int* grid);
+int npg_mlp_bf16_frames();
 int npg_chamfer_vblock(int threads);
 npg_status npg_cg_setup(npg_plan* P);
 void npg_cg_free(npg_plan* P);
@@ -288,13 +289,13 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->Gv, V * P->W));
   TRYP(dalloc(&P->Gt, (int64_t)T * P->W));
   TRYP(dalloc(&P->Gt_part, (int64_t)T * P->n_vblk_mlp * P->W));
-  int64_t n_parts = P->n_vblk_mlp;
-  if (cfg->precision == NPG_PREC_BF16) {
-    npg_bf16_schedule(V, T, P->n_cu, &P->b16_nvb, &P->b16_nch, &P->b16_grid);
-    n_parts = std::max<int64_t>(n_parts, P->b16_grid);
-    if (P->b16_nch > 1) TRYP(dalloc(&P->Gv_part, (int64_t)P->b16_nch * V * P->W));
+  {
+    int nvb = 0;
+    npg_mlp_schedule(V, T, P->n_cu, cfg->precision == NPG_PREC_BF16 ? npg_mlp_bf16_frames() : 0, &nvb,
+                     &P->mlp_nch, &P->mlp_grid);
   }
-  TRYP(dalloc(&P->gW_part, n_parts * P->gw_part_len));
+  if (P->mlp_nch > 1) TRYP(dalloc(&P->Gv_part, (int64_t)P->mlp_nch * V * P->W));
+  TRYP(dalloc(&P->gW_part, (int64_t)P->mlp_grid * P->gw_part_len));
   TRYP(dalloc(&P->fl_part, ((V + 255) / 256) * P->W * 8));
   if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
   else TRYP(npg_cg_setup(P));
