@@ -77,21 +77,22 @@ __device__ __forceinline__ void tile_gemm(const float* __restrict__ A, int Rp, c
     for (int jt = 0; jt < 4; ++jt) acc[i][jt] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nkt = Rp / 16;
   const int ng = Rp / 16;
-  float4 a[2][NKT];
+  // the operands of the current and of the next k-group, in registers (fixed
+  // names, so no dynamically indexed buffer)
+  float4 cur[NKT], nxt[NKT];
 #pragma unroll
   for (int i = 0; i < NKT; ++i) {
     const int kt = wave + 4 * i;
-    a[0][i] = kt < nkt ? *reinterpret_cast<const float4*>(A + (int64_t)(16 * kt + c) * Rp + 4 * q)
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
+    cur[i] = kt < nkt ? *reinterpret_cast<const float4*>(A + (int64_t)(16 * kt + c) * Rp + 4 * q)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    nxt[i] = cur[i];
   }
   for (int g = 0; g < ng; ++g) {
-    const int cb = g & 1;
     if (g + 1 < ng) {
 #pragma unroll
       for (int i = 0; i < NKT; ++i) {
         const int kt = wave + 4 * i;
-        if (kt < nkt)
-          a[cb ^ 1][i] = *reinterpret_cast<const float4*>(A + (int64_t)(16 * kt + c) * Rp + 16 * (g + 1) + 4 * q);
+        if (kt < nkt) nxt[i] = *reinterpret_cast<const float4*>(A + (int64_t)(16 * kt + c) * Rp + 16 * (g + 1) + 4 * q);
       }
     }
 #pragma unroll
@@ -103,9 +104,11 @@ __device__ __forceinline__ void tile_gemm(const float* __restrict__ A, int Rp, c
       for (int i = 0; i < NKT; ++i) {
         if (wave + 4 * i >= nkt) break;
 #pragma unroll
-        for (int jt = 0; jt < 4; ++jt) acc[i][jt] = mfma(comp(a[cb][i], r), b[jt], acc[i][jt]);
+        for (int jt = 0; jt < 4; ++jt) acc[i][jt] = mfma(comp(cur[i], r), b[jt], acc[i][jt]);
       }
     }
+#pragma unroll
+    for (int i = 0; i < NKT; ++i) cur[i] = nxt[i];
   }
 }
 
@@ -160,7 +163,8 @@ __global__ __launch_bounds__(256) void k_dct_pass(float* __restrict__ grad, cons
   float* base = grad + S.poff;
   const int64_t j0 = blk_j0[blockIdx.x];
   const int R = S.R, Rp = S.Rp, F = S.F;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar branches on k-tiles
   const int q = lane >> 4, c = lane & 15;
   const int njl = (int)min((int64_t)kJ, S.lines - j0);
   const int64_t stride = line_stride(pass, R, F);
