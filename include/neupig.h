@@ -159,6 +159,27 @@ npg_status npg_get_state(npg_plan* plan, float* params_dev, float* m_dev, float*
                          int64_t* adam_steps_host);
 
 /*
+ * Parameters by block (Sec. 3.2 grids and the Sec. 3.3 network), one device
+ * buffer each, in this order: the L position grids [R_l^3][F_p] (node
+ * (z, y, x) at (z*R + y)*R + x), the normal grid [R_n^3][F_n], then for the
+ * network's H + 1 layers W_k [out][in] and b_k [out] (first layer
+ * in = F_n + F_p + 2M, or 1 without time frequencies; hidden out = W; last
+ * out = 6, or 7 with the quaternion head). bufs_host holds
+ * L + 1 + 2(H + 1) pointers owned by the caller. Import replaces the plan's
+ * parameters (Adam moments and step count untouched); export copies them
+ * out. Synchronize. NPG_EINVAL for a NULL array or buffer.
+ */
+npg_status npg_params_import(npg_plan* plan, const float* const* bufs_host);
+npg_status npg_params_export(npg_plan* plan, float* const* bufs_host);
+
+/* Checkpoint of the whole optimizer state (flat parameters, Adam moments,
+ * step count): the same as npg_set_state / npg_get_state. */
+npg_status npg_state_import(npg_plan* plan, const float* params_dev, const float* m_dev,
+                            const float* v_dev, int64_t adam_steps);
+npg_status npg_state_export(npg_plan* plan, float* params_dev, float* m_dev, float* v_dev,
+                            int64_t* adam_steps_host);
+
+/*
  * One full optimization step on the plan's own state (all stages below in
  * order, then the Adam update with step count adam_steps + 1).
  *   epoch, n_epochs  0-based epoch e and e_max of the confidence catch-up

@@ -79,6 +79,10 @@ _SIGS = {
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_scale": ([_P, _P, _D, _P, _I32, _I64], ctypes.c_int),
     "npg_tune_nn": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "npg_params_import": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_params_export": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_state_import": ([_P, _P, _P, _P, _I64], ctypes.c_int),
+    "npg_state_export": ([_P, _P, _P, _P, ctypes.POINTER(_I64)], ctypes.c_int),
     "npg_profile": ([_P, _I32], ctypes.c_int),
     "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
 }
@@ -372,6 +376,25 @@ class Plan:
         _check(lib().npg_adam(self._h, _ptr(params, f, n, "params"), _ptr(grad, f, n, "grad"),
                               _ptr(m, f, n, "m"), _ptr(v, f, n, "v"), int(adam_step)))
 
+
+    def params_import(self, blocks):
+        """Replace the parameters from per-block device tensors (order and
+        shapes of param_layout)."""
+        import torch
+        lay, _ = param_layout(self.cfg)
+        if len(blocks) != len(lay):
+            raise ValueError(f"need {len(lay)} blocks, got {len(blocks)}")
+        ptrs = (_P * len(lay))(*[_ptr(b, torch.float32, int(np.prod(s)), n).value for b, (n, _, s) in zip(blocks, lay)])
+        _check(lib().npg_params_import(self._h, ptrs))
+
+    def params_export(self):
+        """The parameters as per-block device tensors (param_layout order)."""
+        import torch
+        lay, _ = param_layout(self.cfg)
+        out = [torch.empty(s, dtype=torch.float32, device=self.device) for _, _, s in lay]
+        ptrs = (_P * len(lay))(*[t.data_ptr() for t in out])
+        _check(lib().npg_params_export(self._h, ptrs))
+        return out
 
     def tune_nn(self, threads=0):
         """Work-group size of the nearest-neighbour pass: 0 = time 64/128/256

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "internal.h"
 
@@ -518,6 +520,56 @@ npg_status npg_deform(npg_plan* P, float* out) {
   hipLaunchKernelGGL(k_unpack_xyz, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P->stream, P->xhat, out, n);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
+}
+
+// Blocks of the flat parameter vector in order: the L position grids
+// [R_l^3][F], the normal grid [R_n^3][F_n], then W_k [out][in] and b_k [out]
+// of the H + 1 MLP layers. (offset, count) in floats.
+static std::vector<std::pair<int64_t, int64_t>> param_blocks(const npg_plan* P) {
+  std::vector<std::pair<int64_t, int64_t>> b;
+  for (int s = 0; s < P->n_sys; ++s) b.emplace_back(P->g[s].poff, P->g[s].nodes * P->g[s].F);
+  int64_t off = P->mlp_off;
+  int din = P->Din;
+  for (int k = 0; k <= P->H; ++k) {
+    const int dout = k < P->H ? P->W : P->n_out;
+    b.emplace_back(off, (int64_t)dout * din);
+    off += (int64_t)dout * din;
+    b.emplace_back(off, dout);
+    off += dout;
+    din = dout;
+  }
+  return b;
+}
+
+static npg_status copy_blocks(npg_plan* P, float* const* dst, const float* const* src, bool import) {
+  const auto blocks = param_blocks(P);
+  for (size_t k = 0; k < blocks.size(); ++k)
+    CHECK_ARG(import ? src[k] != nullptr : dst[k] != nullptr, "block buffer " + std::to_string(k) + " is NULL");
+  for (size_t k = 0; k < blocks.size(); ++k) {
+    const size_t nb = (size_t)blocks[k].second * 4;
+    if (import) NPG_HIP(hipMemcpyAsync(P->params + blocks[k].first, src[k], nb, hipMemcpyDeviceToDevice, P->stream));
+    else NPG_HIP(hipMemcpyAsync(dst[k], P->params + blocks[k].first, nb, hipMemcpyDeviceToDevice, P->stream));
+  }
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  return NPG_OK;
+}
+
+npg_status npg_params_import(npg_plan* P, const float* const* bufs) {
+  CHECK_ARG(P && bufs, "NULL argument");
+  return copy_blocks(P, nullptr, bufs, true);
+}
+
+npg_status npg_params_export(npg_plan* P, float* const* bufs) {
+  CHECK_ARG(P && bufs, "NULL argument");
+  return copy_blocks(P, bufs, nullptr, false);
+}
+
+npg_status npg_state_import(npg_plan* P, const float* params, const float* m, const float* v, int64_t adam_steps) {
+  return npg_set_state(P, params, m, v, adam_steps);
+}
+
+npg_status npg_state_export(npg_plan* P, float* params, float* m, float* v, int64_t* adam_steps) {
+  return npg_get_state(P, params, m, v, adam_steps);
 }
 
 npg_status npg_tune_nn(npg_plan* P, int32_t threads, int32_t* chosen, float* ms) {
