@@ -332,6 +332,17 @@ npg_status npg_encode_bwd(npg_plan* plan, const float* gz_dev, float* grad_dev);
 npg_status npg_precond(npg_plan* plan, float* grad_dev, int32_t* iters_host);
 
 /*
+ * Final relative residuals ||r||_2 / ||b||_2 of the CG recurrence (r updated
+ * as r - alpha A p; float64, the largest over a grid's feature channels) of
+ * the last preconditioning (by
+ * npg_precond or inside npg_step) of the CG form: relres_host
+ * [2*(L+1)], the first solve of every grid (position levels, then the
+ * normal grid), then the second. 0 before any preconditioning, for a zero
+ * right-hand side, and for the DCT form (exact). Host only; no GPU work.
+ */
+npg_status npg_precond_residuals(npg_plan* plan, double* relres_host);
+
+/*
  * Sec. 3.5 "Isometry Loss" on deformed vertices xhat_dev [T][V][4] (as from
  * npg_decode_fwd): iso_dev [1] float64 receives
  *   L_iso = (1/(T E)) sum_t sum_(i,j) | |x^_i,t - x^_j,t| - |x^_i,key - x^_j,key| |

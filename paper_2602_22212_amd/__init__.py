@@ -79,6 +79,7 @@ _SIGS = {
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_scale": ([_P, _P, _D, _P, _I32, _I64], ctypes.c_int),
     "npg_tune_nn": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "npg_precond_residuals": ([_P, ctypes.POINTER(_D)], ctypes.c_int),
     "npg_params_import": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
     "npg_params_export": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
     "npg_state_import": ([_P, _P, _P, _P, _I64], ctypes.c_int),
@@ -368,6 +369,13 @@ class Plan:
         if st not in (NPG_OK, NPG_ENOTCONV):
             _check(st)
         return list(it), st
+
+    def precond_residuals(self):
+        """Final relative residuals of the last preconditioning (CG form),
+        [first solve per grid..., second solve per grid...]."""
+        out = (_D * (2 * (len(self.cfg["levels"]) + 1)))()
+        _check(lib().npg_precond_residuals(self._h, out))
+        return list(out)
 
     def adam(self, params, grad, m, v, adam_step):
         import torch

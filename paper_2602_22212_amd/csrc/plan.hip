@@ -572,6 +572,12 @@ npg_status npg_state_export(npg_plan* P, float* params, float* m, float* v, int6
   return npg_get_state(P, params, m, v, adam_steps);
 }
 
+npg_status npg_precond_residuals(npg_plan* P, double* relres) {
+  CHECK_ARG(P && relres, "NULL argument");
+  for (int k = 0; k < 2 * P->n_sys; ++k) relres[k] = P->cfg.precond == NPG_PRECOND_CG ? P->cg_relres[k] : 0.0;
+  return NPG_OK;
+}
+
 npg_status npg_tune_nn(npg_plan* P, int32_t threads, int32_t* chosen, float* ms) {
   CHECK_ARG(P, "plan is NULL");
   CHECK_ARG(threads == 0 || threads == 64 || threads == 128 || threads == 256, "threads must be 0, 64, 128 or 256");

@@ -656,7 +656,7 @@ void npg_cg_free(npg_plan* P) {
 // Solve (I + lam L) x = b for every system; the solution is left in C.x
 // (b may alias C.x: each node of b is read before its x is cleared).
 // The iteration count of each system goes to iters (if not NULL).
-static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* capped) {
+static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* capped, double* relres) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nb = C.n_blocks;
@@ -715,6 +715,14 @@ static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* ca
     double m = 0;
     for (int c = 0; c < P->g[sy].F; ++c) m = stv[(sy * 4 + c) * kS + 6] > m ? stv[(sy * 4 + c) * kS + 6] : m;
     if (iters) iters[sy] = (int32_t)m;
+    // final relative residual ||r|| / ||b|| in float64, the largest over the channels
+    double rel = 0.0;
+    for (int c = 0; c < P->g[sy].F; ++c) {
+      const double rr = stv[(sy * 4 + c) * kS + 0], bb = stv[(sy * 4 + c) * kS + 1];
+      const double v = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+      rel = v > rel ? v : rel;
+    }
+    relres[sy] = rel;
     // algorithmic traffic of this solve: 6 vector passes (x, r, p read and
     // written) per iteration over the grid's R^3 F float32 unknowns
     P->cg_alg_bytes += m * 6.0 * (double)P->g[sy].nodes * P->g[sy].F * 4.0;
@@ -727,9 +735,9 @@ npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters) {
   bool capped = false;
   P->cg_alg_bytes = 0.0;
   P->cg_iters_sum = 0;
-  npg_status st = cg_solve(P, grad, iters, &capped);
+  npg_status st = cg_solve(P, grad, iters, &capped, P->cg_relres);
   if (st != NPG_OK) return st;
-  st = cg_solve(P, P->cg.x, iters ? iters + P->n_sys : nullptr, &capped);
+  st = cg_solve(P, P->cg.x, iters ? iters + P->n_sys : nullptr, &capped, P->cg_relres + P->n_sys);
   if (st != NPG_OK) return st;
   hipLaunchKernelGGL(k_copy, dim3(nblk(P->n_grid_params, 256)), dim3(256), 0, P->stream, P->cg.x, grad,
                      P->n_grid_params);

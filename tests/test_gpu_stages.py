@@ -289,6 +289,9 @@ def test_preconditioner_matches_exact_operator(case):
     errs.append(rel(got["grid_n"], refn))
     print("precond rel errors per grid:", ["%.2e" % e for e in errs], "iterations:", its)
     assert max(errs) < TOL
+    rr = plan.precond_residuals()  # both CG solves of every grid stopped at the tolerance
+    assert len(rr) == 2 * (len(cfg["levels"]) + 1)
+    assert all(0 < r <= cfg["cg_rtol"] for r in rr), rr
 
 
 def test_preconditioner_special_cases(case):
