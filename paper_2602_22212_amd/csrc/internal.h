@@ -97,7 +97,7 @@ struct npg_plan {
   int mlp_nch, mlp_grid;
   double cg_relres[2 * NPG_MAX_SYS];  // last preconditioning: final ||r||/||b|| per grid, both solves
   float* Gv_part;          // [mlp_nch][V][W] (NULL when mlp_nch == 1)
-  float* fl_part;          // [ceil(V/256)][W][8] first-layer partial sums
+  float* fl_part;          // [ceil(V/64)][W][8] first-layer partial sums
   // preconditioner workspaces
   NpgCG cg;
   NpgDct* dct;

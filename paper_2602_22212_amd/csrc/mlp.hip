@@ -1246,8 +1246,9 @@ __global__ __launch_bounds__(kRG * kRE) void k_gt_reduce(const float* __restrict
 
 // First layer, z part, stage 1: per block of kFLV vertices and per output
 // unit o, sum_i Gv[i][o] z_i[k] (k < Fz), in fixed order (vertex sub-streams
-// of the block, then their sums in order). part [block][W][8].
-constexpr int kFLV = 256;
+// of the block, then their sums in order). part [block][W][8]; the block
+// count is npg_first_layer_blocks(V).
+constexpr int kFLV = 64;
 __global__ __launch_bounds__(256) void k_first_layer_z(const float* __restrict__ Gv, const float* __restrict__ z,
                                                        int64_t V, int W, int Fz, int bf16,
                                                        float* __restrict__ part) {
@@ -1458,6 +1459,7 @@ void npg_mlp_schedule(int64_t V, int T, int n_cu, int tc_max, int* nvb, int* nch
   *grid = (int)std::min<int64_t>((int64_t)nb * best_n, n_cu);
 }
 int npg_mlp_bf16_frames() { return kB16TC; }
+int64_t npg_first_layer_blocks(int64_t V) { return (V + kFLV - 1) / kFLV; }
 
 hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat,
                                  float4* nhat) {

@@ -16,6 +16,7 @@ int64_t npg_wpack_len(int W, int H);
 int64_t npg_gw_part_len(int W, int H, int n_out);
 void npg_mlp_schedule(int64_t V, int T, int n_cu, int tc_max, int* nvb, int* nch, int* grid);
 int npg_mlp_bf16_frames();
+int64_t npg_first_layer_blocks(int64_t V);
 int npg_chamfer_vblock(int threads);
 npg_status npg_cg_setup(npg_plan* P);
 void npg_cg_free(npg_plan* P);
@@ -298,7 +299,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   }
   if (P->mlp_nch > 1) TRYP(dalloc(&P->Gv_part, (int64_t)P->mlp_nch * V * P->W));
   TRYP(dalloc(&P->gW_part, (int64_t)P->mlp_grid * P->gw_part_len));
-  TRYP(dalloc(&P->fl_part, ((V + 255) / 256) * P->W * 8));
+  TRYP(dalloc(&P->fl_part, npg_first_layer_blocks(V) * P->W * 8));
   if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
   else TRYP(npg_cg_setup(P));
   for (auto& e : P->ev) HIPP(hipEventCreate(&e));
