@@ -207,11 +207,13 @@ def run_form(cfg, data, P0, steps, warmup, profile):
     prof = plan.profile_read() if profile else None
     if prof is not None:
         prof["steps"] = steps
+    relres = plan.precond_residuals() if cfg.get("precond", "cg") == "cg" else None
     plan.close()
     return dict(value=steps / t_total, ms_per_step=1e3 * t_total / steps,
                 stage_ms={k: round(v / steps, 3) for k, v in stage_sum.items()},
                 status=sorted(set(int(s) for s in statuses)), prof=prof, loss=loss.item(),
-                nn_tune={"threads": nn_threads, "ms_64_128_256": [round(m, 3) for m in nn_ms]})
+                nn_tune={"threads": nn_threads, "ms_64_128_256": [round(m, 3) for m in nn_ms]},
+                cg_relres_max=None if relres is None else max(relres))
 
 
 def run_metrics(cfg, P0, reps=3):
@@ -453,6 +455,7 @@ def main():
         "stage_roofline": stage_roofline(cfg, data, cg["stage_ms"], "f32", prof),
         "paper_context": PAPER_CONTEXT,
         "cg_iterations_per_step": round(prof["cg_iters"] / args.steps, 1),
+        "cg_final_relres_max": cg["cg_relres_max"],
         "step_status": cg["status"],
         "roofline": roofline,
         "precond_dct": None if dct is None else {
