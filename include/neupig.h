@@ -96,7 +96,7 @@ typedef struct npg_config {
   int32_t mlp_hidden;             /* H hidden layers, 1..3                          */
   int32_t mlp_width;              /* hidden width: 32, 64 or 128                    */
   int32_t act;                    /* NPG_ACT_RELU or NPG_ACT_LEAKY                  */
-  float leaky_slope;              /* negative slope of LeakyReLU (0.01)             */
+  float leaky_slope;              /* negative slope of LeakyReLU, in (0, 1] (0.01)  */
   float alpha_t;                  /* displacement squashing tanh(alpha d), 0.1      */
   float lr_mlp;                   /* Adam learning rate of the MLP (1e-3)           */
   float lr_grid[NPG_MAX_LEVELS];  /* per-level grid learning rates                  */

@@ -842,14 +842,172 @@ __device__ __forceinline__ void dgrad32(const v4s (&g)[W / 16], v4f (&out)[W / 1
   }
 }
 
+// out_u[mt] += sum_k Wl[16mt + c][k] in_u[k] for two 16-sample tiles u: each
+// weight operand read from LDS feeds both tiles' products.
+template <int W>
+__device__ __forceinline__ void dense32x2(const v4s (&in0)[W / 16], const v4s (&in1)[W / 16],
+                                          v4f (&out0)[W / 16], v4f (&out1)[W / 16], const uint16_t* sWl, int q,
+                                          int c) {
+  constexpr int NT = W / 16;
+  using L = WLds<W>;
+  const int sc = L::swz(c);
+  auto frag = [&](int mt, int kb) { return lds8(sWl + (16 * mt + c) * L::LD + (((4 * kb + q) ^ sc) << 3)); };
+  v8s w[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) w[0][mt] = frag(mt, 0);
+#pragma unroll
+  for (int kb = 0; kb < NT / 2; ++kb) {
+    const int cb = kb & 1;
+    if (kb + 1 < NT / 2) {
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) w[cb ^ 1][mt] = frag(mt, kb + 1);
+    }
+    const v8s b0 = cat8(in0[2 * kb], in0[2 * kb + 1]);
+    const v8s b1 = cat8(in1[2 * kb], in1[2 * kb + 1]);
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      out0[mt] = mfma32(w[cb][mt], b0, out0[mt]);
+      out1[mt] = mfma32(w[cb][mt], b1, out1[mt]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// the output rows for two tiles (same summation order as dense_out32)
+template <int W>
+__device__ __forceinline__ void dense_out32x2(const v4s (&in0)[W / 16], const v4s (&in1)[W / 16], v4f init,
+                                              const uint16_t* sWo, int q, int c, v4f& r0, v4f& r1) {
+  using L = WLds<W>;
+  const int sc = L::swz(c);
+  v4f a0 = init, a1 = {0.f, 0.f, 0.f, 0.f}, b0 = init, b1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < W / 32; ++kb) {
+    const v8s w = lds8(sWo + c * L::LD + (((4 * kb + q) ^ sc) << 3));
+    if (kb & 1) {
+      a1 = mfma32(w, cat8(in0[2 * kb], in0[2 * kb + 1]), a1);
+      b1 = mfma32(w, cat8(in1[2 * kb], in1[2 * kb + 1]), b1);
+    } else {
+      a0 = mfma32(w, cat8(in0[2 * kb], in0[2 * kb + 1]), a0);
+      b0 = mfma32(w, cat8(in1[2 * kb], in1[2 * kb + 1]), b0);
+    }
+  }
+  r0 = a0 + a1;
+  r1 = b0 + b1;
+}
+
+// activation of 4 values and bfloat16 packing; relu: max(x, 0); LeakyReLU
+// with slope s in (0, 1]: max(x, s x), equal to x > 0 ? x : s x. The maximum
+// is the median of (a, b, FLT_MAX) (the same for finite values, +inf maps to
+// FLT_MAX), one instruction without the operand quieting that the IEEE
+// maximum adds for matrix-core results.
+template <bool RELU>
+__device__ __forceinline__ v4s act_pack(v4f x, float s) {
+  constexpr float big = 3.40282347e38f;
+  v4f y;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) y[j] = __builtin_amdgcn_fmed3f(x[j], RELU ? 0.f : s * x[j], big);
+  return pack_bf16(y);
+}
+
+// The forward items of one wave (see k_decode_fwd16).
+template <int W, int H, bool RELU>
+__device__ __forceinline__ void fwd16_items(const uint16_t* sW, const float* sB, const float* __restrict__ A,
+                                            const float* __restrict__ B, const float4* __restrict__ xyz,
+                                            float4* __restrict__ xhat, int64_t V, int T, float s, float alpha,
+                                            int quat, const float4* __restrict__ nrm, float4* __restrict__ nhat,
+                                            int pc, int nch, int64_t it0, int64_t stride) {
+  constexpr int NT = W / 16;
+  constexpr int LD = WLds<W>::LD;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, c = lane & 15;
+  const int np = (T + 1) / 2;
+  const int64_t items = (V + 15) / 16 * nch;
+  const float4 bo4 = *reinterpret_cast<const float4*>(sB + (H - 1) * W + 4 * q);
+  const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
+
+  for (int64_t it = it0; it < items; it += stride) {
+    const int64_t vb = it / nch;
+    const int ch = (int)(it - vb * nch);
+    const int p0 = ch * pc, p1 = min(np, p0 + pc);
+    const int64_t i = vb * 16 + c;
+    const bool vvalid = i < V;
+    const int64_t ic = vvalid ? i : V - 1;
+    float4 av[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) av[mt] = *reinterpret_cast<const float4*>(A + ic * W + 16 * mt + 4 * q);
+    const float4 xr = xyz[ic];
+    const float4 nr = nhat ? nrm[ic] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int pp = p0; pp < p1; ++pp) {
+      const int t0 = 2 * pp, t1 = min(2 * pp + 1, T - 1);
+      // first layer: act(A_i + B_t) of both frames
+      v4s h0[NT], h1[NT];
+      {
+        float4 b0[NT], b1[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          b0[mt] = *reinterpret_cast<const float4*>(B + (int64_t)t0 * W + 16 * mt + 4 * q);
+          b1[mt] = *reinterpret_cast<const float4*>(B + (int64_t)t1 * W + 16 * mt + 4 * q);
+        }
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          const float4 a = av[mt];
+          h0[mt] = act_pack<RELU>(v4f{a.x + b0[mt].x, a.y + b0[mt].y, a.z + b0[mt].z, a.w + b0[mt].w}, s);
+          h1[mt] = act_pack<RELU>(v4f{a.x + b1[mt].x, a.y + b1[mt].y, a.z + b1[mt].z, a.w + b1[mt].w}, s);
+        }
+      }
+#pragma unroll
+      for (int l = 1; l < H; ++l) {
+        v4f a[NT], b[NT];
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          const float4 bb = *reinterpret_cast<const float4*>(sB + (l - 1) * W + 16 * mt + 4 * q);
+          a[mt] = v4f{bb.x, bb.y, bb.z, bb.w};
+          b[mt] = a[mt];
+        }
+        dense32x2<W>(h0, h1, a, b, sW + (l - 1) * W * LD, q, c);
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          h0[mt] = act_pack<RELU>(a[mt], s);
+          h1[mt] = act_pack<RELU>(b[mt], s);
+        }
+      }
+      v4f o0, o1;
+      dense_out32x2<W>(h0, h1, boi, sW + (H - 1) * W * LD, q, c, o0, o1);
+      // lanes 0-15 take frame t0's 7 outputs of column c, lanes 16-31 frame t1's
+      float ov[7];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float x1 = __shfl(o1[j], c);
+        ov[j] = q == 0 ? o0[j] : x1;
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float x0 = __shfl(o0[j], c + 16);
+        ov[4 + j] = q == 0 ? x0 : o1[j];
+      }
+      if (q < 2 && vvalid && (q == 0 || 2 * pp + 1 < T)) {
+        const int64_t sidx = (int64_t)(q ? t1 : t0) * V + i;
+        xhat[sidx] = quat ? apply_quat(ov, xr, alpha) : apply_transform(ov, xr, alpha);
+        if (nhat) nhat[sidx] = quat ? rotate_quat(ov, nr) : rotate_expmap(ov, nr);
+      }
+    }
+  }
+}
+
+// Persistent forward pass: the work-group stages the bfloat16 weights once;
+// each wave then takes (16-vertex block, chunk of `pc` frame pairs) items
+// round-robin (nch chunks per block). The block's first-layer term A_i stays
+// in registers over the chunk; per frame pair the two frames run as two
+// 16-sample tiles that share every weight operand, and the 6-DoF transform
+// of frame 2p runs on lanes 0-15 while that of frame 2p+1 runs on lanes
+// 16-31.
 template <int W, int H>
 __global__ __launch_bounds__(512) void k_decode_fwd16(const uint16_t* __restrict__ wp16,
                                                       const float* __restrict__ wp, const float* __restrict__ A,
                                                       const float* __restrict__ B, const float4* __restrict__ xyz,
                                                       float4* __restrict__ xhat, int64_t V, int T, ActP ap,
                                                       float alpha, int quat, const float4* __restrict__ nrm,
-                                                      float4* __restrict__ nhat) {
-  constexpr int NT = W / 16;
+                                                      float4* __restrict__ nhat, int pc, int nch) {
   constexpr int LD = WLds<W>::LD;
   extern __shared__ __attribute__((aligned(16))) float lds[];
   uint16_t* sW = reinterpret_cast<uint16_t*>(lds);                      // [(H-1)W + 16][LD]
@@ -859,50 +1017,13 @@ __global__ __launch_bounds__(512) void k_decode_fwd16(const uint16_t* __restrict
   for (int e = threadIdx.x; e < (H - 1) * W; e += blockDim.x) sB[e] = wp[P.bh + e];
   for (int e = threadIdx.x; e < 16; e += blockDim.x) sB[(H - 1) * W + e] = wp[P.bo + e];
   __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int q = lane >> 4, c = lane & 15;
   const int nw = blockDim.x >> 6;
-  const int64_t S = V * (int64_t)T;
-  const int64_t ntiles = (S + 15) / 16;
-  float4 bo4 = *reinterpret_cast<const float4*>(sB + (H - 1) * W + 4 * q);
-  const v4f boi = v4f{bo4.x, bo4.y, bo4.z, bo4.w};
-
-  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
-    int64_t s = tile * 16 + c;
-    const bool valid = s < S;
-    if (!valid) s = S - 1;
-    const int64_t t = s / V, i = s - t * V;
-    v4s hb[NT];
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      float4 a = *reinterpret_cast<const float4*>(A + i * W + 16 * mt + 4 * q);
-      float4 b = *reinterpret_cast<const float4*>(B + t * W + 16 * mt + 4 * q);
-      hb[mt] = pack_bf16(v4f{actf(a.x + b.x, ap), actf(a.y + b.y, ap), actf(a.z + b.z, ap), actf(a.w + b.w, ap)});
-    }
-#pragma unroll
-    for (int l = 1; l < H; ++l) {
-      v4f o[NT];
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt) {
-        float4 b = *reinterpret_cast<const float4*>(sB + (l - 1) * W + 16 * mt + 4 * q);
-        o[mt] = v4f{b.x, b.y, b.z, b.w};
-      }
-      dense32<W, true>(hb, o, sW + (l - 1) * W * LD, q, c);
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt)
-        hb[mt] = pack_bf16(v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)});
-    }
-    v4f o = dense_out32<W>(hb, boi, sW + (H - 1) * W * LD, q, c);
-    float o4 = __shfl(o[0], (lane + 16) & 63);
-    float o5 = __shfl(o[1], (lane + 16) & 63);
-    float o6 = __shfl(o[2], (lane + 16) & 63);
-    if (q == 0 && valid) {
-      float ov[7] = {o[0], o[1], o[2], o[3], o4, o5, o6};
-      xhat[s] = quat ? apply_quat(ov, xyz[i], alpha) : apply_transform(ov, xyz[i], alpha);
-      if (nhat) nhat[s] = quat ? rotate_quat(ov, nrm[i]) : rotate_expmap(ov, nrm[i]);
-    }
-  }
+  const int64_t it0 = (int64_t)blockIdx.x * nw + (threadIdx.x >> 6), stride = (int64_t)gridDim.x * nw;
+  if (ap.relu)
+    fwd16_items<W, H, true>(sW, sB, A, B, xyz, xhat, V, T, 0.f, alpha, quat, nrm, nhat, pc, nch, it0, stride);
+  else
+    fwd16_items<W, H, false>(sW, sB, A, B, xyz, xhat, V, T, ap.slope, alpha, quat, nrm, nhat, pc, nch, it0,
+                             stride);
 }
 
 // Backward, BF16 form. A persistent work-group of 4 waves (one per SIMD, so
@@ -1384,15 +1505,35 @@ size_t fwd16_lds() {
   return sizeof(uint16_t) * ((size_t)((H - 1) * W + 16) * WLds<W>::LD) + sizeof(float) * ((size_t)(H - 1) * W + 16);
 }
 
+// Forward items: 16-vertex blocks times chunks of pc frame pairs, dealt to
+// nw waves; pc minimizes the largest per-wave pair count (the longest chunk
+// on a tie, so A_i is loaded least often).
+void fwd16_schedule(int64_t V, int T, int64_t nw, int* pc, int* nch) {
+  const int64_t nvb = (V + 15) / 16;
+  const int np = (T + 1) / 2;
+  int64_t best = -1;
+  for (int c = 1; c <= np; ++c) {
+    const int n = (np + c - 1) / c;
+    const int64_t load = (nvb * n + nw - 1) / nw * c;
+    if (best < 0 || load <= best) {
+      best = load;
+      *pc = c;
+      *nch = n;
+    }
+  }
+}
+
 template <int W, int H>
 hipError_t launch_fwd16(const npg_plan* P, float4* xhat, ActP ap, float4* nhat) {
   size_t lds = fwd16_lds<W, H>();
   hipError_t e = hipFuncSetAttribute((const void*)k_decode_fwd16<W, H>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode_fwd16<W, H>), dim3(2 * P->n_cu), dim3(512), lds, P->stream, P->wpack16, P->wpack,
+  int pc = 1, nch = 1;
+  fwd16_schedule(P->V, P->T, (int64_t)P->n_cu * 8, &pc, &nch);
+  hipLaunchKernelGGL((k_decode_fwd16<W, H>), dim3(P->n_cu), dim3(512), lds, P->stream, P->wpack16, P->wpack,
                      P->mlpA, P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->nrm,
-                     nhat);
+                     nhat, pc, nch);
   return hipGetLastError();
 }
 

@@ -87,7 +87,7 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->mlp_hidden >= 1 && c->mlp_hidden <= 3, "mlp_hidden must be in 1..3");
   CHECK_ARG(c->mlp_width == 32 || c->mlp_width == 64 || c->mlp_width == 128, "mlp_width must be 32, 64 or 128");
   CHECK_ARG(c->act == NPG_ACT_RELU || c->act == NPG_ACT_LEAKY, "act must be NPG_ACT_RELU or NPG_ACT_LEAKY");
-  CHECK_ARG(isfinite(c->leaky_slope) && c->leaky_slope > 0.f, "leaky_slope must be > 0");
+  CHECK_ARG(isfinite(c->leaky_slope) && c->leaky_slope > 0.f && c->leaky_slope <= 1.f, "leaky_slope must be in (0, 1]");
   CHECK_ARG(isfinite(c->alpha_t), "alpha_t must be finite");
   CHECK_ARG(c->beta1 >= 0.f && c->beta1 < 1.f && c->beta2 >= 0.f && c->beta2 < 1.f, "Adam betas must be in [0,1)");
   CHECK_ARG(c->eps > 0.f, "eps must be > 0");

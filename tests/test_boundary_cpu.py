@@ -81,6 +81,8 @@ def test_param_count_matches_layout(name, head):
     (dict(eps=0.0), "eps"),
     (dict(cg_maxit=0), "cg_maxit"),
     (dict(w_iso=-1.0), "w_iso"),
+    (dict(act="leaky", leaky_slope=1.5), "leaky_slope"),
+    (dict(act="leaky", leaky_slope=0.0), "leaky_slope"),
 ])
 def test_invalid_configs_are_rejected(bad, msg):
     _lib()
