@@ -29,14 +29,20 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 namespace {
 
+// Activation: x > 0 ? x : slope x, with slope 0 for ReLU and in (0, 1] for
+// LeakyReLU (the host sets it), so that it equals max(x, slope x); the
+// maximum is taken as the median of (x, slope x, FLT_MAX) (the same for finite
+// values), one instruction without the operand quieting that the IEEE maximum
+// adds for matrix-core results.
 struct ActP {
   int relu;
   float slope;
 };
+constexpr float kFltMax = 3.40282347e38f;
 
-__device__ __forceinline__ float actf(float x, ActP a) { return x > 0.f ? x : (a.relu ? 0.f : a.slope * x); }
+__device__ __forceinline__ float actf(float x, ActP a) { return __builtin_amdgcn_fmed3f(x, a.slope * x, kFltMax); }
 // derivative from the activation's output (same sign as its input)
-__device__ __forceinline__ float actd(float h, ActP a) { return h > 0.f ? 1.f : (a.relu ? 0.f : a.slope); }
+__device__ __forceinline__ float actd(float h, ActP a) { return h > 0.f ? 1.f : a.slope; }
 
 __device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -160,23 +166,30 @@ __global__ void k_prep_B(const float* __restrict__ mlp, const float* __restrict_
 
 // ---- exponential map (Rodrigues) in float32 --------------------------------
 // A = sin(th)/th, B = (1-cos th)/th^2 = 2 sin^2(th/2)/th^2, C = (th - sin th)/th^3.
-// The half-angle form of B and a Taylor series of C below th = 0.5 avoid the
+// One sine-cosine pair of the half angle h = th/2 gives both A = (sin h / h)
+// cos h and B = (sin h / h)^2 / 2 (and sin th = 2 sin h cos h); the
+// half-angle form of B and a Taylor series of C below th = 0.5 avoid the
 // cancellation of the textbook forms in float32.
 __device__ __forceinline__ void rod_coef(float th2, float& A, float& B, float& C) {
   float th = sqrtf(th2);
+  float sin_th;
   if (th < 1e-4f) {
     A = 1.f - th2 * (1.f / 6.f);
     B = 0.5f - th2 * (1.f / 24.f);
+    sin_th = th;
   } else {
-    A = sinf(th) / th;
     float h = 0.5f * th;
-    float sh = sinf(h) / h;
+    float s, c;
+    sincosf(h, &s, &c);
+    float sh = s / h;
+    A = sh * c;
     B = 0.5f * sh * sh;
+    sin_th = 2.f * s * c;
   }
   if (th < 0.5f) {
     C = (1.f / 6.f) - th2 * ((1.f / 120.f) - th2 * ((1.f / 5040.f) - th2 * ((1.f / 362880.f) - th2 * (1.f / 39916800.f))));
   } else {
-    C = (th - sinf(th)) / (th2 * th);
+    C = (th - sin_th) / (th2 * th);
   }
 }
 
@@ -895,19 +908,18 @@ __device__ __forceinline__ void dense_out32x2(const v4s (&in0)[W / 16], const v4
   r1 = b0 + b1;
 }
 
-// activation of 4 values and bfloat16 packing; relu: max(x, 0); LeakyReLU
-// with slope s in (0, 1]: max(x, s x), equal to x > 0 ? x : s x. The maximum
-// is the median of (a, b, FLT_MAX) (the same for finite values, +inf maps to
-// FLT_MAX), one instruction without the operand quieting that the IEEE
-// maximum adds for matrix-core results.
+// activation of 4 values and bfloat16 packing (RELU: the median with 0)
 template <bool RELU>
 __device__ __forceinline__ v4s act_pack(v4f x, float s) {
-  constexpr float big = 3.40282347e38f;
   v4f y;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) y[j] = __builtin_amdgcn_fmed3f(x[j], RELU ? 0.f : s * x[j], big);
+  for (int j = 0; j < 4; ++j) y[j] = __builtin_amdgcn_fmed3f(x[j], RELU ? 0.f : s * x[j], kFltMax);
   return pack_bf16(y);
 }
+
+// g * actd(h) for a bfloat16 activation output h (its bits): h > 0 exactly
+// when the bits, read as a 16-bit integer, are positive
+__device__ __forceinline__ float actd_mul(float g, short h, float s) { return h > 0 ? g : s * g; }
 
 // The forward items of one wave (see k_decode_fwd16).
 template <int W, int H, bool RELU>
@@ -1202,7 +1214,7 @@ __global__ __launch_bounds__(64 * kB16W) void k_decode_bwd16(
       for (int mt = 0; mt < NT; ++mt) {
         const v4f a = mfma16(wtr<W>(sW + (H - 1) * W * LD, 4 * q + (c >> 2), mt, c), gotb, v4f{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-        for (int r = 0; r < 4; ++r) gp[mt][r] = a[r] * actd(bf16_val(h[H - 1][mt][r]), ap);
+        for (int r = 0; r < 4; ++r) gp[mt][r] = actd_mul(a[r], h[H - 1][mt][r], ap.slope);
       }
       __syncthreads();
 
@@ -1244,7 +1256,7 @@ __global__ __launch_bounds__(64 * kB16W) void k_decode_bwd16(
 #pragma unroll
         for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) gp[mt][r] = gh[mt][r] * actd(bf16_val(h[l - 1][mt][r]), ap);
+          for (int r = 0; r < 4; ++r) gp[mt][r] = actd_mul(gh[mt][r], h[l - 1][mt][r], ap.slope);
         if (l > 1) __syncthreads();
       }
 
@@ -1606,7 +1618,8 @@ hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const f
                                  float4* nhat) {
   hipError_t e = prep(P, params, z);
   if (e != hipSuccess) return e;
-  ActP ap{P->cfg.act == NPG_ACT_RELU, P->cfg.leaky_slope};
+  const bool relu = P->cfg.act == NPG_ACT_RELU;
+  ActP ap{relu, relu ? 0.f : P->cfg.leaky_slope};
   if (is_bf16(P)) {
     NPG_DISPATCH(launch_fwd16, P, xhat, ap, nhat);
   }
@@ -1640,7 +1653,8 @@ hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const f
                                  float* grad, float* gz) {
   hipError_t e = prep(P, params, z);
   if (e != hipSuccess) return e;
-  ActP ap{P->cfg.act == NPG_ACT_RELU, P->cfg.leaky_slope};
+  const bool relu = P->cfg.act == NPG_ACT_RELU;
+  ActP ap{relu, relu ? 0.f : P->cfg.leaky_slope};
   e = is_bf16(P) ? [&]() -> hipError_t { NPG_DISPATCH(launch_bwd16, P, gxhat, ap); }()
                  : [&]() -> hipError_t { NPG_DISPATCH(launch_bwd, P, gxhat, ap); }();
   if (e != hipSuccess) return e;
