@@ -11,9 +11,15 @@
 // One CG iteration is two streaming kernels:
 //   k_cg_dir_ap:  p = r + beta p, and p.(A p) with A p formed on the fly from
 //                 r and the old p at the 6 neighbours (p is written, A p is not)
-//   k_cg_update:  x += alpha p, r -= alpha A p (A p recomputed from p),
-//                 and r.r
-// i.e. 8 vector passes (r, p, p | p, x, r, x, r) instead of storing A p.
+//   k_cg_update:  r -= alpha A p (A p recomputed from p) and r.r; x is
+//                 updated every second iteration only, with both pending terms
+//                 (x += alpha_{k-1} p_{k-1}, then x += alpha_k p_k: the same
+//                 float32 operations in the same order as one update per
+//                 iteration), the older direction read from the other
+//                 ping-pong buffer
+// i.e. 7.5 vector passes per iteration on average (r, p, p | p, r, r, and
+// every second iteration p_{k-1}, x, x) instead of 10 with A p stored. A
+// term left pending when a system stops is added by a flush pass.
 // A p = p + lam * sum over existing neighbours of (p_n - p_nb): sums of
 // differences keep the float32 rounding proportional to |A p|, not to
 // (1 + 12 lam)|p|.
@@ -31,7 +37,8 @@ constexpr int kB = 256;       // threads per work-group
 constexpr int kPer = 8;       // nodes per thread
 constexpr int kChunk = kB * kPer;
 
-// per (system, channel) scalars: 0 rr, 1 bb, 2 pq, 3 alpha, 4 beta, 5 active, 6 iterations
+// per (system, channel) scalars: 0 rr, 1 bb, 2 pq, 3 alpha, 4 beta, 5 active, 6 iterations,
+// 7 alpha of the pending x term (0 when none)
 constexpr int kS = 8;
 
 // Loads/stores of one node's F channels: vector instructions when the grid's
@@ -214,13 +221,17 @@ __device__ void dir_ap_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
   store_partials<F>(acc, part, blk);
 }
 
-// x += alpha p, r -= alpha A p; rr partial.
-template <int FV, int F = (FV < 0 ? -FV : FV)>
+// r -= alpha A p; rr partial. XM = 1: also x += alpha_prev p_prev, then
+// x += alpha p (the term of the previous iteration and this one's).
+template <int XM, int FV, int F = (FV < 0 ? -FV : FV)>
 __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& fR2, int64_t n0, const double* st,
-                            int s, float* x, float* r, const float* p, double* part, int blk) {
-  float al[F];
+                            int s, float* x, float* r, const float* p, const float* p_prev, double* part, int blk) {
+  float al[F], ap[F];
 #pragma unroll
-  for (int c = 0; c < F; ++c) al[c] = (float)st[(s * 4 + c) * kS + 3];
+  for (int c = 0; c < F; ++c) {
+    al[c] = (float)st[(s * 4 + c) * kS + 3];
+    ap[c] = (float)st[(s * 4 + c) * kS + 7];
+  }
   const float lam = g.lam;
   const float* pb = p + g.poff;
   double acc[4] = {0, 0, 0, 0};
@@ -229,7 +240,7 @@ __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
     if (n >= g.nodes) break;
     const Nb nb = neighbours((uint32_t)n, g.R, fR, fR2);
     const int64_t e = g.poff + n * F;
-    float pc[F], lap[F], xc[F], rc[F];
+    float pc[F], lap[F], rc[F];
     Vec<FV>::load(pb + n * F, pc);
 #pragma unroll
     for (int c = 0; c < F; ++c) lap[c] = 0.f;
@@ -242,15 +253,20 @@ __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
         for (int c = 0; c < F; ++c) lap[c] += pc[c] - pm[c];
       }
     }
-    Vec<FV>::load(x + e, xc);
+    if (XM) {
+      float xc[F], pp[F];
+      Vec<FV>::load(x + e, xc);
+      Vec<FV>::load(p_prev + e, pp);
+#pragma unroll
+      for (int c = 0; c < F; ++c) xc[c] = fmaf(al[c], pc[c], fmaf(ap[c], pp[c], xc[c]));
+      Vec<FV>::store(x + e, xc);
+    }
     Vec<FV>::load(r + e, rc);
 #pragma unroll
     for (int c = 0; c < F; ++c) {
-      xc[c] = fmaf(al[c], pc[c], xc[c]);
       rc[c] = fmaf(-al[c], fmaf(lam, lap[c], pc[c]), rc[c]);
       acc[c] += (double)rc[c] * (double)rc[c];
     }
-    Vec<FV>::store(x + e, xc);
     Vec<FV>::store(r + e, rc);
   }
   store_partials<F>(acc, part, blk);
@@ -438,36 +454,56 @@ __device__ void zm_dir_ap(const NpgGrid& g, const Tile& t, const double* st, int
   store_partials<4>(acc, part, blk);
 }
 
+struct Raw3 {
+  float4 a, b, c;
+};
+
+template <int XM>
 __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, float* x, float* r,
-                          const float* p, double* part, int blk) {
-  float al[4];
+                          const float* p, const float* p_prev, double* part, int blk) {
+  float al[4], ap[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) al[c] = (float)st[(s * 4 + c) * kS + 3];
+  for (int c = 0; c < 4; ++c) {
+    al[c] = (float)st[(s * 4 + c) * kS + 3];
+    ap[c] = (float)st[(s * 4 + c) * kS + 7];
+  }
   const float lam = g.lam;
   const float4* Pp = reinterpret_cast<const float4*>(p + g.poff);
+  const float4* Pq = reinterpret_cast<const float4*>(p_prev + g.poff);
   float4* X = reinterpret_cast<float4*>(x + g.poff);
   float4* Rr = reinterpret_cast<float4*>(r + g.poff);
   double acc[4] = {0, 0, 0, 0};
-  zm_walk<Raw1, Raw2>(
-      g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw2{X[n], Rr[n]}; },
-      [&](const Raw1& v) { return v.a; },
-      [&](int64_t n, const float4& lap, const float4& pc, const Raw2& e) {
-        float4 xv = e.a, rv = e.b;
-        xv.x = fmaf(al[0], pc.x, xv.x);
-        xv.y = fmaf(al[1], pc.y, xv.y);
-        xv.z = fmaf(al[2], pc.z, xv.z);
-        xv.w = fmaf(al[3], pc.w, xv.w);
-        rv.x = fmaf(-al[0], fmaf(lam, lap.x, pc.x), rv.x);
-        rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
-        rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
-        rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
-        X[n] = xv;
-        Rr[n] = rv;
-        acc[0] += (double)rv.x * rv.x;
-        acc[1] += (double)rv.y * rv.y;
-        acc[2] += (double)rv.z * rv.z;
-        acc[3] += (double)rv.w * rv.w;
-      });
+  auto r_update = [&](int64_t n, const float4& lap, const float4& pc, float4 rv) {
+    rv.x = fmaf(-al[0], fmaf(lam, lap.x, pc.x), rv.x);
+    rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
+    rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
+    rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
+    Rr[n] = rv;
+    acc[0] += (double)rv.x * rv.x;
+    acc[1] += (double)rv.y * rv.y;
+    acc[2] += (double)rv.z * rv.z;
+    acc[3] += (double)rv.w * rv.w;
+  };
+  if (XM) {
+    zm_walk<Raw1, Raw3>(
+        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw3{X[n], Rr[n], Pq[n]}; },
+        [&](const Raw1& v) { return v.a; },
+        [&](int64_t n, const float4& lap, const float4& pc, const Raw3& e) {
+          float4 xv = e.a;
+          const float4 pq = e.c;
+          xv.x = fmaf(al[0], pc.x, fmaf(ap[0], pq.x, xv.x));
+          xv.y = fmaf(al[1], pc.y, fmaf(ap[1], pq.y, xv.y));
+          xv.z = fmaf(al[2], pc.z, fmaf(ap[2], pq.z, xv.z));
+          xv.w = fmaf(al[3], pc.w, fmaf(ap[3], pq.w, xv.w));
+          X[n] = xv;
+          r_update(n, lap, pc, e.b);
+        });
+  } else {
+    zm_walk<Raw1, Raw1>(
+        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw1{Rr[n]}; },
+        [&](const Raw1& v) { return v.a; },
+        [&](int64_t n, const float4& lap, const float4& pc, const Raw1& e) { r_update(n, lap, pc, e.a); });
+  }
   store_partials<4>(acc, part, blk);
 }
 
@@ -481,7 +517,6 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
     default: { constexpr int FF = 1; CALL; } break;                         \
   }
 
-// b may alias x (second solve): no __restrict__ on either.
 __global__ __launch_bounds__(kB) void k_cg_init(const NpgGrid* __restrict__ G, int nb, const int* __restrict__ blk_sys,
                                                 const int64_t* __restrict__ blk_start, const float* b, float* x,
                                                 float* __restrict__ r, float* __restrict__ p,
@@ -518,30 +553,42 @@ __global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G,
   NPG_F_SWITCH(g, (dir_ap_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, r, p_old, p_new, part, blk)));
 }
 
+template <int XM>
 __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G, Divs dv, int nb, const int* __restrict__ blk_sys,
                                                   const int64_t* __restrict__ blk_start,
                                                   const int* __restrict__ active, const double* __restrict__ st,
                                                   float* __restrict__ x, float* __restrict__ r,
-                                                  const float* __restrict__ p, double* __restrict__ part) {
+                                                  const float* __restrict__ p, const float* __restrict__ p_prev,
+                                                  double* __restrict__ part) {
   const int blk = logical_block(nb);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   if (!active[s]) return;
   const NpgGrid g = G[s];
   if (use_zm(g)) {
-    zm_update(g, unpack_tile(blk_start[blk]), st, s, x, r, p, part, blk);
+    zm_update<XM>(g, unpack_tile(blk_start[blk]), st, s, x, r, p, p_prev, part, blk);
     return;
   }
-  NPG_F_SWITCH(g, (update_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, x, r, p, part, blk)));
+  NPG_F_SWITCH(g, (update_body<XM, FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, x, r, p, p_prev, part, blk)));
 }
 
+// The pending x term of one system: x += alpha_pending p (flat, F channels).
+__global__ void k_cg_flush(float* __restrict__ x, const float* __restrict__ p, int64_t n, int F, float a0, float a1,
+                           float a2, float a3) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int c = (int)(e % F);
+  const float a = c == 0 ? a0 : (c == 1 ? a1 : (c == 2 ? a2 : a3));
+  x[e] = fmaf(a, p[e], x[e]);
+}
 // Per system (one work-group each): reduce the block partials in order and
 // update the scalars. mode 0: after init (rr, bb); 1: alpha = rr / pq;
-// 2: beta = rr_new / rr and the convergence test.
+// 2: beta = rr_new / rr and the convergence test (defer: the update left
+// this iteration's x term pending).
 constexpr int kR = 1024;
 __global__ __launch_bounds__(kR) void k_cg_reduce(const NpgGrid* __restrict__ G, const int* __restrict__ sys_blk0,
                                                   int* __restrict__ active, const double* __restrict__ part,
-                                                  double* __restrict__ st, int mode, double rtol) {
+                                                  double* __restrict__ st, int mode, double rtol, int defer) {
   const int s = blockIdx.x;
   if (mode != 0 && !active[s]) return;
   __shared__ double red[4][kR / 64];
@@ -573,30 +620,29 @@ __global__ __launch_bounds__(kR) void k_cg_reduce(const NpgGrid* __restrict__ G,
       S[3] = 0.0;
       S[4] = 0.0;
       S[6] = 0.0;
+      S[7] = 0.0;
       S[5] = v > 0.0 ? 1.0 : 0.0;
     } else if (mode == 1) {
       S[3] = (S[5] != 0.0 && v > 0.0) ? S[0] / v : 0.0;
-    } else if (S[5] != 0.0) {
-      S[4] = S[0] > 0.0 ? v / S[0] : 0.0;
-      S[0] = v;
-      S[6] += 1.0;
-      if (!(sqrt(v) > rtol * sqrt(S[1]))) {
-        S[5] = 0.0;
+    } else {
+      S[7] = defer ? S[3] : 0.0;  // this iteration's x term, when the update left it pending
+      if (S[5] != 0.0) {
+        S[4] = S[0] > 0.0 ? v / S[0] : 0.0;
+        S[0] = v;
+        S[6] += 1.0;
+        if (!(sqrt(v) > rtol * sqrt(S[1]))) {
+          S[5] = 0.0;
+          S[3] = 0.0;
+          S[4] = 0.0;
+        }
+      } else {
         S[3] = 0.0;
         S[4] = 0.0;
       }
-    } else {
-      S[3] = 0.0;
-      S[4] = 0.0;
     }
     any |= S[5] != 0.0;
   }
   active[s] = any;
-}
-
-__global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -653,10 +699,14 @@ void npg_cg_free(npg_plan* P) {
   hipFree(C.active); hipFree(C.blk_sys); hipFree(C.blk_start); hipFree(C.sys_blk0);
 }
 
-// Solve (I + lam L) x = b for every system; the solution is left in C.x
-// (b may alias C.x: each node of b is read before its x is cleared).
-// The iteration count of each system goes to iters (if not NULL).
-static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* capped, double* relres) {
+// Solve (I + lam L) x = b for every system (b and x distinct buffers in the
+// grid-block layout). The iteration count of each system goes to iters (if
+// not NULL). Iteration k writes p_k into C.q for even k and into C.p for odd
+// k; the update of an even iteration leaves its x term pending (p_k stays in
+// C.q: later iterations write only the blocks of systems still active), the
+// next odd one adds both terms, and a term still pending when a system stops
+// is added at the end.
+static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters, bool* capped, double* relres) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nb = C.n_blocks;
@@ -666,9 +716,9 @@ static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* ca
     dv.r[sy] = make_fastdiv((uint32_t)P->g[sy].R);
     dv.r2[sy] = make_fastdiv((uint32_t)P->g[sy].R * (uint32_t)P->g[sy].R);
   }
-  hipLaunchKernelGGL(k_cg_init, grid, blk, 0, s, P->d_g, nb, C.blk_sys, C.blk_start, b, C.x, C.r, C.p, C.part);
+  hipLaunchKernelGGL(k_cg_init, grid, blk, 0, s, P->d_g, nb, C.blk_sys, C.blk_start, b, x, C.r, C.p, C.part);
   hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR), 0, s, P->d_g, C.sys_blk0, C.active, C.part, C.st, 0,
-                     P->cfg.cg_rtol);
+                     P->cfg.cg_rtol, 0);
   NPG_HIP(hipGetLastError());
   std::vector<int> act(P->n_sys);
   float* pa = C.p;  // current direction
@@ -679,6 +729,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* ca
   while (it < maxit) {
     const int chunk = 16 < maxit - it ? 16 : maxit - it;
     for (int k = 0; k < chunk; ++k) {
+      const bool odd = ((it + k) & 1) != 0;
       // optional profiling: event pairs around both streaming kernels,
       // resolved after the step (no synchronisation here)
       const bool prof = P->prof_cg && P->prof_n + 4 <= (int)P->prof_ev.size();
@@ -686,18 +737,22 @@ static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* ca
       hipLaunchKernelGGL(k_cg_dir_ap, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st, C.r,
                          pa, pb, C.part);
       if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], s));
-      std::swap(pa, pb);
+      std::swap(pa, pb);  // pa = p_k, pb = p_{k-1}
       hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR), 0, s, P->d_g, C.sys_blk0, C.active, C.part, C.st, 1,
-                         P->cfg.cg_rtol);
+                         P->cfg.cg_rtol, 0);
       if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 2], s));
-      hipLaunchKernelGGL(k_cg_update, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st, C.x,
-                         C.r, pa, C.part);
+      if (odd)
+        hipLaunchKernelGGL(k_cg_update<1>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
+                           x, C.r, pa, pb, C.part);
+      else
+        hipLaunchKernelGGL(k_cg_update<0>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
+                           x, C.r, pa, pb, C.part);
       if (prof) {
         NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 3], s));
         P->prof_n += 4;
       }
       hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR), 0, s, P->d_g, C.sys_blk0, C.active, C.part, C.st, 2,
-                         P->cfg.cg_rtol);
+                         P->cfg.cg_rtol, (int)!odd);
     }
     NPG_HIP(hipGetLastError());
     it += chunk;
@@ -712,22 +767,33 @@ static npg_status cg_solve(npg_plan* P, const float* b, int32_t* iters, bool* ca
   NPG_HIP(hipMemcpyAsync(stv.data(), C.st, stv.size() * 8, hipMemcpyDeviceToHost, s));
   NPG_HIP(hipStreamSynchronize(s));
   for (int sy = 0; sy < P->n_sys; ++sy) {
+    const NpgGrid& g = P->g[sy];
     double m = 0;
-    for (int c = 0; c < P->g[sy].F; ++c) m = stv[(sy * 4 + c) * kS + 6] > m ? stv[(sy * 4 + c) * kS + 6] : m;
+    for (int c = 0; c < g.F; ++c) m = stv[(sy * 4 + c) * kS + 6] > m ? stv[(sy * 4 + c) * kS + 6] : m;
     if (iters) iters[sy] = (int32_t)m;
     // final relative residual ||r|| / ||b|| in float64, the largest over the channels
     double rel = 0.0;
-    for (int c = 0; c < P->g[sy].F; ++c) {
-      const double rr = stv[(sy * 4 + c) * kS + 0], bb = stv[(sy * 4 + c) * kS + 1];
-      const double v = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    float pend[4] = {0.f, 0.f, 0.f, 0.f};
+    bool any = false;
+    for (int c = 0; c < g.F; ++c) {
+      const double* S = stv.data() + (sy * 4 + c) * kS;
+      const double v = S[1] > 0.0 ? sqrt(S[0] / S[1]) : 0.0;
       rel = v > rel ? v : rel;
+      pend[c] = (float)S[7];
+      any |= S[7] != 0.0;
     }
     relres[sy] = rel;
+    if (any) {
+      const int64_t n = g.nodes * g.F;
+      hipLaunchKernelGGL(k_cg_flush, dim3(nblk(n, 256)), dim3(256), 0, s, x + g.poff, C.q + g.poff, n, g.F, pend[0],
+                         pend[1], pend[2], pend[3]);
+    }
     // algorithmic traffic of this solve: 6 vector passes (x, r, p read and
     // written) per iteration over the grid's R^3 F float32 unknowns
-    P->cg_alg_bytes += m * 6.0 * (double)P->g[sy].nodes * P->g[sy].F * 4.0;
+    P->cg_alg_bytes += m * 6.0 * (double)g.nodes * g.F * 4.0;
     P->cg_iters_sum += (int64_t)m;
   }
+  NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
 
@@ -735,12 +801,10 @@ npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters) {
   bool capped = false;
   P->cg_alg_bytes = 0.0;
   P->cg_iters_sum = 0;
-  npg_status st = cg_solve(P, grad, iters, &capped, P->cg_relres);
+  // y = A^-1 g into the workspace, then A^-1 y back into the gradient
+  npg_status st = cg_solve(P, grad, P->cg.x, iters, &capped, P->cg_relres);
   if (st != NPG_OK) return st;
-  st = cg_solve(P, P->cg.x, iters ? iters + P->n_sys : nullptr, &capped, P->cg_relres + P->n_sys);
+  st = cg_solve(P, P->cg.x, grad, iters ? iters + P->n_sys : nullptr, &capped, P->cg_relres + P->n_sys);
   if (st != NPG_OK) return st;
-  hipLaunchKernelGGL(k_copy, dim3(nblk(P->n_grid_params, 256)), dim3(256), 0, P->stream, P->cg.x, grad,
-                     P->n_grid_params);
-  NPG_HIP(hipGetLastError());
   return capped ? NPG_ENOTCONV : NPG_OK;
 }
