@@ -113,6 +113,8 @@ typedef struct npg_config {
   float w_iso;                    /* isometry-loss weight of Sec. 3.5 (paper: 100); */
                                   /* 0 disables the term, > 0 needs the mesh edges  */
   int32_t precision;              /* NPG_PREC_FP32 or NPG_PREC_BF16                 */
+  int32_t cg_mg;                  /* CG form: 1 preconditions every solve with a     */
+                                  /* multigrid V-cycle, 0 runs plain CG             */
 } npg_config;
 
 typedef struct npg_plan npg_plan;
@@ -326,8 +328,12 @@ npg_status npg_encode_bwd(npg_plan* plan, const float* gz_dev, float* grad_dev);
  * in place by (I + lambda L)^-2 g per feature channel, L the 6-neighbour
  * lattice Laplacian with free boundary (degree minus adjacency). MLP block
  * untouched. With NPG_PRECOND_CG: two conjugate-gradient solves from zero
- * with float64 inner products, synchronizing every 16 iterations;
- * iters_host [2*(L+1)] (may be NULL) receives the iteration counts.
+ * with float64 inner products, synchronizing every 16 iterations, each
+ * stopped at ||r|| <= cg_rtol ||b||; with cg_mg = 1 the solves are
+ * preconditioned by a symmetric multigrid V-cycle (2x2x2 aggregates, Galerkin
+ * coarse operators, damped Jacobi smoothing), which cuts the iteration count
+ * several-fold. iters_host [2*(L+1)] (may be NULL) receives the iteration
+ * counts.
  */
 npg_status npg_precond(npg_plan* plan, float* grad_dev, int32_t* iters_host);
 

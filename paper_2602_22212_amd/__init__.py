@@ -41,6 +41,7 @@ class npg_config(ctypes.Structure):
         ("conf_weight", ctypes.c_int32), ("t_key", ctypes.c_int32),
         ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precond", ctypes.c_int32),
         ("rot_head", ctypes.c_int32), ("w_iso", ctypes.c_float), ("precision", ctypes.c_int32),
+        ("cg_mg", ctypes.c_int32),
     ]
 
 
@@ -131,6 +132,7 @@ def make_config(cfg):
     c.t_key = -1 if cfg.get("t_key") is None else int(cfg["t_key"])
     c.cg_rtol, c.cg_maxit = float(cfg["cg_rtol"]), int(cfg["cg_maxit"])
     c.precond = NPG_PRECOND_DCT if cfg.get("precond", "cg") == "dct" else NPG_PRECOND_CG
+    c.cg_mg = int(cfg.get("cg_mg", 1))
     head = cfg.get("rot_head", "expmap")
     if head not in ("expmap", "quat"):
         raise ValueError(f"rot_head must be 'expmap' or 'quat', not {head!r}")

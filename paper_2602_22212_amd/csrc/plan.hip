@@ -93,6 +93,7 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->eps > 0.f, "eps must be > 0");
   CHECK_ARG(c->cg_maxit >= 1 && c->cg_rtol > 0.0, "cg_maxit >= 1 and cg_rtol > 0 are required");
   CHECK_ARG(c->precond == NPG_PRECOND_CG || c->precond == NPG_PRECOND_DCT, "precond must be CG or DCT");
+  CHECK_ARG(c->cg_mg == 0 || c->cg_mg == 1, "cg_mg must be 0 or 1");
   CHECK_ARG(c->rot_head == NPG_ROT_EXPMAP || c->rot_head == NPG_ROT_QUAT, "rot_head must be EXPMAP or QUAT");
   CHECK_ARG(c->w_iso >= 0.f && std::isfinite(c->w_iso), "w_iso must be finite and >= 0");
   CHECK_ARG(c->precision == NPG_PREC_FP32 || c->precision == NPG_PREC_BF16, "precision must be FP32 or BF16");

@@ -31,15 +31,22 @@
 
 #include "internal.h"
 
+#define NPG_TRY_ST(call)                  \
+  do {                                    \
+    const npg_status st_ = (call);        \
+    if (st_ != NPG_OK) return st_;        \
+  } while (0)
+
 namespace {
 
 constexpr int kB = 256;       // threads per work-group
 constexpr int kPer = 8;       // nodes per thread
 constexpr int kChunk = kB * kPer;
 
-// per (system, channel) scalars: 0 rr, 1 bb, 2 pq, 3 alpha, 4 beta, 5 active, 6 iterations,
-// 7 alpha of the pending x term (0 when none)
+// per (system, channel) scalars: 0 rho (r.z with the V-cycle, else r.r), 1 bb, 2 rr, 3 alpha,
+// 4 beta, 5 active, 6 iterations, 7 alpha of the pending x term (0 when none)
 constexpr int kS = 8;
+constexpr int kR_THREADS = 1024, kR_WAVES = kR_THREADS / 64;  // reduction work-group
 
 // Loads/stores of one node's F channels: vector instructions when the grid's
 // offset keeps every node 4F-byte aligned (always for F = 1 and 3, which use
@@ -581,21 +588,13 @@ __global__ void k_cg_flush(float* __restrict__ x, const float* __restrict__ p, i
   const float a = c == 0 ? a0 : (c == 1 ? a1 : (c == 2 ? a2 : a3));
   x[e] = fmaf(a, p[e], x[e]);
 }
-// Per system (one work-group each): reduce the block partials in order and
-// update the scalars. mode 0: after init (rr, bb); 1: alpha = rr / pq;
-// 2: beta = rr_new / rr and the convergence test (defer: the update left
-// this iteration's x term pending).
-constexpr int kR = 1024;
-__global__ __launch_bounds__(kR) void k_cg_reduce(const NpgGrid* __restrict__ G, const int* __restrict__ sys_blk0,
-                                                  int* __restrict__ active, const double* __restrict__ part,
-                                                  double* __restrict__ st, int mode, double rtol, int defer) {
-  const int s = blockIdx.x;
-  if (mode != 0 && !active[s]) return;
-  __shared__ double red[4][kR / 64];
-  const int F = G[s].F;
-  const int b0 = sys_blk0[s], b1 = sys_blk0[s + 1];
+// Sum of the block partials [b0, b1) of part per channel, in a fixed order
+// (strided per thread, then per wave, then the waves in order); the result
+// is valid in thread 0.
+__device__ __forceinline__ void reduce_range(const double* part, int b0, int b1, double (*red)[kR_WAVES],
+                                             double (&out)[4]) {
   double acc[4] = {0, 0, 0, 0};
-  for (int b = b0 + threadIdx.x; b < b1; b += kR) {
+  for (int b = b0 + threadIdx.x; b < b1; b += kR_THREADS) {
     const double4 v = *reinterpret_cast<const double4*>(part + (int64_t)b * 4);
     acc[0] += v.x;
     acc[1] += v.y;
@@ -608,15 +607,42 @@ __global__ __launch_bounds__(kR) void k_cg_reduce(const NpgGrid* __restrict__ G,
     if (lane == 0) red[c][wave] = v;
   }
   __syncthreads();
+  for (int c = 0; c < 4; ++c) {
+    double v = 0.0;
+    for (int w = 0; w < kR_WAVES; ++w) v += red[c][w];
+    out[c] = v;
+  }
+}
+
+// Per system (one work-group each): reduce the block partials in order and
+// update the scalars (S[0] rho = r.z, or r.r without the V-cycle; S[2] r.r).
+// mode 0: after init (bb, rho); 1: alpha = rho / pq; 2: beta = rho_new / rho
+// and the convergence test on r.r (defer: the update left this iteration's x
+// term pending). part2 (NULL without the V-cycle): the r.z partials.
+__global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restrict__ G,
+                                                          const int* __restrict__ sys_blk0, int* __restrict__ active,
+                                                          const double* __restrict__ part,
+                                                          const double* __restrict__ part2,
+                                                          const int* __restrict__ mg_blk0, double* __restrict__ st,
+                                                          int mode, double rtol, int defer) {
+  const int s = blockIdx.x;
+  if (mode != 0 && !active[s]) return;
+  __shared__ double red[4][kR_WAVES], red2[4][kR_WAVES];
+  const int F = G[s].F;
+  double vv[4], rho[4];
+  reduce_range(part, sys_blk0[s], sys_blk0[s + 1], red, vv);
+  if (part2 && mode != 1) reduce_range(part2, mg_blk0[s], mg_blk0[s + 1], red2, rho);
+  else
+    for (int c = 0; c < 4; ++c) rho[c] = vv[c];
   if (threadIdx.x != 0) return;
   int any = 0;
   for (int c = 0; c < F; ++c) {
-    double v = 0.0;
-    for (int w = 0; w < kR / 64; ++w) v += red[c][w];
+    const double v = vv[c];
     double* S = st + (s * 4 + c) * kS;
     if (mode == 0) {
-      S[0] = v;
+      S[0] = rho[c];
       S[1] = v;
+      S[2] = v;
       S[3] = 0.0;
       S[4] = 0.0;
       S[6] = 0.0;
@@ -627,8 +653,9 @@ __global__ __launch_bounds__(kR) void k_cg_reduce(const NpgGrid* __restrict__ G,
     } else {
       S[7] = defer ? S[3] : 0.0;  // this iteration's x term, when the update left it pending
       if (S[5] != 0.0) {
-        S[4] = S[0] > 0.0 ? v / S[0] : 0.0;
-        S[0] = v;
+        S[4] = S[0] > 0.0 ? rho[c] / S[0] : 0.0;
+        S[0] = rho[c];
+        S[2] = v;
         S[6] += 1.0;
         if (!(sqrt(v) > rtol * sqrt(S[1]))) {
           S[5] = 0.0;
@@ -645,10 +672,521 @@ __global__ __launch_bounds__(kR) void k_cg_reduce(const NpgGrid* __restrict__ G,
   active[s] = any;
 }
 
+// ---- multigrid V-cycle preconditioner ----------------------------------------
+// Level l of a system aggregates 2^l x 2^l x 2^l fine nodes (fewer at the far
+// faces): n_l = ceil(R / 2^l) nodes per axis, extent e(i) = min(2^l, R - 2^l i)
+// fine nodes along an axis. With piecewise-constant prolongation P the
+// Galerkin operator P^T A P of A = I + lam L is again "mass + lam weighted
+// Laplacian": mass = ex ey ez, the weight of a face = its area in fine nodes
+// (ey ez across x, ...). One V-cycle (preconditioner input b, output x):
+// x0 = w D^-1 b; restrict b - A x0 to the next level; recurse; x = x0 + P e;
+// x += w D^-1 (b - A x). The coarsest level (n <= 8) takes kMgCoarse damped
+// Jacobi sweeps from zero. Smoothing before and after is the same symmetric
+// Jacobi step and the restriction is P^T, so the preconditioner is symmetric
+// and positive definite (w < 1 < 2 / rho(D^-1 A)).
+constexpr float kMgOmega = 0.8f;
+constexpr int kMgCoarse = 4;
+constexpr int kMgMinN = 8;
+constexpr int kMgB = 256;
+
+struct MgLvl {
+  int64_t off;  // float offset of the level's [node][F] array
+  int n, s, R, F;
+  float lam;
+  FastDiv fn, fn2;  // division by n and n^2
+};
+struct MgTask {
+  int sys, blk0;  // system; first block of the system in its launch
+  int64_t nodes;  // threads of the system
+  MgLvl lo, hi;   // finer and coarser level (the coarsest launch uses lo)
+  // fast path of a level with uniform aggregates (F = 4, 16-byte aligned):
+  // mass s^3, lam times the face weight s^2, and the divisions of the
+  // prolongation's thread index (one thread per pair of x-adjacent nodes:
+  // ceil(n/2) x n x n threads)
+  int fast;
+  float mass, lw;
+  FastDiv fx, fx2;
+};
+
+__device__ __forceinline__ int mg_ext(int i, const MgLvl& L) { return min(L.s, L.R - L.s * i); }
+
+// Mass, face weights and neighbour mask (bit d: neighbour d exists; order
+// -x, +x, -y, +y, -z, +z) of node (i, j, k), and its Jacobi diagonal.
+struct MgNode {
+  float mass, wx, wy, wz, diag;
+  int mask;
+};
+__device__ __forceinline__ MgNode mg_node(int i, int j, int k, const MgLvl& L) {
+  const float ex = (float)mg_ext(i, L), ey = (float)mg_ext(j, L), ez = (float)mg_ext(k, L);
+  MgNode m;
+  m.mass = ex * ey * ez;
+  m.wx = ey * ez;
+  m.wy = ex * ez;
+  m.wz = ex * ey;
+  m.mask = (i > 0) | ((i < L.n - 1) << 1) | ((j > 0) << 2) | ((j < L.n - 1) << 3) | ((k > 0) << 4) |
+           ((k < L.n - 1) << 5);
+  const float nx = (float)((i > 0) + (i < L.n - 1)), ny = (float)((j > 0) + (j < L.n - 1)),
+              nz = (float)((k > 0) + (k < L.n - 1));
+  m.diag = m.mass + L.lam * (m.wx * nx + m.wy * ny + m.wz * nz);
+  return m;
+}
+__device__ __forceinline__ void mg_load(const float* p, int F, float (&v)[4]) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = c < F ? p[c] : 0.f;
+}
+__device__ __forceinline__ int64_t mg_idx(int i, int j, int k, int n) { return ((int64_t)k * n + j) * n + i; }
+
+// x0 = w b / d at node (i, j, k) of level L (b: the level's array)
+__device__ __forceinline__ void mg_x0(const float* b, const MgLvl& L, int i, int j, int k, float (&x)[4]) {
+  const MgNode m = mg_node(i, j, k, L);
+  mg_load(b + L.off + mg_idx(i, j, k, L.n) * L.F, L.F, x);
+  const float f = kMgOmega * __builtin_amdgcn_rcpf(m.diag);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) x[c] *= f;
+}
+
+// Logical block of a launch of nblk blocks (grid padded to a multiple of 8):
+// work-groups go to the 8 XCDs in turn, and XCD x takes the x-th contiguous
+// eighth of the logical blocks in order, so the neighbour rows and planes a
+// block reads were fetched into the same L2 by the blocks just before it.
+// -1 for the padding.
+__device__ __forceinline__ int mg_block(int nblk) {
+  const int per = (nblk + kXCD - 1) / kXCD;
+  const int b = (int)blockIdx.x;
+  const int L = (b % kXCD) * per + b / kXCD;
+  return L < nblk ? L : -1;
+}
+// Logical block -> task (tasks sorted by blk0)
+__device__ __forceinline__ const MgTask* mg_task(const MgTask* T, int nt, int blk) {
+  int t = 0;
+  while (t + 1 < nt && blk >= T[t + 1].blk0) ++t;
+  return T + t;
+}
+
+__device__ __forceinline__ void mg_coords(int64_t m, const MgLvl& L, int& i, int& j, int& k) {
+  k = (int)fdiv((uint32_t)m, L.fn2);
+  const uint32_t rem = (uint32_t)m - (uint32_t)k * L.fn2.d;
+  j = (int)fdiv(rem, L.fn);
+  i = (int)(rem - (uint32_t)j * (uint32_t)L.n);
+}
+
+// ---- levels with uniform aggregates (R a multiple of the extent s) and F = 4:
+// float4 loads, 32-bit node indices, mass s^3 and face weight s^2 for every
+// node, Jacobi factor w / (s^3 + lam s^2 deg) from the node's degree
+__device__ __forceinline__ int mg_deg1(int i, int n) { return (i > 0) + (i < n - 1); }
+__device__ __forceinline__ float mg_f(const MgTask* tk, int d) {
+  return kMgOmega * __builtin_amdgcn_rcpf(fmaf(tk->lw, (float)d, tk->mass));
+}
+__device__ __forceinline__ float4 f4sub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+__device__ __forceinline__ float4 f4add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+__device__ __forceinline__ float4 f4scale(float s, float4 a) { return make_float4(s * a.x, s * a.y, s * a.z, s * a.w); }
+__device__ __forceinline__ float4 f4axpy(float s, float4 a, float4 y) {  // y + s a
+  return make_float4(fmaf(s, a.x, y.x), fmaf(s, a.y, y.y), fmaf(s, a.z, y.z), fmaf(s, a.w, y.w));
+}
+
+// Restriction, one coarse node: the sum over the block's children of
+// b - A x0 equals sum(b - mass x0) minus lam w times the differences across
+// the block's outer faces (the inner edges cancel).
+__device__ __forceinline__ void mg_down_u4(const MgTask* tk, const float* __restrict__ bl, float* __restrict__ bh,
+                                           int m) {
+  const MgLvl& lo = tk->lo;
+  const MgLvl& hi = tk->hi;
+  const int R = lo.n;
+  int I, J, K;
+  mg_coords(m, hi, I, J, K);
+  const float4* B = reinterpret_cast<const float4*>(bl + lo.off);
+  const float nlw = -tk->lw, mass = tk->mass;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int cz = 0; cz < 2; ++cz) {
+    const int k = 2 * K + cz;
+    if (k >= R) break;
+    const int dk = mg_deg1(k, R);
+    for (int cy = 0; cy < 2; ++cy) {
+      const int j = 2 * J + cy;
+      if (j >= R) break;
+      const int dj = mg_deg1(j, R);
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const int i = 2 * I + cx;
+        if (i >= R) break;
+        const int di = mg_deg1(i, R);
+        const int n = (k * R + j) * R + i;
+        const float4 bc = B[n];
+        const float4 xc = f4scale(mg_f(tk, di + dj + dk), bc);
+        acc = f4add(acc, f4axpy(-mass, xc, bc));
+        const int ox = cx ? i + 1 : i - 1, oy = cy ? j + 1 : j - 1, oz = cz ? k + 1 : k - 1;
+        if (ox >= 0 && ox < R) {
+          const float4 xn = f4scale(mg_f(tk, mg_deg1(ox, R) + dj + dk), B[n + (ox - i)]);
+          acc = f4axpy(nlw, f4sub(xc, xn), acc);
+        }
+        if (oy >= 0 && oy < R) {
+          const float4 xn = f4scale(mg_f(tk, di + mg_deg1(oy, R) + dk), B[n + (oy - j) * R]);
+          acc = f4axpy(nlw, f4sub(xc, xn), acc);
+        }
+        if (oz >= 0 && oz < R) {
+          const float4 xn = f4scale(mg_f(tk, di + dj + mg_deg1(oz, R)), B[n + (oz - k) * R * R]);
+          acc = f4axpy(nlw, f4sub(xc, xn), acc);
+        }
+      }
+    }
+  }
+  reinterpret_cast<float4*>(bh + hi.off)[m] = acc;
+}
+
+// Prolongation and post-smoothing for the x-adjacent node pair (2I, 2I+1)
+// of row (j, k), which shares one parent in x; r.z of the pair into acc on
+// the finest level.
+__device__ __forceinline__ void mg_up_u4(const MgTask* tk, const float* __restrict__ bl,
+                                         const float* __restrict__ eh, float* __restrict__ out, int m,
+                                         double (&acc)[4]) {
+  const MgLvl& lo = tk->lo;
+  const MgLvl& hi = tk->hi;
+  const int R = lo.n, nh = hi.n;
+  const int k = (int)fdiv((uint32_t)m, tk->fx2);
+  const uint32_t rem = (uint32_t)m - (uint32_t)k * tk->fx2.d;
+  const int j = (int)fdiv(rem, tk->fx);
+  const int I = (int)(rem - (uint32_t)j * tk->fx.d);
+  const float4* B = reinterpret_cast<const float4*>(bl + lo.off);
+  const float4* E = reinterpret_cast<const float4*>(eh + hi.off);
+  float4* Z = reinterpret_cast<float4*>(out + lo.off);
+  const float lw = tk->lw, mass = tk->mass;
+  const bool fine = lo.s == 1, ident = fine && lo.lam == 0.f;
+  const int dj = mg_deg1(j, R), dk = mg_deg1(k, R);
+  const int J = j >> 1, K = k >> 1;
+  auto eat = [&](int a, int b2, int c2) { return E[(c2 * nh + b2) * nh + a]; };
+  // x = w D^-1 b + P e at node (i, jj, kk), e its parent's correction
+  auto xat = [&](int i, int jj, int kk, int dsum, float4 e) {
+    return f4add(f4scale(mg_f(tk, dsum), B[(kk * R + jj) * R + i]), e);
+  };
+  const float4 e0 = eat(I, J, K);
+  const int i0 = 2 * I, i1 = 2 * I + 1;
+  const bool has1 = i1 < R;
+  const int d0 = mg_deg1(i0, R), d1 = has1 ? mg_deg1(i1, R) : 0;
+  const float4 x0 = xat(i0, j, k, d0 + dj + dk, e0);
+  const float4 x1 = has1 ? xat(i1, j, k, d1 + dj + dk, e0) : x0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1 && !has1) break;
+    const int i = h ? i1 : i0;
+    const int di = h ? d1 : d0;
+    const float4 xc = h ? x1 : x0;
+    float4 nb = make_float4(0.f, 0.f, 0.f, 0.f);  // sum over neighbours of (x_c - x_nb)
+    if (h == 0) {
+      if (has1) nb = f4add(nb, f4sub(xc, x1));
+      if (i0 > 0) nb = f4add(nb, f4sub(xc, xat(i0 - 1, j, k, mg_deg1(i0 - 1, R) + dj + dk, eat(I - 1, J, K))));
+    } else {
+      nb = f4add(nb, f4sub(xc, x0));
+      if (i1 + 1 < R) nb = f4add(nb, f4sub(xc, xat(i1 + 1, j, k, mg_deg1(i1 + 1, R) + dj + dk, eat(I + 1, J, K))));
+    }
+    if (j > 0) nb = f4add(nb, f4sub(xc, xat(i, j - 1, k, di + mg_deg1(j - 1, R) + dk, eat(I, (j - 1) >> 1, K))));
+    if (j < R - 1) nb = f4add(nb, f4sub(xc, xat(i, j + 1, k, di + mg_deg1(j + 1, R) + dk, eat(I, (j + 1) >> 1, K))));
+    if (k > 0) nb = f4add(nb, f4sub(xc, xat(i, j, k - 1, di + dj + mg_deg1(k - 1, R), eat(I, J, (k - 1) >> 1))));
+    if (k < R - 1) nb = f4add(nb, f4sub(xc, xat(i, j, k + 1, di + dj + mg_deg1(k + 1, R), eat(I, J, (k + 1) >> 1))));
+    const int n = (k * R + j) * R + i;
+    const float4 bc = B[n];
+    const float4 ax = f4axpy(lw, nb, f4scale(mass, xc));
+    // lam = 0 (A = I): the identity preconditioner
+    const float4 z = ident ? bc : f4axpy(mg_f(tk, di + dj + dk), f4sub(bc, ax), xc);
+    Z[n] = z;
+    if (fine) {
+      acc[0] += (double)bc.x * (double)z.x;
+      acc[1] += (double)bc.y * (double)z.y;
+      acc[2] += (double)bc.z * (double)z.z;
+      acc[3] += (double)bc.w * (double)z.w;
+    }
+  }
+}
+
+// Restriction of the smoothed residual: thread per coarse node J,
+// bh[J] = sum over the children j of (b - A x0)[j], x0 = w D^-1 b.
+__global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, int nt, int nblk,
+                                                  const int* __restrict__ active, int check_active,
+                                                  const float* __restrict__ bl, float* __restrict__ bh) {
+  const int blk = mg_block(nblk);
+  if (blk < 0) return;
+  const MgTask* tk = mg_task(T, nt, blk);
+  if (check_active && !active[tk->sys]) return;
+  const int64_t m = (int64_t)(blk - tk->blk0) * kMgB + threadIdx.x;
+  if (m >= tk->nodes) return;
+  if (tk->fast) {
+    mg_down_u4(tk, bl, bh, (int)m);
+    return;
+  }
+  const MgLvl& lo = tk->lo;
+  const MgLvl& hi = tk->hi;
+  int I, J, K;
+  mg_coords(m, hi, I, J, K);
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int c3 = 0; c3 < 8; ++c3) {
+    const int i = 2 * I + (c3 & 1), j = 2 * J + ((c3 >> 1) & 1), k = 2 * K + (c3 >> 2);
+    if (i >= lo.n || j >= lo.n || k >= lo.n) continue;
+    const MgNode nd = mg_node(i, j, k, lo);
+    float bc[4], xc[4];
+    mg_load(bl + lo.off + mg_idx(i, j, k, lo.n) * lo.F, lo.F, bc);
+    const float f = kMgOmega * __builtin_amdgcn_rcpf(nd.diag);
+    float ax[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      xc[c] = bc[c] * f;
+      ax[c] = nd.mass * xc[c];
+    }
+    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    const float w[6] = {nd.wx, nd.wx, nd.wy, nd.wy, nd.wz, nd.wz};
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (!(nd.mask & (1 << d))) continue;
+      float xn[4];
+      mg_x0(bl, lo, i + di[d], j + dj[d], k + dk[d], xn);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ax[c] += lo.lam * w[d] * (xc[c] - xn[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] += bc[c] - ax[c];
+  }
+  float* o = bh + hi.off + m * hi.F;
+  for (int c = 0; c < hi.F; ++c) o[c] = acc[c];
+}
+
+// Prolongation and post-smoothing: thread per node j of the finer level,
+// x = w D^-1 b + P e (at j and its neighbours), out[j] = x + w D^-1 (b - A x).
+// On the finest level (out = z, b = r) the block partials of r.z per channel
+// go to part. A system with lam = 0 (A = I) gets z = r.
+__global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, int nt, int nblk,
+                                                const int* __restrict__ active, int check_active,
+                                                const float* __restrict__ bl, const float* __restrict__ eh,
+                                                float* __restrict__ out, double* __restrict__ part) {
+  const int blk = mg_block(nblk);
+  if (blk < 0) return;
+  const MgTask* tk = mg_task(T, nt, blk);
+  if (check_active && !active[tk->sys]) return;
+  const int64_t m = (int64_t)(blk - tk->blk0) * kMgB + threadIdx.x;
+  const MgLvl& lo = tk->lo;
+  const MgLvl& hi = tk->hi;
+  double acc[4] = {0, 0, 0, 0};
+  if (tk->fast) {
+    if (m < tk->nodes) mg_up_u4(tk, bl, eh, out, (int)m, acc);
+  } else if (m < tk->nodes) {
+    int i, j, k;
+    mg_coords(m, lo, i, j, k);
+    const MgNode nd = mg_node(i, j, k, lo);
+    auto xat = [&](int a, int b2, int c2, float (&x)[4]) {
+      mg_x0(bl, lo, a, b2, c2, x);
+      float e[4];
+      mg_load(eh + hi.off + mg_idx(a >> 1, b2 >> 1, c2 >> 1, hi.n) * hi.F, hi.F, e);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[c] += e[c];
+    };
+    float xc[4], bc[4], ax[4];
+    xat(i, j, k, xc);
+    mg_load(bl + lo.off + m * lo.F, lo.F, bc);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ax[c] = nd.mass * xc[c];
+    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    const float w[6] = {nd.wx, nd.wx, nd.wy, nd.wy, nd.wz, nd.wz};
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      if (!(nd.mask & (1 << d))) continue;
+      float xn[4];
+      xat(i + di[d], j + dj[d], k + dk[d], xn);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ax[c] += lo.lam * w[d] * (xc[c] - xn[c]);
+    }
+    const float f = kMgOmega * __builtin_amdgcn_rcpf(nd.diag);
+    const bool ident = lo.lam == 0.f;  // A = I: the identity preconditioner (CG then solves it in one step)
+    float* o = out + lo.off + m * lo.F;
+    for (int c = 0; c < lo.F; ++c) {
+      const float v = ident ? bc[c] : xc[c] + f * (bc[c] - ax[c]);
+      o[c] = v;
+      acc[c] = (double)bc[c] * (double)v;
+    }
+  }
+  if (part) store_partials<4>(acc, part, blk);
+}
+
+// Coarsest level of every system (n <= 8): one work-group per system, damped
+// Jacobi sweeps from zero in LDS.
+constexpr int kMgCN = 512 * 4;
+__global__ __launch_bounds__(512) void k_mg_coarse(const MgTask* __restrict__ T, const int* __restrict__ active,
+                                                   int check_active, const float* __restrict__ b,
+                                                   float* __restrict__ x) {
+  const MgTask* tk = T + blockIdx.x;
+  if (check_active && !active[tk->sys]) return;
+  const MgLvl& L = tk->lo;
+  __shared__ float sb[kMgCN], sx[2][kMgCN];
+  const int nodes = L.n * L.n * L.n;
+  const int m = threadIdx.x;
+  int i = 0, j = 0, k = 0;
+  MgNode nd{};
+  float f = 0.f;
+  if (m < nodes) {
+    i = m % L.n;
+    j = (m / L.n) % L.n;
+    k = m / (L.n * L.n);
+    nd = mg_node(i, j, k, L);
+    f = kMgOmega / nd.diag;
+    for (int c = 0; c < L.F; ++c) {
+      const float v = b[L.off + (int64_t)m * L.F + c];
+      sb[m * 4 + c] = v;
+      sx[0][m * 4 + c] = f * v;
+    }
+  }
+  __syncthreads();
+  const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+  for (int it = 1; it < kMgCoarse; ++it) {
+    const float* xs = sx[(it - 1) & 1];
+    float* xd = sx[it & 1];
+    if (m < nodes) {
+      const float w[6] = {nd.wx, nd.wx, nd.wy, nd.wy, nd.wz, nd.wz};
+      for (int c = 0; c < L.F; ++c) {
+        const float xc = xs[m * 4 + c];
+        float ax = nd.mass * xc;
+        for (int d = 0; d < 6; ++d)
+          if (nd.mask & (1 << d)) {
+            const int mn = ((k + dk[d]) * L.n + (j + dj[d])) * L.n + (i + di[d]);
+            ax += L.lam * w[d] * (xc - xs[mn * 4 + c]);
+          }
+        xd[m * 4 + c] = xc + f * (sb[m * 4 + c] - ax);
+      }
+    }
+    __syncthreads();
+  }
+  if (m < nodes)
+    for (int c = 0; c < L.F; ++c) x[L.off + (int64_t)m * L.F + c] = sx[(kMgCoarse - 1) & 1][m * 4 + c];
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+inline unsigned mg_grid(int nb) { return (unsigned)((nb + kXCD - 1) / kXCD * kXCD); }
 inline unsigned xcd_grid(int nb) { return (unsigned)((nb + kXCD * kXG - 1) / (kXCD * kXG) * (kXCD * kXG)); }
 
 }  // namespace
+
+// V-cycle hierarchy of every system and its launch table. Launch l (l = 0 ..
+// nlev-2) restricts level l to l+1, launch nlev-1+l prolongs level l+1 back
+// to l, launch 2(nlev-1) solves every system's coarsest level. A system has
+// at least two levels (the grid and one coarser) and coarsens until a level
+// has at most kMgMinN nodes per axis; it takes part in the launches of the
+// levels it has.
+static npg_status mg_setup(npg_plan* P) {
+  NpgCG& C = P->cg;
+  std::vector<std::vector<MgLvl>> lv(P->n_sys);
+  int64_t coarse = 0;
+  int nlev = 0;
+  for (int sy = 0; sy < P->n_sys; ++sy) {
+    const NpgGrid& g = P->g[sy];
+    MgLvl L{};
+    L.off = g.poff;
+    L.n = g.R;
+    L.s = 1;
+    L.R = g.R;
+    L.F = g.F;
+    L.lam = g.lam;
+    C.mg_elems[sy] = 0.0;
+    while (true) {
+      L.fn = make_fastdiv((uint32_t)L.n);
+      L.fn2 = make_fastdiv((uint32_t)L.n * (uint32_t)L.n);
+      lv[sy].push_back(L);
+      if (lv[sy].size() >= 2 && L.n <= kMgMinN) break;
+      L.n = (L.n + 1) / 2;
+      L.s *= 2;
+      L.off = coarse;
+      const int64_t e = (int64_t)L.n * L.n * L.n * L.F;
+      coarse += (e + 3) / 4 * 4;  // every level 16-byte aligned
+      C.mg_elems[sy] += (double)e;
+    }
+    nlev = std::max(nlev, (int)lv[sy].size());
+  }
+  std::vector<MgTask> tasks;
+  C.mg_l_task0.assign(2 * nlev - 1, 0);
+  C.mg_l_ntask.assign(2 * nlev - 1, 0);
+  C.mg_l_nblk.assign(2 * nlev - 1, 0);
+  auto add_launch = [&](int li, int l, bool up) {
+    C.mg_l_task0[li] = (int)tasks.size();
+    int blk = 0;
+    for (int sy = 0; sy < P->n_sys; ++sy) {
+      if ((int)lv[sy].size() <= l + 1) continue;
+      MgTask t{};
+      t.sys = sy;
+      t.blk0 = blk;
+      t.lo = lv[sy][l];
+      t.hi = lv[sy][l + 1];
+      const MgLvl& W = up ? t.lo : t.hi;
+      t.nodes = (int64_t)W.n * W.n * W.n;
+      t.fast = t.lo.F == 4 && t.lo.off % 4 == 0 && t.hi.off % 4 == 0 && t.lo.R % t.lo.s == 0;
+      if (t.fast) {
+        const float sz = (float)t.lo.s;
+        t.mass = sz * sz * sz;
+        t.lw = t.lo.lam * sz * sz;
+        const int nx = (t.lo.n + 1) / 2;
+        t.fx = make_fastdiv((uint32_t)nx);
+        t.fx2 = make_fastdiv((uint32_t)nx * (uint32_t)t.lo.n);
+        if (up) t.nodes = (int64_t)nx * t.lo.n * t.lo.n;  // one thread per x-adjacent pair
+      }
+      blk += (int)((t.nodes + kMgB - 1) / kMgB);
+      tasks.push_back(t);
+    }
+    C.mg_l_ntask[li] = (int)tasks.size() - C.mg_l_task0[li];
+    C.mg_l_nblk[li] = blk;
+  };
+  for (int l = 0; l + 1 < nlev; ++l) add_launch(l, l, false);
+  for (int l = 0; l + 1 < nlev; ++l) add_launch(nlev - 1 + l, l, true);
+  {  // coarsest levels: one work-group per system
+    const int li = 2 * (nlev - 1);
+    C.mg_l_task0[li] = (int)tasks.size();
+    for (int sy = 0; sy < P->n_sys; ++sy) {
+      MgTask t{};
+      t.sys = sy;
+      t.blk0 = sy;
+      t.lo = lv[sy].back();
+      t.nodes = (int64_t)t.lo.n * t.lo.n * t.lo.n;
+      if (t.nodes * 4 > kMgCN || t.lo.F > 4) return npg_fail(NPG_EINVAL, "multigrid: coarsest level too large");
+      tasks.push_back(t);
+    }
+    C.mg_l_ntask[li] = P->n_sys;
+    C.mg_l_nblk[li] = P->n_sys;
+  }
+  // r.z partials: the blocks of the finest prolongation (every system takes part)
+  std::vector<int> b0(P->n_sys + 1);
+  {
+    const int li = nlev - 1;
+    for (int t = 0; t < C.mg_l_ntask[li]; ++t) b0[t] = tasks[C.mg_l_task0[li] + t].blk0;
+    b0[P->n_sys] = C.mg_l_nblk[li];
+  }
+  C.mg_nlev = nlev;
+  NPG_HIP(hipMalloc(&C.z, P->n_grid_params * 4));
+  NPG_HIP(hipMalloc(&C.mgB, std::max<int64_t>(coarse, 1) * 4));
+  NPG_HIP(hipMalloc(&C.mgX, std::max<int64_t>(coarse, 1) * 4));
+  NPG_HIP(hipMalloc(&C.part2, (int64_t)b0[P->n_sys] * 4 * 8));
+  NPG_HIP(hipMalloc(&C.mg_blk0, (P->n_sys + 1) * 4));
+  NPG_HIP(hipMalloc(&C.mg_tasks, tasks.size() * sizeof(MgTask)));
+  NPG_HIP(hipMemcpy(C.mg_blk0, b0.data(), (P->n_sys + 1) * 4, hipMemcpyHostToDevice));
+  NPG_HIP(hipMemcpy(C.mg_tasks, tasks.data(), tasks.size() * sizeof(MgTask), hipMemcpyHostToDevice));
+  return NPG_OK;
+}
+
+// z = M^-1 r (one V-cycle for every system; with check_active only the
+// systems still iterating), r.z partials into part2.
+static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_active) {
+  NpgCG& C = P->cg;
+  hipStream_t s = P->stream;
+  const int nl = C.mg_nlev;
+  const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
+  for (int l = 0; l + 1 < nl; ++l)
+    if (C.mg_l_ntask[l] > 0)
+      hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(C.mg_l_nblk[l])), dim3(kMgB), 0, s, T + C.mg_l_task0[l],
+                         C.mg_l_ntask[l], C.mg_l_nblk[l], C.active, check_active, l == 0 ? r : C.mgB, C.mgB);
+  const int lc = 2 * (nl - 1);
+  hipLaunchKernelGGL(k_mg_coarse, dim3(C.mg_l_nblk[lc]), dim3(512), 0, s, T + C.mg_l_task0[lc], C.active,
+                     check_active, C.mgB, C.mgX);
+  for (int l = nl - 2; l >= 0; --l) {
+    const int li = nl - 1 + l;
+    if (C.mg_l_ntask[li] > 0)
+      hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[li])), dim3(kMgB), 0, s, T + C.mg_l_task0[li],
+                         C.mg_l_ntask[li], C.mg_l_nblk[li], C.active, check_active, l == 0 ? r : C.mgB, C.mgX,
+                         l == 0 ? z : C.mgX, l == 0 ? C.part2 : nullptr);
+  }
+  NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
 
 npg_status npg_cg_setup(npg_plan* P) {
   NpgCG& C = P->cg;
@@ -690,13 +1228,20 @@ npg_status npg_cg_setup(npg_plan* P) {
   NPG_HIP(hipMemcpy(C.blk_sys, bsys.data(), C.n_blocks * 4, hipMemcpyHostToDevice));
   NPG_HIP(hipMemcpy(C.blk_start, bstart.data(), C.n_blocks * 8, hipMemcpyHostToDevice));
   NPG_HIP(hipMemcpy(C.sys_blk0, s0.data(), (P->n_sys + 1) * 4, hipMemcpyHostToDevice));
+  C.mg = P->cfg.cg_mg != 0;
+  if (C.mg) {
+    const npg_status st = mg_setup(P);
+    if (st != NPG_OK) return st;
+  }
   return NPG_OK;
 }
 
 void npg_cg_free(npg_plan* P) {
   NpgCG& C = P->cg;
-  hipFree(C.x); hipFree(C.r); hipFree(C.p); hipFree(C.q); hipFree(C.part); hipFree(C.st);
-  hipFree(C.active); hipFree(C.blk_sys); hipFree(C.blk_start); hipFree(C.sys_blk0);
+  void* bufs[] = {C.x, C.r, C.p, C.q, C.part, C.st, C.active, C.blk_sys, C.blk_start, C.sys_blk0,
+                  C.z, C.mgB, C.mgX, C.part2, C.mg_blk0, C.mg_tasks};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
 }
 
 // Solve (I + lam L) x = b for every system (b and x distinct buffers in the
@@ -716,9 +1261,13 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
     dv.r[sy] = make_fastdiv((uint32_t)P->g[sy].R);
     dv.r2[sy] = make_fastdiv((uint32_t)P->g[sy].R * (uint32_t)P->g[sy].R);
   }
+  const bool mg = C.mg != 0;
+  double* part2 = mg ? C.part2 : nullptr;
+  const float* dir_src = mg ? C.z : C.r;  // p = z + beta p (z = r without the V-cycle)
   hipLaunchKernelGGL(k_cg_init, grid, blk, 0, s, P->d_g, nb, C.blk_sys, C.blk_start, b, x, C.r, C.p, C.part);
-  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR), 0, s, P->d_g, C.sys_blk0, C.active, C.part, C.st, 0,
-                     P->cfg.cg_rtol, 0);
+  if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0));
+  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
+                     part2, C.mg_blk0, C.st, 0, P->cfg.cg_rtol, 0);
   NPG_HIP(hipGetLastError());
   std::vector<int> act(P->n_sys);
   float* pa = C.p;  // current direction
@@ -734,12 +1283,12 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
       // resolved after the step (no synchronisation here)
       const bool prof = P->prof_cg && P->prof_n + 4 <= (int)P->prof_ev.size();
       if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n], s));
-      hipLaunchKernelGGL(k_cg_dir_ap, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st, C.r,
-                         pa, pb, C.part);
+      hipLaunchKernelGGL(k_cg_dir_ap, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
+                         dir_src, pa, pb, C.part);
       if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], s));
       std::swap(pa, pb);  // pa = p_k, pb = p_{k-1}
-      hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR), 0, s, P->d_g, C.sys_blk0, C.active, C.part, C.st, 1,
-                         P->cfg.cg_rtol, 0);
+      hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
+                         part2, C.mg_blk0, C.st, 1, P->cfg.cg_rtol, 0);
       if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 2], s));
       if (odd)
         hipLaunchKernelGGL(k_cg_update<1>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
@@ -747,12 +1296,13 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
       else
         hipLaunchKernelGGL(k_cg_update<0>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
                            x, C.r, pa, pb, C.part);
+      if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 1));
       if (prof) {
         NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 3], s));
         P->prof_n += 4;
       }
-      hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR), 0, s, P->d_g, C.sys_blk0, C.active, C.part, C.st, 2,
-                         P->cfg.cg_rtol, (int)!odd);
+      hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
+                         part2, C.mg_blk0, C.st, 2, P->cfg.cg_rtol, (int)!odd);
     }
     NPG_HIP(hipGetLastError());
     it += chunk;
@@ -777,7 +1327,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
     bool any = false;
     for (int c = 0; c < g.F; ++c) {
       const double* S = stv.data() + (sy * 4 + c) * kS;
-      const double v = S[1] > 0.0 ? sqrt(S[0] / S[1]) : 0.0;
+      const double v = S[1] > 0.0 ? sqrt(S[2] / S[1]) : 0.0;
       rel = v > rel ? v : rel;
       pend[c] = (float)S[7];
       any |= S[7] != 0.0;
@@ -788,9 +1338,12 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
       hipLaunchKernelGGL(k_cg_flush, dim3(nblk(n, 256)), dim3(256), 0, s, x + g.poff, C.q + g.poff, n, g.F, pend[0],
                          pend[1], pend[2], pend[3]);
     }
-    // algorithmic traffic of this solve: 6 vector passes (x, r, p read and
-    // written) per iteration over the grid's R^3 F float32 unknowns
-    P->cg_alg_bytes += m * 6.0 * (double)g.nodes * g.F * 4.0;
+    // algorithmic traffic of this solve per iteration: 6 vector passes (x,
+    // r, p read and written) over the grid's R^3 F float32 unknowns; with the
+    // V-cycle also z (written, read) and each coarse level's right-hand side
+    // and correction (written, read)
+    const double fine = (double)g.nodes * g.F;
+    P->cg_alg_bytes += m * 4.0 * (mg ? 8.0 * fine + 4.0 * C.mg_elems[sy] : 6.0 * fine);
     P->cg_iters_sum += (int64_t)m;
   }
   NPG_HIP(hipGetLastError());

@@ -35,6 +35,7 @@ def _base(**kw):
         beta1=0.9, beta2=0.999, eps=1e-8,
         conf_weight=1, t_key=None,
         cg_rtol=1e-7, cg_maxit=400,
+        cg_mg=1,                    # CG form: 1 = multigrid-preconditioned solves, 0 = plain CG
         n_steps=10,
         grid_init_std=0.0,
     )

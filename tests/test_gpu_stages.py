@@ -341,18 +341,19 @@ def test_adam_matches_oracle(case):
     assert L >= 1
 
 
-@pytest.mark.parametrize("method", ["cg", "dct"])
+@pytest.mark.parametrize("method", ["cg", "cg_plain", "dct"])
 @pytest.mark.parametrize("levels,feat", [([100, 129, 20], 4), ([256], 4), ([7, 33, 50], 2), ([17, 24], 3)])
 def test_preconditioner_large_grids(levels, feat, method):
     """Grids of >= 100 nodes per axis run the z-column CG kernels; 129 gives
     partial tiles in x, y and z; F = 2, 3 and odd sizes exercise the generic
-    paths of both methods. Sparse vertex-gradient input as in a step, plus a
-    dense random component."""
+    paths of both methods (odd sizes also give partial multigrid aggregates).
+    cg: V-cycle preconditioned CG; cg_plain: plain CG. Sparse vertex-gradient
+    input as in a step, plus a dense random component."""
     import torch
 
     import paper_2602_22212_amd as npg
     cfg = synth.config_small(levels=levels, feat_p=feat, mlp_width=32, V=3000, T=1, N=10, t_key=0, seed=33,
-                             precond=method)
+                             precond="dct" if method == "dct" else "cg", cg_mg=int(method == "cg"))
     data = synth.make_workload(cfg)
     plan = gpu_plan(cfg, data)
     rng = np.random.default_rng(12)
@@ -371,3 +372,42 @@ def test_preconditioner_large_grids(levels, feat, method):
     print("precond rel errors:", ["%.2e" % e for e in errs], "iterations:", its)
     assert max(errs) < TOL
     plan.close()
+
+
+def test_multigrid_preconditioned_cg_cuts_iterations():
+    """The V-cycle preconditioned solves and plain CG reach the exact operator
+    within the tolerance on the same input (smoothness up to the headline's
+    finest 6.83), both stop at the residual tolerance, and the preconditioned
+    solves need at most half the iterations on every grid with lambda >= 1."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    lam = [0.4, 1.35, 6.834375]
+    res = {}
+    for mg in (0, 1):
+        cfg = synth.config_small(levels=[16, 35, 64], lam=lam, feat_p=4, mlp_width=32, V=3000, T=1, N=10, t_key=0,
+                                 seed=34, cg_mg=mg)
+        data = synth.make_workload(cfg)
+        plan = gpu_plan(cfg, data)
+        rng = np.random.default_rng(13)
+        grad = torch.zeros(plan.n_params, dtype=torch.float32, device="cuda")
+        plan.encode_bwd(torch.from_numpy(rng.normal(size=(plan.V * plan.Fz)).astype(np.float32)).cuda(), grad)
+        n_grid = dict((name, o) for name, o, _ in npg.param_layout(cfg)[0])["W0"]
+        grad[:n_grid] += 1e-3 * torch.from_numpy(rng.normal(size=n_grid).astype(np.float32)).cuda()
+        g_in = npg.unpack_params(cfg, to_np(grad))
+        its, st = plan.precond(grad)
+        assert st == npg.NPG_OK, its
+        got = npg.unpack_params(cfg, to_np(grad))
+        errs = [rel(g, O.precond_dct(gi.astype(np.float64), R, la))
+                for g, gi, R, la in zip(got["grid_p"], g_in["grid_p"], cfg["levels"], lam)]
+        errs.append(rel(got["grid_n"], O.precond_dct(g_in["grid_n"].astype(np.float64), cfg["res_n"], cfg["lam_n"])))
+        rr = plan.precond_residuals()
+        print("cg_mg", mg, "errors", ["%.2e" % e for e in errs], "iterations", its)
+        assert max(errs) < TOL and all(0 < r <= cfg["cg_rtol"] for r in rr), (errs, rr)
+        res[mg] = its
+        plan.close()
+    L = len(lam)
+    for k in range(2 * (L + 1)):
+        la = lam[k % (L + 1)] if k % (L + 1) < L else 0.4
+        if la >= 1.0:
+            assert 2 * res[1][k] <= res[0][k], (k, res)
