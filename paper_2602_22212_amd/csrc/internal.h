@@ -35,8 +35,7 @@ struct NpgCG {  // conjugate-gradient workspace
   int mg;                      // 1: preconditioned CG
   float* z;                    // [n_grid_params] preconditioned residual
   float *mgB, *mgX;            // coarse levels of every system: right-hand sides, corrections
-  double* part2;               // [fine-level blocks][4] partial r.z
-  int* mg_blk0;                // [n_sys+1] first r.z block of each system
+  double* part2;               // [n_blocks][4] partial r.z (the CG work-group table)
   void* mg_tasks;              // device table of the V-cycle launches (struct MgTask)
   std::vector<int> mg_l_task0, mg_l_ntask, mg_l_nblk;  // per launch: first task, tasks, blocks
   int mg_nlev;                 // levels of the deepest hierarchy

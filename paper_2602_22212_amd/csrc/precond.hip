@@ -357,8 +357,11 @@ struct ZPlane {
 // the body's extra data; BODY(node, lap, operand, extra) runs at every node
 // of the grid inside the tile. Every thread of the work-group must call this
 // (it synchronises the work-group once per plane).
-template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY>
-__device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body) {
+// POST(z) runs in every thread after the plane's BODY (it may synchronise
+// the work-group).
+template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY, typename POST>
+__device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body,
+                                             POST post) {
   __shared__ float4 sh[3][kTY + 2][kTX];
   const int R = g.R;
   const int64_t R2 = (int64_t)R * R;
@@ -404,12 +407,17 @@ __device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LD ld, 
     f4lap(lap, cur, prev);
     f4lap(lap, cur, nxt);
     if (inside) body(n, lap, cur, ex);
+    post(z);
     prev = cur;
     cur = nxt;
     edge = nedge;
     ex = A.ex;
     A = B;
   }
+}
+template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY>
+__device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body) {
+  zm_walk_post<RAW, EX>(g, t, ld, ldc, op, body, [](int) {});
 }
 
 __device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* x, float* r, float* p, double* part,
@@ -618,12 +626,13 @@ __device__ __forceinline__ void reduce_range(const double* part, int b0, int b1,
 // update the scalars (S[0] rho = r.z, or r.r without the V-cycle; S[2] r.r).
 // mode 0: after init (bb, rho); 1: alpha = rho / pq; 2: beta = rho_new / rho
 // and the convergence test on r.r (defer: the update left this iteration's x
-// term pending). part2 (NULL without the V-cycle): the r.z partials.
+// term pending). part2 (NULL without the V-cycle): the r.z partials, blocks
+// [blk0_2[s], blk0_2[s+1]) of system s.
 __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restrict__ G,
                                                           const int* __restrict__ sys_blk0, int* __restrict__ active,
                                                           const double* __restrict__ part,
                                                           const double* __restrict__ part2,
-                                                          const int* __restrict__ mg_blk0, double* __restrict__ st,
+                                                          const int* __restrict__ blk0_2, double* __restrict__ st,
                                                           int mode, double rtol, int defer) {
   const int s = blockIdx.x;
   if (mode != 0 && !active[s]) return;
@@ -631,7 +640,7 @@ __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restr
   const int F = G[s].F;
   double vv[4], rho[4];
   reduce_range(part, sys_blk0[s], sys_blk0[s + 1], red, vv);
-  if (part2 && mode != 1) reduce_range(part2, mg_blk0[s], mg_blk0[s + 1], red2, rho);
+  if (part2 && mode != 1) reduce_range(part2, blk0_2[s], blk0_2[s + 1], red2, rho);
   else
     for (int c = 0; c < 4; ++c) rho[c] = vv[c];
   if (threadIdx.x != 0) return;
@@ -706,6 +715,7 @@ struct MgTask {
   int fast;
   float mass, lw;
   FastDiv fx, fx2;
+  int zm0;  // finest restriction of a grid walked in z-column tiles (k_mg_down0)
 };
 
 __device__ __forceinline__ int mg_ext(int i, const MgLvl& L) { return min(L.s, L.R - L.s * i); }
@@ -905,7 +915,7 @@ __global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, 
   const int blk = mg_block(nblk);
   if (blk < 0) return;
   const MgTask* tk = mg_task(T, nt, blk);
-  if (check_active && !active[tk->sys]) return;
+  if (tk->zm0 || (check_active && !active[tk->sys])) return;
   const int64_t m = (int64_t)(blk - tk->blk0) * kMgB + threadIdx.x;
   if (m >= tk->nodes) return;
   if (tk->fast) {
@@ -951,56 +961,192 @@ __global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, 
 // x = w D^-1 b + P e (at j and its neighbours), out[j] = x + w D^-1 (b - A x).
 // On the finest level (out = z, b = r) the block partials of r.z per channel
 // go to part. A system with lam = 0 (A = I) gets z = r.
+// One node m of the finer level, any F and extents; adds r.z to acc (used
+// on the finest level, where b = r and out = z).
+__device__ __forceinline__ void mg_up_node(const MgTask* tk, const float* __restrict__ bl,
+                                           const float* __restrict__ eh, float* __restrict__ out, int64_t m,
+                                           double (&acc)[4]) {
+  const MgLvl& lo = tk->lo;
+  const MgLvl& hi = tk->hi;
+  int i, j, k;
+  mg_coords(m, lo, i, j, k);
+  const MgNode nd = mg_node(i, j, k, lo);
+  auto xat = [&](int a, int b2, int c2, float (&x)[4]) {
+    mg_x0(bl, lo, a, b2, c2, x);
+    float e[4];
+    mg_load(eh + hi.off + mg_idx(a >> 1, b2 >> 1, c2 >> 1, hi.n) * hi.F, hi.F, e);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] += e[c];
+  };
+  float xc[4], bc[4], ax[4];
+  xat(i, j, k, xc);
+  mg_load(bl + lo.off + m * lo.F, lo.F, bc);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) ax[c] = nd.mass * xc[c];
+  const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+  const float w[6] = {nd.wx, nd.wx, nd.wy, nd.wy, nd.wz, nd.wz};
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    if (!(nd.mask & (1 << d))) continue;
+    float xn[4];
+    xat(i + di[d], j + dj[d], k + dk[d], xn);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ax[c] += lo.lam * w[d] * (xc[c] - xn[c]);
+  }
+  const float f = kMgOmega * __builtin_amdgcn_rcpf(nd.diag);
+  const bool ident = lo.lam == 0.f;  // A = I: the identity preconditioner (CG then solves it in one step)
+  float* o = out + lo.off + m * lo.F;
+  for (int c = 0; c < lo.F; ++c) {
+    const float v = ident ? bc[c] : xc[c] + f * (bc[c] - ax[c]);
+    o[c] = v;
+    acc[c] += (double)bc[c] * (double)v;
+  }
+}
+
+// Prolongation and post-smoothing from level l+1 to l >= 1 (l = 0: k_mg_up0).
 __global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, int nt, int nblk,
                                                 const int* __restrict__ active, int check_active,
                                                 const float* __restrict__ bl, const float* __restrict__ eh,
-                                                float* __restrict__ out, double* __restrict__ part) {
+                                                float* __restrict__ out) {
   const int blk = mg_block(nblk);
   if (blk < 0) return;
   const MgTask* tk = mg_task(T, nt, blk);
   if (check_active && !active[tk->sys]) return;
   const int64_t m = (int64_t)(blk - tk->blk0) * kMgB + threadIdx.x;
-  const MgLvl& lo = tk->lo;
-  const MgLvl& hi = tk->hi;
+  if (m >= tk->nodes) return;
   double acc[4] = {0, 0, 0, 0};
-  if (tk->fast) {
-    if (m < tk->nodes) mg_up_u4(tk, bl, eh, out, (int)m, acc);
-  } else if (m < tk->nodes) {
-    int i, j, k;
-    mg_coords(m, lo, i, j, k);
-    const MgNode nd = mg_node(i, j, k, lo);
-    auto xat = [&](int a, int b2, int c2, float (&x)[4]) {
-      mg_x0(bl, lo, a, b2, c2, x);
-      float e[4];
-      mg_load(eh + hi.off + mg_idx(a >> 1, b2 >> 1, c2 >> 1, hi.n) * hi.F, hi.F, e);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) x[c] += e[c];
-    };
-    float xc[4], bc[4], ax[4];
-    xat(i, j, k, xc);
-    mg_load(bl + lo.off + m * lo.F, lo.F, bc);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ax[c] = nd.mass * xc[c];
-    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-    const float w[6] = {nd.wx, nd.wx, nd.wy, nd.wy, nd.wz, nd.wz};
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      if (!(nd.mask & (1 << d))) continue;
-      float xn[4];
-      xat(i + di[d], j + dj[d], k + dk[d], xn);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) ax[c] += lo.lam * w[d] * (xc[c] - xn[c]);
-    }
-    const float f = kMgOmega * __builtin_amdgcn_rcpf(nd.diag);
-    const bool ident = lo.lam == 0.f;  // A = I: the identity preconditioner (CG then solves it in one step)
-    float* o = out + lo.off + m * lo.F;
-    for (int c = 0; c < lo.F; ++c) {
-      const float v = ident ? bc[c] : xc[c] + f * (bc[c] - ax[c]);
-      o[c] = v;
-      acc[c] = (double)bc[c] * (double)v;
+  if (tk->fast) mg_up_u4(tk, bl, eh, out, (int)m, acc);
+  else mg_up_node(tk, bl, eh, out, m, acc);
+}
+
+// Restriction from the finest level of a large grid over its z-column tiles
+// (each row read once): the residual b - A x0 of every node, x0 = w D^-1 b,
+// summed over x-adjacent lanes, then y-adjacent waves (through LDS), then
+// z-adjacent planes (registers), and written by the even lane of the even
+// wave at the odd plane (or at the last plane of an odd-sized grid). Tiles
+// start at even x, y and z, so no 2x2x2 block straddles two tiles.
+__device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const FastDiv& fR, const FastDiv& fR2,
+                            const MgTask* tk, const float* __restrict__ r, float* __restrict__ bh) {
+  __shared__ float4 ys[2][kTY / 2][kTX];
+  const int R = g.R;
+  const int nh = tk->hi.n;
+  const float lam = g.lam;
+  const float4* B = reinterpret_cast<const float4*>(r + g.poff);
+  float4* H = reinterpret_cast<float4*>(bh + tk->hi.off);
+  const int lane = threadIdx.x & (kTX - 1), w = threadIdx.x / kTX;
+  const int x = t.x0 + lane, y = t.y0 + w;
+  auto fdeg = [&](int64_t m) {
+    const int k = (int)fdiv((uint32_t)m, fR2);
+    const uint32_t rem = (uint32_t)m - (uint32_t)k * fR2.d;
+    const int j = (int)fdiv(rem, fR);
+    const int i = (int)(rem - (uint32_t)j * (uint32_t)R);
+    const int d = mg_deg1(i, R) + mg_deg1(j, R) + mg_deg1(k, R);
+    return kMgOmega * __builtin_amdgcn_rcpf(fmaf(lam, (float)d, 1.f));
+  };
+  float4 rs = make_float4(0.f, 0.f, 0.f, 0.f), zacc = rs;
+  zm_walk_post<Raw1, Raw1>(
+      g, t, [&](int64_t m) { return Raw1{f4scale(fdeg(m), B[m])}; }, [&](int64_t m) { return Raw1{B[m]}; },
+      [&](const Raw1& v) { return v.a; },
+      [&](int64_t, const float4& lap, const float4& xc, const Raw1& e) { rs = f4sub(e.a, f4axpy(lam, lap, xc)); },
+      [&](int z) {
+        float4 v = f4add(rs, make_float4(__shfl_xor(rs.x, 1), __shfl_xor(rs.y, 1), __shfl_xor(rs.z, 1),
+                                         __shfl_xor(rs.w, 1)));
+        rs = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (w & 1) ys[z & 1][w >> 1][lane] = v;
+        __syncthreads();
+        if (!(w & 1)) v = f4add(v, ys[z & 1][w >> 1][lane]);
+        const bool last = (z & 1) || z + 1 >= R;
+        if (z & 1) v = f4add(zacc, v);
+        else zacc = v;
+        if (last && !(w & 1) && !(lane & 1) && x < R && y < R)
+          H[((z >> 1) * nh + (y >> 1)) * nh + (x >> 1)] = v;
+      });
+}
+
+__global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, Divs dv, int nb,
+                                                 const int* __restrict__ blk_sys,
+                                                 const int64_t* __restrict__ blk_start,
+                                                 const int* __restrict__ active, int check_active,
+                                                 const MgTask* __restrict__ T0, const float* __restrict__ r,
+                                                 float* __restrict__ bh) {
+  const int blk = logical_block(nb);
+  if (blk < 0) return;
+  const int s = blk_sys[blk];
+  if (check_active && !active[s]) return;
+  const MgTask* tk = T0 + s;
+  if (!tk->zm0) return;
+  const NpgGrid g = G[s];
+  mg_down0_zm(g, unpack_tile(blk_start[blk]), dv.r[s], dv.r2[s], tk, r, bh);
+}
+
+// Prolongation and post-smoothing onto the finest level (z = M^-1 r) over the
+// CG work-group table: the z-column walk for the large grids (each row read
+// once; x = w D^-1 r + P e formed as it is loaded), node chunks otherwise;
+// r.z partials per work-group. T0: the system's task (system order).
+__device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const FastDiv& fR, const FastDiv& fR2, const MgTask* tk,
+                          const float* __restrict__ r, const float* __restrict__ eh, float* __restrict__ z,
+                          double (&acc)[4]) {
+  const int R = g.R;
+  const int nh = tk->hi.n;
+  const float lam = g.lam;
+  const float4* B = reinterpret_cast<const float4*>(r + g.poff);
+  const float4* E = reinterpret_cast<const float4*>(eh + tk->hi.off);
+  float4* Z = reinterpret_cast<float4*>(z + g.poff);
+  auto coords = [&](int64_t m, int& i, int& j, int& k) {
+    k = (int)fdiv((uint32_t)m, fR2);
+    const uint32_t rem = (uint32_t)m - (uint32_t)k * fR2.d;
+    j = (int)fdiv(rem, fR);
+    i = (int)(rem - (uint32_t)j * (uint32_t)R);
+  };
+  auto fdeg = [&](int i, int j, int k) {
+    const int d = mg_deg1(i, R) + mg_deg1(j, R) + mg_deg1(k, R);
+    return kMgOmega * __builtin_amdgcn_rcpf(fmaf(lam, (float)d, 1.f));
+  };
+  zm_walk<Raw1, Raw1>(
+      g, t,
+      [&](int64_t m) {
+        int i, j, k;
+        coords(m, i, j, k);
+        return Raw1{f4add(f4scale(fdeg(i, j, k), B[m]), E[((k >> 1) * nh + (j >> 1)) * nh + (i >> 1)])};
+      },
+      [&](int64_t m) { return Raw1{B[m]}; }, [&](const Raw1& v) { return v.a; },
+      [&](int64_t n, const float4& lap, const float4& xc, const Raw1& e) {
+        int i, j, k;
+        coords(n, i, j, k);
+        const float4 bc = e.a;
+        const float4 ax = f4axpy(lam, lap, xc);
+        const float4 zz = lam == 0.f ? bc : f4axpy(fdeg(i, j, k), f4sub(bc, ax), xc);
+        Z[n] = zz;
+        acc[0] += (double)bc.x * (double)zz.x;
+        acc[1] += (double)bc.y * (double)zz.y;
+        acc[2] += (double)bc.z * (double)zz.z;
+        acc[3] += (double)bc.w * (double)zz.w;
+      });
+}
+
+__global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, Divs dv, int nb,
+                                               const int* __restrict__ blk_sys, const int64_t* __restrict__ blk_start,
+                                               const int* __restrict__ active, int check_active,
+                                               const MgTask* __restrict__ T0, const float* __restrict__ r,
+                                               const float* __restrict__ eh, float* __restrict__ z,
+                                               double* __restrict__ part) {
+  const int blk = logical_block(nb);
+  if (blk < 0) return;
+  const int s = blk_sys[blk];
+  if (check_active && !active[s]) return;
+  const NpgGrid g = G[s];
+  const MgTask* tk = T0 + s;
+  double acc[4] = {0, 0, 0, 0};
+  if (use_zm(g) && tk->hi.off % 4 == 0) {
+    mg_up0_zm(g, unpack_tile(blk_start[blk]), dv.r[s], dv.r2[s], tk, r, eh, z, acc);
+  } else {
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t n = blk_start[blk] + k * kB + threadIdx.x;
+      if (n >= g.nodes) break;
+      mg_up_node(tk, r, eh, z, n, acc);
     }
   }
-  if (part) store_partials<4>(acc, part, blk);
+  store_partials<4>(acc, part, blk);
 }
 
 // Coarsest level of every system (n <= 8): one work-group per system, damped
@@ -1112,6 +1258,8 @@ static npg_status mg_setup(npg_plan* P) {
       const MgLvl& W = up ? t.lo : t.hi;
       t.nodes = (int64_t)W.n * W.n * W.n;
       t.fast = t.lo.F == 4 && t.lo.off % 4 == 0 && t.hi.off % 4 == 0 && t.lo.R % t.lo.s == 0;
+      // the z-column tiles of the CG table (same test as use_zm)
+      t.zm0 = !up && l == 0 && t.lo.R >= kZmR && t.lo.F == 4 && t.lo.off % 4 == 0 && t.hi.off % 4 == 0;
       if (t.fast) {
         const float sz = (float)t.lo.s;
         t.mass = sz * sz * sz;
@@ -1144,32 +1292,29 @@ static npg_status mg_setup(npg_plan* P) {
     C.mg_l_ntask[li] = P->n_sys;
     C.mg_l_nblk[li] = P->n_sys;
   }
-  // r.z partials: the blocks of the finest prolongation (every system takes part)
-  std::vector<int> b0(P->n_sys + 1);
-  {
-    const int li = nlev - 1;
-    for (int t = 0; t < C.mg_l_ntask[li]; ++t) b0[t] = tasks[C.mg_l_task0[li] + t].blk0;
-    b0[P->n_sys] = C.mg_l_nblk[li];
-  }
+  // the finest prolongation runs over the CG work-group table (its tasks are
+  // looked up by system: every system takes part, in order)
+  if (C.mg_l_ntask[0] != P->n_sys || C.mg_l_ntask[nlev - 1] != P->n_sys)
+    return npg_fail(NPG_EINVAL, "multigrid: finest level table");
   C.mg_nlev = nlev;
   NPG_HIP(hipMalloc(&C.z, P->n_grid_params * 4));
   NPG_HIP(hipMalloc(&C.mgB, std::max<int64_t>(coarse, 1) * 4));
   NPG_HIP(hipMalloc(&C.mgX, std::max<int64_t>(coarse, 1) * 4));
-  NPG_HIP(hipMalloc(&C.part2, (int64_t)b0[P->n_sys] * 4 * 8));
-  NPG_HIP(hipMalloc(&C.mg_blk0, (P->n_sys + 1) * 4));
+  NPG_HIP(hipMalloc(&C.part2, (int64_t)C.n_blocks * 4 * 8));
   NPG_HIP(hipMalloc(&C.mg_tasks, tasks.size() * sizeof(MgTask)));
-  NPG_HIP(hipMemcpy(C.mg_blk0, b0.data(), (P->n_sys + 1) * 4, hipMemcpyHostToDevice));
   NPG_HIP(hipMemcpy(C.mg_tasks, tasks.data(), tasks.size() * sizeof(MgTask), hipMemcpyHostToDevice));
   return NPG_OK;
 }
 
 // z = M^-1 r (one V-cycle for every system; with check_active only the
 // systems still iterating), r.z partials into part2.
-static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_active) {
+static npg_status mg_apply(npg_plan* P, const Divs& dv, const float* r, float* z, int check_active) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nl = C.mg_nlev;
   const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
+  hipLaunchKernelGGL(k_mg_down0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, dv, C.n_blocks, C.blk_sys,
+                     C.blk_start, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB);
   for (int l = 0; l + 1 < nl; ++l)
     if (C.mg_l_ntask[l] > 0)
       hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(C.mg_l_nblk[l])), dim3(kMgB), 0, s, T + C.mg_l_task0[l],
@@ -1177,13 +1322,14 @@ static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_acti
   const int lc = 2 * (nl - 1);
   hipLaunchKernelGGL(k_mg_coarse, dim3(C.mg_l_nblk[lc]), dim3(512), 0, s, T + C.mg_l_task0[lc], C.active,
                      check_active, C.mgB, C.mgX);
-  for (int l = nl - 2; l >= 0; --l) {
+  for (int l = nl - 2; l >= 1; --l) {
     const int li = nl - 1 + l;
     if (C.mg_l_ntask[li] > 0)
       hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[li])), dim3(kMgB), 0, s, T + C.mg_l_task0[li],
-                         C.mg_l_ntask[li], C.mg_l_nblk[li], C.active, check_active, l == 0 ? r : C.mgB, C.mgX,
-                         l == 0 ? z : C.mgX, l == 0 ? C.part2 : nullptr);
+                         C.mg_l_ntask[li], C.mg_l_nblk[li], C.active, check_active, C.mgB, C.mgX, C.mgX);
   }
+  hipLaunchKernelGGL(k_mg_up0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, dv, C.n_blocks, C.blk_sys,
+                     C.blk_start, C.active, check_active, T + C.mg_l_task0[nl - 1], r, C.mgX, z, C.part2);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
@@ -1239,7 +1385,7 @@ npg_status npg_cg_setup(npg_plan* P) {
 void npg_cg_free(npg_plan* P) {
   NpgCG& C = P->cg;
   void* bufs[] = {C.x, C.r, C.p, C.q, C.part, C.st, C.active, C.blk_sys, C.blk_start, C.sys_blk0,
-                  C.z, C.mgB, C.mgX, C.part2, C.mg_blk0, C.mg_tasks};
+                  C.z, C.mgB, C.mgX, C.part2, C.mg_tasks};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -1265,9 +1411,9 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
   double* part2 = mg ? C.part2 : nullptr;
   const float* dir_src = mg ? C.z : C.r;  // p = z + beta p (z = r without the V-cycle)
   hipLaunchKernelGGL(k_cg_init, grid, blk, 0, s, P->d_g, nb, C.blk_sys, C.blk_start, b, x, C.r, C.p, C.part);
-  if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0));
+  if (mg) NPG_TRY_ST(mg_apply(P, dv, C.r, C.z, 0));
   hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                     part2, C.mg_blk0, C.st, 0, P->cfg.cg_rtol, 0);
+                     part2, C.sys_blk0, C.st, 0, P->cfg.cg_rtol, 0);
   NPG_HIP(hipGetLastError());
   std::vector<int> act(P->n_sys);
   float* pa = C.p;  // current direction
@@ -1288,7 +1434,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
       if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], s));
       std::swap(pa, pb);  // pa = p_k, pb = p_{k-1}
       hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                         part2, C.mg_blk0, C.st, 1, P->cfg.cg_rtol, 0);
+                         part2, C.sys_blk0, C.st, 1, P->cfg.cg_rtol, 0);
       if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 2], s));
       if (odd)
         hipLaunchKernelGGL(k_cg_update<1>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
@@ -1296,13 +1442,13 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
       else
         hipLaunchKernelGGL(k_cg_update<0>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
                            x, C.r, pa, pb, C.part);
-      if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 1));
+      if (mg) NPG_TRY_ST(mg_apply(P, dv, C.r, C.z, 1));
       if (prof) {
         NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 3], s));
         P->prof_n += 4;
       }
       hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                         part2, C.mg_blk0, C.st, 2, P->cfg.cg_rtol, (int)!odd);
+                         part2, C.sys_blk0, C.st, 2, P->cfg.cg_rtol, (int)!odd);
     }
     NPG_HIP(hipGetLastError());
     it += chunk;
