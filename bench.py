@@ -2,7 +2,8 @@
 
 One step = encode, decode (MLP + transform), bidirectional NN Chamfer and
 confidence-weighted loss, backward of all of them, Sobolev preconditioning
-(two CG solves per grid) and Adam, on the human workload: 30,000 reference
+(two CG solves per grid, each preconditioned by a multigrid V-cycle) and
+Adam, on the human workload: 30,000 reference
 vertices, 100 frames, 10,000 points per frame, 8-level position grid 16..256
 with 4 features, normal grid 4^3 x 2, MLP 14 -> 128 x 3 -> 6 (float32).
 Inputs are resident in HBM before timing starts; the state is a seeded
@@ -10,9 +11,10 @@ non-degenerate one (random grids and last layer) so every stage does its
 full work from the first timed step.
 
 Prints one JSON line (see the keys below). `roofline` is measured live for
-the dominant kernel, the preconditioner's CG iteration pair (k_cg_dir_ap +
-k_cg_update), with HIP events recorded on the plan's stream; `cpu_baseline`
-times the FP64 oracle on a bounded sample of the same workload.
+the dominant kernel group, the preconditioner's CG iteration (k_cg_dir_ap,
+k_cg_update and the V-cycle kernels), with HIP events recorded on the plan's
+stream; `cpu_baseline` times the FP64 oracle on a bounded sample of the same
+workload.
 """
 import argparse
 import hashlib
@@ -50,8 +52,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,dct,quat,iso,metrics,bf16,batch,animal",
-                    help="forms to time: cg (headline), dct (exact DCT preconditioner), "
+    ap.add_argument("--forms", default="cg,cg_plain,dct,quat,iso,metrics,bf16,batch,animal",
+                    help="forms to time: cg (headline: CG preconditioned by a multigrid V-cycle), "
+                         "cg_plain (the same solves by plain CG), dct (exact DCT preconditioner), "
                          "quat (quaternion rotation head, DCT preconditioner), "
                          "iso (isometry loss w_iso = 100 on a 6-NN edge graph, DCT preconditioner), "
                          "metrics (inference export + evaluation metrics on ground truth), "
@@ -66,7 +69,7 @@ def parse():
 
 
 def traffic_from_profile():
-    """HBM bytes per CG iteration (k_cg_dir_ap + k_cg_update) from the
+    """HBM bytes per preconditioned CG iteration (CG and V-cycle kernels) from the
     committed rocprofv3 counter summary, if it was taken on the current
     kernel source (its `precond.hip sha256` line names the source)."""
     path = os.path.join(ROOT, "profiles", "cg_iteration_human_pmc.md")
@@ -412,6 +415,8 @@ def main():
         print("the headline form is cg: --forms must include it", file=sys.stderr)
         sys.exit(2)
     cg = run_form(dict(cfg, precond="cg"), data, P0, args.steps, args.warmup, profile=True)
+    plain = (run_form(dict(cfg, precond="cg", cg_mg=0), data, P0, args.steps, args.warmup, profile=True)
+             if "cg_plain" in forms else None)
     dct = run_form(dict(cfg, precond="dct"), data, P0, args.steps, args.warmup, profile=False) if "dct" in forms else None
     quat = None
     if "quat" in forms:
@@ -427,10 +432,15 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=traffic,
-                    traffic_unit="HBM bytes per CG iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    traffic_unit=("HBM bytes per preconditioned CG iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                  "copy-calibrated)"),
                     traffic_over_algorithmic=(None if traffic is None else round(
                         traffic * prof["cg_iters"] / max(prof["cg_bytes"], 1), 4)),
-                    kernel="CG iteration (k_cg_dir_ap + k_cg_update)",
+                    kernel=("preconditioned CG iteration (k_cg_dir_ap + k_cg_update + the V-cycle: k_mg_down0, "
+                            "k_mg_down, k_mg_coarse, k_mg_up, k_mg_up0)"),
+                    alg_bytes_definition=("per iteration and grid: x, r, p read and written and z written and read "
+                                          "(8 float32 passes over R^3 F) plus every coarse level's right-hand side "
+                                          "and correction written and read"),
                     avg_ms_per_iteration=round(cg_iter_ms, 4),
                     alg_bytes_per_iteration=round(prof["cg_bytes"] / max(prof["cg_iters"], 1)))
     out = {
@@ -448,7 +458,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"human_v{V}_t{T}_n{cfg['N']}", "levels": cfg["levels"], "feat_p": cfg["feat_p"],
                    "mlp": f"{cfg['feat_n'] + cfg['feat_p'] + 2 * cfg['time_freqs']}->{cfg['mlp_width']}x"
-                          f"{cfg['mlp_hidden']}->6", "precond": "cg", "cg_rtol": cfg["cg_rtol"],
+                          f"{cfg['mlp_hidden']}->6", "precond": "cg", "cg_mg": 1, "cg_rtol": cfg["cg_rtol"],
                    "parallelism": "single-gpu"},
         "stage_ms": cg["stage_ms"],
         "nn_autotune": cg["nn_tune"],
@@ -458,6 +468,12 @@ def main():
         "cg_final_relres_max": cg["cg_relres_max"],
         "step_status": cg["status"],
         "roofline": roofline,
+        "precond_cg_plain": None if plain is None else {
+            "value": round(plain["value"], 4), "unit": "steps/s", "ms_per_step": round(plain["ms_per_step"], 3),
+            "stage_ms": plain["stage_ms"],
+            "cg_iterations_per_step": round(plain["prof"]["cg_iters"] / args.steps, 1),
+            "cg_final_relres_max": plain["cg_relres_max"],
+            "note": "same step with the solves by plain CG (no V-cycle, cg_mg = 0)"},
         "precond_dct": None if dct is None else {
             "value": round(dct["value"], 4), "unit": "steps/s", "ms_per_step": round(dct["ms_per_step"], 3),
             "stage_ms": dct["stage_ms"], "note": "same step with the exact DCT form of (I + lambda L)^-2"},
