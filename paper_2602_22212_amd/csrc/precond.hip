@@ -693,7 +693,7 @@ __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restr
 // Jacobi sweeps from zero. Smoothing before and after is the same symmetric
 // Jacobi step and the restriction is P^T, so the preconditioner is symmetric
 // and positive definite (w < 1 < 2 / rho(D^-1 A)).
-constexpr float kMgOmega = 0.8f;
+constexpr float kMgOmega = 0.85f;
 constexpr int kMgCoarse = 4;
 constexpr int kMgMinN = 8;
 constexpr int kMgB = 256;
