@@ -342,11 +342,13 @@ def test_adam_matches_oracle(case):
 
 
 @pytest.mark.parametrize("method", ["cg", "cg_plain", "dct"])
-@pytest.mark.parametrize("levels,feat", [([100, 129, 20], 4), ([256], 4), ([7, 33, 50], 2), ([17, 24], 3)])
+@pytest.mark.parametrize("levels,feat", [([100, 129, 20], 4), ([256], 4), ([7, 33, 50], 2), ([17, 24], 3),
+                                         ([2, 3, 5, 9], 1)])
 def test_preconditioner_large_grids(levels, feat, method):
     """Grids of >= 100 nodes per axis run the z-column CG kernels; 129 gives
     partial tiles in x, y and z; F = 2, 3 and odd sizes exercise the generic
-    paths of both methods (odd sizes also give partial multigrid aggregates).
+    paths of both methods (odd sizes also give partial multigrid aggregates;
+    2 and 3 nodes per axis give single-node coarse levels).
     cg: V-cycle preconditioned CG; cg_plain: plain CG. Sparse vertex-gradient
     input as in a step, plus a dense random component."""
     import torch
