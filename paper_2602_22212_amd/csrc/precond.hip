@@ -806,39 +806,31 @@ __device__ __forceinline__ void mg_down_u4(const MgTask* tk, const float* __rest
   mg_coords(m, hi, I, J, K);
   const float4* B = reinterpret_cast<const float4*>(bl + lo.off);
   const float nlw = -tk->lw, mass = tk->mass;
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int cz = 0; cz < 2; ++cz) {
-    const int k = 2 * K + cz;
-    if (k >= R) break;
-    const int dk = mg_deg1(k, R);
-    for (int cy = 0; cy < 2; ++cy) {
-      const int j = 2 * J + cy;
-      if (j >= R) break;
-      const int dj = mg_deg1(j, R);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 acc = zero;
+  // all 8 children and their 24 outer neighbours, branch-free: indices
+  // clamped into the grid, absent nodes masked to 0 (loads in flight together)
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const int i = 2 * I + cx;
-        if (i >= R) break;
-        const int di = mg_deg1(i, R);
-        const int n = (k * R + j) * R + i;
-        const float4 bc = B[n];
-        const float4 xc = f4scale(mg_f(tk, di + dj + dk), bc);
-        acc = f4add(acc, f4axpy(-mass, xc, bc));
-        const int ox = cx ? i + 1 : i - 1, oy = cy ? j + 1 : j - 1, oz = cz ? k + 1 : k - 1;
-        if (ox >= 0 && ox < R) {
-          const float4 xn = f4scale(mg_f(tk, mg_deg1(ox, R) + dj + dk), B[n + (ox - i)]);
-          acc = f4axpy(nlw, f4sub(xc, xn), acc);
-        }
-        if (oy >= 0 && oy < R) {
-          const float4 xn = f4scale(mg_f(tk, di + mg_deg1(oy, R) + dk), B[n + (oy - j) * R]);
-          acc = f4axpy(nlw, f4sub(xc, xn), acc);
-        }
-        if (oz >= 0 && oz < R) {
-          const float4 xn = f4scale(mg_f(tk, di + dj + mg_deg1(oz, R)), B[n + (oz - k) * R * R]);
-          acc = f4axpy(nlw, f4sub(xc, xn), acc);
-        }
-      }
-    }
+  for (int c3 = 0; c3 < 8; ++c3) {
+    const int cx = c3 & 1, cy = (c3 >> 1) & 1, cz = c3 >> 2;
+    const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
+    const bool valid = i < R && j < R && k < R;
+    const int ic = min(i, R - 1), jc = min(j, R - 1), kc = min(k, R - 1);
+    const int di = mg_deg1(ic, R), dj = mg_deg1(jc, R), dk = mg_deg1(kc, R);
+    const int n = (kc * R + jc) * R + ic;
+    const int ox = cx ? ic + 1 : ic - 1, oy = cy ? jc + 1 : jc - 1, oz = cz ? kc + 1 : kc - 1;
+    const bool vx = valid && ox >= 0 && ox < R, vy = valid && oy >= 0 && oy < R, vz = valid && oz >= 0 && oz < R;
+    const int oxc = vx ? ox : ic, oyc = vy ? oy : jc, ozc = vz ? oz : kc;
+    const float4 bc = B[n];
+    const float4 bx = B[n + (oxc - ic)];
+    const float4 by = B[n + (oyc - jc) * R];
+    const float4 bz = B[n + (ozc - kc) * R * R];
+    const float4 xc = f4scale(mg_f(tk, di + dj + dk), bc);
+    float4 t = f4axpy(-mass, xc, bc);
+    t = f4axpy(vx ? nlw : 0.f, f4sub(xc, f4scale(mg_f(tk, mg_deg1(oxc, R) + dj + dk), bx)), t);
+    t = f4axpy(vy ? nlw : 0.f, f4sub(xc, f4scale(mg_f(tk, di + mg_deg1(oyc, R) + dk), by)), t);
+    t = f4axpy(vz ? nlw : 0.f, f4sub(xc, f4scale(mg_f(tk, di + dj + mg_deg1(ozc, R)), bz)), t);
+    acc = f4add(acc, valid ? t : zero);
   }
   reinterpret_cast<float4*>(bh + hi.off)[m] = acc;
 }
@@ -861,42 +853,31 @@ __device__ __forceinline__ void mg_up_u4(const MgTask* tk, const float* __restri
   float4* Z = reinterpret_cast<float4*>(out + lo.off);
   const float lw = tk->lw, mass = tk->mass;
   const bool fine = lo.s == 1, ident = fine && lo.lam == 0.f;
-  const int dj = mg_deg1(j, R), dk = mg_deg1(k, R);
-  const int J = j >> 1, K = k >> 1;
-  auto eat = [&](int a, int b2, int c2) { return E[(c2 * nh + b2) * nh + a]; };
-  // x = w D^-1 b + P e at node (i, jj, kk), e its parent's correction
-  auto xat = [&](int i, int jj, int kk, int dsum, float4 e) {
-    return f4add(f4scale(mg_f(tk, dsum), B[(kk * R + jj) * R + i]), e);
+  // x = w D^-1 b + P e at node (a, b2, c2). A neighbour index clamped into the
+  // grid lands on the node itself, whose x is bitwise the same, so an absent
+  // neighbour adds exactly 0 and every load can be issued unconditionally.
+  auto xat = [&](int a, int b2, int c2) {
+    const int d = mg_deg1(a, R) + mg_deg1(b2, R) + mg_deg1(c2, R);
+    return f4add(f4scale(mg_f(tk, d), B[(c2 * R + b2) * R + a]), E[((c2 >> 1) * nh + (b2 >> 1)) * nh + (a >> 1)]);
   };
-  const float4 e0 = eat(I, J, K);
-  const int i0 = 2 * I, i1 = 2 * I + 1;
-  const bool has1 = i1 < R;
-  const int d0 = mg_deg1(i0, R), d1 = has1 ? mg_deg1(i1, R) : 0;
-  const float4 x0 = xat(i0, j, k, d0 + dj + dk, e0);
-  const float4 x1 = has1 ? xat(i1, j, k, d1 + dj + dk, e0) : x0;
+  const int i0 = 2 * I, i1 = min(2 * I + 1, R - 1);  // i1 = i0 when the pair has one node
+  const int jm = max(j - 1, 0), jp = min(j + 1, R - 1), km = max(k - 1, 0), kp = min(k + 1, R - 1);
+  const float4 x0 = xat(i0, j, k), x1 = xat(i1, j, k);
+  const float4 xl = xat(max(i0 - 1, 0), j, k), xr = xat(min(i1 + 1, R - 1), j, k);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    if (h == 1 && !has1) break;
+    if (h == 1 && 2 * I + 1 >= R) break;
     const int i = h ? i1 : i0;
-    const int di = h ? d1 : d0;
     const float4 xc = h ? x1 : x0;
-    float4 nb = make_float4(0.f, 0.f, 0.f, 0.f);  // sum over neighbours of (x_c - x_nb)
-    if (h == 0) {
-      if (has1) nb = f4add(nb, f4sub(xc, x1));
-      if (i0 > 0) nb = f4add(nb, f4sub(xc, xat(i0 - 1, j, k, mg_deg1(i0 - 1, R) + dj + dk, eat(I - 1, J, K))));
-    } else {
-      nb = f4add(nb, f4sub(xc, x0));
-      if (i1 + 1 < R) nb = f4add(nb, f4sub(xc, xat(i1 + 1, j, k, mg_deg1(i1 + 1, R) + dj + dk, eat(I + 1, J, K))));
-    }
-    if (j > 0) nb = f4add(nb, f4sub(xc, xat(i, j - 1, k, di + mg_deg1(j - 1, R) + dk, eat(I, (j - 1) >> 1, K))));
-    if (j < R - 1) nb = f4add(nb, f4sub(xc, xat(i, j + 1, k, di + mg_deg1(j + 1, R) + dk, eat(I, (j + 1) >> 1, K))));
-    if (k > 0) nb = f4add(nb, f4sub(xc, xat(i, j, k - 1, di + dj + mg_deg1(k - 1, R), eat(I, J, (k - 1) >> 1))));
-    if (k < R - 1) nb = f4add(nb, f4sub(xc, xat(i, j, k + 1, di + dj + mg_deg1(k + 1, R), eat(I, J, (k + 1) >> 1))));
+    float4 nb = f4add(f4sub(xc, h ? x0 : xl), f4sub(xc, h ? xr : x1));  // sum over neighbours of (x_c - x_nb)
+    nb = f4add(nb, f4add(f4sub(xc, xat(i, jm, k)), f4sub(xc, xat(i, jp, k))));
+    nb = f4add(nb, f4add(f4sub(xc, xat(i, j, km)), f4sub(xc, xat(i, j, kp))));
     const int n = (k * R + j) * R + i;
     const float4 bc = B[n];
     const float4 ax = f4axpy(lw, nb, f4scale(mass, xc));
     // lam = 0 (A = I): the identity preconditioner
-    const float4 z = ident ? bc : f4axpy(mg_f(tk, di + dj + dk), f4sub(bc, ax), xc);
+    const int dc = mg_deg1(i, R) + mg_deg1(j, R) + mg_deg1(k, R);
+    const float4 z = ident ? bc : f4axpy(mg_f(tk, dc), f4sub(bc, ax), xc);
     Z[n] = z;
     if (fine) {
       acc[0] += (double)bc.x * (double)z.x;
