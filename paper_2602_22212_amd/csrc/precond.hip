@@ -46,6 +46,7 @@ constexpr int kChunk = kB * kPer;
 // per (system, channel) scalars: 0 rho (r.z with the V-cycle, else r.r), 1 bb, 2 rr, 3 alpha,
 // 4 beta, 5 active, 6 iterations, 7 alpha of the pending x term (0 when none)
 constexpr int kS = 8;
+constexpr float kMgOmegaW = 0.85f;  // Jacobi damping of the V-cycle (kMgOmega below)
 constexpr int kR_THREADS = 1024, kR_WAVES = kR_THREADS / 64;  // reduction work-group
 
 // Loads/stores of one node's F channels: vector instructions when the grid's
@@ -358,7 +359,9 @@ struct ZPlane {
 // of the grid inside the tile. Every thread of the work-group must call this
 // (it synchronises the work-group once per plane).
 // POST(z) runs in every thread after the plane's BODY (it may synchronise
-// the work-group).
+// the work-group). LD also receives which of the thread's three columns it
+// reads (0 its own, 1 the x neighbour beyond the tile, 2 the halo row) and the
+// plane, BODY the plane, so callers can precompute per-column data.
 template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY, typename POST>
 __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body,
                                              POST post) {
@@ -376,24 +379,24 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
   const int hy = w == 0 ? max(t.y0 - 1, 0) : min(t.y0 + kTY, R - 1);
   const int hrow = w == 0 ? 0 : kTY + 1;
   const int64_t dh = (int64_t)(hy - ye) * R;
-  auto load_plane = [&](int64_t m, ZPlane<RAW, EX>& P) {
-    P.c = ld(m);
+  auto load_plane = [&](int64_t m, int zz, ZPlane<RAW, EX>& P) {
+    P.c = ld(m, 0, zz);
     P.ex = ldc(m);
-    if (edge_lane) P.e = ld(m + de);
-    if (halo) P.h = ld(m + dh);
+    if (edge_lane) P.e = ld(m + de, 1, zz);
+    if (halo) P.h = ld(m + dh, 2, zz);
   };
   int64_t n = (int64_t)t.z0 * R2 + (int64_t)ye * R + xe;
   ZPlane<RAW, EX> A = {}, B = {};
-  load_plane(n, A);
+  load_plane(n, t.z0, A);
   float4 cur = op(A.c), edge = op(A.e);
   EX ex = A.ex;
   sh[t.z0 % 3][w + 1][lane] = cur;
   if (halo) sh[t.z0 % 3][hrow][lane] = op(A.h);
-  float4 prev = t.z0 > 0 ? op(ld(n - R2)) : cur;
-  load_plane(t.z0 + 1 < R ? n + R2 : n, A);
+  float4 prev = t.z0 > 0 ? op(ld(n - R2, 0, t.z0 - 1)) : cur;
+  load_plane(t.z0 + 1 < R ? n + R2 : n, min(t.z0 + 1, R - 1), A);
   for (int z = t.z0; z < t.z1; ++z, n += R2) {
     const int64_t n1 = z + 1 < R ? n + R2 : n;
-    load_plane(z + 2 < R ? n1 + R2 : n1, B);
+    load_plane(z + 2 < R ? n1 + R2 : n1, min(z + 2, R - 1), B);
     // plane z+1 (clamped to z at the top face, where it then adds 0)
     const float4 nxt = op(A.c), nedge = op(A.e);
     sh[(z + 1) % 3][w + 1][lane] = nxt;
@@ -406,7 +409,7 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
     f4lap(lap, cur, sh[z % 3][w + 2][lane]);
     f4lap(lap, cur, prev);
     f4lap(lap, cur, nxt);
-    if (inside) body(n, lap, cur, ex);
+    if (inside) body(n, lap, cur, ex, z);
     post(z);
     prev = cur;
     cur = nxt;
@@ -417,7 +420,33 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
 }
 template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY>
 __device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body) {
-  zm_walk_post<RAW, EX>(g, t, ld, ldc, op, body, [](int) {});
+  zm_walk_post<RAW, EX>(
+      g, t, [&](int64_t m, int, int) { return ld(m); }, ldc, op,
+      [&](int64_t n, const float4& lap, const float4& c, const EX& e, int) { body(n, lap, c, e); }, [](int) {});
+}
+
+// Per-column data of a z-column walk for the V-cycle's finest level: the
+// Jacobi factor w / (1 + lam deg) of the thread's three columns (own, x
+// neighbour beyond the tile, halo row) on interior and on boundary planes,
+// and the parent row offset (x/2, y/2) on the level below.
+struct ZmCols {
+  float fin[3], fbd[3];
+  int pxy[3];
+};
+__device__ __forceinline__ ZmCols zm_cols(const Tile& t, int R, float lam, int nh) {
+  const int lane = threadIdx.x & (kTX - 1), w = threadIdx.x / kTX;
+  const int xe = min(t.x0 + lane, R - 1), ye = min(t.y0 + w, R - 1);
+  const int xs[3] = {xe, lane == 0 ? max(xe - 1, 0) : min(xe + 1, R - 1), xe};
+  const int ys[3] = {ye, ye, w == 0 ? max(t.y0 - 1, 0) : min(t.y0 + kTY, R - 1)};
+  ZmCols c;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int d = ((xs[s] > 0) + (xs[s] < R - 1)) + ((ys[s] > 0) + (ys[s] < R - 1));
+    c.fin[s] = kMgOmegaW * __builtin_amdgcn_rcpf(fmaf(lam, (float)(d + 2), 1.f));
+    c.fbd[s] = kMgOmegaW * __builtin_amdgcn_rcpf(fmaf(lam, (float)(d + 1), 1.f));
+    c.pxy[s] = (ys[s] >> 1) * nh + (xs[s] >> 1);
+  }
+  return c;
 }
 
 __device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* x, float* r, float* p, double* part,
@@ -693,7 +722,7 @@ __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restr
 // Jacobi sweeps from zero. Smoothing before and after is the same symmetric
 // Jacobi step and the restriction is P^T, so the preconditioner is symmetric
 // and positive definite (w < 1 < 2 / rho(D^-1 A)).
-constexpr float kMgOmega = 0.85f;
+constexpr float kMgOmega = kMgOmegaW;
 constexpr int kMgCoarse = 4;
 constexpr int kMgMinN = 8;
 constexpr int kMgB = 256;
@@ -1006,8 +1035,8 @@ __global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, in
 // z-adjacent planes (registers), and written by the even lane of the even
 // wave at the odd plane (or at the last plane of an odd-sized grid). Tiles
 // start at even x, y and z, so no 2x2x2 block straddles two tiles.
-__device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const FastDiv& fR, const FastDiv& fR2,
-                            const MgTask* tk, const float* __restrict__ r, float* __restrict__ bh) {
+__device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, const float* __restrict__ r,
+                            float* __restrict__ bh) {
   __shared__ float4 ys[2][kTY / 2][kTX];
   const int R = g.R;
   const int nh = tk->hi.n;
@@ -1016,19 +1045,17 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const FastDiv& fR, 
   float4* H = reinterpret_cast<float4*>(bh + tk->hi.off);
   const int lane = threadIdx.x & (kTX - 1), w = threadIdx.x / kTX;
   const int x = t.x0 + lane, y = t.y0 + w;
-  auto fdeg = [&](int64_t m) {
-    const int k = (int)fdiv((uint32_t)m, fR2);
-    const uint32_t rem = (uint32_t)m - (uint32_t)k * fR2.d;
-    const int j = (int)fdiv(rem, fR);
-    const int i = (int)(rem - (uint32_t)j * (uint32_t)R);
-    const int d = mg_deg1(i, R) + mg_deg1(j, R) + mg_deg1(k, R);
-    return kMgOmega * __builtin_amdgcn_rcpf(fmaf(lam, (float)d, 1.f));
-  };
+  const ZmCols cols = zm_cols(t, R, lam, nh);
   float4 rs = make_float4(0.f, 0.f, 0.f, 0.f), zacc = rs;
   zm_walk_post<Raw1, Raw1>(
-      g, t, [&](int64_t m) { return Raw1{f4scale(fdeg(m), B[m])}; }, [&](int64_t m) { return Raw1{B[m]}; },
-      [&](const Raw1& v) { return v.a; },
-      [&](int64_t, const float4& lap, const float4& xc, const Raw1& e) { rs = f4sub(e.a, f4axpy(lam, lap, xc)); },
+      g, t,
+      [&](int64_t m, int s, int zz) {
+        return Raw1{f4scale((zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s], B[m])};
+      },
+      [&](int64_t m) { return Raw1{B[m]}; }, [&](const Raw1& v) { return v.a; },
+      [&](int64_t, const float4& lap, const float4& xc, const Raw1& e, int) {
+        rs = f4sub(e.a, f4axpy(lam, lap, xc));
+      },
       [&](int z) {
         float4 v = f4add(rs, make_float4(__shfl_xor(rs.x, 1), __shfl_xor(rs.y, 1), __shfl_xor(rs.z, 1),
                                          __shfl_xor(rs.w, 1)));
@@ -1057,52 +1084,43 @@ __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, 
   const MgTask* tk = T0 + s;
   if (!tk->zm0) return;
   const NpgGrid g = G[s];
-  mg_down0_zm(g, unpack_tile(blk_start[blk]), dv.r[s], dv.r2[s], tk, r, bh);
+  (void)dv;
+  mg_down0_zm(g, unpack_tile(blk_start[blk]), tk, r, bh);
 }
 
 // Prolongation and post-smoothing onto the finest level (z = M^-1 r) over the
 // CG work-group table: the z-column walk for the large grids (each row read
 // once; x = w D^-1 r + P e formed as it is loaded), node chunks otherwise;
 // r.z partials per work-group. T0: the system's task (system order).
-__device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const FastDiv& fR, const FastDiv& fR2, const MgTask* tk,
-                          const float* __restrict__ r, const float* __restrict__ eh, float* __restrict__ z,
-                          double (&acc)[4]) {
+__device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, const float* __restrict__ r,
+                          const float* __restrict__ eh, float* __restrict__ z, double (&acc)[4]) {
   const int R = g.R;
   const int nh = tk->hi.n;
   const float lam = g.lam;
   const float4* B = reinterpret_cast<const float4*>(r + g.poff);
   const float4* E = reinterpret_cast<const float4*>(eh + tk->hi.off);
   float4* Z = reinterpret_cast<float4*>(z + g.poff);
-  auto coords = [&](int64_t m, int& i, int& j, int& k) {
-    k = (int)fdiv((uint32_t)m, fR2);
-    const uint32_t rem = (uint32_t)m - (uint32_t)k * fR2.d;
-    j = (int)fdiv(rem, fR);
-    i = (int)(rem - (uint32_t)j * (uint32_t)R);
-  };
-  auto fdeg = [&](int i, int j, int k) {
-    const int d = mg_deg1(i, R) + mg_deg1(j, R) + mg_deg1(k, R);
-    return kMgOmega * __builtin_amdgcn_rcpf(fmaf(lam, (float)d, 1.f));
-  };
-  zm_walk<Raw1, Raw1>(
+  const ZmCols cols = zm_cols(t, R, lam, nh);
+  const int nh2 = nh * nh;
+  zm_walk_post<Raw1, Raw1>(
       g, t,
-      [&](int64_t m) {
-        int i, j, k;
-        coords(m, i, j, k);
-        return Raw1{f4add(f4scale(fdeg(i, j, k), B[m]), E[((k >> 1) * nh + (j >> 1)) * nh + (i >> 1)])};
+      [&](int64_t m, int s, int zz) {
+        const float f = (zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s];
+        return Raw1{f4add(f4scale(f, B[m]), E[(zz >> 1) * nh2 + cols.pxy[s]])};
       },
       [&](int64_t m) { return Raw1{B[m]}; }, [&](const Raw1& v) { return v.a; },
-      [&](int64_t n, const float4& lap, const float4& xc, const Raw1& e) {
-        int i, j, k;
-        coords(n, i, j, k);
+      [&](int64_t n, const float4& lap, const float4& xc, const Raw1& e, int zz) {
         const float4 bc = e.a;
         const float4 ax = f4axpy(lam, lap, xc);
-        const float4 zz = lam == 0.f ? bc : f4axpy(fdeg(i, j, k), f4sub(bc, ax), xc);
-        Z[n] = zz;
-        acc[0] += (double)bc.x * (double)zz.x;
-        acc[1] += (double)bc.y * (double)zz.y;
-        acc[2] += (double)bc.z * (double)zz.z;
-        acc[3] += (double)bc.w * (double)zz.w;
-      });
+        const float f = (zz == 0 || zz == R - 1) ? cols.fbd[0] : cols.fin[0];
+        const float4 zv = lam == 0.f ? bc : f4axpy(f, f4sub(bc, ax), xc);
+        Z[n] = zv;
+        acc[0] += (double)bc.x * (double)zv.x;
+        acc[1] += (double)bc.y * (double)zv.y;
+        acc[2] += (double)bc.z * (double)zv.z;
+        acc[3] += (double)bc.w * (double)zv.w;
+      },
+      [](int) {});
 }
 
 __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, Divs dv, int nb,
@@ -1119,7 +1137,7 @@ __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, Di
   const MgTask* tk = T0 + s;
   double acc[4] = {0, 0, 0, 0};
   if (use_zm(g) && tk->hi.off % 4 == 0) {
-    mg_up0_zm(g, unpack_tile(blk_start[blk]), dv.r[s], dv.r2[s], tk, r, eh, z, acc);
+    mg_up0_zm(g, unpack_tile(blk_start[blk]), tk, r, eh, z, acc);
   } else {
     for (int k = 0; k < kPer; ++k) {
       const int64_t n = blk_start[blk] + k * kB + threadIdx.x;
