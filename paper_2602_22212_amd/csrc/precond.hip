@@ -1,6 +1,9 @@
 // Sobolev preconditioning of the grid gradients (Sec. 3.5): g~ = (I+lam L)^-2 g
 // per grid and feature channel, L the 6-neighbour lattice Laplacian with free
-// boundary, as two conjugate-gradient solves from a zero start.
+// boundary, as two conjugate-gradient solves from a zero start, each stopped
+// at ||r|| <= rtol ||b||. With cg_mg = 1 every solve is preconditioned by one
+// multigrid V-cycle per iteration (z = M^-1 r; p = z + beta p, rho = r.z; see
+// "multigrid V-cycle preconditioner" below), otherwise plain CG (z = r).
 //
 // All grids (every position level and the normal grid) iterate together:
 // each launch covers the blocks of every system still active, through a
@@ -8,16 +11,16 @@
 // layout ([node][F] per grid); inner products are float64, reduced per wave
 // and then per system in a fixed order (bitwise reproducible).
 //
-// One CG iteration is two streaming kernels:
-//   k_cg_dir_ap:  p = r + beta p, and p.(A p) with A p formed on the fly from
-//                 r and the old p at the 6 neighbours (p is written, A p is not)
+// One CG iteration is two streaming kernels (plus the V-cycle):
+//   k_cg_dir_ap:  p = z + beta p, and p.(A p) with A p formed on the fly from
+//                 z and the old p at the 6 neighbours (p is written, A p is not)
 //   k_cg_update:  r -= alpha A p (A p recomputed from p) and r.r; x is
 //                 updated every second iteration only, with both pending terms
 //                 (x += alpha_{k-1} p_{k-1}, then x += alpha_k p_k: the same
 //                 float32 operations in the same order as one update per
 //                 iteration), the older direction read from the other
 //                 ping-pong buffer
-// i.e. 7.5 vector passes per iteration on average (r, p, p | p, r, r, and
+// i.e. 7.5 vector passes per iteration on average (z, p, p | p, r, r, and
 // every second iteration p_{k-1}, x, x) instead of 10 with A p stored. A
 // term left pending when a system stops is added by a flush pass.
 // A p = p + lam * sum over existing neighbours of (p_n - p_nb): sums of
