@@ -1241,11 +1241,23 @@ __global__ __launch_bounds__(64 * kB16W) void k_decode_bwd16(
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < kB16S / 32; ++ks) {
+          // owned tile k is (row tile (wave + 4k) / NT, column tile (wave + 4k) % NT):
+          // every row tile's gradient operand and the wave's NKT column tiles'
+          // input operands are read once per K block and reused across tiles
+          constexpr int NKT = NT >= 8 ? 2 : 1;
+          v8s gk[NT], hk[NKT];
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) gk[mt] = kop(sG, mt, ks);
+#pragma unroll
+          for (int j = 0; j < NKT; ++j) hk[j] = kop(sH, (wave + kB16W * j) % NT, ks);
 #pragma unroll
           for (int k = 0; k < NTT; ++k) {
             const unsigned tau = (unsigned)wave + kB16W * k;
-            if (tau < (unsigned)(NT * NT))
-              accW[l - 1][k] = mfma32(kop(sG, tau / NT, ks), kop(sH, tau % NT, ks), accW[l - 1][k]);
+            if (tau < (unsigned)(NT * NT)) {
+              // row tile: k / 2 for NT = 8, k for NT = 4, wave / 2 for NT = 2
+              const v8s g = NT == 2 ? ((wave >> 1) ? gk[NT - 1] : gk[0]) : gk[(kB16W * k) / NT];
+              accW[l - 1][k] = mfma32(g, hk[k % NKT], accW[l - 1][k]);
+            }
           }
           __builtin_amdgcn_sched_barrier(0);
         }
