@@ -38,16 +38,17 @@ def test_library_exports_every_declared_symbol():
 def test_config_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "neupig.h"\n'
-                    "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(npg_config),"
+                    "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(npg_config),"
                     " offsetof(npg_config, lam), offsetof(npg_config, cg_rtol),"
                     " offsetof(npg_config, cg_maxit), offsetof(npg_config, precond),"
-                    " offsetof(npg_config, rot_head), offsetof(npg_config, precision));return 0;}\n")
+                    " offsetof(npg_config, rot_head), offsetof(npg_config, precision),"
+                    " offsetof(npg_config, cg_mg));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
     C = npg.npg_config
     assert vals == [ctypes.sizeof(C), C.lam.offset, C.cg_rtol.offset, C.cg_maxit.offset, C.precond.offset,
-                    C.rot_head.offset, C.precision.offset]
+                    C.rot_head.offset, C.precision.offset, C.cg_mg.offset]
 
 
 @pytest.mark.parametrize("name,head", [("c1", "expmap"), ("c2", "expmap"), ("c3", "expmap"), ("small", "expmap"),
@@ -83,6 +84,7 @@ def test_param_count_matches_layout(name, head):
     (dict(w_iso=-1.0), "w_iso"),
     (dict(act="leaky", leaky_slope=1.5), "leaky_slope"),
     (dict(act="leaky", leaky_slope=0.0), "leaky_slope"),
+    (dict(cg_mg=2), "cg_mg"),
 ])
 def test_invalid_configs_are_rejected(bad, msg):
     _lib()

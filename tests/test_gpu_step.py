@@ -190,11 +190,12 @@ def test_nonfinite_inputs_are_rejected():
     assert e.value.status == npg.NPG_EINVAL
 
 
-def test_cg_cap_is_reported():
+@pytest.mark.parametrize("cg_mg", [1, 0])
+def test_cg_cap_is_reported(cg_mg):
     import torch
 
     import paper_2602_22212_amd as npg
-    cfg = synth.config_small(mlp_width=32, cg_maxit=1, cg_rtol=1e-12, levels=[6, 9])
+    cfg = synth.config_small(mlp_width=32, cg_maxit=1, cg_rtol=1e-12, levels=[6, 9], cg_mg=cg_mg)
     data = synth.make_workload(cfg)
     plan = gpu_plan(cfg, data)
     plan.set_state(flat_params(cfg, synth.random_state(cfg, 2)), adam_steps=0)
