@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, Di
   const NpgGrid g = G[s];
   const MgTask* tk = T0 + s;
   double acc[4] = {0, 0, 0, 0};
-  if (use_zm(g) && tk->hi.off % 4 == 0) {
+  if (use_zm(g)) {  // the block table holds z-column tiles for these grids
     mg_up0_zm(g, unpack_tile(blk_start[blk]), tk, r, eh, z, acc);
   } else {
     for (int k = 0; k < kPer; ++k) {
@@ -1238,7 +1238,7 @@ static npg_status mg_setup(npg_plan* P) {
       L.s *= 2;
       L.off = coarse;
       const int64_t e = (int64_t)L.n * L.n * L.n * L.F;
-      coarse += (e + 3) / 4 * 4;  // every level 16-byte aligned
+      coarse += (e + 3) / 4 * 4;  // every level 16-byte aligned (the z-column kernels rely on it)
       C.mg_elems[sy] += (double)e;
     }
     nlev = std::max(nlev, (int)lv[sy].size());
@@ -1260,8 +1260,9 @@ static npg_status mg_setup(npg_plan* P) {
       const MgLvl& W = up ? t.lo : t.hi;
       t.nodes = (int64_t)W.n * W.n * W.n;
       t.fast = t.lo.F == 4 && t.lo.off % 4 == 0 && t.hi.off % 4 == 0 && t.lo.R % t.lo.s == 0;
-      // the z-column tiles of the CG table (same test as use_zm)
-      t.zm0 = !up && l == 0 && t.lo.R >= kZmR && t.lo.F == 4 && t.lo.off % 4 == 0 && t.hi.off % 4 == 0;
+      // the z-column tiles of the CG table (same test as use_zm; every coarse
+      // level is 16-byte aligned, so the float4 access to level 1 holds too)
+      t.zm0 = !up && l == 0 && t.lo.R >= kZmR && t.lo.F == 4 && t.lo.off % 4 == 0;
       if (t.fast) {
         const float sz = (float)t.lo.s;
         t.mass = sz * sz * sz;
