@@ -313,13 +313,14 @@ def _batch_time(cfgs, datas, steps, warmup, state):
         batch.step(e, max(steps + warmup, 500))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    statuses = set()
     for e in range(steps):
-        batch.step(warmup + e, max(steps + warmup, 500))
+        statuses.add(int(batch.step(warmup + e, max(steps + warmup, 500))))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     final = [plan_cd(p) for p in batch.plans]
     batch.close()
-    return dt, final, tuned
+    return dt, final, tuned, sorted(statuses)
 
 
 def plan_cd(plan):
@@ -358,9 +359,9 @@ def run_batch(steps=2, warmup=1, quality_steps=20):
     res = {}
     for prec in ("bf16", "fp32"):
         cs = [dict(c, precision=prec) for c in cfgs]
-        dt, _, tuned = _batch_time(cs, datas, steps, warmup, "random")
-        dq, final, _ = _batch_time([dict(c, precond="dct") for c in cs], datas, quality_steps, 0, "init")
-        res[prec] = dict(dt=dt, dq=dq, final=final, tuned=tuned)
+        dt, _, tuned, st = _batch_time(cs, datas, steps, warmup, "random")
+        dq, final, _, _ = _batch_time([dict(c, precond="dct") for c in cs], datas, quality_steps, 0, "init")
+        res[prec] = dict(dt=dt, dq=dq, final=final, tuned=tuned, status=st)
     pairs = sum(len(d["xyz"]) * int(d["frame_off"][-1]) for d in datas)
     samples = sum(len(d["xyz"]) * d["T"] for d in datas)
     b, f = res["bf16"], res["fp32"]
@@ -374,6 +375,7 @@ def run_batch(steps=2, warmup=1, quality_steps=20):
                         "mean_ratio_bf16_over_fp32_final_cd": round(ratio, 5),
                         "note": "mean per-frame Chamfer distance of each sequence after the last step, averaged"},
             "nn_autotune_threads": res["bf16"]["tuned"],
+            "step_status": {"bf16": res["bf16"]["status"], "fp32": res["fp32"]["status"]},
             "sequences": len(cfgs), "steps": steps, "warmup": warmup,
             "samples_per_step": samples, "chamfer_pairs_per_direction": pairs,
             "sequence_shapes": [(len(d["xyz"]), d["T"], int(d["frame_off"][-1])) for d in datas],
@@ -393,9 +395,10 @@ def run_animal(steps=2, warmup=1):
     r = run_form(cfg, data, synth.random_state(cfg, 9, grid_std=0.05), steps, warmup, profile=False)
     return {"value": round(r["value"], 4), "unit": "steps/s", "ms_per_step": round(r["ms_per_step"], 2),
             "steps": steps, "warmup": warmup, "stage_ms": r["stage_ms"],
+            "step_status": r["status"], "cg_final_relres_max": r["cg_relres_max"],
             "stage_roofline": stage_roofline(cfg, data, r["stage_ms"], "f32"),
             "workload": f"quadruped_v{len(data['xyz'])}_t{data['T']}_n{int(data['frame_off'][-1])}",
-            "note": "13-capsule quadruped, 8-level grids 16..256 x 4, 14->128x3->6 MLP, float32, CG"}
+            "note": "13-capsule quadruped, 8-level grids 16..256 x 4, 14->128x3->6 MLP, float32, CG with the V-cycle"}
 
 
 def main():
@@ -495,6 +498,7 @@ def main():
         out["bf16"] = {"value": round(b16["value"], 4), "unit": "steps/s", "ms_per_step": round(b16["ms_per_step"], 3),
                        "stage_ms": b16["stage_ms"],
                        "stage_roofline": stage_roofline(cfg, data, b16["stage_ms"], "bf16"),
+                       "step_status": b16["status"],
                        "note": "headline step with the MLP's matrix operands in bfloat16 (float32 accumulation)",
                        "quality": None if args.no_quality else run_quality(cfg)}
     if "batch" in forms:
