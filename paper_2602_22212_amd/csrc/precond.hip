@@ -1074,7 +1074,7 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
       });
 }
 
-__global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, Divs dv, int nb,
+__global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, int nb,
                                                  const int* __restrict__ blk_sys,
                                                  const int64_t* __restrict__ blk_start,
                                                  const int* __restrict__ active, int check_active,
@@ -1087,7 +1087,6 @@ __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, 
   const MgTask* tk = T0 + s;
   if (!tk->zm0) return;
   const NpgGrid g = G[s];
-  (void)dv;
   mg_down0_zm(g, unpack_tile(blk_start[blk]), tk, r, bh);
 }
 
@@ -1126,7 +1125,7 @@ __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, con
       [](int) {});
 }
 
-__global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, Divs dv, int nb,
+__global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, int nb,
                                                const int* __restrict__ blk_sys, const int64_t* __restrict__ blk_start,
                                                const int* __restrict__ active, int check_active,
                                                const MgTask* __restrict__ T0, const float* __restrict__ r,
@@ -1311,12 +1310,12 @@ static npg_status mg_setup(npg_plan* P) {
 
 // z = M^-1 r (one V-cycle for every system; with check_active only the
 // systems still iterating), r.z partials into part2.
-static npg_status mg_apply(npg_plan* P, const Divs& dv, const float* r, float* z, int check_active) {
+static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_active) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nl = C.mg_nlev;
   const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
-  hipLaunchKernelGGL(k_mg_down0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, dv, C.n_blocks, C.blk_sys,
+  hipLaunchKernelGGL(k_mg_down0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
                      C.blk_start, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB);
   for (int l = 0; l + 1 < nl; ++l)
     if (C.mg_l_ntask[l] > 0)
@@ -1331,7 +1330,7 @@ static npg_status mg_apply(npg_plan* P, const Divs& dv, const float* r, float* z
       hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[li])), dim3(kMgB), 0, s, T + C.mg_l_task0[li],
                          C.mg_l_ntask[li], C.mg_l_nblk[li], C.active, check_active, C.mgB, C.mgX, C.mgX);
   }
-  hipLaunchKernelGGL(k_mg_up0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, dv, C.n_blocks, C.blk_sys,
+  hipLaunchKernelGGL(k_mg_up0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
                      C.blk_start, C.active, check_active, T + C.mg_l_task0[nl - 1], r, C.mgX, z, C.part2);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
@@ -1414,7 +1413,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
   double* part2 = mg ? C.part2 : nullptr;
   const float* dir_src = mg ? C.z : C.r;  // p = z + beta p (z = r without the V-cycle)
   hipLaunchKernelGGL(k_cg_init, grid, blk, 0, s, P->d_g, nb, C.blk_sys, C.blk_start, b, x, C.r, C.p, C.part);
-  if (mg) NPG_TRY_ST(mg_apply(P, dv, C.r, C.z, 0));
+  if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0));
   hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
                      part2, C.sys_blk0, C.st, 0, P->cfg.cg_rtol, 0);
   NPG_HIP(hipGetLastError());
@@ -1445,7 +1444,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
       else
         hipLaunchKernelGGL(k_cg_update<0>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
                            x, C.r, pa, pb, C.part);
-      if (mg) NPG_TRY_ST(mg_apply(P, dv, C.r, C.z, 1));
+      if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 1));
       if (prof) {
         NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 3], s));
         P->prof_n += 4;
