@@ -28,12 +28,17 @@ def _mid_bf16(**kw):
     return synth.config_small(**base)
 
 
-@pytest.mark.parametrize("width,hidden,head", [(128, 3, "expmap"), (64, 2, "quat"), (32, 1, "expmap")])
-def test_bf16_stages(width, hidden, head):
+@pytest.mark.parametrize("width,hidden,head,shape", [(128, 3, "expmap", None), (64, 2, "quat", None),
+                                                      (32, 1, "expmap", None), (128, 3, "expmap", "tiny")])
+def test_bf16_stages(width, hidden, head, shape):
     import torch
 
     import paper_2602_22212_amd as npg
     cfg = _mid_bf16(mlp_width=width, mlp_hidden=hidden, rot_head=head)
+    if shape == "tiny":
+        # one frame (a single, half-empty frame pair) and 17 vertices (a second,
+        # one-vertex block) for the forward's frame-pair items
+        cfg = _mid_bf16(mlp_width=width, mlp_hidden=hidden, rot_head=head, V=17, T=1, N=[40], t_key=0)
     data = synth.make_workload(cfg)
     plan = gpu_plan(cfg, data)
     T, V = data["T"], len(data["xyz"])
@@ -51,7 +56,9 @@ def test_bf16_stages(width, hidden, head):
     ff = O.forward(P, data, dict(cfg, precision="fp32"))
     d32 = [rel(fw["xhat"][t], ff["xhat"][t]) for t in range(T)]
     print("bf16 decode error per frame:", ["%.1e" % e for e in ex], "bf16 vs fp32 oracle:", ["%.1e" % e for e in d32])
-    assert max(ex) < TOL_X and min(d32) > 10 * max(ex)
+    assert max(ex) < TOL_X
+    if shape is None:  # at 17 samples the two forms differ by only ~10x the error; the larger cases check it
+        assert min(d32) > 10 * max(ex)
     # decode backward with a fixed upstream gradient
     rng = np.random.default_rng(7)
     gx = rng.normal(size=(T, V, 3)).astype(np.float32)
