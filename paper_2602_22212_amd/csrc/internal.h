@@ -37,6 +37,7 @@ struct NpgCG {  // conjugate-gradient workspace
   float *mgB, *mgX;            // coarse levels of every system: right-hand sides, corrections
   double* part2;               // [n_blocks][4] partial r.z (the CG work-group table)
   void* mg_tasks;              // device table of the V-cycle launches (struct MgTask)
+  std::vector<std::vector<int>> mg_l_blk0;  // per launch: first block of each task, padded with INT_MAX
   std::vector<int> mg_l_task0, mg_l_ntask, mg_l_nblk;  // per launch: first task, tasks, blocks
   int mg_nlev;                 // levels of the deepest hierarchy
   double mg_elems[NPG_MAX_SYS];  // per system: coarse-level floats summed over the levels

@@ -31,6 +31,7 @@
 // neighbours, lane shifts the x neighbours, LDS the y neighbours); small grids
 // in contiguous node chunks. Work-groups are dispatched largest grid first.
 #include <algorithm>
+#include <climits>
 
 #include "internal.h"
 
@@ -357,17 +358,24 @@ struct ZPlane {
   EX ex;
 };
 
-// LD(node) loads the raw stencil operand, OP(raw) forms it, LDC(node) loads
-// the body's extra data; BODY(node, lap, operand, extra) runs at every node
-// of the grid inside the tile. Every thread of the work-group must call this
-// (it synchronises the work-group once per plane).
-// POST(z) runs in every thread after the plane's BODY (it may synchronise
-// the work-group). LD also receives which of the thread's three columns it
-// reads (0 its own, 1 the x neighbour beyond the tile, 2 the halo row) and the
-// plane, BODY the plane, so callers can precompute per-column data.
-template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY, typename POST>
+// LD(node, column, plane) loads the raw stencil operand, OP(raw, column,
+// plane) forms it, LDC(node) loads the body's extra data; BODY(node, lap,
+// operand, extra, plane) runs at every node of the grid inside the tile.
+// The column argument says which of the thread's three columns is meant (0
+// its own, 1 the x neighbour beyond the tile, 2 the halo row), so callers can
+// precompute per-column data. Every thread of the work-group must call this
+// (it synchronises the work-group once per plane). POST(z) runs in every
+// thread after the plane's BODY (it may synchronise the work-group).
+//
+// The raw loads run DEPTH planes ahead of the arithmetic (DEPTH 2 or 3 plane
+// buffers whose roles rotate; the loop is unrolled by DEPTH so no buffer is
+// copied) and are formed by OP only when their plane is reached, so they stay
+// in flight across the work-group barriers of DEPTH-1 planes.
+template <typename RAW, typename EX, int DEPTH = 2, typename LD, typename LDC, typename OP, typename BODY,
+          typename POST>
 __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body,
                                              POST post) {
+  static_assert(DEPTH == 2 || DEPTH == 3, "planes loaded ahead of the arithmetic: 2 or 3");
   __shared__ float4 sh[3][kTY + 2][kTX];
   const int R = g.R;
   const int64_t R2 = (int64_t)R * R;
@@ -377,33 +385,40 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
   const bool inside = x < R && y < R;
   const int oxm = xe > 0 ? -1 : 0, oxp = xe < R - 1 ? 1 : 0;
   const bool edge_lane = lane == 0 || lane == kTX - 1;
-  const int64_t de = lane == 0 ? oxm : oxp;
   const bool halo = w == 0 || w == kTY - 1;
   const int hy = w == 0 ? max(t.y0 - 1, 0) : min(t.y0 + kTY, R - 1);
   const int hrow = w == 0 ? 0 : kTY + 1;
-  const int64_t dh = (int64_t)(hy - ye) * R;
-  auto load_plane = [&](int64_t m, int zz, ZPlane<RAW, EX>& P) {
+  // every thread issues all three loads (threads without an x neighbour or
+  // halo row beyond the tile reload their own node), so no load sits behind a
+  // branch and the wait for a plane never has to cover later planes' loads
+  const int64_t nxy = (int64_t)ye * R + xe;
+  const int64_t de = edge_lane ? (lane == 0 ? oxm : oxp) : 0;
+  const int64_t dh = halo ? (int64_t)(hy - ye) * R : 0;
+  auto load_plane = [&](int zz, ZPlane<RAW, EX>& P) {  // zz already clamped to [0, R)
+    const int64_t m = (int64_t)zz * R2 + nxy;
     P.c = ld(m, 0, zz);
     P.ex = ldc(m);
-    if (edge_lane) P.e = ld(m + de, 1, zz);
-    if (halo) P.h = ld(m + dh, 2, zz);
+    P.e = ld(m + de, 1, zz);
+    P.h = ld(m + dh, 2, zz);
   };
-  int64_t n = (int64_t)t.z0 * R2 + (int64_t)ye * R + xe;
-  ZPlane<RAW, EX> A = {}, B = {};
-  load_plane(n, t.z0, A);
-  float4 cur = op(A.c), edge = op(A.e);
+  int64_t n = (int64_t)t.z0 * R2 + nxy;
+  ZPlane<RAW, EX> A, B, C;
+  load_plane(t.z0, A);
+  float4 cur = op(A.c, 0, t.z0), edge = op(A.e, 1, t.z0);
   EX ex = A.ex;
   sh[t.z0 % 3][w + 1][lane] = cur;
-  if (halo) sh[t.z0 % 3][hrow][lane] = op(A.h);
-  float4 prev = t.z0 > 0 ? op(ld(n - R2, 0, t.z0 - 1)) : cur;
-  load_plane(t.z0 + 1 < R ? n + R2 : n, min(t.z0 + 1, R - 1), A);
-  for (int z = t.z0; z < t.z1; ++z, n += R2) {
-    const int64_t n1 = z + 1 < R ? n + R2 : n;
-    load_plane(z + 2 < R ? n1 + R2 : n1, min(z + 2, R - 1), B);
-    // plane z+1 (clamped to z at the top face, where it then adds 0)
-    const float4 nxt = op(A.c), nedge = op(A.e);
+  if (halo) sh[t.z0 % 3][hrow][lane] = op(A.h, 2, t.z0);
+  float4 prev = t.z0 > 0 ? op(ld(n - R2, 0, t.z0 - 1), 0, t.z0 - 1) : cur;
+  load_plane(min(t.z0 + 1, R - 1), B);
+  if (DEPTH == 3) load_plane(min(t.z0 + 2, R - 1), C);
+  // Pn holds plane z+1 (clamped to z at the top face, where it then adds 0);
+  // Pl held plane z and receives plane z+DEPTH.
+  auto step = [&](int z, ZPlane<RAW, EX>& Pn, ZPlane<RAW, EX>& Pl) {
+    const int z1c = min(z + 1, R - 1);
+    load_plane(min(z + DEPTH, R - 1), Pl);
+    const float4 nxt = op(Pn.c, 0, z1c), nedge = op(Pn.e, 1, z1c);
     sh[(z + 1) % 3][w + 1][lane] = nxt;
-    if (halo) sh[(z + 1) % 3][hrow][lane] = op(A.h);
+    if (halo) sh[(z + 1) % 3][hrow][lane] = op(Pn.h, 2, z1c);
     __syncthreads();
     float4 lap = make_float4(0.f, 0.f, 0.f, 0.f);
     f4lap(lap, cur, from_left(edge, cur));
@@ -417,14 +432,29 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
     prev = cur;
     cur = nxt;
     edge = nedge;
-    ex = A.ex;
-    A = B;
+    ex = Pn.ex;
+    n += R2;
+  };
+  if (DEPTH == 2) {
+    for (int z = t.z0; z < t.z1; z += 2) {
+      step(z, B, A);
+      if (z + 1 >= t.z1) break;
+      step(z + 1, A, B);
+    }
+  } else {
+    for (int z = t.z0; z < t.z1; z += 3) {
+      step(z, B, A);
+      if (z + 1 >= t.z1) break;
+      step(z + 1, C, B);
+      if (z + 2 >= t.z1) break;
+      step(z + 2, A, C);
+    }
   }
 }
 template <typename RAW, typename EX, typename LD, typename LDC, typename OP, typename BODY>
 __device__ __forceinline__ void zm_walk(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body) {
   zm_walk_post<RAW, EX>(
-      g, t, [&](int64_t m, int, int) { return ld(m); }, ldc, op,
+      g, t, [&](int64_t m, int, int) { return ld(m); }, ldc, [&](const RAW& v, int, int) { return op(v); },
       [&](int64_t n, const float4& lap, const float4& c, const EX& e, int) { body(n, lap, c, e); }, [](int) {});
 }
 
@@ -798,11 +828,18 @@ __device__ __forceinline__ int mg_block(int nblk) {
   const int L = (b % kXCD) * per + b / kXCD;
   return L < nblk ? L : -1;
 }
-// Logical block -> task (tasks sorted by blk0)
-__device__ __forceinline__ const MgTask* mg_task(const MgTask* T, int nt, int blk) {
+// The first block of each task of one launch (tasks sorted by blk0, at most
+// one per system; unused slots hold INT_MAX), passed by value so the lookup
+// of a block's task reads kernel arguments only, all at once.
+constexpr int kMgTaskMax = NPG_MAX_SYS;
+struct MgBlk0 {
+  int b[kMgTaskMax];
+};
+__device__ __forceinline__ int mg_task_of(const MgBlk0& B, int blk) {
   int t = 0;
-  while (t + 1 < nt && blk >= T[t + 1].blk0) ++t;
-  return T + t;
+#pragma unroll
+  for (int q = 1; q < kMgTaskMax; ++q) t += blk >= B.b[q] ? 1 : 0;
+  return t;
 }
 
 __device__ __forceinline__ void mg_coords(int64_t m, const MgLvl& L, int& i, int& j, int& k) {
@@ -922,12 +959,13 @@ __device__ __forceinline__ void mg_up_u4(const MgTask* tk, const float* __restri
 
 // Restriction of the smoothed residual: thread per coarse node J,
 // bh[J] = sum over the children j of (b - A x0)[j], x0 = w D^-1 b.
-__global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, int nt, int nblk,
+__global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, MgBlk0 B0, int nblk,
                                                   const int* __restrict__ active, int check_active,
                                                   const float* __restrict__ bl, float* __restrict__ bh) {
   const int blk = mg_block(nblk);
   if (blk < 0) return;
-  const MgTask* tk = mg_task(T, nt, blk);
+  const MgTask task = T[mg_task_of(B0, blk)];
+  const MgTask* tk = &task;
   if (tk->zm0 || (check_active && !active[tk->sys])) return;
   const int64_t m = (int64_t)(blk - tk->blk0) * kMgB + threadIdx.x;
   if (m >= tk->nodes) return;
@@ -1017,13 +1055,14 @@ __device__ __forceinline__ void mg_up_node(const MgTask* tk, const float* __rest
 }
 
 // Prolongation and post-smoothing from level l+1 to l >= 1 (l = 0: k_mg_up0).
-__global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, int nt, int nblk,
+__global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, MgBlk0 B0, int nblk,
                                                 const int* __restrict__ active, int check_active,
                                                 const float* __restrict__ bl, const float* __restrict__ eh,
                                                 float* __restrict__ out) {
   const int blk = mg_block(nblk);
   if (blk < 0) return;
-  const MgTask* tk = mg_task(T, nt, blk);
+  const MgTask task = T[mg_task_of(B0, blk)];
+  const MgTask* tk = &task;
   if (check_active && !active[tk->sys]) return;
   const int64_t m = (int64_t)(blk - tk->blk0) * kMgB + threadIdx.x;
   if (m >= tk->nodes) return;
@@ -1050,12 +1089,12 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
   const int x = t.x0 + lane, y = t.y0 + w;
   const ZmCols cols = zm_cols(t, R, lam, nh);
   float4 rs = make_float4(0.f, 0.f, 0.f, 0.f), zacc = rs;
-  zm_walk_post<Raw1, Raw1>(
+  zm_walk_post<Raw1, Raw1, 3>(
       g, t,
-      [&](int64_t m, int s, int zz) {
-        return Raw1{f4scale((zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s], B[m])};
+      [&](int64_t m, int, int) { return Raw1{B[m]}; }, [&](int64_t m) { return Raw1{B[m]}; },
+      [&](const Raw1& v, int s, int zz) {
+        return f4scale((zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s], v.a);
       },
-      [&](int64_t m) { return Raw1{B[m]}; }, [&](const Raw1& v) { return v.a; },
       [&](int64_t, const float4& lap, const float4& xc, const Raw1& e, int) {
         rs = f4sub(e.a, f4axpy(lam, lap, xc));
       },
@@ -1104,13 +1143,14 @@ __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, con
   float4* Z = reinterpret_cast<float4*>(z + g.poff);
   const ZmCols cols = zm_cols(t, R, lam, nh);
   const int nh2 = nh * nh;
-  zm_walk_post<Raw1, Raw1>(
+  zm_walk_post<Raw2, Raw1>(
       g, t,
-      [&](int64_t m, int s, int zz) {
+      [&](int64_t m, int s, int zz) { return Raw2{B[m], E[(zz >> 1) * nh2 + cols.pxy[s]]}; },
+      [&](int64_t m) { return Raw1{B[m]}; },
+      [&](const Raw2& v, int s, int zz) {
         const float f = (zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s];
-        return Raw1{f4add(f4scale(f, B[m]), E[(zz >> 1) * nh2 + cols.pxy[s]])};
+        return f4add(f4scale(f, v.a), v.b);
       },
-      [&](int64_t m) { return Raw1{B[m]}; }, [&](const Raw1& v) { return v.a; },
       [&](int64_t n, const float4& lap, const float4& xc, const Raw1& e, int zz) {
         const float4 bc = e.a;
         const float4 ax = f4axpy(lam, lap, xc);
@@ -1156,9 +1196,9 @@ constexpr int kMgCN = 512 * 4;
 __global__ __launch_bounds__(512) void k_mg_coarse(const MgTask* __restrict__ T, const int* __restrict__ active,
                                                    int check_active, const float* __restrict__ b,
                                                    float* __restrict__ x) {
-  const MgTask* tk = T + blockIdx.x;
-  if (check_active && !active[tk->sys]) return;
-  const MgLvl& L = tk->lo;
+  const MgTask task = T[blockIdx.x];
+  if (check_active && !active[task.sys]) return;
+  const MgLvl& L = task.lo;
   __shared__ float sb[kMgCN], sx[2][kMgCN];
   const int nodes = L.n * L.n * L.n;
   const int m = threadIdx.x;
@@ -1271,7 +1311,9 @@ static npg_status mg_setup(npg_plan* P) {
         t.fx2 = make_fastdiv((uint32_t)nx * (uint32_t)t.lo.n);
         if (up) t.nodes = (int64_t)nx * t.lo.n * t.lo.n;  // one thread per x-adjacent pair
       }
-      blk += (int)((t.nodes + kMgB - 1) / kMgB);
+      // a task restricted by k_mg_down0 gets no blocks here (it keeps its
+      // slot: k_mg_down0 and k_mg_up0 look tasks up by system)
+      if (!t.zm0) blk += (int)((t.nodes + kMgB - 1) / kMgB);
       tasks.push_back(t);
     }
     C.mg_l_ntask[li] = (int)tasks.size() - C.mg_l_task0[li];
@@ -1303,6 +1345,11 @@ static npg_status mg_setup(npg_plan* P) {
   NPG_HIP(hipMalloc(&C.mgB, std::max<int64_t>(coarse, 1) * 4));
   NPG_HIP(hipMalloc(&C.mgX, std::max<int64_t>(coarse, 1) * 4));
   NPG_HIP(hipMalloc(&C.part2, (int64_t)C.n_blocks * 4 * 8));
+  C.mg_l_blk0.assign(2 * nlev - 1, std::vector<int>(kMgTaskMax, INT_MAX));
+  for (int li = 0; li < 2 * nlev - 1; ++li) {
+    if (C.mg_l_ntask[li] > kMgTaskMax) return npg_fail(NPG_EINVAL, "multigrid: too many tasks in one launch");
+    for (int q = 0; q < C.mg_l_ntask[li]; ++q) C.mg_l_blk0[li][q] = tasks[C.mg_l_task0[li] + q].blk0;
+  }
   NPG_HIP(hipMalloc(&C.mg_tasks, tasks.size() * sizeof(MgTask)));
   NPG_HIP(hipMemcpy(C.mg_tasks, tasks.data(), tasks.size() * sizeof(MgTask), hipMemcpyHostToDevice));
   return NPG_OK;
@@ -1317,18 +1364,23 @@ static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_acti
   const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
   hipLaunchKernelGGL(k_mg_down0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
                      C.blk_start, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB);
+  auto blk0 = [&](int li) {
+    MgBlk0 b;
+    for (int q = 0; q < kMgTaskMax; ++q) b.b[q] = C.mg_l_blk0[li][q];
+    return b;
+  };
   for (int l = 0; l + 1 < nl; ++l)
-    if (C.mg_l_ntask[l] > 0)
-      hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(C.mg_l_nblk[l])), dim3(kMgB), 0, s, T + C.mg_l_task0[l],
-                         C.mg_l_ntask[l], C.mg_l_nblk[l], C.active, check_active, l == 0 ? r : C.mgB, C.mgB);
+    if (C.mg_l_nblk[l] > 0)
+      hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(C.mg_l_nblk[l])), dim3(kMgB), 0, s, T + C.mg_l_task0[l], blk0(l),
+                         C.mg_l_nblk[l], C.active, check_active, l == 0 ? r : C.mgB, C.mgB);
   const int lc = 2 * (nl - 1);
   hipLaunchKernelGGL(k_mg_coarse, dim3(C.mg_l_nblk[lc]), dim3(512), 0, s, T + C.mg_l_task0[lc], C.active,
                      check_active, C.mgB, C.mgX);
   for (int l = nl - 2; l >= 1; --l) {
     const int li = nl - 1 + l;
-    if (C.mg_l_ntask[li] > 0)
+    if (C.mg_l_nblk[li] > 0)
       hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[li])), dim3(kMgB), 0, s, T + C.mg_l_task0[li],
-                         C.mg_l_ntask[li], C.mg_l_nblk[li], C.active, check_active, C.mgB, C.mgX, C.mgX);
+                         blk0(li), C.mg_l_nblk[li], C.active, check_active, C.mgB, C.mgX, C.mgX);
   }
   hipLaunchKernelGGL(k_mg_up0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
                      C.blk_start, C.active, check_active, T + C.mg_l_task0[nl - 1], r, C.mgX, z, C.part2);
