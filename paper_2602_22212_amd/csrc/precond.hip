@@ -878,7 +878,21 @@ __device__ __forceinline__ void mg_down_u4(const MgTask* tk, const float* __rest
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
   float4 acc = zero;
   // all 8 children and their 24 outer neighbours, branch-free: indices
-  // clamped into the grid, absent nodes masked to 0 (loads in flight together)
+  // clamped into the grid, absent nodes masked to 0; every load is issued
+  // before the first is used
+  float4 ld[8][4];
+#pragma unroll
+  for (int c3 = 0; c3 < 8; ++c3) {
+    const int cx = c3 & 1, cy = (c3 >> 1) & 1, cz = c3 >> 2;
+    const int ic = min(2 * I + cx, R - 1), jc = min(2 * J + cy, R - 1), kc = min(2 * K + cz, R - 1);
+    const int n = (kc * R + jc) * R + ic;
+    const int ox = cx ? ic + 1 : ic - 1, oy = cy ? jc + 1 : jc - 1, oz = cz ? kc + 1 : kc - 1;
+    const int oxc = ox >= 0 && ox < R ? ox : ic, oyc = oy >= 0 && oy < R ? oy : jc, ozc = oz >= 0 && oz < R ? oz : kc;
+    ld[c3][0] = B[n];
+    ld[c3][1] = B[n + (oxc - ic)];
+    ld[c3][2] = B[n + (oyc - jc) * R];
+    ld[c3][3] = B[n + (ozc - kc) * R * R];
+  }
 #pragma unroll
   for (int c3 = 0; c3 < 8; ++c3) {
     const int cx = c3 & 1, cy = (c3 >> 1) & 1, cz = c3 >> 2;
@@ -886,14 +900,10 @@ __device__ __forceinline__ void mg_down_u4(const MgTask* tk, const float* __rest
     const bool valid = i < R && j < R && k < R;
     const int ic = min(i, R - 1), jc = min(j, R - 1), kc = min(k, R - 1);
     const int di = mg_deg1(ic, R), dj = mg_deg1(jc, R), dk = mg_deg1(kc, R);
-    const int n = (kc * R + jc) * R + ic;
     const int ox = cx ? ic + 1 : ic - 1, oy = cy ? jc + 1 : jc - 1, oz = cz ? kc + 1 : kc - 1;
     const bool vx = valid && ox >= 0 && ox < R, vy = valid && oy >= 0 && oy < R, vz = valid && oz >= 0 && oz < R;
     const int oxc = vx ? ox : ic, oyc = vy ? oy : jc, ozc = vz ? oz : kc;
-    const float4 bc = B[n];
-    const float4 bx = B[n + (oxc - ic)];
-    const float4 by = B[n + (oyc - jc) * R];
-    const float4 bz = B[n + (ozc - kc) * R * R];
+    const float4 bc = ld[c3][0], bx = ld[c3][1], by = ld[c3][2], bz = ld[c3][3];
     const float4 xc = f4scale(mg_f(tk, di + dj + dk), bc);
     float4 t = f4axpy(-mass, xc, bc);
     t = f4axpy(vx ? nlw : 0.f, f4sub(xc, f4scale(mg_f(tk, mg_deg1(oxc, R) + dj + dk), bx)), t);
@@ -925,24 +935,36 @@ __device__ __forceinline__ void mg_up_u4(const MgTask* tk, const float* __restri
   // x = w D^-1 b + P e at node (a, b2, c2). A neighbour index clamped into the
   // grid lands on the node itself, whose x is bitwise the same, so an absent
   // neighbour adds exactly 0 and every load can be issued unconditionally.
-  auto xat = [&](int a, int b2, int c2) {
-    const int d = mg_deg1(a, R) + mg_deg1(b2, R) + mg_deg1(c2, R);
-    return f4add(f4scale(mg_f(tk, d), B[(c2 * R + b2) * R + a]), E[((c2 >> 1) * nh + (b2 >> 1)) * nh + (a >> 1)]);
-  };
+  // The 12 nodes (the pair, its two x neighbours and the y and z neighbours of
+  // each of the pair) are loaded before any is used.
   const int i0 = 2 * I, i1 = min(2 * I + 1, R - 1);  // i1 = i0 when the pair has one node
   const int jm = max(j - 1, 0), jp = min(j + 1, R - 1), km = max(k - 1, 0), kp = min(k + 1, R - 1);
-  const float4 x0 = xat(i0, j, k), x1 = xat(i1, j, k);
-  const float4 xl = xat(max(i0 - 1, 0), j, k), xr = xat(min(i1 + 1, R - 1), j, k);
+  const int na[12] = {i0, i1, max(i0 - 1, 0), min(i1 + 1, R - 1), i0, i0, i0, i0, i1, i1, i1, i1};
+  const int nb2[12] = {j, j, j, j, jm, jp, j, j, jm, jp, j, j};
+  const int nc2[12] = {k, k, k, k, k, k, km, kp, k, k, km, kp};
+  float4 vb[12], ve[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    vb[q] = B[(nc2[q] * R + nb2[q]) * R + na[q]];
+    ve[q] = E[((nc2[q] >> 1) * nh + (nb2[q] >> 1)) * nh + (na[q] >> 1)];
+  }
+  float4 xv[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    const int d = mg_deg1(na[q], R) + mg_deg1(nb2[q], R) + mg_deg1(nc2[q], R);
+    xv[q] = f4add(f4scale(mg_f(tk, d), vb[q]), ve[q]);
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (h == 1 && 2 * I + 1 >= R) break;
     const int i = h ? i1 : i0;
-    const float4 xc = h ? x1 : x0;
-    float4 nb = f4add(f4sub(xc, h ? x0 : xl), f4sub(xc, h ? xr : x1));  // sum over neighbours of (x_c - x_nb)
-    nb = f4add(nb, f4add(f4sub(xc, xat(i, jm, k)), f4sub(xc, xat(i, jp, k))));
-    nb = f4add(nb, f4add(f4sub(xc, xat(i, j, km)), f4sub(xc, xat(i, j, kp))));
+    const float4 xc = xv[h];
+    // sum over the neighbours of (x_c - x_nb)
+    float4 nb = f4add(f4sub(xc, h ? xv[0] : xv[2]), f4sub(xc, h ? xv[3] : xv[1]));
+    nb = f4add(nb, f4add(f4sub(xc, xv[4 + 4 * h]), f4sub(xc, xv[5 + 4 * h])));
+    nb = f4add(nb, f4add(f4sub(xc, xv[6 + 4 * h]), f4sub(xc, xv[7 + 4 * h])));
     const int n = (k * R + j) * R + i;
-    const float4 bc = B[n];
+    const float4 bc = vb[h];
     const float4 ax = f4axpy(lw, nb, f4scale(mass, xc));
     // lam = 0 (A = I): the identity preconditioner
     const int dc = mg_deg1(i, R) + mg_deg1(j, R) + mg_deg1(k, R);
@@ -955,6 +977,61 @@ __device__ __forceinline__ void mg_up_u4(const MgTask* tk, const float* __restri
       acc[3] += (double)bc.w * (double)z.w;
     }
   }
+}
+
+// Restriction for any level (aggregate extents that differ at the upper
+// faces, F < 4, unaligned arrays), in the same form as mg_down_u4: each child
+// takes the mass term and the faces to its three outer neighbours (the faces
+// between two children cancel in the sum), every load issued first with
+// indices clamped into the grid, absent nodes masked to 0.
+__device__ __forceinline__ void mg_down_gen(const MgTask* tk, const float* __restrict__ bl, float* __restrict__ bh,
+                                            int64_t m) {
+  const MgLvl& lo = tk->lo;
+  const MgLvl& hi = tk->hi;
+  const int R = lo.n;
+  int I, J, K;
+  mg_coords(m, hi, I, J, K);
+  const float* Bb = bl + lo.off;
+  float ld[8][4][4];
+#pragma unroll
+  for (int c3 = 0; c3 < 8; ++c3) {
+    const int cx = c3 & 1, cy = (c3 >> 1) & 1, cz = c3 >> 2;
+    const int ic = min(2 * I + cx, R - 1), jc = min(2 * J + cy, R - 1), kc = min(2 * K + cz, R - 1);
+    const int ox = cx ? ic + 1 : ic - 1, oy = cy ? jc + 1 : jc - 1, oz = cz ? kc + 1 : kc - 1;
+    const int oxc = ox >= 0 && ox < R ? ox : ic, oyc = oy >= 0 && oy < R ? oy : jc, ozc = oz >= 0 && oz < R ? oz : kc;
+    mg_load(Bb + mg_idx(ic, jc, kc, R) * lo.F, lo.F, ld[c3][0]);
+    mg_load(Bb + mg_idx(oxc, jc, kc, R) * lo.F, lo.F, ld[c3][1]);
+    mg_load(Bb + mg_idx(ic, oyc, kc, R) * lo.F, lo.F, ld[c3][2]);
+    mg_load(Bb + mg_idx(ic, jc, ozc, R) * lo.F, lo.F, ld[c3][3]);
+  }
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c3 = 0; c3 < 8; ++c3) {
+    const int cx = c3 & 1, cy = (c3 >> 1) & 1, cz = c3 >> 2;
+    const int i = 2 * I + cx, j = 2 * J + cy, k = 2 * K + cz;
+    const bool valid = i < R && j < R && k < R;
+    const int ic = min(i, R - 1), jc = min(j, R - 1), kc = min(k, R - 1);
+    const int ox = cx ? ic + 1 : ic - 1, oy = cy ? jc + 1 : jc - 1, oz = cz ? kc + 1 : kc - 1;
+    const bool vx = valid && ox >= 0 && ox < R, vy = valid && oy >= 0 && oy < R, vz = valid && oz >= 0 && oz < R;
+    const int oxc = vx ? ox : ic, oyc = vy ? oy : jc, ozc = vz ? oz : kc;
+    const MgNode nd = mg_node(ic, jc, kc, lo);
+    const float f = kMgOmega * __builtin_amdgcn_rcpf(nd.diag);
+    const float fx = kMgOmega * __builtin_amdgcn_rcpf(mg_node(oxc, jc, kc, lo).diag);
+    const float fy = kMgOmega * __builtin_amdgcn_rcpf(mg_node(ic, oyc, kc, lo).diag);
+    const float fz = kMgOmega * __builtin_amdgcn_rcpf(mg_node(ic, jc, ozc, lo).diag);
+    const float lx = vx ? lo.lam * nd.wx : 0.f, ly = vy ? lo.lam * nd.wy : 0.f, lz = vz ? lo.lam * nd.wz : 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float bc = ld[c3][0][c], xc = f * bc;
+      float t = bc - nd.mass * xc;
+      t -= lx * (xc - fx * ld[c3][1][c]);
+      t -= ly * (xc - fy * ld[c3][2][c]);
+      t -= lz * (xc - fz * ld[c3][3][c]);
+      acc[c] += valid ? t : 0.f;
+    }
+  }
+  float* o = bh + hi.off + m * hi.F;
+  for (int c = 0; c < hi.F; ++c) o[c] = acc[c];
 }
 
 // Restriction of the smoothed residual: thread per coarse node J,
@@ -973,39 +1050,7 @@ __global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, 
     mg_down_u4(tk, bl, bh, (int)m);
     return;
   }
-  const MgLvl& lo = tk->lo;
-  const MgLvl& hi = tk->hi;
-  int I, J, K;
-  mg_coords(m, hi, I, J, K);
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int c3 = 0; c3 < 8; ++c3) {
-    const int i = 2 * I + (c3 & 1), j = 2 * J + ((c3 >> 1) & 1), k = 2 * K + (c3 >> 2);
-    if (i >= lo.n || j >= lo.n || k >= lo.n) continue;
-    const MgNode nd = mg_node(i, j, k, lo);
-    float bc[4], xc[4];
-    mg_load(bl + lo.off + mg_idx(i, j, k, lo.n) * lo.F, lo.F, bc);
-    const float f = kMgOmega * __builtin_amdgcn_rcpf(nd.diag);
-    float ax[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      xc[c] = bc[c] * f;
-      ax[c] = nd.mass * xc[c];
-    }
-    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-    const float w[6] = {nd.wx, nd.wx, nd.wy, nd.wy, nd.wz, nd.wz};
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      if (!(nd.mask & (1 << d))) continue;
-      float xn[4];
-      mg_x0(bl, lo, i + di[d], j + dj[d], k + dk[d], xn);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) ax[c] += lo.lam * w[d] * (xc[c] - xn[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] += bc[c] - ax[c];
-  }
-  float* o = bh + hi.off + m * hi.F;
-  for (int c = 0; c < hi.F; ++c) o[c] = acc[c];
+  mg_down_gen(tk, bl, bh, m);
 }
 
 // Prolongation and post-smoothing: thread per node j of the finer level,
