@@ -52,9 +52,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,cg_plain,dct,quat,iso,metrics,bf16,batch,animal",
+    ap.add_argument("--forms", default="cg,cg_plain,dct,graph,quat,iso,metrics,bf16,batch,animal",
                     help="forms to time: cg (headline: CG preconditioned by a multigrid V-cycle), "
                          "cg_plain (the same solves by plain CG), dct (exact DCT preconditioner), "
+                         "graph (the DCT-form step replayed as one captured HIP graph, on the human "
+                         "workload and on the small icosphere one, against the eager step), "
                          "quat (quaternion rotation head, DCT preconditioner), "
                          "iso (isometry loss w_iso = 100 on a 6-NN edge graph, DCT preconditioner), "
                          "metrics (inference export + evaluation metrics on ground truth), "
@@ -181,8 +183,9 @@ def stage_roofline(cfg, data, stage_ms, precision, prof=None):
     return out
 
 
-def run_form(cfg, data, P0, steps, warmup, profile):
-    """Time `steps` full optimization steps of one preconditioner form."""
+def run_form(cfg, data, P0, steps, warmup, profile, graph=False):
+    """Time `steps` full optimization steps of one preconditioner form (graph:
+    each step replayed as the captured HIP graph, npg_step_graph)."""
     import torch
 
     import paper_2602_22212_amd as npg
@@ -191,8 +194,9 @@ def run_form(cfg, data, P0, steps, warmup, profile):
     nn_threads, nn_ms = plan.tune_nn(0)  # autotuned nearest-neighbour work-group size
     E = cfg["n_steps"]
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    step = plan.step_graph if graph else plan.step
     for e in range(warmup):
-        plan.step(e, E, loss)
+        step(e, E, loss)
     torch.cuda.synchronize()
     if profile:
         plan.profile(True)
@@ -202,18 +206,19 @@ def run_form(cfg, data, P0, steps, warmup, profile):
     for k in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        statuses.append(plan.step(warmup + k, E, loss))
+        statuses.append(step(warmup + k, E, loss))
         torch.cuda.synchronize()
         t_total += time.perf_counter() - t0
-        for name, ms in plan.stage_times().items():
-            stage_sum[name] += ms
+        if not graph:  # the graph records no per-stage events
+            for name, ms in plan.stage_times().items():
+                stage_sum[name] += ms
     prof = plan.profile_read() if profile else None
     if prof is not None:
         prof["steps"] = steps
     relres = plan.precond_residuals() if cfg.get("precond", "cg") == "cg" else None
     plan.close()
     return dict(value=steps / t_total, ms_per_step=1e3 * t_total / steps,
-                stage_ms={k: round(v / steps, 3) for k, v in stage_sum.items()},
+                stage_ms=None if graph else {k: round(v / steps, 3) for k, v in stage_sum.items()},
                 status=sorted(set(int(s) for s in statuses)), prof=prof, loss=loss.item(),
                 nn_tune={"threads": nn_threads, "ms_64_128_256": [round(m, 3) for m in nn_ms]},
                 cg_relres_max=None if relres is None else max(relres))
@@ -421,6 +426,25 @@ def main():
     plain = (run_form(dict(cfg, precond="cg", cg_mg=0), data, P0, args.steps, args.warmup, profile=True)
              if "cg_plain" in forms else None)
     dct = run_form(dict(cfg, precond="dct"), data, P0, args.steps, args.warmup, profile=False) if "dct" in forms else None
+    graph = None
+    if "graph" in forms:
+        gh = run_form(dict(cfg, precond="dct"), data, P0, args.steps, args.warmup, profile=False, graph=True)
+        cs = dict(synth.config_c1(), precond="dct", n_steps=100)
+        ds = synth.make_workload(cs)
+        Ps = synth.random_state(cs, 5, grid_std=0.05)
+        small = {m: run_form(cs, ds, Ps, 50, 5, profile=False, graph=(m == "graph")) for m in ("eager", "graph")}
+        graph = {"value": round(gh["value"], 4), "unit": "steps/s", "ms_per_step": round(gh["ms_per_step"], 3),
+                 "status": gh["status"],
+                 "eager_value": None if dct is None else round(dct["value"], 4),
+                 "small": {"workload": f"icosphere_v{len(ds['xyz'])}_t{ds['T']}_n{int(ds['frame_off'][-1])}",
+                           "steps": 50,
+                           "eager": {"value": round(small["eager"]["value"], 2),
+                                     "ms_per_step": round(small["eager"]["ms_per_step"], 4)},
+                           "graph": {"value": round(small["graph"]["value"], 2),
+                                     "ms_per_step": round(small["graph"]["ms_per_step"], 4)}},
+                 "note": "npg_step_graph: the DCT-form step recorded once as a HIP graph and replayed (results "
+                         "bitwise those of npg_step); value on the human workload, eager_value = precond_dct; "
+                         "small = the 2562-vertex, 10-frame icosphere workload, where launches dominate"}
     quat = None
     if "quat" in forms:
         cq = dict(cfg, precond="dct", rot_head="quat")
@@ -480,6 +504,7 @@ def main():
         "precond_dct": None if dct is None else {
             "value": round(dct["value"], 4), "unit": "steps/s", "ms_per_step": round(dct["ms_per_step"], 3),
             "stage_ms": dct["stage_ms"], "note": "same step with the exact DCT form of (I + lambda L)^-2"},
+        "step_graph": graph,
         "rot_quat": None if quat is None else {
             "value": round(quat["value"], 4), "unit": "steps/s", "ms_per_step": round(quat["ms_per_step"], 3),
             "stage_ms": quat["stage_ms"],

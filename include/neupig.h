@@ -197,6 +197,21 @@ npg_status npg_step(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* los
                     double* cd_dev);
 
 /*
+ * The same step as npg_step, replayed as one HIP graph: the first call
+ * records every stage's launches into a graph (on a stream of the plan's
+ * own; nothing runs while recording) and each call replays it on the plan's
+ * stream after a one-thread kernel has written the step's scalars (the
+ * confidence exponent of `epoch`, the Adam bias corrections) to device
+ * memory. Results are bitwise those of npg_step. Only for the DCT
+ * preconditioner (precond = 1): NPG_EINVAL for the CG form, whose solves test
+ * convergence on the host. npg_tune_nn and npg_plan_set_edges drop the
+ * recorded graph (the next call records it again). Synchronizes at the end,
+ * like npg_step; per-stage times (npg_stage_times) are not recorded.
+ */
+npg_status npg_step_graph(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* loss_dev,
+                          double* cd_dev);
+
+/*
  * Mesh edges of the reference surface for the isometry loss (Sec. 3.5):
  * edges_host [n_edges][2] int32 vertex pairs (host memory, read during the
  * call; 1 <= n_edges < 2^30, endpoints in [0, V), i != j; a repeated edge

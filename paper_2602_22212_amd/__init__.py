@@ -57,6 +57,7 @@ _SIGS = {
     "npg_set_state": ([_P, _P, _P, _P, _I64], ctypes.c_int),
     "npg_get_state": ([_P, _P, _P, _P, ctypes.POINTER(_I64)], ctypes.c_int),
     "npg_step": ([_P, _I32, _I32, _P, _P], ctypes.c_int),
+    "npg_step_graph": ([_P, _I32, _I32, _P, _P], ctypes.c_int),
     "npg_deform": ([_P, _P], ctypes.c_int),
     "npg_encode_fwd": ([_P, _P, _P], ctypes.c_int),
     "npg_decode_fwd": ([_P, _P, _P, _P], ctypes.c_int),
@@ -267,6 +268,12 @@ class Plan:
         if st == NPG_ENOTCONV:
             return st
         return _check(st)
+
+    def step_graph(self, epoch, n_epochs, loss=None, cd=None):
+        """npg_step replayed as one captured HIP graph (DCT preconditioner only)."""
+        import torch
+        return _check(lib().npg_step_graph(self._h, int(epoch), int(n_epochs), _ptr(loss, torch.float64, 1, "loss"),
+                                           _ptr(cd, torch.float64, self.T, "cd")))
 
     def set_edges(self, edges):
         """Mesh edges [E, 2] (host array) for the isometry loss."""

@@ -13,9 +13,13 @@ struct Segs {
 
 __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, int64_t n, Segs sg, float b1, float b2, float eps, float inv_bc1,
-                       float inv_sqrt_bc2, int* __restrict__ flag) {
+                       float inv_sqrt_bc2, const NpgStepScal* __restrict__ sc, int* __restrict__ flag) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (sc) {
+    inv_bc1 = sc->inv_bc1;
+    inv_sqrt_bc2 = sc->inv_sqrt_bc2;
+  }
   int s = 0;
   while (s + 1 < sg.n && i >= sg.start[s + 1]) ++s;
   const float gi = g[i];
@@ -31,8 +35,15 @@ __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, floa
 
 }  // namespace
 
+void npg_adam_scalars(const npg_plan* P, int64_t k, float* inv_bc1, float* inv_sqrt_bc2) {
+  const double bc1 = 1.0 - pow((double)P->cfg.beta1, (double)k);
+  const double bc2 = 1.0 - pow((double)P->cfg.beta2, (double)k);
+  *inv_bc1 = (float)(1.0 / bc1);
+  *inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+}
+
 hipError_t npg_launch_adam(const npg_plan* P, float* params, const float* grad, float* m, float* v, int64_t k,
-                           int* flag) {
+                           int* flag, const NpgStepScal* sc) {
   Segs sg;
   sg.n = P->n_sys + 1;
   for (int s = 0; s < P->n_sys; ++s) {
@@ -42,10 +53,10 @@ hipError_t npg_launch_adam(const npg_plan* P, float* params, const float* grad, 
   sg.start[P->n_sys] = P->mlp_off;
   sg.lr[P->n_sys] = P->cfg.lr_mlp;
   sg.start[P->n_sys + 1] = P->n_params;
-  const double bc1 = 1.0 - pow((double)P->cfg.beta1, (double)k);
-  const double bc2 = 1.0 - pow((double)P->cfg.beta2, (double)k);
+  float ib1 = 1.f, ib2 = 1.f;
+  if (!sc) npg_adam_scalars(P, k, &ib1, &ib2);
   const int64_t n = P->n_params;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P->stream, params, grad, m, v, n, sg,
-                     P->cfg.beta1, P->cfg.beta2, P->cfg.eps, (float)(1.0 / bc1), (float)(1.0 / sqrt(bc2)), flag);
+                     P->cfg.beta1, P->cfg.beta2, P->cfg.eps, ib1, ib2, sc, flag);
   return hipGetLastError();
 }

@@ -215,8 +215,9 @@ __global__ void k_frame_sums(const float* __restrict__ da, const float* __restri
 // omega^delta over the frames between t_key and t (inclusive), delta =
 // 1 - sqrt(e/e_max); L_def = (1/T) sum_t w_t cd_t.
 __global__ void k_loss(const double* __restrict__ cd, int T, int t_key, int conf, double delta,
-                       double* __restrict__ w, double* __restrict__ loss) {
+                       const NpgStepScal* __restrict__ sc, double* __restrict__ w, double* __restrict__ loss) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (sc) delta = sc->delta;
   const double ck = cd[t_key];
   if (!conf) {
     for (int t = 0; t < T; ++t) w[t] = 1.0;
@@ -327,11 +328,13 @@ hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t
   return hipGetLastError();
 }
 
+double npg_loss_delta(int epoch, int n_epochs) { return 1.0 - sqrt((double)epoch / (double)n_epochs); }
+
 hipError_t npg_launch_loss(const npg_plan* P, const double* cd, int epoch, int n_epochs, double* w,
-                           double* loss) {
-  double delta = 1.0 - sqrt((double)epoch / (double)n_epochs);
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, P->stream, cd, P->T, P->t_key, P->cfg.conf_weight, delta, w,
-                     loss);
+                           double* loss, const NpgStepScal* sc) {
+  const double delta = npg_loss_delta(epoch, n_epochs);
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, P->stream, cd, P->T, P->t_key, P->cfg.conf_weight, delta, sc,
+                     w, loss);
   return hipGetLastError();
 }
 

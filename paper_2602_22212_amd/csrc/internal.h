@@ -45,6 +45,13 @@ struct NpgCG {  // conjugate-gradient workspace
 
 struct NpgDct;
 
+// Per-step scalars the loss and Adam kernels of a graph-captured step read
+// from device memory (the eager step passes them as kernel arguments).
+struct NpgStepScal {
+  double delta;                // confidence catch-up exponent 1 - sqrt(e / e_max)
+  float inv_bc1, inv_sqrt_bc2;  // Adam bias corrections 1 / (1 - b1^k), 1 / sqrt(1 - b2^k)
+};
+
 struct npg_plan {
   npg_config cfg;
   hipStream_t stream;
@@ -125,7 +132,12 @@ struct npg_plan {
   float stage_ms[8];
   // optional per-launch timing of the CG iteration kernels (profiling only)
   int prof_cg;
-  std::vector<hipEvent_t> prof_ev;  // 4 per CG iteration
+  std::vector<hipEvent_t> prof_ev;
+  // graph-captured step (npg_step_graph): its scalars, graph and capture stream
+  NpgStepScal* d_scal = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;  // 4 per CG iteration
   int prof_n;                       // events recorded in the current step
   double prof_cg_ms;                // accumulated kernel time of resolved steps
   int64_t prof_cg_launches;         // accumulated CG iterations (kernel pairs)
@@ -160,8 +172,10 @@ hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const f
 // chamfer.hip
 hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t* a, float* da,
                                   int32_t* b, float* db, double* cd);
+// sc: NULL, or the step scalars in device memory (then delta is read there)
+double npg_loss_delta(int epoch, int n_epochs);
 hipError_t npg_launch_loss(const npg_plan* P, const double* cd, int epoch, int n_epochs, double* w,
-                           double* loss);
+                           double* loss, const NpgStepScal* sc = nullptr);
 hipError_t npg_launch_chamfer_bwd(const npg_plan* P, const float4* xhat, const int32_t* a,
                                   const int32_t* b, const double* w, float4* gxhat);
 // precond.hip
@@ -179,9 +193,14 @@ hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pt
 hipError_t npg_launch_iso(const npg_plan* P, const float4* xhat, float4* gxhat, double* iso, int8_t* sign,
                           double* loss);
 npg_status npg_run_precond_dct(npg_plan* P, float* grad);
+// plan.hip: drop the captured step (after a change that alters its launches)
+void npg_graph_reset(npg_plan* P);
 // adam.hip
+// sc: NULL, or the step scalars in device memory (then the bias corrections
+// are read there and k is not used)
+void npg_adam_scalars(const npg_plan* P, int64_t k, float* inv_bc1, float* inv_sqrt_bc2);
 hipError_t npg_launch_adam(const npg_plan* P, float* params, const float* grad, float* m, float* v,
-                           int64_t k, int* flag);
+                           int64_t k, int* flag, const NpgStepScal* sc = nullptr);
 
 // ---- device helpers shared by the kernels ----------------------------------
 // Cell of a coordinate in a grid of R nodes per axis spanning [-1,1] (corner

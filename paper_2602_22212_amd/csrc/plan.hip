@@ -112,6 +112,60 @@ npg_status npg_fail(npg_status s, const std::string& msg) {
   return s;
 }
 
+void npg_graph_reset(npg_plan* P) {
+  if (P->graph_exec) hipGraphExecDestroy(P->graph_exec);
+  if (P->graph) hipGraphDestroy(P->graph);
+  P->graph_exec = nullptr;
+  P->graph = nullptr;
+}
+
+namespace {
+__global__ void k_set_step_scal(NpgStepScal* __restrict__ sc, double delta, float inv_bc1, float inv_sqrt_bc2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->delta = delta;
+    sc->inv_bc1 = inv_bc1;
+    sc->inv_sqrt_bc2 = inv_sqrt_bc2;
+  }
+}
+
+// Records the stages of npg_step (DCT preconditioner) into P->graph on a
+// stream of its own; the loss and Adam kernels take their per-step scalars
+// from P->d_scal. Nothing is executed.
+npg_status capture_step(npg_plan* P) {
+  if (!P->d_scal) NPG_HIP(hipMalloc(&P->d_scal, sizeof(NpgStepScal)));
+  if (!P->cap_stream) NPG_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  hipStream_t keep = P->stream;
+  P->stream = P->cap_stream;
+  NPG_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
+  auto enqueue = [&]() -> npg_status {
+    NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
+    NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+    NPG_HIP(npg_launch_chamfer_fwd(P, P->xhat, P->a, P->da, P->b, P->db, P->cd));
+    NPG_HIP(npg_launch_loss(P, P->cd, 0, 1, P->w, P->loss, P->d_scal));
+    NPG_HIP(npg_launch_chamfer_bwd(P, P->xhat, P->a, P->b, P->w, P->gxhat));
+    if (P->cfg.w_iso > 0.f) NPG_HIP(npg_launch_iso(P, P->xhat, P->gxhat, P->iso_val, nullptr, P->loss));
+    NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz));
+    NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
+    npg_status st = npg_run_precond_dct(P, P->grad);
+    if (st != NPG_OK) return st;
+    NPG_HIP(npg_launch_adam(P, P->params, P->grad, P->m, P->v, 1, P->d_flag, P->d_scal));
+    return NPG_OK;
+  };
+  const npg_status st = enqueue();
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);  // always ends the capture
+  P->stream = keep;
+  if (st != NPG_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  NPG_HIP(e);
+  P->graph = g;
+  NPG_HIP(hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0));
+  return NPG_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* npg_last_error(void) { return g_err.c_str(); }
@@ -139,6 +193,9 @@ npg_status npg_plan_destroy(npg_plan* P) {
                   P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->fl_part, P->gam, P->d_flag};
   for (void* b : bufs)
     if (b) hipFree(b);
+  npg_graph_reset(P);
+  if (P->cap_stream) hipStreamDestroy(P->cap_stream);
+  if (P->d_scal) hipFree(P->d_scal);
   npg_cg_free(P);
   npg_dct_free(P);
   npg_iso_free(P);
@@ -455,6 +512,39 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
   return NPG_OK;
 }
 
+npg_status npg_step_graph(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_out, double* cd_out) {
+  CHECK_ARG(P, "plan is NULL");
+  CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
+  CHECK_ARG(P->cfg.w_iso == 0.f || P->n_edges > 0, "w_iso > 0 needs the mesh edges (npg_plan_set_edges)");
+  CHECK_ARG(P->cfg.precond == NPG_PRECOND_DCT,
+            "npg_step_graph needs the DCT preconditioner (the CG solves test convergence on the host)");
+  if (!P->graph_exec) {
+    const npg_status st = capture_step(P);
+    if (st != NPG_OK) {
+      npg_graph_reset(P);
+      return st;
+    }
+  }
+  hipStream_t s = P->stream;
+  P->adam_k += 1;
+  float ib1 = 1.f, ib2 = 1.f;
+  npg_adam_scalars(P, P->adam_k, &ib1, &ib2);
+  hipLaunchKernelGGL(k_set_step_scal, dim3(1), dim3(64), 0, s, P->d_scal, npg_loss_delta(epoch, n_epochs), ib1,
+                     ib2);
+  NPG_HIP(hipGetLastError());
+  NPG_HIP(hipGraphLaunch(P->graph_exec, s));
+  if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
+  if (cd_out) NPG_HIP(hipMemcpyAsync(cd_out, P->cd, 8 * (size_t)P->T, hipMemcpyDeviceToDevice, s));
+  int flag = 0;
+  NPG_HIP(hipMemcpyAsync(&flag, P->d_flag, 4, hipMemcpyDeviceToHost, s));
+  NPG_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    NPG_HIP(hipMemsetAsync(P->d_flag, 0, 4, s));
+    return npg_fail(NPG_ENONFINITE, "a non-finite value was produced during the step");
+  }
+  return NPG_OK;
+}
+
 npg_status npg_profile(npg_plan* P, int32_t enable) {
   CHECK_ARG(P, "plan is NULL");
   if (enable && P->prof_ev.empty()) {
@@ -486,6 +576,7 @@ npg_status npg_stage_times(npg_plan* P, float* ms) {
 npg_status npg_plan_set_edges(npg_plan* P, int64_t n_edges, const int32_t* edges_host) {
   CHECK_ARG(P && edges_host, "plan and edges_host must be non-NULL");
   CHECK_ARG(n_edges >= 1 && n_edges < (int64_t)1 << 30, "need 1 <= n_edges < 2^30");
+  npg_graph_reset(P);  // a captured step holds the old edge buffers
   return npg_iso_set_edges(P, n_edges, edges_host);
 }
 
@@ -583,6 +674,7 @@ npg_status npg_precond_residuals(npg_plan* P, double* relres) {
 npg_status npg_tune_nn(npg_plan* P, int32_t threads, int32_t* chosen, float* ms) {
   CHECK_ARG(P, "plan is NULL");
   CHECK_ARG(threads == 0 || threads == 64 || threads == 128 || threads == 256, "threads must be 0, 64, 128 or 256");
+  npg_graph_reset(P);  // a captured step holds the old launch shape
   auto set = [&](int kt) {
     P->nn_threads = kt;
     const int vb = npg_chamfer_vblock(kt);
