@@ -190,7 +190,8 @@ npg_status npg_state_export(npg_plan* plan, float* params_dev, float* m_dev, flo
  *              forward pass
  *   cd_dev     [T] float64 (may be NULL): per-frame Chamfer distances
  * Returns NPG_ENOTCONV (after completing the step) if a CG solve hit its cap.
- * With the CG preconditioner the call synchronizes every 16 iterations to test
+ * With the CG preconditioner the call synchronizes between batches of
+ * iterations (the first as long as the previous call's solve) to test
  * convergence.
  */
 npg_status npg_step(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* loss_dev,
@@ -343,7 +344,7 @@ npg_status npg_encode_bwd(npg_plan* plan, const float* gz_dev, float* grad_dev);
  * in place by (I + lambda L)^-2 g per feature channel, L the 6-neighbour
  * lattice Laplacian with free boundary (degree minus adjacency). MLP block
  * untouched. With NPG_PRECOND_CG: two conjugate-gradient solves from zero
- * with float64 inner products, synchronizing every 16 iterations, each
+ * with float64 inner products, synchronizing between batches of iterations, each
  * stopped at ||r|| <= cg_rtol ||b||; with cg_mg = 1 the solves are
  * preconditioned by a symmetric multigrid V-cycle (2x2x2 aggregates, Galerkin
  * coarse operators, damped Jacobi smoothing), which cuts the iteration count

@@ -23,6 +23,7 @@ struct NpgGrid {
 
 struct NpgCG {  // conjugate-gradient workspace
   float *x, *r, *p, *q;        // [n_grid_params] each, grid layout (p, q: ping-pong directions)
+  int last_iters[2] = {0, 0};  // iterations the last first / second solve took (its first batch)
   double* part;                // [n_blocks][4 waves][4 channels] partial dots
   double* st;                  // [n_sys][4][8] per-system/channel scalars
   int* active;                 // [n_sys] any channel still iterating

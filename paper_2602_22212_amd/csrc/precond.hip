@@ -1496,7 +1496,8 @@ void npg_cg_free(npg_plan* P) {
 // C.q: later iterations write only the blocks of systems still active), the
 // next odd one adds both terms, and a term still pending when a system stops
 // is added at the end.
-static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters, bool* capped, double* relres) {
+static npg_status cg_solve(npg_plan* P, int which, const float* b, float* x, int32_t* iters, bool* capped,
+                           double* relres) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nb = C.n_blocks;
@@ -1520,8 +1521,15 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
   int it = 0;
   bool done = false;
   const int maxit = P->cfg.cg_maxit;
+  // Iterations are launched in batches between host convergence tests (an
+  // iteration whose systems have all converged only launches empty
+  // work-groups, so the batching changes no result). The first batch is what
+  // the same solve of the previous call took (16 the first time); later
+  // batches are short, as the solve is then close to its end.
+  const int first = C.last_iters[which] > 0 ? C.last_iters[which] : 16;
   while (it < maxit) {
-    const int chunk = 16 < maxit - it ? 16 : maxit - it;
+    const int want = it == 0 ? first : (C.last_iters[which] > 0 ? 2 : 16);
+    const int chunk = want < maxit - it ? want : maxit - it;
     for (int k = 0; k < chunk; ++k) {
       const bool odd = ((it + k) & 1) != 0;
       // optional profiling: event pairs around both streaming kernels,
@@ -1558,6 +1566,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
     if (done) break;
   }
   if (!done) *capped = true;
+  int taken = 0;  // iterations of the slowest system, read below
   std::vector<double> stv((size_t)P->n_sys * 4 * kS);
   NPG_HIP(hipMemcpyAsync(stv.data(), C.st, stv.size() * 8, hipMemcpyDeviceToHost, s));
   NPG_HIP(hipStreamSynchronize(s));
@@ -1566,6 +1575,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
     double m = 0;
     for (int c = 0; c < g.F; ++c) m = stv[(sy * 4 + c) * kS + 6] > m ? stv[(sy * 4 + c) * kS + 6] : m;
     if (iters) iters[sy] = (int32_t)m;
+    taken = std::max(taken, (int)m);
     // final relative residual ||r|| / ||b|| in float64, the largest over the channels
     double rel = 0.0;
     float pend[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1591,6 +1601,7 @@ static npg_status cg_solve(npg_plan* P, const float* b, float* x, int32_t* iters
     P->cg_alg_bytes += m * 4.0 * (mg ? 8.0 * fine + 4.0 * C.mg_elems[sy] : 6.0 * fine);
     P->cg_iters_sum += (int64_t)m;
   }
+  C.last_iters[which] = taken;
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
@@ -1600,9 +1611,9 @@ npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters) {
   P->cg_alg_bytes = 0.0;
   P->cg_iters_sum = 0;
   // y = A^-1 g into the workspace, then A^-1 y back into the gradient
-  npg_status st = cg_solve(P, grad, P->cg.x, iters, &capped, P->cg_relres);
+  npg_status st = cg_solve(P, 0, grad, P->cg.x, iters, &capped, P->cg_relres);
   if (st != NPG_OK) return st;
-  st = cg_solve(P, P->cg.x, grad, iters ? iters + P->n_sys : nullptr, &capped, P->cg_relres + P->n_sys);
+  st = cg_solve(P, 1, P->cg.x, grad, iters ? iters + P->n_sys : nullptr, &capped, P->cg_relres + P->n_sys);
   if (st != NPG_OK) return st;
   return capped ? NPG_ENOTCONV : NPG_OK;
 }
