@@ -367,15 +367,15 @@ struct ZPlane {
 // (it synchronises the work-group once per plane). POST(z) runs in every
 // thread after the plane's BODY (it may synchronise the work-group).
 //
-// The raw loads run DEPTH planes ahead of the arithmetic (DEPTH 2 or 3 plane
-// buffers whose roles rotate; the loop is unrolled by DEPTH so no buffer is
-// copied) and are formed by OP only when their plane is reached, so they stay
+// The raw loads run DEPTH-1 planes ahead of the arithmetic (DEPTH = 2 to 4
+// plane buffers whose roles rotate; the loop is unrolled by DEPTH so no buffer
+// is copied) and are formed by OP only when their plane is reached, so they stay
 // in flight across the work-group barriers of DEPTH-1 planes.
 template <typename RAW, typename EX, int DEPTH = 2, typename LD, typename LDC, typename OP, typename BODY,
           typename POST>
 __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD ld, LDC ldc, OP op, BODY body,
                                              POST post) {
-  static_assert(DEPTH == 2 || DEPTH == 3, "planes loaded ahead of the arithmetic: 2 or 3");
+  static_assert(DEPTH >= 2 && DEPTH <= 4, "planes loaded ahead of the arithmetic: 2 to 4");
   __shared__ float4 sh[3][kTY + 2][kTX];
   const int R = g.R;
   const int64_t R2 = (int64_t)R * R;
@@ -402,7 +402,7 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
     P.h = ld(m + dh, 2, zz);
   };
   int64_t n = (int64_t)t.z0 * R2 + nxy;
-  ZPlane<RAW, EX> A, B, C;
+  ZPlane<RAW, EX> A, B, C, D;
   load_plane(t.z0, A);
   float4 cur = op(A.c, 0, t.z0), edge = op(A.e, 1, t.z0);
   EX ex = A.ex;
@@ -410,7 +410,8 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
   if (halo) sh[t.z0 % 3][hrow][lane] = op(A.h, 2, t.z0);
   float4 prev = t.z0 > 0 ? op(ld(n - R2, 0, t.z0 - 1), 0, t.z0 - 1) : cur;
   load_plane(min(t.z0 + 1, R - 1), B);
-  if (DEPTH == 3) load_plane(min(t.z0 + 2, R - 1), C);
+  if (DEPTH >= 3) load_plane(min(t.z0 + 2, R - 1), C);
+  if (DEPTH == 4) load_plane(min(t.z0 + 3, R - 1), D);
   // Pn holds plane z+1 (clamped to z at the top face, where it then adds 0);
   // Pl held plane z and receives plane z+DEPTH.
   auto step = [&](int z, ZPlane<RAW, EX>& Pn, ZPlane<RAW, EX>& Pl) {
@@ -441,13 +442,23 @@ __device__ __forceinline__ void zm_walk_post(const NpgGrid& g, const Tile& t, LD
       if (z + 1 >= t.z1) break;
       step(z + 1, A, B);
     }
-  } else {
+  } else if (DEPTH == 3) {
     for (int z = t.z0; z < t.z1; z += 3) {
       step(z, B, A);
       if (z + 1 >= t.z1) break;
       step(z + 1, C, B);
       if (z + 2 >= t.z1) break;
       step(z + 2, A, C);
+    }
+  } else {
+    for (int z = t.z0; z < t.z1; z += 4) {
+      step(z, B, A);
+      if (z + 1 >= t.z1) break;
+      step(z + 1, C, B);
+      if (z + 2 >= t.z1) break;
+      step(z + 2, D, C);
+      if (z + 3 >= t.z1) break;
+      step(z + 3, A, D);
     }
   }
 }
@@ -1134,7 +1145,7 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
   const int x = t.x0 + lane, y = t.y0 + w;
   const ZmCols cols = zm_cols(t, R, lam, nh);
   float4 rs = make_float4(0.f, 0.f, 0.f, 0.f), zacc = rs;
-  zm_walk_post<Raw1, Raw1, 3>(
+  zm_walk_post<Raw1, Raw1, 4>(
       g, t,
       [&](int64_t m, int, int) { return Raw1{B[m]}; }, [&](int64_t m) { return Raw1{B[m]}; },
       [&](const Raw1& v, int s, int zz) {
