@@ -29,12 +29,14 @@ def _same_state(a, b):
         assert np.array_equal(to_np(x), to_np(y))
 
 
-@pytest.mark.parametrize("variant", ["plain", "iso_quat"])
+@pytest.mark.parametrize("variant", ["plain", "iso_quat", "bf16"])
 def test_graph_step_is_bitwise_the_eager_step(variant):
     import torch
     cfg = dict(synth.config_c1(), precond="dct")
     if variant == "iso_quat":
         cfg.update(w_iso=100.0, rot_head="quat")
+    if variant == "bf16":
+        cfg.update(precision="bf16")
     data = synth.make_workload(cfg)
     P = synth.random_state(cfg, 7, grid_std=0.05)
     zeros = O.zeros_like_params(P)
