@@ -343,12 +343,14 @@ def test_adam_matches_oracle(case):
 
 @pytest.mark.parametrize("method", ["cg", "cg_plain", "dct"])
 @pytest.mark.parametrize("levels,feat", [([100, 129, 20], 4), ([256], 4), ([7, 33, 50], 2), ([17, 24], 3),
-                                         ([2, 3, 5, 9], 1)])
+                                         ([2, 3, 5, 9], 1), (list(range(2, 18)), 4)])
 def test_preconditioner_large_grids(levels, feat, method):
     """Grids of >= 100 nodes per axis run the z-column CG kernels; 129 gives
     partial tiles in x, y and z; F = 2, 3 and odd sizes exercise the generic
     paths of both methods (odd sizes also give partial multigrid aggregates;
-    2 and 3 nodes per axis give single-node coarse levels).
+    2 and 3 nodes per axis give single-node coarse levels). Sixteen levels
+    (2..17 nodes per axis, lambda up to 175) and the normal grid make 17
+    systems, the most one V-cycle launch holds tasks for.
     cg: V-cycle preconditioned CG; cg_plain: plain CG. Sparse vertex-gradient
     input as in a step, plus a dense random component."""
     import torch
