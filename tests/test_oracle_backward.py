@@ -326,3 +326,60 @@ def test_bf16_backward_rounds_only_the_matrix_operands():
     got2, _ = O.mlp_backward(mlp, go2, pres, ins, "relu", 0.0, bf16=True)
     np.testing.assert_array_equal(got2[1][0], O.bf16_round(go2).T @ ins[1])
     np.testing.assert_array_equal(got2[1][1], go2.sum(0))
+
+
+@pytest.mark.parametrize("method", ["dct", "cg"])
+def test_step_composition_per_block(method):
+    """How one step is put together (Sec. 3.5 "Preconditioning" and
+    "Implementation Details"; Table 7 names the base smoothness 0.4): grid
+    level l = 1..L (coarsest first) is preconditioned by (I + lam_l L)^-2 with
+    lam_l = 0.4 * 1.5^(l-1) and updated with lr_l = 0.005 * 2.5^(l-1); the
+    normal grid uses lam 0.4 and lr 0.005; the MLP gradient is not
+    preconditioned and uses lr 1e-3. At Adam step 1 from zero moments every
+    entry moves by -lr g~ / (|g~| + eps) and the moments are (1 - b1) g~ and
+    (1 - b2) g~^2. The preconditioner is evaluated here by dense solves of the
+    explicit edge-loop Laplacian (levels of 3, 4, 5 and 4 nodes per axis), so
+    a swapped level order, a wrong level's lam or lr, or a preconditioned MLP
+    gradient fails."""
+    cfg = synth.config_small(precond=method)
+    L = len(cfg["levels"])
+    lam = [0.4 * 1.5 ** (l - 1) for l in range(1, L + 1)]
+    lr = [0.005 * 2.5 ** (l - 1) for l in range(1, L + 1)]
+    np.testing.assert_allclose(cfg["lam"], lam, rtol=1e-15)
+    np.testing.assert_allclose(cfg["lr_grid"], lr, rtol=1e-15)
+    assert cfg["lam_n"] == 0.4 and cfg["lr_n"] == 0.005 and cfg["lr_mlp"] == 1e-3
+    data = synth.make_workload(cfg)
+    p = O.to64(synth.random_state(cfg, 21))
+    zero = O.zeros_like_params(p)
+    fw = O.forward(p, data, cfg)
+    ls = O.losses(fw, data, cfg, 0, cfg["n_steps"])
+    g, _ = O.backward(p, data, cfg, fw, ls)
+    p1, m1, v1, d = O.step(p, zero, O.zeros_like_params(p), 1, data, cfg, 0, cfg["n_steps"], precond=method)
+    b1, b2, eps = cfg["beta1"], cfg["beta2"], cfg["eps"]
+    tol = 1e-12 if method == "dct" else 1e-9
+
+    def dense_precond(gl, R, lm):
+        A = np.eye(R ** 3) + lm * _dense_laplacian(R)
+        return np.linalg.solve(A, np.linalg.solve(A, gl))
+
+    def check(th0, th1, mm, vv, gt, rate, name):
+        np.testing.assert_allclose(mm, (1 - b1) * gt, rtol=tol, atol=1e-300, err_msg=name)
+        np.testing.assert_allclose(vv, (1 - b2) * gt * gt, rtol=2 * tol, atol=1e-300, err_msg=name)
+        np.testing.assert_allclose(th1, th0 - rate * gt / (np.abs(gt) + eps), rtol=tol, atol=tol * rate,
+                                   err_msg=name)
+
+    grids = list(zip(p["grid_p"], p1["grid_p"], m1["grid_p"], v1["grid_p"], g["grid_p"], cfg["levels"]))
+    assert len(set(cfg["levels"])) == L  # distinct sizes: a level permutation cannot pass
+    for l, (th0, th1, mm, vv, gl, R) in enumerate(grids):
+        gt = dense_precond(gl, R, lam[l])
+        assert np.abs(gt - gl).max() > 1e-3 * np.abs(gl).max()  # the preconditioner acts
+        check(th0, th1, mm, vv, gt, lr[l], f"level {l + 1}")
+    gt = dense_precond(g["grid_n"], cfg["res_n"], 0.4)
+    check(p["grid_n"], p1["grid_n"], m1["grid_n"], v1["grid_n"], gt, 0.005, "normal grid")
+    for k, ((W0, b0), (W1, b1_), (mW, mb), (vW, vb), (gW, gb)) in enumerate(
+            zip(p["mlp"], p1["mlp"], m1["mlp"], v1["mlp"], g["mlp"])):
+        check(W0, W1, mW, vW, gW, 1e-3, f"W{k}")
+        check(b0, b1_, mb, vb, gb, 1e-3, f"b{k}")
+    # the step reports the preconditioned gradients it fed to Adam
+    for l, (gl, R) in enumerate(zip(g["grid_p"], cfg["levels"])):
+        np.testing.assert_allclose(d["pgrads"]["grid_p"][l], dense_precond(gl, R, lam[l]), rtol=tol, atol=1e-14)
