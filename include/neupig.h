@@ -191,8 +191,9 @@ npg_status npg_state_export(npg_plan* plan, float* params_dev, float* m_dev, flo
  *   cd_dev     [T] float64 (may be NULL): per-frame Chamfer distances
  * Returns NPG_ENOTCONV (after completing the step) if a CG solve hit its cap.
  * With the CG preconditioner the call synchronizes between batches of
- * iterations (the first as long as the previous call's solve) to test
- * convergence.
+ * iterations to test convergence (the first batch as long as the previous
+ * call's same solve, at most 128, and 16 after a solve that reached the cap;
+ * then 2 at a time).
  */
 npg_status npg_step(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* loss_dev,
                     double* cd_dev);
@@ -203,11 +204,19 @@ npg_status npg_step(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* los
  * own; nothing runs while recording) and each call replays it on the plan's
  * stream after a one-thread kernel has written the step's scalars (the
  * confidence exponent of `epoch`, the Adam bias corrections) to device
- * memory. Results are bitwise those of npg_step. Only for the DCT
- * preconditioner (precond = 1): NPG_EINVAL for the CG form, whose solves test
- * convergence on the host. npg_tune_nn and npg_plan_set_edges drop the
- * recorded graph (the next call records it again). Synchronizes at the end,
- * like npg_step; per-stage times (npg_stage_times) are not recorded.
+ * memory. Results are bitwise those of npg_step, for both preconditioners.
+ * The CG form records a fixed number of iterations per solve (what the same
+ * solve took last time plus 2; 16 before any solve) and a device-side test of
+ * the convergence flags after each solve: a solve that has not converged
+ * within them leaves the optimizer state untouched (Adam is skipped on the
+ * device), and the call records twice the iterations (at most cg_maxit) and
+ * runs the step again; iterations recorded past convergence change nothing.
+ * The recording is renewed when the counts leave more than 6 idle iterations.
+ * Returns NPG_ENOTCONV (after completing the step) if a solve recorded with
+ * cg_maxit iterations did not converge. npg_tune_nn and npg_plan_set_edges
+ * drop the recorded graph (the next call records it again). Synchronizes at
+ * the end, like npg_step; per-stage times (npg_stage_times) and CG iteration
+ * profiling (npg_profile) are not recorded.
  */
 npg_status npg_step_graph(npg_plan* plan, int32_t epoch, int32_t n_epochs, double* loss_dev,
                           double* cd_dev);
@@ -417,20 +426,23 @@ npg_status npg_adam(npg_plan* plan, float* params_dev, const float* grad_dev, fl
 npg_status npg_stage_times(npg_plan* plan, float* ms_host);
 
 /*
- * Profiling of the preconditioner's CG iteration (the k_cg_dir_ap +
- * k_cg_update kernel pair): with enable != 0, npg_step records HIP events
- * around both kernels of every iteration on the plan's stream and resolves
- * them after the step (one extra stream synchronisation per step). Enabling
- * resets the accumulators.
+ * Profiling of the preconditioner's CG iterations: with enable != 0,
+ * npg_step records HIP events around every iteration on the plan's stream and
+ * resolves them after the step (one extra stream synchronisation per step).
+ * Enabling resets the accumulators.
  */
 npg_status npg_profile(npg_plan* plan, int32_t enable);
 
-/* Accumulated since npg_profile(plan, 1): summed kernel time of the CG
- * iteration pairs (ms), number of iterations, and their algorithmic bytes
- * (6 float32 vector passes -- x, r, p each read and written -- over every
- * active grid's R^3 F unknowns per iteration). */
+/* Accumulated since npg_profile(plan, 1) over the eager steps: summed time
+ * of the CG iterations (ms; HIP events on the plan's stream bracket each whole
+ * iteration: both streaming kernels, the V-cycle and both reductions), the
+ * number of iterations launched, and their algorithmic bytes: cg_bytes_host
+ * counts 6 float32 vector passes (x, r, p each read and written) over the R^3 F
+ * unknowns of every grid for each iteration that grid took; cg_bytes_mg_host
+ * (may be NULL) counts, for the V-cycle form, also z (written and read) and
+ * every coarse level's right-hand side and correction (written and read). */
 npg_status npg_profile_read(npg_plan* plan, double* cg_ms_host, int64_t* cg_iters_host,
-                            double* cg_bytes_host);
+                            double* cg_bytes_host, double* cg_bytes_mg_host);
 
 #ifdef __cplusplus
 }

@@ -87,7 +87,8 @@ _SIGS = {
     "npg_state_import": ([_P, _P, _P, _P, _I64], ctypes.c_int),
     "npg_state_export": ([_P, _P, _P, _P, ctypes.POINTER(_I64)], ctypes.c_int),
     "npg_profile": ([_P, _I32], ctypes.c_int),
-    "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D)], ctypes.c_int),
+    "npg_profile_read": ([_P, ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D)],
+                         ctypes.c_int),
 }
 
 
@@ -270,10 +271,13 @@ class Plan:
         return _check(st)
 
     def step_graph(self, epoch, n_epochs, loss=None, cd=None):
-        """npg_step replayed as one captured HIP graph (DCT preconditioner only)."""
+        """npg_step replayed as one captured HIP graph (both preconditioners)."""
         import torch
-        return _check(lib().npg_step_graph(self._h, int(epoch), int(n_epochs), _ptr(loss, torch.float64, 1, "loss"),
-                                           _ptr(cd, torch.float64, self.T, "cd")))
+        st = lib().npg_step_graph(self._h, int(epoch), int(n_epochs), _ptr(loss, torch.float64, 1, "loss"),
+                                  _ptr(cd, torch.float64, self.T, "cd"))
+        if st == NPG_ENOTCONV:
+            return st
+        return _check(st)
 
     def set_edges(self, edges):
         """Mesh edges [E, 2] (host array) for the isometry loss."""
@@ -319,9 +323,10 @@ class Plan:
         _check(lib().npg_profile(self._h, int(bool(enable))))
 
     def profile_read(self):
-        ms, it, by = _D(), _I64(), _D()
-        _check(lib().npg_profile_read(self._h, ctypes.byref(ms), ctypes.byref(it), ctypes.byref(by)))
-        return dict(cg_ms=ms.value, cg_iters=it.value, cg_bytes=by.value)
+        ms, it, by, bm = _D(), _I64(), _D(), _D()
+        _check(lib().npg_profile_read(self._h, ctypes.byref(ms), ctypes.byref(it), ctypes.byref(by),
+                                      ctypes.byref(bm)))
+        return dict(cg_ms=ms.value, cg_iters=it.value, cg_bytes=by.value, cg_bytes_mg=bm.value)
 
     # -- stages ---------------------------------------------------------------
     def encode_fwd(self, params, z):

@@ -17,6 +17,7 @@ __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, floa
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (sc) {
+    if (sc->cg_state & 3) return;  // a recorded CG solve stopped short: the step is redone
     inv_bc1 = sc->inv_bc1;
     inv_sqrt_bc2 = sc->inv_sqrt_bc2;
   }

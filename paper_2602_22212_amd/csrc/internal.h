@@ -51,6 +51,9 @@ struct NpgDct;
 struct NpgStepScal {
   double delta;                // confidence catch-up exponent 1 - sqrt(e / e_max)
   float inv_bc1, inv_sqrt_bc2;  // Adam bias corrections 1 / (1 - b1^k), 1 / sqrt(1 - b2^k)
+  int cg_state;                 // recorded CG solves: bit w set if solve w had not converged within its
+                                // recorded iterations (Adam then leaves the state untouched); bit 2: a
+                                // solve recorded with cg_maxit iterations did not converge
 };
 
 struct npg_plan {
@@ -138,12 +141,15 @@ struct npg_plan {
   NpgStepScal* d_scal = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  hipStream_t cap_stream = nullptr;  // 4 per CG iteration
+  hipStream_t cap_stream = nullptr;
+  int graph_iters[2] = {0, 0};       // CG form: iterations recorded for each solve
   int prof_n;                       // events recorded in the current step
   double prof_cg_ms;                // accumulated kernel time of resolved steps
   int64_t prof_cg_launches;         // accumulated CG iterations (kernel pairs)
   double prof_cg_bytes;             // accumulated algorithmic bytes
-  double cg_alg_bytes;              // algorithmic bytes of the last preconditioner call
+  double cg_alg_bytes;              // algorithmic bytes of the last preconditioner call (6 passes)
+  double cg_alg_bytes_mg;           // the same counting z and the V-cycle's coarse levels
+  double prof_cg_bytes_mg;          // accumulated cg_alg_bytes_mg
   int64_t cg_iters_sum;             // sum over grids and solves of the iteration counts
 };
 
@@ -181,6 +187,12 @@ hipError_t npg_launch_chamfer_bwd(const npg_plan* P, const float4* xhat, const i
                                   const int32_t* b, const double* w, float4* gxhat);
 // precond.hip
 npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters);
+// graph-recordable CG preconditioning: n_iter[w] iterations of solve w, then
+// a device-side convergence check into *state_dev (bits as NpgStepScal::cg_state)
+npg_status npg_run_precond_cg_fixed(npg_plan* P, float* grad, const int n_iter[2], int* state_dev);
+// host bookkeeping of the last CG preconditioning (iteration counts, residuals,
+// algorithmic bytes); synchronizes
+npg_status npg_cg_report(npg_plan* P, int32_t* iters);
 // dct.hip
 npg_status npg_dct_setup(npg_plan* P);
 void npg_dct_free(npg_plan* P);

@@ -125,16 +125,20 @@ __global__ void k_set_step_scal(NpgStepScal* __restrict__ sc, double delta, floa
     sc->delta = delta;
     sc->inv_bc1 = inv_bc1;
     sc->inv_sqrt_bc2 = inv_sqrt_bc2;
+    sc->cg_state = 0;
   }
 }
 
-// Records the stages of npg_step (DCT preconditioner) into P->graph on a
-// stream of its own; the loss and Adam kernels take their per-step scalars
-// from P->d_scal. Nothing is executed.
+// Records the stages of npg_step into P->graph on a stream of its own; the
+// loss and Adam kernels take their per-step scalars from P->d_scal. The CG
+// form records P->graph_iters[w] iterations of solve w and a device-side
+// convergence check (NpgStepScal::cg_state). Nothing is executed.
 npg_status capture_step(npg_plan* P) {
   if (!P->d_scal) NPG_HIP(hipMalloc(&P->d_scal, sizeof(NpgStepScal)));
   if (!P->cap_stream) NPG_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   hipStream_t keep = P->stream;
+  const int keep_prof = P->prof_cg;
+  P->prof_cg = 0;  // no profiling events inside the recording
   P->stream = P->cap_stream;
   NPG_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
   auto enqueue = [&]() -> npg_status {
@@ -146,7 +150,9 @@ npg_status capture_step(npg_plan* P) {
     if (P->cfg.w_iso > 0.f) NPG_HIP(npg_launch_iso(P, P->xhat, P->gxhat, P->iso_val, nullptr, P->loss));
     NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz));
     NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
-    npg_status st = npg_run_precond_dct(P, P->grad);
+    npg_status st = P->cfg.precond == NPG_PRECOND_DCT
+                        ? npg_run_precond_dct(P, P->grad)
+                        : npg_run_precond_cg_fixed(P, P->grad, P->graph_iters, &P->d_scal->cg_state);
     if (st != NPG_OK) return st;
     NPG_HIP(npg_launch_adam(P, P->params, P->grad, P->m, P->v, 1, P->d_flag, P->d_scal));
     return NPG_OK;
@@ -155,6 +161,7 @@ npg_status capture_step(npg_plan* P) {
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);  // always ends the capture
   P->stream = keep;
+  P->prof_cg = keep_prof;
   if (st != NPG_OK) {
     if (g) hipGraphDestroy(g);
     return st;
@@ -487,16 +494,18 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
   NPG_HIP(npg_launch_adam(P, P->params, P->grad, P->m, P->v, P->adam_k, P->d_flag));
   NPG_HIP(hipEventRecord(P->ev[9], s));
   if (P->prof_cg) {
-    // resolve this step's CG kernel timings (the stream is drained below)
+    // resolve this step's CG iteration timings (the stream is drained below)
     NPG_HIP(hipStreamSynchronize(s));
-    for (int k = 0; k + 3 < P->prof_n; k += 4) {
-      float a = 0.f, b = 0.f;
+    for (int k = 0; k + 1 < P->prof_n; k += 2) {
+      float a = 0.f;
       NPG_HIP(hipEventElapsedTime(&a, P->prof_ev[k], P->prof_ev[k + 1]));
-      NPG_HIP(hipEventElapsedTime(&b, P->prof_ev[k + 2], P->prof_ev[k + 3]));
-      P->prof_cg_ms += (double)a + (double)b;
+      P->prof_cg_ms += (double)a;
     }
-    P->prof_cg_launches += P->prof_n / 4;
-    P->prof_cg_bytes += P->cg_alg_bytes;
+    P->prof_cg_launches += P->prof_n / 2;
+    if (P->cfg.precond == NPG_PRECOND_CG) {
+      P->prof_cg_bytes += P->cg_alg_bytes;
+      P->prof_cg_bytes_mg += P->cg_alg_bytes_mg;
+    }
     P->prof_n = 0;
   }
   if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
@@ -516,39 +525,70 @@ npg_status npg_step_graph(npg_plan* P, int32_t epoch, int32_t n_epochs, double* 
   CHECK_ARG(P, "plan is NULL");
   CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
   CHECK_ARG(P->cfg.w_iso == 0.f || P->n_edges > 0, "w_iso > 0 needs the mesh edges (npg_plan_set_edges)");
-  CHECK_ARG(P->cfg.precond == NPG_PRECOND_DCT,
-            "npg_step_graph needs the DCT preconditioner (the CG solves test convergence on the host)");
-  if (!P->graph_exec) {
-    const npg_status st = capture_step(P);
-    if (st != NPG_OK) {
-      npg_graph_reset(P);
-      return st;
+  const bool cg = P->cfg.precond == NPG_PRECOND_CG;
+  const int maxit = P->cfg.cg_maxit;
+  if (cg) {
+    // iterations recorded per solve: what the last preconditioning took plus
+    // 2 (16 without one); recorded again when that leaves more than 6 idle
+    for (int w = 0; w < 2; ++w) {
+      const int last = P->cg.last_iters[w];
+      const int want = std::min(maxit, last > 0 ? last + 2 : 16);
+      if (P->graph_iters[w] == 0 || (last > 0 && P->graph_iters[w] > last + 6)) {
+        if (P->graph_iters[w] != want) npg_graph_reset(P);
+        P->graph_iters[w] = want;
+      }
     }
   }
   hipStream_t s = P->stream;
-  P->adam_k += 1;
+  const int64_t k = P->adam_k + 1;
   float ib1 = 1.f, ib2 = 1.f;
-  npg_adam_scalars(P, P->adam_k, &ib1, &ib2);
-  hipLaunchKernelGGL(k_set_step_scal, dim3(1), dim3(64), 0, s, P->d_scal, npg_loss_delta(epoch, n_epochs), ib1,
-                     ib2);
-  NPG_HIP(hipGetLastError());
-  NPG_HIP(hipGraphLaunch(P->graph_exec, s));
+  npg_adam_scalars(P, k, &ib1, &ib2);
+  NpgStepScal sc_h{};
+  int flag = 0;
+  for (;;) {
+    if (!P->graph_exec) {
+      const npg_status st = capture_step(P);
+      if (st != NPG_OK) {
+        npg_graph_reset(P);
+        return st;
+      }
+    }
+    hipLaunchKernelGGL(k_set_step_scal, dim3(1), dim3(64), 0, s, P->d_scal, npg_loss_delta(epoch, n_epochs), ib1,
+                       ib2);
+    NPG_HIP(hipGetLastError());
+    NPG_HIP(hipGraphLaunch(P->graph_exec, s));
+    NPG_HIP(hipMemcpyAsync(&sc_h, P->d_scal, sizeof(NpgStepScal), hipMemcpyDeviceToHost, s));
+    NPG_HIP(hipMemcpyAsync(&flag, P->d_flag, 4, hipMemcpyDeviceToHost, s));
+    NPG_HIP(hipStreamSynchronize(s));
+    if (!(sc_h.cg_state & 3)) break;
+    // a solve had not converged within its recorded iterations: Adam left the
+    // state untouched; record more iterations (up to cg_maxit) and redo the step
+    for (int w = 0; w < 2; ++w)
+      if (sc_h.cg_state & (1 << w)) P->graph_iters[w] = std::min(maxit, 2 * P->graph_iters[w]);
+    npg_graph_reset(P);
+    if (flag) NPG_HIP(hipMemsetAsync(P->d_flag, 0, 4, s));
+  }
+  P->adam_k = k;  // the update has been applied
+  if (cg) {
+    const npg_status st = npg_cg_report(P, nullptr);
+    if (st != NPG_OK) return st;
+  }
   if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
   if (cd_out) NPG_HIP(hipMemcpyAsync(cd_out, P->cd, 8 * (size_t)P->T, hipMemcpyDeviceToDevice, s));
-  int flag = 0;
-  NPG_HIP(hipMemcpyAsync(&flag, P->d_flag, 4, hipMemcpyDeviceToHost, s));
   NPG_HIP(hipStreamSynchronize(s));
   if (flag) {
     NPG_HIP(hipMemsetAsync(P->d_flag, 0, 4, s));
+    NPG_HIP(hipStreamSynchronize(s));
     return npg_fail(NPG_ENONFINITE, "a non-finite value was produced during the step");
   }
+  if (sc_h.cg_state & 4) return npg_fail(NPG_ENOTCONV, "a CG solve reached cg_maxit");
   return NPG_OK;
 }
 
 npg_status npg_profile(npg_plan* P, int32_t enable) {
   CHECK_ARG(P, "plan is NULL");
   if (enable && P->prof_ev.empty()) {
-    P->prof_ev.resize(4 * 2 * (size_t)P->cfg.cg_maxit + 8, nullptr);
+    P->prof_ev.resize(2 * 2 * (size_t)P->cfg.cg_maxit + 8, nullptr);
     for (auto& e : P->prof_ev) NPG_HIP(hipEventCreate(&e));
   }
   P->prof_cg = enable ? 1 : 0;
@@ -556,14 +596,16 @@ npg_status npg_profile(npg_plan* P, int32_t enable) {
   P->prof_cg_ms = 0.0;
   P->prof_cg_launches = 0;
   P->prof_cg_bytes = 0.0;
+  P->prof_cg_bytes_mg = 0.0;
   return NPG_OK;
 }
 
-npg_status npg_profile_read(npg_plan* P, double* cg_ms, int64_t* cg_iters, double* cg_bytes) {
+npg_status npg_profile_read(npg_plan* P, double* cg_ms, int64_t* cg_iters, double* cg_bytes, double* cg_bytes_mg) {
   CHECK_ARG(P && cg_ms && cg_iters && cg_bytes, "NULL argument");
   *cg_ms = P->prof_cg_ms;
   *cg_iters = P->prof_cg_launches;
   *cg_bytes = P->prof_cg_bytes;
+  if (cg_bytes_mg) *cg_bytes_mg = P->prof_cg_bytes_mg;
   return NPG_OK;
 }
 

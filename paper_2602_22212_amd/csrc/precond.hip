@@ -660,15 +660,41 @@ __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G,
   NPG_F_SWITCH(g, (update_body<XM, FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, x, r, p, p_prev, part, blk)));
 }
 
-// The pending x term of one system: x += alpha_pending p (flat, F channels).
-__global__ void k_cg_flush(float* __restrict__ x, const float* __restrict__ p, int64_t n, int F, float a0, float a1,
-                           float a2, float a3) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int c = (int)(e % F);
-  const float a = c == 0 ? a0 : (c == 1 ? a1 : (c == 2 ? a2 : a3));
-  x[e] = fmaf(a, p[e], x[e]);
+// The pending x terms a solve left when it stopped after an even iteration:
+// x += alpha_pending q for every system and channel, the factors (float32 of
+// the float64 scalar 7) read from the solve's scalars on the device. One
+// launch covers every system; a system with nothing pending is skipped by
+// every work-group.
+__global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G, int n_sys,
+                                                  const double* __restrict__ st, float* __restrict__ x,
+                                                  const float* __restrict__ q) {
+  for (int s = 0; s < n_sys; ++s) {
+    const NpgGrid g = G[s];
+    float a[4];
+    bool any = false;
+    for (int c = 0; c < 4; ++c) {
+      a[c] = c < g.F ? (float)st[(s * 4 + c) * kS + 7] : 0.f;
+      any |= a[c] != 0.f;
+    }
+    if (!any) continue;
+    const int64_t n = g.nodes * g.F;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+      const int c = (int)(e % g.F);
+      const float ac = c == 0 ? a[0] : (c == 1 ? a[1] : (c == 2 ? a[2] : a[3]));
+      x[g.poff + e] = fmaf(ac, q[g.poff + e], x[g.poff + e]);
+    }
+  }
 }
+
+// After a fixed number of launched iterations: sets `bit` in *state when
+// some system is still iterating (one thread).
+__global__ void k_cg_done(const int* __restrict__ active, int n_sys, int* __restrict__ state, int bit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int any = 0;
+  for (int s = 0; s < n_sys; ++s) any |= active[s];
+  if (any) *state = *state | bit;
+}
+
 // Sum of the block partials [b0, b1) of part per channel, in a fixed order
 // (strided per thread, then per wave, then the waves in order); the result
 // is valid in thread 0.
@@ -1476,7 +1502,7 @@ npg_status npg_cg_setup(npg_plan* P) {
   NPG_HIP(hipMalloc(&C.p, n * 4));
   NPG_HIP(hipMalloc(&C.q, n * 4));
   NPG_HIP(hipMalloc(&C.part, (int64_t)C.n_blocks * 4 * 8));
-  NPG_HIP(hipMalloc(&C.st, (int64_t)P->n_sys * 4 * kS * 8));
+  NPG_HIP(hipMalloc(&C.st, 2 * (int64_t)P->n_sys * 4 * kS * 8));  // one block per solve
   NPG_HIP(hipMalloc(&C.active, P->n_sys * 4));
   NPG_HIP(hipMalloc(&C.blk_sys, C.n_blocks * 4));
   NPG_HIP(hipMalloc(&C.blk_start, C.n_blocks * 8));
@@ -1500,75 +1526,119 @@ void npg_cg_free(npg_plan* P) {
     if (b) (void)hipFree(b);
 }
 
+// ---- the two solves ------------------------------------------------------------
 // Solve (I + lam L) x = b for every system (b and x distinct buffers in the
-// grid-block layout). The iteration count of each system goes to iters (if
-// not NULL). Iteration k writes p_k into C.q for even k and into C.p for odd
-// k; the update of an even iteration leaves its x term pending (p_k stays in
-// C.q: later iterations write only the blocks of systems still active), the
-// next odd one adds both terms, and a term still pending when a system stops
-// is added at the end.
-static npg_status cg_solve(npg_plan* P, int which, const float* b, float* x, int32_t* iters, bool* capped,
-                           double* relres) {
+// grid-block layout); solve `which` (0 first, 1 second) keeps its scalars in
+// its own block of C.st. Iteration k writes p_k into C.q for even k and into
+// C.p for odd k; the update of an even iteration leaves its x term pending
+// (p_k stays in C.q: later iterations write only the blocks of systems still
+// active), the next odd one adds both terms, and a term still pending when a
+// system stops is added by k_cg_flush at the end. An iteration launched after
+// every system of the solve has converged changes nothing (each work-group
+// returns on the system's device-side active flag), so the result does not
+// depend on how many iterations are launched past convergence: the eager
+// form launches them in batches between host tests of the flags, the
+// graph-recorded form a fixed count followed by a device-side check.
+namespace {
+
+struct CgCtx {
+  dim3 grid, blk;
+  Divs dv;
+  bool mg;
+  double* part2;
+  const float* dir_src;
+  double* st;
+};
+
+CgCtx cg_ctx(const npg_plan* P, int which) {
+  const NpgCG& C = P->cg;
+  CgCtx c;
+  c.grid = dim3(xcd_grid(C.n_blocks));
+  c.blk = dim3(kB);
+  for (int sy = 0; sy < P->n_sys; ++sy) {
+    c.dv.r[sy] = make_fastdiv((uint32_t)P->g[sy].R);
+    c.dv.r2[sy] = make_fastdiv((uint32_t)P->g[sy].R * (uint32_t)P->g[sy].R);
+  }
+  c.mg = C.mg != 0;
+  c.part2 = c.mg ? C.part2 : nullptr;
+  c.dir_src = c.mg ? C.z : C.r;  // p = z + beta p (z = r without the V-cycle)
+  c.st = C.st + (size_t)which * P->n_sys * 4 * kS;
+  return c;
+}
+
+npg_status cg_start(npg_plan* P, const CgCtx& c, const float* b, float* x) {
+  NpgCG& C = P->cg;
+  hipStream_t s = P->stream;
+  hipLaunchKernelGGL(k_cg_init, c.grid, c.blk, 0, s, P->d_g, C.n_blocks, C.blk_sys, C.blk_start, b, x, C.r, C.p,
+                     C.part);
+  if (c.mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0));
+  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
+                     c.part2, C.sys_blk0, c.st, 0, P->cfg.cg_rtol, 0);
+  NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
+
+// Iteration k (0-based) of a solve. With profiling on, HIP events bracket
+// the whole iteration (both streaming kernels, the V-cycle and both
+// reductions), resolved after the step.
+npg_status cg_iteration(npg_plan* P, const CgCtx& c, float* x, int k) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nb = C.n_blocks;
-  const dim3 grid(xcd_grid(nb)), blk(kB);
-  Divs dv;
-  for (int sy = 0; sy < P->n_sys; ++sy) {
-    dv.r[sy] = make_fastdiv((uint32_t)P->g[sy].R);
-    dv.r2[sy] = make_fastdiv((uint32_t)P->g[sy].R * (uint32_t)P->g[sy].R);
-  }
-  const bool mg = C.mg != 0;
-  double* part2 = mg ? C.part2 : nullptr;
-  const float* dir_src = mg ? C.z : C.r;  // p = z + beta p (z = r without the V-cycle)
-  hipLaunchKernelGGL(k_cg_init, grid, blk, 0, s, P->d_g, nb, C.blk_sys, C.blk_start, b, x, C.r, C.p, C.part);
-  if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0));
+  const bool odd = (k & 1) != 0;
+  float* p_old = odd ? C.q : C.p;
+  float* p_new = odd ? C.p : C.q;
+  const bool prof = P->prof_cg && P->prof_n + 2 <= (int)P->prof_ev.size();
+  if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n], s));
+  hipLaunchKernelGGL(k_cg_dir_ap, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active, c.st,
+                     c.dir_src, p_old, p_new, C.part);
   hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                     part2, C.sys_blk0, C.st, 0, P->cfg.cg_rtol, 0);
+                     c.part2, C.sys_blk0, c.st, 1, P->cfg.cg_rtol, 0);
+  if (odd)
+    hipLaunchKernelGGL(k_cg_update<1>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
+                       c.st, x, C.r, p_new, p_old, C.part);
+  else
+    hipLaunchKernelGGL(k_cg_update<0>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
+                       c.st, x, C.r, p_new, p_old, C.part);
+  if (c.mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 1));
+  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
+                     c.part2, C.sys_blk0, c.st, 2, P->cfg.cg_rtol, (int)!odd);
+  if (prof) {
+    NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], s));
+    P->prof_n += 2;
+  }
   NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
+
+npg_status cg_finish(npg_plan* P, const CgCtx& c, float* x) {
+  hipLaunchKernelGGL(k_cg_flush, dim3((unsigned)(4 * P->n_cu)), dim3(256), 0, P->stream, P->d_g, P->n_sys, c.st, x,
+                     P->cg.q);
+  NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
+
+// Eager solve: iterations launched in batches between host tests of the
+// active flags. The first batch is what the same solve of the previous call
+// took (16 the first time, at most kFirstMax, and not carried over from a
+// solve that reached the cap); later batches are 2 iterations long.
+constexpr int kFirstMax = 128;
+
+npg_status cg_solve_eager(npg_plan* P, int which, const float* b, float* x, bool* capped) {
+  NpgCG& C = P->cg;
+  hipStream_t s = P->stream;
+  const CgCtx c = cg_ctx(P, which);
+  NPG_TRY_ST(cg_start(P, c, b, x));
   std::vector<int> act(P->n_sys);
-  float* pa = C.p;  // current direction
-  float* pb = C.q;  // next direction
+  const int maxit = P->cfg.cg_maxit;
+  const int last = C.last_iters[which];
+  const int first = last > 0 ? std::min(last, kFirstMax) : 16;
   int it = 0;
   bool done = false;
-  const int maxit = P->cfg.cg_maxit;
-  // Iterations are launched in batches between host convergence tests (an
-  // iteration whose systems have all converged only launches empty
-  // work-groups, so the batching changes no result). The first batch is what
-  // the same solve of the previous call took (16 the first time); later
-  // batches are short, as the solve is then close to its end.
-  const int first = C.last_iters[which] > 0 ? C.last_iters[which] : 16;
   while (it < maxit) {
-    const int want = it == 0 ? first : (C.last_iters[which] > 0 ? 2 : 16);
-    const int chunk = want < maxit - it ? want : maxit - it;
-    for (int k = 0; k < chunk; ++k) {
-      const bool odd = ((it + k) & 1) != 0;
-      // optional profiling: event pairs around both streaming kernels,
-      // resolved after the step (no synchronisation here)
-      const bool prof = P->prof_cg && P->prof_n + 4 <= (int)P->prof_ev.size();
-      if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n], s));
-      hipLaunchKernelGGL(k_cg_dir_ap, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
-                         dir_src, pa, pb, C.part);
-      if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], s));
-      std::swap(pa, pb);  // pa = p_k, pb = p_{k-1}
-      hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                         part2, C.sys_blk0, C.st, 1, P->cfg.cg_rtol, 0);
-      if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 2], s));
-      if (odd)
-        hipLaunchKernelGGL(k_cg_update<1>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
-                           x, C.r, pa, pb, C.part);
-      else
-        hipLaunchKernelGGL(k_cg_update<0>, grid, blk, 0, s, P->d_g, dv, nb, C.blk_sys, C.blk_start, C.active, C.st,
-                           x, C.r, pa, pb, C.part);
-      if (mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 1));
-      if (prof) {
-        NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 3], s));
-        P->prof_n += 4;
-      }
-      hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                         part2, C.sys_blk0, C.st, 2, P->cfg.cg_rtol, (int)!odd);
-    }
-    NPG_HIP(hipGetLastError());
+    const int want = it == 0 ? first : (last > 0 ? 2 : 16);
+    const int chunk = std::min(want, maxit - it);
+    for (int k = 0; k < chunk; ++k) NPG_TRY_ST(cg_iteration(P, c, x, it + k));
     it += chunk;
     NPG_HIP(hipMemcpyAsync(act.data(), C.active, P->n_sys * 4, hipMemcpyDeviceToHost, s));
     NPG_HIP(hipStreamSynchronize(s));
@@ -1577,54 +1647,78 @@ static npg_status cg_solve(npg_plan* P, int which, const float* b, float* x, int
     if (done) break;
   }
   if (!done) *capped = true;
-  int taken = 0;  // iterations of the slowest system, read below
-  std::vector<double> stv((size_t)P->n_sys * 4 * kS);
-  NPG_HIP(hipMemcpyAsync(stv.data(), C.st, stv.size() * 8, hipMemcpyDeviceToHost, s));
-  NPG_HIP(hipStreamSynchronize(s));
-  for (int sy = 0; sy < P->n_sys; ++sy) {
-    const NpgGrid& g = P->g[sy];
-    double m = 0;
-    for (int c = 0; c < g.F; ++c) m = stv[(sy * 4 + c) * kS + 6] > m ? stv[(sy * 4 + c) * kS + 6] : m;
-    if (iters) iters[sy] = (int32_t)m;
-    taken = std::max(taken, (int)m);
-    // final relative residual ||r|| / ||b|| in float64, the largest over the channels
-    double rel = 0.0;
-    float pend[4] = {0.f, 0.f, 0.f, 0.f};
-    bool any = false;
-    for (int c = 0; c < g.F; ++c) {
-      const double* S = stv.data() + (sy * 4 + c) * kS;
-      const double v = S[1] > 0.0 ? sqrt(S[2] / S[1]) : 0.0;
-      rel = v > rel ? v : rel;
-      pend[c] = (float)S[7];
-      any |= S[7] != 0.0;
+  return cg_finish(P, c, x);
+}
+
+}  // namespace
+
+// Host bookkeeping of the last preconditioning from both solves' scalars
+// (synchronizes): iteration counts (iters may be NULL), final relative
+// residuals, the algorithmic bytes of the iterations, the first batch of the
+// next eager call (not carried over from a solve that reached the cap).
+npg_status npg_cg_report(npg_plan* P, int32_t* iters) {
+  NpgCG& C = P->cg;
+  const bool mg = C.mg != 0;
+  std::vector<double> stv((size_t)2 * P->n_sys * 4 * kS);
+  NPG_HIP(hipMemcpyAsync(stv.data(), C.st, stv.size() * 8, hipMemcpyDeviceToHost, P->stream));
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  P->cg_alg_bytes = 0.0;
+  P->cg_alg_bytes_mg = 0.0;
+  P->cg_iters_sum = 0;
+  for (int which = 0; which < 2; ++which) {
+    int taken = 0;  // iterations of the slowest system
+    for (int sy = 0; sy < P->n_sys; ++sy) {
+      const NpgGrid& g = P->g[sy];
+      const double* S0 = stv.data() + ((size_t)which * P->n_sys + sy) * 4 * kS;
+      double m = 0.0, rel = 0.0;
+      for (int ch = 0; ch < g.F; ++ch) {
+        const double* S = S0 + ch * kS;
+        m = S[6] > m ? S[6] : m;
+        // final relative residual ||r|| / ||b|| in float64, the largest over the channels
+        const double v = S[1] > 0.0 ? sqrt(S[2] / S[1]) : 0.0;
+        rel = v > rel ? v : rel;
+      }
+      if (iters) iters[which * P->n_sys + sy] = (int32_t)m;
+      P->cg_relres[which * P->n_sys + sy] = rel;
+      taken = std::max(taken, (int)m);
+      // algorithmic traffic per iteration: 6 vector passes (x, r, p read and
+      // written) over the grid's R^3 F float32 unknowns; the V-cycle form
+      // also moves z (written, read) and each coarse level's right-hand side
+      // and correction (written, read)
+      const double fine = (double)g.nodes * g.F;
+      P->cg_alg_bytes += m * 4.0 * 6.0 * fine;
+      P->cg_alg_bytes_mg += m * 4.0 * (mg ? 8.0 * fine + 4.0 * C.mg_elems[sy] : 6.0 * fine);
+      P->cg_iters_sum += (int64_t)m;
     }
-    relres[sy] = rel;
-    if (any) {
-      const int64_t n = g.nodes * g.F;
-      hipLaunchKernelGGL(k_cg_flush, dim3(nblk(n, 256)), dim3(256), 0, s, x + g.poff, C.q + g.poff, n, g.F, pend[0],
-                         pend[1], pend[2], pend[3]);
-    }
-    // algorithmic traffic of this solve per iteration: 6 vector passes (x,
-    // r, p read and written) over the grid's R^3 F float32 unknowns; with the
-    // V-cycle also z (written, read) and each coarse level's right-hand side
-    // and correction (written, read)
-    const double fine = (double)g.nodes * g.F;
-    P->cg_alg_bytes += m * 4.0 * (mg ? 8.0 * fine + 4.0 * C.mg_elems[sy] : 6.0 * fine);
-    P->cg_iters_sum += (int64_t)m;
+    C.last_iters[which] = taken >= P->cfg.cg_maxit ? 0 : taken;
   }
-  C.last_iters[which] = taken;
-  NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
 
 npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters) {
   bool capped = false;
-  P->cg_alg_bytes = 0.0;
-  P->cg_iters_sum = 0;
   // y = A^-1 g into the workspace, then A^-1 y back into the gradient
-  npg_status st = cg_solve(P, 0, grad, P->cg.x, iters, &capped, P->cg_relres);
-  if (st != NPG_OK) return st;
-  st = cg_solve(P, 1, P->cg.x, grad, iters ? iters + P->n_sys : nullptr, &capped, P->cg_relres + P->n_sys);
-  if (st != NPG_OK) return st;
+  NPG_TRY_ST(cg_solve_eager(P, 0, grad, P->cg.x, &capped));
+  NPG_TRY_ST(cg_solve_eager(P, 1, P->cg.x, grad, &capped));
+  NPG_TRY_ST(npg_cg_report(P, iters));
   return capped ? NPG_ENOTCONV : NPG_OK;
+}
+
+// Graph-recordable form (no host synchronisation): solve `which` launches
+// exactly n_iter[which] iterations, then k_cg_done sets bit (1 << which) of
+// *state_dev if a system is still iterating, or bit 4 when the count is the
+// cap cg_maxit (the eager form's NPG_ENOTCONV case, whose result stands).
+npg_status npg_run_precond_cg_fixed(npg_plan* P, float* grad, const int n_iter[2], int* state_dev) {
+  const float* b[2] = {grad, P->cg.x};
+  float* x[2] = {P->cg.x, grad};
+  for (int which = 0; which < 2; ++which) {
+    const CgCtx c = cg_ctx(P, which);
+    NPG_TRY_ST(cg_start(P, c, b[which], x[which]));
+    for (int k = 0; k < n_iter[which]; ++k) NPG_TRY_ST(cg_iteration(P, c, x[which], k));
+    const int bit = n_iter[which] >= P->cfg.cg_maxit ? 4 : (1 << which);
+    hipLaunchKernelGGL(k_cg_done, dim3(1), dim3(64), 0, P->stream, P->cg.active, P->n_sys, state_dev, bit);
+    NPG_HIP(hipGetLastError());
+    NPG_TRY_ST(cg_finish(P, c, x[which]));
+  }
+  return NPG_OK;
 }

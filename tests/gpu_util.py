@@ -86,3 +86,34 @@ def block_rel(cfg, flat_gpu, structured_ref):
         out[f"W{k}"] = rel(W, Wr)
         out[f"b{k}"] = rel(b, br)
     return out
+
+
+def touched_nodes(cfg, data):
+    """Nodes read by the grid lookup of some reference vertex (per grid:
+    position levels, then the normal grid)."""
+    import oracle as O
+    X = data["xyz"].astype(np.float64)
+    Nr = data["nrm"].astype(np.float64)
+    out = []
+    for R in list(cfg["levels"]) + [cfg["res_n"]]:
+        Q = X if len(out) < len(cfg["levels"]) else Nr
+        nodes = set()
+        for node, _ in O.neupig._corners(Q, R):
+            nodes.update(node.tolist())
+        out.append(np.array(sorted(nodes)))
+    return out
+
+
+def f32_hyper(cfg):
+    """The config with every hyper-parameter the C ABI carries as float32
+    (learning rates, smoothness weights, Adam constants, activation slope,
+    displacement scale) replaced by its float32 value, so that a float64
+    oracle step runs the constants the library was given (1 - 0.999 and
+    1 - float32(0.999) differ by 1.3e-5 relative)."""
+    f = lambda x: float(np.float32(x))
+    out = dict(cfg)
+    for k in ("beta1", "beta2", "eps", "lr_mlp", "lr_n", "lam_n", "leaky_slope", "alpha_t"):
+        out[k] = f(cfg[k])
+    out["lr_grid"] = [f(x) for x in cfg["lr_grid"]]
+    out["lam"] = [f(x) for x in cfg["lam"]]
+    return out

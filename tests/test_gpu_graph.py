@@ -29,14 +29,22 @@ def _same_state(a, b):
         assert np.array_equal(to_np(x), to_np(y))
 
 
-@pytest.mark.parametrize("variant", ["plain", "iso_quat", "bf16"])
+@pytest.mark.parametrize("variant", ["plain", "iso_quat", "bf16", "cg", "cg_plain"])
 def test_graph_step_is_bitwise_the_eager_step(variant):
+    """DCT form (plain, with the isometry term and the quaternion head, BF16)
+    and CG form (V-cycle preconditioned and plain). The graph plan's first
+    recording of the CG form takes 16 iterations per solve; plain CG needs
+    more on the finer levels, so its first replays find a solve unfinished,
+    leave the state untouched and record again with more iterations: the
+    step's result is the eager one all the same."""
     import torch
     cfg = dict(synth.config_c1(), precond="dct")
     if variant == "iso_quat":
         cfg.update(w_iso=100.0, rot_head="quat")
     if variant == "bf16":
         cfg.update(precision="bf16")
+    if variant.startswith("cg"):
+        cfg.update(precond="cg", cg_mg=0 if variant == "cg_plain" else 1)
     data = synth.make_workload(cfg)
     P = synth.random_state(cfg, 7, grid_std=0.05)
     zeros = O.zeros_like_params(P)
@@ -86,12 +94,20 @@ def test_graph_step_matches_the_oracle():
     plan.close()
 
 
-def test_graph_step_refuses_the_cg_form():
+def test_graph_step_cg_cap_is_reported():
+    """A solve that reaches cg_maxit: the graph step completes like the eager
+    one (the capped solve's result stands), reports NPG_ENOTCONV and leaves
+    the same state, bitwise."""
     import paper_2602_22212_amd as npg
-    cfg = dict(synth.config_small(mlp_width=32), precond="cg")
+    cfg = synth.config_small(mlp_width=32, cg_maxit=3, cg_rtol=1e-12, levels=[6, 9], precond="cg")
     data = synth.make_workload(cfg)
-    plan = gpu_plan(cfg, data)
-    with pytest.raises(npg.NpgError) as e:
-        plan.step_graph(0, 1)
-    assert e.value.status == npg.NPG_EINVAL and "DCT" in str(e.value)
-    plan.close()
+    P = synth.random_state(cfg, 2)
+    zeros = O.zeros_like_params(P)
+    state = (flat_params(cfg, P), flat_params(cfg, zeros), flat_params(cfg, zeros), 0)
+    eager, graph = _pair(cfg, data, state)
+    for e in range(3):
+        assert eager.step(e, 3) == npg.NPG_ENOTCONV
+        assert graph.step_graph(e, 3) == npg.NPG_ENOTCONV
+        _same_state(eager, graph)
+    eager.close()
+    graph.close()

@@ -5,24 +5,10 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import block_rel, flat_params, gpu_plan, nn_check, rel, to_np
+from gpu_util import block_rel, flat_params, gpu_plan, nn_check, rel, to_np, touched_nodes
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
-
-
-def _touched_nodes(cfg, data):
-    """Nodes read by the grid lookup of some reference vertex (per grid)."""
-    X = data["xyz"].astype(np.float64)
-    Nr = data["nrm"].astype(np.float64)
-    out = []
-    for R in list(cfg["levels"]) + [cfg["res_n"]]:
-        Q = X if len(out) < len(cfg["levels"]) else Nr
-        nodes = set()
-        for node, _ in O.neupig._corners(Q, R):
-            nodes.update(node.tolist())
-        out.append(np.array(sorted(nodes)))
-    return out
 
 
 @pytest.mark.parametrize("method,head", [("cg", "expmap"), ("dct", "expmap"), ("cg", "quat")])
@@ -37,7 +23,7 @@ def test_teacher_forced_steps_on_icosphere(method, head):
     cfg = dict(synth.config_c1(), precond=method, rot_head=head)
     data = synth.make_workload(cfg)
     plan = gpu_plan(cfg, data)
-    touched = _touched_nodes(cfg, data)
+    touched = touched_nodes(cfg, data)
     P = O.to64(synth.init_params(cfg))
     m, v = O.zeros_like_params(P), O.zeros_like_params(P)
     E = cfg["n_steps"]
@@ -83,7 +69,7 @@ def test_teacher_forced_steps_with_isometry():
     E = data["edges"]
     T, V = data["T"], len(data["xyz"])
     t_key = (T - 1) // 2 if cfg["t_key"] is None else cfg["t_key"]
-    touched = _touched_nodes(cfg, data)
+    touched = touched_nodes(cfg, data)
     P = O.to64(synth.random_state(cfg, 4, grid_std=0.05))
     m, v = O.zeros_like_params(P), O.zeros_like_params(P)
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
