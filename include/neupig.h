@@ -262,6 +262,23 @@ npg_status npg_metrics(npg_plan* plan, const float* xhat_dev, const float* nhat_
                        const float* gtn_dev, float tau, double* out_dev);
 
 /*
+ * npg_metrics for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, layouts and results (bitwise), with the workspace taken from a
+ * fixed array of the library (64 MiB per GPU, created when the library is
+ * loaded on that GPU and held until the process ends) instead of temporary
+ * allocations. Frames are processed in chunks that fit the array. Enqueues on
+ * the plan's stream and returns without synchronizing; calls no allocating
+ * routine. Every call on one GPU uses that GPU's one array: calls that can
+ * overlap in time on one GPU (other streams, other host threads) race;
+ * calls enqueued on one stream are ordered. NPG_EINVAL (nothing enqueued) if
+ * one frame's workspace, about V * (20 + 8 * ceil(V / (16 * nn_threads)))
+ * bytes with the plan's nearest-neighbour work-group size, exceeds 64 MiB.
+ */
+npg_status npg_metrics_noalloc(npg_plan* plan, const float* xhat_dev, const float* nhat_dev, const float* gt_dev,
+                               const float* gtn_dev, float tau, double* out_dev);
+
+/*
  * Batched sequences (survey config 5: many independent sequences at once).
  * n_seq sequences, each described exactly as for npg_plan_create by the
  * k-th entry of every array (its own config, so its own grids and MLP; host

@@ -79,6 +79,7 @@ _SIGS = {
     "npg_batch_step": ([_P, _I32, _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "npg_batch_destroy": ([_P], ctypes.c_int),
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
+    "npg_metrics_noalloc": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_scale": ([_P, _P, _D, _P, _I32, _I64], ctypes.c_int),
     "npg_tune_nn": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "npg_precond_residuals": ([_P, ctypes.POINTER(_D)], ctypes.c_int),
@@ -309,6 +310,16 @@ class Plan:
                                  _ptr(nhat, torch.float32, 4 * TV, "nhat"), _ptr(gt, torch.float32, 4 * TV, "gt"),
                                  _ptr(gtn, torch.float32, 4 * TV, "gtn"), float(tau),
                                  _ptr(out, torch.float64, 4 * self.T, "out")))
+
+    def metrics_noalloc(self, xhat, nhat, gt, gtn, tau, out):
+        """npg_metrics with the library's fixed scratch array (no device
+        allocation, no synchronisation)."""
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_metrics_noalloc(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
+                                         _ptr(nhat, torch.float32, 4 * TV, "nhat"), _ptr(gt, torch.float32, 4 * TV, "gt"),
+                                         _ptr(gtn, torch.float32, 4 * TV, "gtn"), float(tau),
+                                         _ptr(out, torch.float64, 4 * self.T, "out")))
 
     def deform(self, out):
         import torch

@@ -300,19 +300,20 @@ int npg_chamfer_vblock(int threads) { return threads * kK; }
 // Nmax; colpart holds T * nvb * Nmax 64-bit column records).
 hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pts, const int64_t* off,
                          const int* pt_frame, int64_t Ntot, int64_t Nmax, void* colpart, int32_t* a, float* da,
-                         int32_t* b, float* db) {
+                         int32_t* b, float* db, int nT) {
   unsigned long long* cp = reinterpret_cast<unsigned long long*>(colpart);
+  const unsigned frames = (unsigned)(nT > 0 ? nT : P->T);
   switch (P->nn_threads) {
     case 64:
-      hipLaunchKernelGGL(k_chamfer_main<64>, dim3(P->nvb, P->T), dim3(64), 0, P->stream, xhat, pts, off, P->V,
+      hipLaunchKernelGGL(k_chamfer_main<64>, dim3(P->nvb, frames), dim3(64), 0, P->stream, xhat, pts, off, P->V,
                          P->nvb, Nmax, a, da, cp);
       break;
     case 256:
-      hipLaunchKernelGGL(k_chamfer_main<256>, dim3(P->nvb, P->T), dim3(256), 0, P->stream, xhat, pts, off, P->V,
+      hipLaunchKernelGGL(k_chamfer_main<256>, dim3(P->nvb, frames), dim3(256), 0, P->stream, xhat, pts, off, P->V,
                          P->nvb, Nmax, a, da, cp);
       break;
     default:
-      hipLaunchKernelGGL(k_chamfer_main<128>, dim3(P->nvb, P->T), dim3(128), 0, P->stream, xhat, pts, off, P->V,
+      hipLaunchKernelGGL(k_chamfer_main<128>, dim3(P->nvb, frames), dim3(128), 0, P->stream, xhat, pts, off, P->V,
                          P->nvb, Nmax, a, da, cp);
   }
   hipLaunchKernelGGL(k_chamfer_cols, dim3(nblk(Ntot, 256)), dim3(256), 0, P->stream, xhat, pts, off, pt_frame, Ntot,

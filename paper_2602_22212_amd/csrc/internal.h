@@ -142,6 +142,7 @@ struct npg_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
+  unsigned char* scratch = nullptr;  // this device's copy of the library's fixed scratch array
   int graph_iters[2] = {0, 0};       // CG form: iterations recorded for each solve
   int prof_n;                       // events recorded in the current step
   double prof_cg_ms;                // accumulated kernel time of resolved steps
@@ -200,9 +201,17 @@ npg_status npg_iso_set_edges(npg_plan* P, int64_t E, const int32_t* edges_host);
 void npg_iso_free(npg_plan* P);
 npg_status npg_run_metrics(npg_plan* P, const float4* xhat, const float4* nhat, const float4* gt, const float4* gtn,
                            float tau, double* out);
+// the same metrics in a fixed device array of the library (no allocation,
+// no synchronisation); the array's address on the plan's device is found at
+// plan creation by npg_scratch_setup
+npg_status npg_scratch_setup(npg_plan* P);
+npg_status npg_run_metrics_noalloc(npg_plan* P, const float4* xhat, const float4* nhat, const float4* gt,
+                                   const float4* gtn, float tau, double* out);
+// nT: frames in this launch (xhat, a, da hold nT frames of V vertices; off
+// [nT+1] and pt_frame index the nT frames' points); 0 means all T frames
 hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pts, const int64_t* off,
                          const int* pt_frame, int64_t Ntot, int64_t Nmax, void* colpart, int32_t* a, float* da,
-                         int32_t* b, float* db);
+                         int32_t* b, float* db, int nT = 0);
 hipError_t npg_launch_iso(const npg_plan* P, const float4* xhat, float4* gxhat, double* iso, int8_t* sign,
                           double* loss);
 npg_status npg_run_precond_dct(npg_plan* P, float* grad);

@@ -11,6 +11,8 @@
 // The nearest-neighbour search is the Chamfer kernel pair with the true
 // vertices as the point set; one work-group per frame reduces the sums in
 // float64 in a fixed order.
+#include <mutex>
+
 #include "internal.h"
 
 namespace {
@@ -76,7 +78,87 @@ __global__ __launch_bounds__(kB) void k_metrics(const float4* __restrict__ xhat,
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Fixed workspace of npg_metrics_noalloc: one copy per GPU, created when the
+// library's code object is loaded on that GPU and held until the process
+// ends. In host code `scratch` names a host-side stand-in; kernels receive
+// the device address found by hipGetSymbolAddress (npg_scratch_setup).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_addr[kMaxDevices] = {};
+
+inline size_t a256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Workspace of nT frames: frame offsets, frame of every true vertex, column
+// records, both directions' indices and distances (256-byte aligned parts).
+size_t metrics_bytes(const npg_plan* P, int64_t nT) {
+  const int64_t n = nT * P->V;
+  return a256((size_t)(nT + 1) * 8) + a256((size_t)n * 4) + a256((size_t)nT * P->nvb * P->V * 8) +
+         4 * a256((size_t)n * 4);
+}
+
 }  // namespace
+
+npg_status npg_scratch_setup(npg_plan* P) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (P->device < 0 || P->device >= kMaxDevices) return npg_fail(NPG_EINVAL, "device ordinal beyond 63");
+  if (!g_scratch_addr[P->device]) {
+    void* ptr = nullptr;
+    NPG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));  // with the plan's device current
+    g_scratch_addr[P->device] = static_cast<unsigned char*>(ptr);
+  }
+  P->scratch = g_scratch_addr[P->device];
+  return NPG_OK;
+}
+
+// The metrics of npg_run_metrics with their workspace in the fixed array:
+// frames are processed in chunks that fit it, one chunk after the other on the
+// plan's stream (frames are independent, so results are bitwise those of
+// npg_run_metrics). Every workspace entry a kernel reads was written earlier
+// in the same chunk, so nothing needs clearing. No allocation, no
+// synchronisation.
+npg_status npg_run_metrics_noalloc(npg_plan* P, const float4* xhat, const float4* nhat, const float4* gt,
+                                   const float4* gtn, float tau, double* out) {
+  if (!P->scratch) return npg_fail(NPG_EHIP, "the scratch array has no device address on this GPU");
+  const int64_t V = P->V, T = P->T;
+  if (metrics_bytes(P, 1) > kScratchBytes)
+    return npg_fail(NPG_EINVAL, "one frame's metrics workspace (" + std::to_string(metrics_bytes(P, 1)) +
+                                    " bytes) exceeds the fixed scratch array (" + std::to_string(kScratchBytes) +
+                                    " bytes)");
+  // the most frames whose workspace fits (the size grows with the frame count)
+  int64_t lo = 1, hi = T;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (metrics_bytes(P, mid) <= kScratchBytes) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t nT = lo;
+  for (int64_t t0 = 0; t0 < T; t0 += nT) {
+    const int64_t nt = std::min(nT, T - t0), n = nt * V;
+    unsigned char* w = P->scratch;
+    int64_t* off = reinterpret_cast<int64_t*>(w);
+    w += a256((size_t)(nt + 1) * 8);
+    int* pt_frame = reinterpret_cast<int*>(w);
+    w += a256((size_t)n * 4);
+    void* colpart = w;
+    w += a256((size_t)nt * P->nvb * V * 8);
+    int32_t* a = reinterpret_cast<int32_t*>(w);
+    w += a256((size_t)n * 4);
+    int32_t* b = reinterpret_cast<int32_t*>(w);
+    w += a256((size_t)n * 4);
+    float* da = reinterpret_cast<float*>(w);
+    w += a256((size_t)n * 4);
+    float* db = reinterpret_cast<float*>(w);
+    const int64_t e0 = t0 * V;
+    hipLaunchKernelGGL(k_frame_index, dim3(nblk(n + 1, 256)), dim3(256), 0, P->stream, V, (int)nt, off, pt_frame);
+    NPG_HIP(npg_launch_nn(P, xhat + e0, gt + e0, off, pt_frame, n, V, colpart, a, da, b, db, (int)nt));
+    hipLaunchKernelGGL(k_metrics, dim3((unsigned)nt), dim3(kB), 0, P->stream, xhat + e0, nhat + e0, gt + e0,
+                       gtn + e0, a, da, b, db, V, tau * tau, out + 4 * t0);
+    NPG_HIP(hipGetLastError());
+  }
+  return NPG_OK;
+}
 
 npg_status npg_run_metrics(npg_plan* P, const float4* xhat, const float4* nhat, const float4* gt, const float4* gtn,
                            float tau, double* out) {

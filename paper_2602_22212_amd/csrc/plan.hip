@@ -260,6 +260,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   } while (0)
 
   HIPP(hipGetDevice(&P->device));
+  TRYP(npg_scratch_setup(P));  // this device's address of the fixed scratch array
   int ncu = 0;
   HIPP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device));
   P->n_cu = ncu > 0 ? ncu : 256;
@@ -645,6 +646,15 @@ npg_status npg_metrics(npg_plan* P, const float* xhat_dev, const float* nhat_dev
   return npg_run_metrics(P, reinterpret_cast<const float4*>(xhat_dev), reinterpret_cast<const float4*>(nhat_dev),
                          reinterpret_cast<const float4*>(gt_dev), reinterpret_cast<const float4*>(gtn_dev), tau,
                          out_dev);
+}
+
+npg_status npg_metrics_noalloc(npg_plan* P, const float* xhat_dev, const float* nhat_dev, const float* gt_dev,
+                               const float* gtn_dev, float tau, double* out_dev) {
+  CHECK_ARG(P && xhat_dev && nhat_dev && gt_dev && gtn_dev && out_dev, "NULL argument");
+  CHECK_ARG(tau > 0.f && std::isfinite(tau), "tau must be finite and > 0");
+  return npg_run_metrics_noalloc(P, reinterpret_cast<const float4*>(xhat_dev),
+                                 reinterpret_cast<const float4*>(nhat_dev), reinterpret_cast<const float4*>(gt_dev),
+                                 reinterpret_cast<const float4*>(gtn_dev), tau, out_dev);
 }
 
 npg_status npg_deform(npg_plan* P, float* out) {
