@@ -349,6 +349,32 @@ npg_status npg_chamfer_bwd(npg_plan* plan, const float* xhat_dev, const int32_t*
                            const int32_t* b_dev, const double* w_dev, float* gxhat_dev);
 
 /*
+ * Sec. 3.5 objective on deformed vertices xhat_dev [T][V][4]: the Chamfer
+ * outputs of npg_chamfer_fwd (a_dev, da_dev, b_dev, db_dev, cd_dev), the
+ * confidence weights of npg_loss (w_dev [T]) and
+ *   loss_dev [1] = L_def + w_iso L_iso
+ * (the isometry term with the plan's w_iso and mesh edges, only when
+ * w_iso > 0; iso_dev [1] (may be NULL) then receives L_iso). Everything in
+ * float64 on the device. NPG_EINVAL when w_iso > 0 and no edges are set.
+ */
+npg_status npg_objective_fwd(npg_plan* plan, const float* xhat_dev, int32_t epoch, int32_t n_epochs,
+                             int32_t* a_dev, float* da_dev, int32_t* b_dev, float* db_dev, double* cd_dev,
+                             double* w_dev, double* iso_dev, double* loss_dev);
+
+/*
+ * Gradient of that objective w.r.t. x^ with the assignments a, b and the
+ * weights w of npg_objective_fwd held fixed (the weights and the key-frame
+ * edge lengths are stop-gradients of Sec. 3.5), times an upstream factor g:
+ *   gxhat_dev [T][V][4] = g (dL_def/dx^ + w_iso dL_iso/dx^)
+ * g_dev: one float64 on the device (a reverse-mode caller's upstream
+ * gradient), or NULL for g = 1 (then bitwise the gradient npg_step forms).
+ * The factor multiplies the float64 frame weights and the isometry term's
+ * float64 scale before any float32 rounding.
+ */
+npg_status npg_objective_bwd(npg_plan* plan, const float* xhat_dev, const int32_t* a_dev, const int32_t* b_dev,
+                             const double* w_dev, const double* g_dev, float* gxhat_dev);
+
+/*
  * Backward of decode: recomputes the MLP forward per tile (activations are
  * never stored), back-propagates gxhat through the transform and the MLP.
  *   grad_dev [P]: the MLP block of the flat gradient is overwritten (grid

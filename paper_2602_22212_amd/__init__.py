@@ -80,6 +80,8 @@ _SIGS = {
     "npg_batch_destroy": ([_P], ctypes.c_int),
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_metrics_noalloc": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
+    "npg_objective_fwd": ([_P, _P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "npg_objective_bwd": ([_P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "npg_scale": ([_P, _P, _D, _P, _I32, _I64], ctypes.c_int),
     "npg_tune_nn": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "npg_precond_residuals": ([_P, ctypes.POINTER(_D)], ctypes.c_int),
@@ -365,6 +367,25 @@ class Plan:
         d = torch.float64
         _check(lib().npg_loss(self._h, _ptr(cd, d, self.T, "cd"), int(epoch), int(n_epochs),
                               _ptr(w, d, self.T, "w"), _ptr(loss, d, 1, "loss")))
+
+    def objective_fwd(self, xhat, epoch, n_epochs, a, da, b, db, cd, w, loss, iso=None):
+        """L_def + w_iso L_iso (Sec. 3.5) with the Chamfer outputs and weights."""
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_objective_fwd(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"), int(epoch), int(n_epochs),
+                                       _ptr(a, torch.int32, TV, "a"), _ptr(da, torch.float32, TV, "da"),
+                                       _ptr(b, torch.int32, self.Ntot, "b"), _ptr(db, torch.float32, self.Ntot, "db"),
+                                       _ptr(cd, torch.float64, self.T, "cd"), _ptr(w, torch.float64, self.T, "w"),
+                                       _ptr(iso, torch.float64, 1, "iso"), _ptr(loss, torch.float64, 1, "loss")))
+
+    def objective_bwd(self, xhat, a, b, w, g, gxhat):
+        """g (dL_def/dx^ + w_iso dL_iso/dx^); g a one-element float64 device tensor or None (1)."""
+        import torch
+        TV = self.T * self.V
+        _check(lib().npg_objective_bwd(self._h, _ptr(xhat, torch.float32, 4 * TV, "xhat"),
+                                       _ptr(a, torch.int32, TV, "a"), _ptr(b, torch.int32, self.Ntot, "b"),
+                                       _ptr(w, torch.float64, self.T, "w"), _ptr(g, torch.float64, 1, "g"),
+                                       _ptr(gxhat, torch.float32, 4 * TV, "gxhat")))
 
     def chamfer_bwd(self, xhat, a, b, w, gxhat):
         import torch

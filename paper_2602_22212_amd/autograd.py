@@ -10,8 +10,12 @@ sequence) and the flat float32 parameter vector of the plan's layout.
   DecodeApplyFn     params, z -> x^ [T, V, 4]                    (Sec. 3.3-3.4)
   ChamferLossFn     x^ -> L_def, cd [T]                          (Sec. 3.5)
   IsoFn             x^ -> L_iso                                  (Sec. 3.5)
+  ObjectiveFn       x^ -> L_def + w_iso L_iso, cd [T]: the whole objective
+                    and its x^ gradient formed by the library (Sec. 3.5)
   DeformChamferLossFn params, z -> L_def, cd: decode + Chamfer with x^
                     recomputed in backward instead of kept
+  DeformObjectiveFn params, z -> L_def + w_iso L_iso, cd: decode + the
+                    objective with x^ recomputed in backward
   NeuPigOptimizer   (I + lambda L)^-2 on the grid blocks of the gradient,
                     then Adam (Sec. 3.5)
 
@@ -184,17 +188,89 @@ class IsoFn(torch.autograd.Function):
         return gx, None
 
 
-def objective(plan, params, epoch, n_epochs):
+def _objective_forward(plan, xhat, epoch, n_epochs):
+    a = _empty(plan, plan.T * plan.V, _I32)
+    da = _empty(plan, plan.T * plan.V)
+    b = _empty(plan, plan.Ntot, _I32)
+    db = _empty(plan, plan.Ntot)
+    cd = _empty(plan, plan.T, _F64)
+    w = _empty(plan, plan.T, _F64)
+    loss = _empty(plan, 1, _F64)
+    plan.objective_fwd(xhat, epoch, n_epochs, a, da, b, db, cd, w, loss)
+    return a, b, cd, w, loss
+
+
+def _objective_backward(plan, xhat, a, b, w, g_loss):
+    gx = _empty(plan, (plan.T, plan.V, 4))
+    plan.objective_bwd(xhat, a, b, w, g_loss.detach().reshape(1).to(_F64).contiguous(), gx.view(-1))
+    return gx
+
+
+class ObjectiveFn(torch.autograd.Function):
+    """The objective of Sec. 3.5, L_def + w_iso L_iso (0-d float64; the
+    isometry term with the plan's w_iso and mesh edges when w_iso > 0), and
+    cd [T] (not differentiable). Forward and backward are single library
+    calls (npg_objective_fwd / npg_objective_bwd): the two terms and their x^
+    gradients are summed by the library."""
+
+    @staticmethod
+    def forward(ctx, xhat, plan, epoch, n_epochs):
+        xf = _flat(xhat)
+        a, b, cd, w, loss = _objective_forward(plan, xf, epoch, n_epochs)
+        ctx.save_for_backward(xf, a, b, w)
+        ctx.plan = plan
+        ctx.mark_non_differentiable(cd)
+        return loss.view(()), cd
+
+    @staticmethod
+    def backward(ctx, g_loss, g_cd):
+        xf, a, b, w = ctx.saved_tensors
+        return _objective_backward(ctx.plan, xf, a, b, w, g_loss), None, None, None
+
+
+class DeformObjectiveFn(torch.autograd.Function):
+    """DecodeApplyFn followed by ObjectiveFn without keeping x^ (only the
+    nearest-neighbour indices and the frame weights are stored; the backward
+    decodes x^ again)."""
+
+    @staticmethod
+    def forward(ctx, params, z, plan, epoch, n_epochs):
+        p, zf = _flat(params), _flat(z)
+        xhat = _empty(plan, plan.T * plan.V * 4)
+        plan.decode_fwd(p, zf, xhat)
+        a, b, cd, w, loss = _objective_forward(plan, xhat, epoch, n_epochs)
+        del xhat
+        ctx.save_for_backward(p, zf, a, b, w)
+        ctx.plan = plan
+        ctx.mark_non_differentiable(cd)
+        return loss.view(()), cd
+
+    @staticmethod
+    def backward(ctx, g_loss, g_cd):
+        plan = ctx.plan
+        p, zf, a, b, w = ctx.saved_tensors
+        xhat = _empty(plan, plan.T * plan.V * 4)
+        plan.decode_fwd(p, zf, xhat)
+        gx = _objective_backward(plan, xhat, a, b, w, g_loss)
+        del xhat
+        grad = _zeros(plan, plan.n_params)
+        gz = _empty(plan, (plan.V, plan.Fz))
+        plan.decode_bwd(p, zf, gx.view(-1), grad, gz.view(-1))
+        return grad, gz, None, None, None
+
+
+def objective(plan, params, epoch, n_epochs, recompute=False):
     """The training objective of one step, L_def + w_iso L_iso (the isometry
     term only when the plan's w_iso > 0), and the per-frame Chamfer
-    distances."""
+    distances. recompute: x^ is decoded again in backward instead of kept.
+    No arithmetic here: the library forms the objective and every gradient;
+    the autograd engine only adds the grid-block gradient of EncodeFn to the
+    MLP-block gradient of the decoder (disjoint blocks of params)."""
     z = EncodeFn.apply(params, plan)
+    if recompute:
+        return DeformObjectiveFn.apply(params, z, plan, epoch, n_epochs)
     xhat = DecodeApplyFn.apply(params, z, plan)
-    loss, cd = ChamferLossFn.apply(xhat, plan, epoch, n_epochs)
-    w_iso = float(plan.cfg.get("w_iso", 0.0))
-    if w_iso > 0.0:
-        loss = loss + w_iso * IsoFn.apply(xhat, plan)
-    return loss, cd
+    return ObjectiveFn.apply(xhat, plan, epoch, n_epochs)
 
 
 class NeuPigOptimizer:

@@ -17,7 +17,18 @@ __global__ __launch_bounds__(kB) void k_scale(const double* __restrict__ s, doub
   for (int64_t k = blockIdx.x * (int64_t)kB + threadIdx.x; k < n; k += stride) x[k] = (F)((double)x[k] * f);
 }
 
+__global__ void k_scaled_copy(const double* __restrict__ w, const double* __restrict__ g, double* __restrict__ out,
+                              int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = w[k] * g[0];
+}
+
 }  // namespace
+
+hipError_t npg_launch_scaled_copy(const npg_plan* P, const double* w, const double* g, double* out, int n) {
+  hipLaunchKernelGGL(k_scaled_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P->stream, w, g, out, n);
+  return hipGetLastError();
+}
 
 extern "C" npg_status npg_scale(npg_plan* P, const double* s, double c, void* x, int32_t is_f64, int64_t n) {
   if (!P || !s || (!x && n > 0) || n < 0) return npg_fail(NPG_EINVAL, "npg_scale: NULL plan/factor/vector or n < 0");

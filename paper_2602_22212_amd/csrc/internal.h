@@ -97,6 +97,7 @@ struct npg_plan {
   int32_t *a, *b;
   float *da, *db;
   double *cd, *w, *loss;
+  double* w_g;             // [T] confidence weights times an upstream factor (npg_objective_bwd)
   // chamfer workspace
   int nvb;                 // vertex blocks per frame of the NN main pass
   int nn_threads;          // its work-group size (64, 128, 256; npg_tune_nn)
@@ -212,8 +213,11 @@ npg_status npg_run_metrics_noalloc(npg_plan* P, const float4* xhat, const float4
 hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pts, const int64_t* off,
                          const int* pt_frame, int64_t Ntot, int64_t Nmax, void* colpart, int32_t* a, float* da,
                          int32_t* b, float* db, int nT = 0);
+// gs: NULL, or an upstream factor in device memory multiplying the gradient
 hipError_t npg_launch_iso(const npg_plan* P, const float4* xhat, float4* gxhat, double* iso, int8_t* sign,
-                          double* loss);
+                          double* loss, const double* gs = nullptr);
+// chain.hip: out[t] = w[t] * g[0] (float64), t < n
+hipError_t npg_launch_scaled_copy(const npg_plan* P, const double* w, const double* g, double* out, int n);
 npg_status npg_run_precond_dct(npg_plan* P, float* grad);
 // plan.hip: drop the captured step (after a change that alters its launches)
 void npg_graph_reset(npg_plan* P);

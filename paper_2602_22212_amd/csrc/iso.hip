@@ -40,8 +40,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 __global__ __launch_bounds__(kB) void k_iso(const float4* __restrict__ xhat, int64_t V, int T, int t_key,
                                             const int* __restrict__ row, const int* __restrict__ nbr,
                                             const uint32_t* __restrict__ eid, int64_t E, double scale,
-                                            float4* __restrict__ gxhat, int8_t* __restrict__ sign,
-                                            double* __restrict__ part) {
+                                            const double* __restrict__ gs, float4* __restrict__ gxhat,
+                                            int8_t* __restrict__ sign, double* __restrict__ part) {
+  if (gs) scale *= gs[0];  // upstream factor of a reverse-mode caller
   __shared__ double ws[kB / 64];
   const int64_t s = blockIdx.x * (int64_t)kB + threadIdx.x;
   double acc = 0.0;
@@ -159,11 +160,11 @@ void npg_iso_free(npg_plan* P) {
 }
 
 hipError_t npg_launch_iso(const npg_plan* P, const float4* xhat, float4* gxhat, double* iso, int8_t* sign,
-                          double* loss) {
+                          double* loss, const double* gs) {
   const double inv_te = 1.0 / ((double)P->T * (double)P->n_edges);
   const double scale = (double)P->cfg.w_iso * inv_te;
   hipLaunchKernelGGL(k_iso, dim3(P->n_iso_blk), dim3(kB), 0, P->stream, xhat, P->V, P->T, P->t_key, P->iso_row,
-                     P->iso_nbr, P->iso_eid, P->n_edges, scale, gxhat, sign, P->iso_part);
+                     P->iso_nbr, P->iso_eid, P->n_edges, scale, gs, gxhat, sign, P->iso_part);
   hipLaunchKernelGGL(k_iso_finish, dim3(1), dim3(kR), 0, P->stream, P->iso_part, P->n_iso_blk, inv_te,
                      (double)P->cfg.w_iso, iso, loss);
   return hipGetLastError();

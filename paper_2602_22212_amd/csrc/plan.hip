@@ -197,7 +197,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
   void* bufs[] = {P->xyz, P->nrm, P->pts, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
                   P->seg_chunk0, P->chunk_start, P->chunk_sum, P->chunk_sys, P->params, P->m, P->v, P->grad,
                   P->z, P->gz, P->xhat, P->gxhat, P->a, P->b, P->da, P->db, P->cd, P->w, P->loss, P->colpart,
-                  P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->fl_part, P->gam, P->d_flag};
+                  P->w_g, P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->fl_part, P->gam, P->d_flag};
   for (void* b : bufs)
     if (b) hipFree(b);
   npg_graph_reset(P);
@@ -343,6 +343,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->cd, T));
   TRYP(dalloc(&P->w, T));
   TRYP(dalloc(&P->loss, 1));
+  TRYP(dalloc(&P->w_g, T));
   P->nn_threads = 128;
   P->nvb = (int)((V + npg_chamfer_vblock(128) - 1) / npg_chamfer_vblock(128));
   P->nvb_max = (int)((V + npg_chamfer_vblock(64) - 1) / npg_chamfer_vblock(64));
@@ -425,6 +426,34 @@ npg_status npg_loss(npg_plan* P, const double* cd, int32_t epoch, int32_t n_epoc
   CHECK_ARG(P && cd && w && loss, "NULL argument");
   CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
   NPG_HIP(npg_launch_loss(P, cd, epoch, n_epochs, w, loss));
+  return NPG_OK;
+}
+
+npg_status npg_objective_fwd(npg_plan* P, const float* xhat, int32_t epoch, int32_t n_epochs, int32_t* a, float* da,
+                             int32_t* b, float* db, double* cd, double* w, double* iso, double* loss) {
+  CHECK_ARG(P && xhat && a && da && b && db && cd && w && loss, "NULL argument");
+  CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
+  CHECK_ARG(P->cfg.w_iso == 0.f || P->n_edges > 0, "w_iso > 0 needs the mesh edges (npg_plan_set_edges)");
+  const float4* x = reinterpret_cast<const float4*>(xhat);
+  NPG_HIP(npg_launch_chamfer_fwd(P, x, a, da, b, db, cd));
+  NPG_HIP(npg_launch_loss(P, cd, epoch, n_epochs, w, loss));
+  if (P->cfg.w_iso > 0.f) NPG_HIP(npg_launch_iso(P, x, nullptr, iso ? iso : P->iso_val, nullptr, loss));
+  return NPG_OK;
+}
+
+npg_status npg_objective_bwd(npg_plan* P, const float* xhat, const int32_t* a, const int32_t* b, const double* w,
+                             const double* g, float* gxhat) {
+  CHECK_ARG(P && xhat && a && b && w && gxhat, "NULL argument");
+  CHECK_ARG(P->cfg.w_iso == 0.f || P->n_edges > 0, "w_iso > 0 needs the mesh edges (npg_plan_set_edges)");
+  const float4* x = reinterpret_cast<const float4*>(xhat);
+  float4* gx = reinterpret_cast<float4*>(gxhat);
+  const double* wg = w;
+  if (g) {  // the upstream factor enters the float64 frame weights
+    NPG_HIP(npg_launch_scaled_copy(P, w, g, P->w_g, P->T));
+    wg = P->w_g;
+  }
+  NPG_HIP(npg_launch_chamfer_bwd(P, x, a, b, wg, gx));
+  if (P->cfg.w_iso > 0.f) NPG_HIP(npg_launch_iso(P, x, gx, P->iso_val, nullptr, nullptr, g));
   return NPG_OK;
 }
 

@@ -197,13 +197,16 @@ def test_gradient_matches_central_differences_of_gpu_loss():
 
 def test_optimizer_step_equals_npg_step():
     """Two steps through the Functions and NeuPigOptimizer (preconditioning,
-    then Adam) give bitwise the parameters and moments of two npg_step calls."""
+    then Adam) give bitwise the parameters and moments of two npg_step calls,
+    with and without the isometry term (the objective and its x^ gradient
+    formed by the library: ObjectiveFn, DeformObjectiveFn)."""
     import torch
 
     import paper_2602_22212_amd as npg
     from paper_2602_22212_amd import autograd as AG
-    for method in ("cg", "dct"):
-        cfg = _cfg(precond=method)
+    for method, w_iso, recompute in (("cg", 0.0, False), ("dct", 0.0, True), ("dct", 100.0, False),
+                                     ("cg", 100.0, True)):
+        cfg = _cfg(precond=method, w_iso=w_iso)
         data = synth.make_workload(cfg)
         plan = gpu_plan(cfg, data)
         flat = flat_params(cfg, synth.random_state(cfg, 104))
@@ -215,7 +218,7 @@ def test_optimizer_step_equals_npg_step():
         for e in range(2):
             assert plan.step(e, 9, loss) == npg.NPG_OK
             opt.zero_grad()
-            l_ag, _ = AG.objective(plan, params, e, 9)
+            l_ag, _ = AG.objective(plan, params, e, 9, recompute=recompute)
             l_ag.backward()
             assert opt.step() == npg.NPG_OK
             pg, mg, vg, k = plan.get_state()

@@ -421,3 +421,47 @@ def test_long_quadruped_sequence_sampled():
     print(f"3 steps: {time.time() - t0:.2f} s, loss {l0.item():.4e} -> {l1.item():.4e}")
     assert l1.item() < l0.item()
     plan.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_nonfinite_parameters_are_reported(graph):
+    """A NaN rotation bias in the last MLP layer makes every deformed vertex NaN: the
+    step completes and reports NPG_ENONFINITE (device flag raised by the
+    Chamfer backward and by Adam), eager and graph-replayed; the Chamfer
+    indices of NaN vertices stay inside their ranges; a step from a finite
+    state afterwards is NPG_OK (the flag is cleared)."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = dict(synth.config_c1(), precond="cg", w_iso=100.0)
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    T, V = data["T"], len(data["xyz"])
+    P = synth.random_state(cfg, 3)
+    W, b = P["mlp"][-1]
+    bad = dict(P, mlp=P["mlp"][:-1] + [(W, np.where(np.arange(len(b)) == 0, np.nan, b).astype(np.float32))])
+    step = plan.step_graph if graph else plan.step
+    plan.set_state(flat_params(cfg, bad), adam_steps=0)
+    with pytest.raises(npg.NpgError) as e:
+        step(0, cfg["n_steps"])
+    assert e.value.status == npg.NPG_ENONFINITE
+    z = torch.empty(V * plan.Fz, device="cuda")
+    xh = torch.empty(T * V * 4, device="cuda")
+    flat = flat_params(cfg, bad)
+    plan.encode_fwd(flat, z)
+    plan.decode_fwd(flat, z, xh)
+    assert torch.isnan(xh.view(T, V, 4)[..., :3]).all()
+    a = torch.empty(T * V, dtype=torch.int32, device="cuda")
+    da = torch.empty(T * V, device="cuda")
+    bb = torch.empty(plan.Ntot, dtype=torch.int32, device="cuda")
+    db = torch.empty(plan.Ntot, device="cuda")
+    cd = torch.empty(T, dtype=torch.float64, device="cuda")
+    plan.chamfer_fwd(xh, a, da, bb, db, cd)
+    off = data["frame_off"]
+    an = to_np(a).reshape(T, V)
+    for t in range(T):
+        assert an[t].min() >= 0 and an[t].max() < off[t + 1] - off[t]
+    assert to_np(bb).min() >= 0 and to_np(bb).max() < V
+    plan.set_state(flat_params(cfg, P), adam_steps=0)
+    assert step(0, cfg["n_steps"]) == npg.NPG_OK
+    plan.close()
