@@ -305,6 +305,22 @@ npg_status npg_batch_plan(npg_batch* batch, int32_t k, npg_plan** out);
  */
 npg_status npg_batch_step(npg_batch* batch, int32_t epoch, int32_t n_epochs, double* const* loss_dev);
 
+/*
+ * The same batch step with every sequence's step replayed from recorded HIP
+ * graphs (each plan's npg_step_graph recording, made on first use and again
+ * when that recording changes). Mode NPG_BATCH_ONE_GRAPH (default): one batch
+ * graph holds the recordings as independent branches (child graphs) and is
+ * launched on a stream of the batch's own after the work already enqueued on
+ * the sequences' streams. Mode NPG_BATCH_GRAPH_PER_STREAM: each recording is
+ * launched on its sequence's own stream, all before the first wait. A
+ * sequence whose recorded CG solve stops short runs its step again alone, as
+ * npg_step_graph does. Results are bitwise those of npg_batch_step (either
+ * mode); status and loss_dev as there. Synchronizes.
+ */
+enum { NPG_BATCH_ONE_GRAPH = 0, NPG_BATCH_GRAPH_PER_STREAM = 1 };
+npg_status npg_batch_step_graph(npg_batch* batch, int32_t epoch, int32_t n_epochs, double* const* loss_dev);
+npg_status npg_batch_graph_mode(npg_batch* batch, int32_t mode);
+
 npg_status npg_batch_destroy(npg_batch* batch);
 
 /* ---- stage entry points (stateless with respect to parameters) ---------- */

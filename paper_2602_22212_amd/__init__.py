@@ -77,6 +77,8 @@ _SIGS = {
                                  ctypes.POINTER(ctypes.POINTER(_I64)), ctypes.POINTER(_P)], ctypes.c_int),
     "npg_batch_plan": ([_P, _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "npg_batch_step": ([_P, _I32, _I32, ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_batch_step_graph": ([_P, _I32, _I32, ctypes.POINTER(_P)], ctypes.c_int),
+    "npg_batch_graph_mode": ([_P, _I32], ctypes.c_int),
     "npg_batch_destroy": ([_P], ctypes.c_int),
     "npg_metrics": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
     "npg_metrics_noalloc": ([_P, _P, _P, _P, _P, ctypes.c_float, _P], ctypes.c_int),
@@ -518,6 +520,23 @@ class Batch:
             arr = (_P * len(self.plans))(*[None if l is None else _ptr(l, torch.float64, 1, "loss").value
                                           for l in losses])
         st = lib().npg_batch_step(self._h, int(epoch), int(n_epochs), arr)
+        if st == NPG_ENOTCONV:
+            return st
+        return _check(st)
+
+    def graph_mode(self, per_stream):
+        """npg_batch_graph_mode: False = one batch graph, True = each
+        sequence's recording on its own stream."""
+        _check(lib().npg_batch_graph_mode(self._h, 1 if per_stream else 0))
+
+    def step_graph(self, epoch, n_epochs, losses=None):
+        """The batch step replayed from recorded HIP graphs (npg_batch_step_graph)."""
+        import torch
+        arr = None
+        if losses is not None:
+            arr = (_P * len(self.plans))(*[None if l is None else _ptr(l, torch.float64, 1, "loss").value
+                                          for l in losses])
+        st = lib().npg_batch_step_graph(self._h, int(epoch), int(n_epochs), arr)
         if st == NPG_ENOTCONV:
             return st
         return _check(st)

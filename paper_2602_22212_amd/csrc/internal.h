@@ -145,6 +145,7 @@ struct npg_plan {
   hipStream_t cap_stream = nullptr;
   unsigned char* scratch = nullptr;  // this device's copy of the library's fixed scratch array
   int graph_iters[2] = {0, 0};       // CG form: iterations recorded for each solve
+  int64_t graph_gen = 0;             // incremented by every recording (batch graphs compare it)
   int prof_n;                       // events recorded in the current step
   double prof_cg_ms;                // accumulated kernel time of resolved steps
   int64_t prof_cg_launches;         // accumulated CG iterations (kernel pairs)
@@ -221,6 +222,13 @@ hipError_t npg_launch_scaled_copy(const npg_plan* P, const double* w, const doub
 npg_status npg_run_precond_dct(npg_plan* P, float* grad);
 // plan.hip: drop the captured step (after a change that alters its launches)
 void npg_graph_reset(npg_plan* P);
+// plan.hip: pieces of the graph-replayed step (npg_step_graph, batch graph)
+npg_status npg_graph_prepare(npg_plan* P);
+npg_status npg_graph_set_scalars(npg_plan* P, int epoch, int n_epochs, hipStream_t s);
+npg_status npg_graph_read(npg_plan* P, hipStream_t s, NpgStepScal* sc, int* flag);
+bool npg_graph_redo(npg_plan* P, const NpgStepScal& sc);
+npg_status npg_graph_finish(npg_plan* P, const NpgStepScal& sc, int flag, double* loss_out, double* cd_out,
+                            hipStream_t s);
 // adam.hip
 // sc: NULL, or the step scalars in device memory (then the bias corrections
 // are read there and k is not used)

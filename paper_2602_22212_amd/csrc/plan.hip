@@ -168,10 +168,85 @@ npg_status capture_step(npg_plan* P) {
   }
   NPG_HIP(e);
   P->graph = g;
+  P->graph_gen += 1;
   NPG_HIP(hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0));
   return NPG_OK;
 }
 }  // namespace
+
+// ---- the graph-replayed step (npg_step_graph, npg_batch_step_graph) -------
+// Iteration counts of the CG form's recorded solves: what the last
+// preconditioning took plus 2 (16 without one), recorded again when that
+// leaves more than 6 idle; then the graph is recorded if there is none.
+npg_status npg_graph_prepare(npg_plan* P) {
+  if (P->cfg.precond == NPG_PRECOND_CG) {
+    const int maxit = P->cfg.cg_maxit;
+    for (int w = 0; w < 2; ++w) {
+      const int last = P->cg.last_iters[w];
+      const int want = std::min(maxit, last > 0 ? last + 2 : 16);
+      if (P->graph_iters[w] == 0 || (last > 0 && P->graph_iters[w] > last + 6)) {
+        if (P->graph_iters[w] != want) npg_graph_reset(P);
+        P->graph_iters[w] = want;
+      }
+    }
+  }
+  if (!P->graph_exec) {
+    const npg_status st = capture_step(P);
+    if (st != NPG_OK) {
+      npg_graph_reset(P);
+      return st;
+    }
+  }
+  return NPG_OK;
+}
+
+// The scalars of the next step (Adam step adam_k + 1) on stream s.
+npg_status npg_graph_set_scalars(npg_plan* P, int epoch, int n_epochs, hipStream_t s) {
+  float ib1 = 1.f, ib2 = 1.f;
+  npg_adam_scalars(P, P->adam_k + 1, &ib1, &ib2);
+  hipLaunchKernelGGL(k_set_step_scal, dim3(1), dim3(64), 0, s, P->d_scal, npg_loss_delta(epoch, n_epochs), ib1, ib2);
+  NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
+
+// Enqueue the reads of the replay's outcome (step scalars, non-finite flag).
+npg_status npg_graph_read(npg_plan* P, hipStream_t s, NpgStepScal* sc, int* flag) {
+  NPG_HIP(hipMemcpyAsync(sc, P->d_scal, sizeof(NpgStepScal), hipMemcpyDeviceToHost, s));
+  NPG_HIP(hipMemcpyAsync(flag, P->d_flag, 4, hipMemcpyDeviceToHost, s));
+  return NPG_OK;
+}
+
+// After a replay: true when a recorded solve stopped short (Adam left the
+// state untouched); the next npg_graph_prepare records twice the iterations
+// of that solve (at most cg_maxit) and the step is to be run again.
+bool npg_graph_redo(npg_plan* P, const NpgStepScal& sc) {
+  if (!(sc.cg_state & 3)) return false;
+  for (int w = 0; w < 2; ++w)
+    if (sc.cg_state & (1 << w)) P->graph_iters[w] = std::min(P->cfg.cg_maxit, 2 * P->graph_iters[w]);
+  npg_graph_reset(P);
+  return true;
+}
+
+// After a completed replay: the step count, the CG bookkeeping, the outputs
+// and the status (synchronizes s).
+npg_status npg_graph_finish(npg_plan* P, const NpgStepScal& sc, int flag, double* loss_out, double* cd_out,
+                            hipStream_t s) {
+  P->adam_k += 1;  // the update has been applied
+  if (P->cfg.precond == NPG_PRECOND_CG) {
+    const npg_status st = npg_cg_report(P, nullptr);
+    if (st != NPG_OK) return st;
+  }
+  if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
+  if (cd_out) NPG_HIP(hipMemcpyAsync(cd_out, P->cd, 8 * (size_t)P->T, hipMemcpyDeviceToDevice, s));
+  NPG_HIP(hipStreamSynchronize(s));
+  if (flag) {
+    NPG_HIP(hipMemsetAsync(P->d_flag, 0, 4, s));
+    NPG_HIP(hipStreamSynchronize(s));
+    return npg_fail(NPG_ENONFINITE, "a non-finite value was produced during the step");
+  }
+  if (sc.cg_state & 4) return npg_fail(NPG_ENOTCONV, "a CG solve reached cg_maxit");
+  return NPG_OK;
+}
 
 extern "C" {
 
@@ -555,64 +630,19 @@ npg_status npg_step_graph(npg_plan* P, int32_t epoch, int32_t n_epochs, double* 
   CHECK_ARG(P, "plan is NULL");
   CHECK_ARG(n_epochs >= 1 && epoch >= 0 && epoch <= n_epochs, "need 0 <= epoch <= n_epochs, n_epochs >= 1");
   CHECK_ARG(P->cfg.w_iso == 0.f || P->n_edges > 0, "w_iso > 0 needs the mesh edges (npg_plan_set_edges)");
-  const bool cg = P->cfg.precond == NPG_PRECOND_CG;
-  const int maxit = P->cfg.cg_maxit;
-  if (cg) {
-    // iterations recorded per solve: what the last preconditioning took plus
-    // 2 (16 without one); recorded again when that leaves more than 6 idle
-    for (int w = 0; w < 2; ++w) {
-      const int last = P->cg.last_iters[w];
-      const int want = std::min(maxit, last > 0 ? last + 2 : 16);
-      if (P->graph_iters[w] == 0 || (last > 0 && P->graph_iters[w] > last + 6)) {
-        if (P->graph_iters[w] != want) npg_graph_reset(P);
-        P->graph_iters[w] = want;
-      }
-    }
-  }
   hipStream_t s = P->stream;
-  const int64_t k = P->adam_k + 1;
-  float ib1 = 1.f, ib2 = 1.f;
-  npg_adam_scalars(P, k, &ib1, &ib2);
   NpgStepScal sc_h{};
   int flag = 0;
   for (;;) {
-    if (!P->graph_exec) {
-      const npg_status st = capture_step(P);
-      if (st != NPG_OK) {
-        npg_graph_reset(P);
-        return st;
-      }
-    }
-    hipLaunchKernelGGL(k_set_step_scal, dim3(1), dim3(64), 0, s, P->d_scal, npg_loss_delta(epoch, n_epochs), ib1,
-                       ib2);
-    NPG_HIP(hipGetLastError());
+    TRY(npg_graph_prepare(P));
+    TRY(npg_graph_set_scalars(P, epoch, n_epochs, s));
     NPG_HIP(hipGraphLaunch(P->graph_exec, s));
-    NPG_HIP(hipMemcpyAsync(&sc_h, P->d_scal, sizeof(NpgStepScal), hipMemcpyDeviceToHost, s));
-    NPG_HIP(hipMemcpyAsync(&flag, P->d_flag, 4, hipMemcpyDeviceToHost, s));
+    TRY(npg_graph_read(P, s, &sc_h, &flag));
     NPG_HIP(hipStreamSynchronize(s));
-    if (!(sc_h.cg_state & 3)) break;
-    // a solve had not converged within its recorded iterations: Adam left the
-    // state untouched; record more iterations (up to cg_maxit) and redo the step
-    for (int w = 0; w < 2; ++w)
-      if (sc_h.cg_state & (1 << w)) P->graph_iters[w] = std::min(maxit, 2 * P->graph_iters[w]);
-    npg_graph_reset(P);
+    if (!npg_graph_redo(P, sc_h)) break;
     if (flag) NPG_HIP(hipMemsetAsync(P->d_flag, 0, 4, s));
   }
-  P->adam_k = k;  // the update has been applied
-  if (cg) {
-    const npg_status st = npg_cg_report(P, nullptr);
-    if (st != NPG_OK) return st;
-  }
-  if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
-  if (cd_out) NPG_HIP(hipMemcpyAsync(cd_out, P->cd, 8 * (size_t)P->T, hipMemcpyDeviceToDevice, s));
-  NPG_HIP(hipStreamSynchronize(s));
-  if (flag) {
-    NPG_HIP(hipMemsetAsync(P->d_flag, 0, 4, s));
-    NPG_HIP(hipStreamSynchronize(s));
-    return npg_fail(NPG_ENONFINITE, "a non-finite value was produced during the step");
-  }
-  if (sc_h.cg_state & 4) return npg_fail(NPG_ENOTCONV, "a CG solve reached cg_maxit");
-  return NPG_OK;
+  return npg_graph_finish(P, sc_h, flag, loss_out, cd_out, s);
 }
 
 npg_status npg_profile(npg_plan* P, int32_t enable) {

@@ -53,6 +53,40 @@ def test_batch_step_equals_individual_plans():
     batch.close()
 
 
+@pytest.mark.parametrize("per_stream", [False, True])
+def test_batch_graph_step_equals_eager_batch_step(per_stream):
+    """npg_batch_step_graph (one HIP graph, the sequences' recorded steps as
+    branches) against npg_batch_step, bitwise, step after step; a new launch
+    shape of one sequence (autotuner) makes the next call rebuild the batch
+    graph."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfgs, datas = _small_batch()
+    states = [flat_params(c, synth.random_state(c, 60 + k, grid_std=0.05)) for k, c in enumerate(cfgs)]
+    eager, graph = npg.Batch(cfgs, datas), npg.Batch(cfgs, datas)
+    graph.graph_mode(per_stream)
+    for b in (eager, graph):
+        for p, s in zip(b.plans, states):
+            p.set_state(s, adam_steps=0)
+    le = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in cfgs]
+    lg = [torch.empty(1, dtype=torch.float64, device="cuda") for _ in cfgs]
+    for e in range(5):
+        if e == 3:
+            for b in (eager, graph):
+                b.plans[1].tune_nn(64)
+        assert eager.step(e, 10, le) == npg.NPG_OK
+        assert graph.step_graph(e, 10, lg) == npg.NPG_OK
+        for k in range(len(cfgs)):
+            assert to_np(le[k]).tobytes() == to_np(lg[k]).tobytes(), (e, k)
+            sa, sb = eager.plans[k].get_state(), graph.plans[k].get_state()
+            assert sa[3] == sb[3] == e + 1
+            for x, y in zip(sa[:3], sb[:3]):
+                assert torch.equal(x, y), (e, k)
+    eager.close()
+    graph.close()
+
+
 def test_batch_sequence_matches_the_oracle_step():
     import torch
 
