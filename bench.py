@@ -244,7 +244,11 @@ def run_form(cfg, data, P0, steps, warmup, profile, graph=False):
     import paper_2602_22212_amd as npg
     plan = npg.plan_from_workload(cfg, data)
     plan.set_state(torch.from_numpy(npg.pack_params(cfg, P0)).cuda(), adam_steps=0)
-    nn_threads, nn_ms = plan.tune_nn(0)  # autotuned nearest-neighbour work-group size
+    # autotuned launch shapes: nearest-neighbour work-group size, decode
+    # backward frame chunks, CG tile depth
+    nn_threads, nn_ms = plan.tune_nn(0)
+    mlp_chunks, mlp_cand, mlp_ms = plan.tune_mlp(0)
+    cg_zs, cg_ms = plan.tune_cg(0) if cfg.get("precond", "cg") == "cg" else (None, None)
     E = cfg["n_steps"]
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     step = plan.step_graph if graph else plan.step
@@ -279,7 +283,10 @@ def run_form(cfg, data, P0, steps, warmup, profile, graph=False):
                           "min": round(float(ev_ms.min()), 4)},
                 stage_ms=None if graph else {k: round(v / steps, 3) for k, v in stage_sum.items()},
                 status=sorted(set(int(s) for s in statuses)), prof=prof, loss=loss.item(),
-                nn_tune={"threads": nn_threads, "ms_64_128_256": [round(m, 3) for m in nn_ms]},
+                nn_tune={"threads": nn_threads, "ms_64_128_256": [round(m, 3) for m in nn_ms],
+                         "mlp_frame_chunks": mlp_chunks,
+                         "mlp_ms": {str(c): round(m, 3) for c, m in zip(mlp_cand, mlp_ms) if c},
+                         "cg_tile_z": cg_zs, "cg_ms_32_64_128": None if cg_ms is None else [round(m, 3) for m in cg_ms]},
                 cg_relres_max=None if relres is None else max(relres))
 
 
@@ -404,7 +411,7 @@ def _batch_time(cfgs, datas, steps, warmup, state, graph=False, per_stream=True)
     for k, (c, p) in enumerate(zip(cfgs, batch.plans)):
         P = synth.random_state(c, 900 + k, grid_std=0.05) if state == "random" else synth.init_params(c)
         p.set_state(torch.from_numpy(npg.pack_params(c, P)).cuda(), adam_steps=0)
-        tuned.append(p.tune_nn(0)[0])
+        tuned.append((p.tune_nn(0)[0], p.tune_mlp(0)[0], p.tune_cg(0)[0] if c.get("precond", "cg") == "cg" else None))
     if graph:
         batch.graph_mode(per_stream)
     step = batch.step_graph if graph else batch.step
@@ -484,7 +491,7 @@ def run_batch(steps=3, warmup=2, quality_steps=20):
                         "bf16_final_cd_mean": float(np.mean(b["final"])), "fp32_final_cd_mean": float(np.mean(f["final"])),
                         "mean_ratio_bf16_over_fp32_final_cd": round(ratio, 5),
                         "note": "mean per-frame Chamfer distance of each sequence after the last step, averaged"},
-            "nn_autotune_threads": res["bf16"]["tuned"],
+            "autotuned_nn_threads_mlp_chunks_cg_tile_z": res["bf16"]["tuned"],
             "step_status": {"bf16": res["bf16"]["status"], "fp32": res["fp32"]["status"]},
             "sequences": len(cfgs), "steps": steps, "warmup": warmup,
             "samples_per_step": samples, "chamfer_pairs_per_direction": pairs,

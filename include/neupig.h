@@ -461,6 +461,37 @@ npg_status npg_iso(npg_plan* plan, const float* xhat_dev, float* gxhat_dev, doub
 npg_status npg_tune_nn(npg_plan* plan, int32_t threads, int32_t* chosen_host, float* ms_host);
 
 /*
+ * Autotuner of the decode backward's schedule: its work items are 64-vertex
+ * blocks times nch frame chunks, dealt to min(items, CUs) persistent
+ * work-groups. nch = 0 times up to 4 candidates (the load-balancing default
+ * h, h/2, 2h and 4h within [n_min, T]; n_min = ceil(T/16) in the BF16 form,
+ * else 1) on the plan's current parameters (one warm-up and two timed calls
+ * each) and keeps the fastest; nch > 0 sets it without timing. cand_host [4]
+ * and ms_host [4] (may be NULL) receive the candidates (0: unused slot) and
+ * their milliseconds per call; chosen_host [1] (may be NULL) the count in use.
+ * The chunk count fixes the grouping of the float32 per-chunk sums of the
+ * first-layer gradient: results are deterministic for a given count and agree
+ * within float32 rounding between counts (not bitwise). Grows workspace when
+ * needed; synchronizes. NPG_EINVAL for a count outside [n_min, T].
+ */
+npg_status npg_tune_mlp(npg_plan* plan, int32_t nch, int32_t* chosen_host, int32_t* cand_host, float* ms_host);
+
+/*
+ * Autotuner of the CG preconditioner's work-group tiles on grids with
+ * R >= 100 (F = 4): z planes per 64 x 4-column tile, 32, 64 (the default) or
+ * 128. zs = 0 times four iterations of both solves per candidate on a fixed
+ * non-zero right-hand side in the plan's gradient buffer (workspace between
+ * steps; parameters and Adam state untouched) and keeps the fastest; zs > 0
+ * sets it without timing. ms_host [3] (may be NULL): milliseconds per timed
+ * call for 32, 64, 128 (0 when not timed). The tiles fix the grouping of the
+ * float64 inner-product partial sums: results are deterministic for a given
+ * choice and agree within the solver tolerance between choices (not bitwise).
+ * Rebuilds the CG workspace; synchronizes. NPG_EINVAL for other values or the
+ * DCT form.
+ */
+npg_status npg_tune_cg(npg_plan* plan, int32_t zs, int32_t* chosen_host, float* ms_host);
+
+/*
  * Chain rule for reverse-mode callers (torch.autograd Functions built on the
  * stage entry points above): x_dev[k] *= c * s_dev[0] for 0 <= k < n, the
  * factor formed in float64 on the device (s_dev: one float64, typically the

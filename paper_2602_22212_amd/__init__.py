@@ -86,6 +86,9 @@ _SIGS = {
     "npg_objective_bwd": ([_P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "npg_scale": ([_P, _P, _D, _P, _I32, _I64], ctypes.c_int),
     "npg_tune_nn": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "npg_tune_mlp": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)],
+                     ctypes.c_int),
+    "npg_tune_cg": ([_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
     "npg_precond_residuals": ([_P, ctypes.POINTER(_D)], ctypes.c_int),
     "npg_params_import": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
     "npg_params_export": ([_P, ctypes.POINTER(_P)], ctypes.c_int),
@@ -458,6 +461,23 @@ class Plan:
         ch = _I32()
         ms = (ctypes.c_float * 3)()
         _check(lib().npg_tune_nn(self._h, int(threads), ctypes.byref(ch), ms))
+        return ch.value, list(ms)
+
+    def tune_mlp(self, nch=0):
+        """Frame chunks of the decode backward: 0 = time the candidates and
+        keep the fastest. Returns (chosen, candidates [4], ms [4])."""
+        ch = _I32()
+        cand = (_I32 * 4)()
+        ms = (ctypes.c_float * 4)()
+        _check(lib().npg_tune_mlp(self._h, int(nch), ctypes.byref(ch), cand, ms))
+        return ch.value, list(cand), list(ms)
+
+    def tune_cg(self, zs=0):
+        """z planes per CG tile (32/64/128): 0 = time them and keep the
+        fastest. Returns (chosen, ms [3])."""
+        ch = _I32()
+        ms = (ctypes.c_float * 3)()
+        _check(lib().npg_tune_cg(self._h, int(zs), ctypes.byref(ch), ms))
         return ch.value, list(ms)
 
     def scale(self, s, x, c=1.0):

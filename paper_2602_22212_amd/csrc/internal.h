@@ -117,6 +117,8 @@ struct npg_plan {
   // mlp_nch frame chunks, items dealt round-robin to mlp_grid persistent
   // work-groups; per-chunk vertex sums in Gv_part
   int mlp_nch, mlp_grid;
+  int mlp_nch_alloc = 0, mlp_grid_alloc = 0;  // capacity of Gv_part (chunks) and gW_part (work-groups)
+  int cg_zs = 64;          // z planes per work-group tile of the CG kernels on large grids (npg_tune_cg)
   double cg_relres[2 * NPG_MAX_SYS];  // last preconditioning: final ||r||/||b|| per grid, both solves
   float* Gv_part;          // [mlp_nch][V][W] (NULL when mlp_nch == 1)
   float* fl_part;          // [ceil(V/64)][W][8] first-layer partial sums

@@ -120,6 +120,12 @@ void npg_graph_reset(npg_plan* P) {
 }
 
 namespace {
+// a deterministic non-zero vector (autotuner input)
+__global__ void k_fill_pattern(float* __restrict__ x, int64_t n) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) x[e] = (float)((e * 2654435761u) % 2048u) * (1.0f / 1024.0f) - 1.0f;
+}
+
 __global__ void k_set_step_scal(NpgStepScal* __restrict__ sc, double delta, float inv_bc1, float inv_sqrt_bc2) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->delta = delta;
@@ -245,6 +251,47 @@ npg_status npg_graph_finish(npg_plan* P, const NpgStepScal& sc, int flag, double
     return npg_fail(NPG_ENONFINITE, "a non-finite value was produced during the step");
   }
   if (sc.cg_state & 4) return npg_fail(NPG_ENOTCONV, "a CG solve reached cg_maxit");
+  return NPG_OK;
+}
+
+// Frame chunks of the MLP backward: the decode backward's work items are
+// 64-vertex blocks x nch frame chunks on min(items, n_cu) persistent
+// work-groups; grows the per-chunk and per-work-group partial buffers when
+// needed (synchronizes).
+static npg_status set_mlp_chunks(npg_plan* P, int nch) {
+  const int64_t nb = (P->V + 63) / 64;
+  const int grid = (int)std::min<int64_t>(nb * nch, P->n_cu);
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  if (nch > 1 && nch > P->mlp_nch_alloc) {
+    if (P->Gv_part) NPG_HIP(hipFree(P->Gv_part));
+    P->Gv_part = nullptr;
+    P->mlp_nch_alloc = 0;
+    NPG_HIP(hipMalloc(&P->Gv_part, (size_t)nch * P->V * P->W * 4));
+    P->mlp_nch_alloc = nch;
+  }
+  if (grid > P->mlp_grid_alloc) {
+    NPG_HIP(hipFree(P->gW_part));
+    P->gW_part = nullptr;
+    P->mlp_grid_alloc = 0;
+    NPG_HIP(hipMalloc(&P->gW_part, (size_t)grid * P->gw_part_len * 4));
+    P->mlp_grid_alloc = grid;
+  }
+  P->mlp_nch = nch;
+  P->mlp_grid = grid;
+  return NPG_OK;
+}
+
+// Milliseconds per call of `run` (one warm-up, two timed calls, HIP events
+// on the plan's stream).
+template <typename F>
+static npg_status time_calls(npg_plan* P, F run, float* ms) {
+  TRY(run());
+  NPG_HIP(hipEventRecord(P->ev[0], P->stream));
+  for (int r = 0; r < 2; ++r) TRY(run());
+  NPG_HIP(hipEventRecord(P->ev[1], P->stream));
+  NPG_HIP(hipEventSynchronize(P->ev[1]));
+  NPG_HIP(hipEventElapsedTime(ms, P->ev[0], P->ev[1]));
+  *ms *= 0.5f;
   return NPG_OK;
 }
 
@@ -441,6 +488,8 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   }
   if (P->mlp_nch > 1) TRYP(dalloc(&P->Gv_part, (int64_t)P->mlp_nch * V * P->W));
   TRYP(dalloc(&P->gW_part, (int64_t)P->mlp_grid * P->gw_part_len));
+  P->mlp_nch_alloc = P->mlp_nch > 1 ? P->mlp_nch : 0;
+  P->mlp_grid_alloc = P->mlp_grid;
   TRYP(dalloc(&P->fl_part, npg_first_layer_blocks(V) * P->W * 8));
   if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
   else TRYP(npg_cg_setup(P));
@@ -824,6 +873,98 @@ npg_status npg_tune_nn(npg_plan* P, int32_t threads, int32_t* chosen, float* ms)
     set(best_kt);
   }
   if (chosen) *chosen = P->nn_threads;
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  return NPG_OK;
+}
+
+npg_status npg_tune_mlp(npg_plan* P, int32_t nch, int32_t* chosen, int32_t* cand, float* ms) {
+  CHECK_ARG(P, "plan is NULL");
+  const int tc = P->cfg.precision == NPG_PREC_BF16 ? npg_mlp_bf16_frames() : 0;
+  const int n_min = tc > 0 ? (P->T + tc - 1) / tc : 1;
+  CHECK_ARG(nch == 0 || (nch >= n_min && nch <= P->T),
+            "nch must be 0 or a chunk count in [" + std::to_string(n_min) + ", T]");
+  npg_graph_reset(P);  // a captured step holds the old launch shape
+  for (int k = 0; k < 4; ++k) {
+    if (cand) cand[k] = 0;
+    if (ms) ms[k] = 0.f;
+  }
+  if (nch != 0) {
+    TRY(set_mlp_chunks(P, nch));
+  } else {
+    int nvb = 0, h = 1, g = 0;
+    npg_mlp_schedule(P->V, P->T, P->n_cu, tc, &nvb, &h, &g);
+    std::vector<int> c = {h};
+    for (int n : {std::max(n_min, h / 2), std::min(P->T, 2 * h), std::min(P->T, 4 * h)})
+      if (std::find(c.begin(), c.end(), n) == c.end()) c.push_back(n);
+    // the plan's current decoder input and deformed vertices (the latter as
+    // the upstream gradient: finite values of the right shape)
+    NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
+    NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+    float best = 0.f;
+    int best_n = h;
+    for (size_t k = 0; k < c.size(); ++k) {
+      TRY(set_mlp_chunks(P, c[k]));
+      float t = 0.f;
+      TRY(time_calls(
+          P,
+          [&]() -> npg_status {
+            NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->xhat, P->grad, P->gz));
+            return NPG_OK;
+          },
+          &t));
+      if (cand) cand[k] = c[k];
+      if (ms) ms[k] = t;
+      if (k == 0 || t < best) {
+        best = t;
+        best_n = c[k];
+      }
+    }
+    TRY(set_mlp_chunks(P, best_n));
+  }
+  if (chosen) *chosen = P->mlp_nch;
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  return NPG_OK;
+}
+
+npg_status npg_tune_cg(npg_plan* P, int32_t zs, int32_t* chosen, float* ms) {
+  CHECK_ARG(P, "plan is NULL");
+  CHECK_ARG(zs == 0 || zs == 32 || zs == 64 || zs == 128, "zs must be 0, 32, 64 or 128");
+  CHECK_ARG(P->cfg.precond == NPG_PRECOND_CG, "npg_tune_cg needs the CG preconditioner");
+  npg_graph_reset(P);  // a captured step holds the old work-group table
+  if (ms)
+    for (int k = 0; k < 3; ++k) ms[k] = 0.f;
+  auto set = [&](int z) -> npg_status {
+    NPG_HIP(hipStreamSynchronize(P->stream));
+    npg_cg_free(P);
+    P->cg_zs = z;
+    return npg_cg_setup(P);
+  };
+  if (zs != 0) {
+    TRY(set(zs));
+  } else {
+    if (!P->d_scal) NPG_HIP(hipMalloc(&P->d_scal, sizeof(NpgStepScal)));
+    const int cand[3] = {32, 64, 128};
+    const int iters[2] = {4, 4};
+    float best = 0.f;
+    int best_z = 64;
+    for (int k = 0; k < 3; ++k) {
+      TRY(set(cand[k]));
+      // a fixed number of iterations of both solves on a non-zero right-hand
+      // side (the gradient buffer is workspace between steps)
+      hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)((P->n_grid_params + 255) / 256)), dim3(256), 0,
+                         P->stream, P->grad, P->n_grid_params);
+      NPG_HIP(hipGetLastError());
+      float t = 0.f;
+      TRY(time_calls(P, [&] { return npg_run_precond_cg_fixed(P, P->grad, iters, &P->d_scal->cg_state); }, &t));
+      if (ms) ms[k] = t;
+      if (k == 0 || t < best) {
+        best = t;
+        best_z = cand[k];
+      }
+    }
+    TRY(set(best_z));
+  }
+  if (chosen) *chosen = P->cg_zs;
   NPG_HIP(hipStreamSynchronize(P->stream));
   return NPG_OK;
 }

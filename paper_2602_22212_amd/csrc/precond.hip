@@ -297,7 +297,7 @@ __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
 // Missing neighbours (grid boundary) and lanes/rows past the grid edge are
 // clamped to the nearest node inside, whose difference then contributes 0.
 constexpr int kZmR = 100;  // grids with R >= kZmR, F = 4 and 16-byte alignment
-constexpr int kTX = 64, kTY = 4, kZS = 64;
+constexpr int kTX = 64, kTY = 4;  // tile columns; the z planes per tile are the plan's cg_zs (even)
 static_assert(kTX * kTY == kB, "one wave per tile row");
 
 __device__ __forceinline__ bool use_zm(const NpgGrid& g) { return g.R >= kZmR && g.F == 4 && (g.poff % 4) == 0; }
@@ -1481,11 +1481,11 @@ npg_status npg_cg_setup(npg_plan* P) {
     if (g.R >= kZmR && g.F == 4 && g.poff % 4 == 0) {
       // z-marching tiles, z ranges interleaved so concurrently running
       // work-groups share planes
-      for (int z0 = 0; z0 < g.R; z0 += kZS)
+      for (int z0 = 0; z0 < g.R; z0 += P->cg_zs)
         for (int y0 = 0; y0 < g.R; y0 += kTY)
           for (int x0 = 0; x0 < g.R; x0 += kTX) {
             bsys.push_back(s);
-            bstart.push_back(pack_tile(x0, y0, z0, std::min(g.R, z0 + kZS)));
+            bstart.push_back(pack_tile(x0, y0, z0, std::min(g.R, z0 + P->cg_zs)));
           }
     } else {
       for (int64_t n = 0; n < g.nodes; n += kChunk) {
@@ -1524,6 +1524,10 @@ void npg_cg_free(npg_plan* P) {
                   C.z, C.mgB, C.mgX, C.part2, C.mg_tasks};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  const int keep[2] = {C.last_iters[0], C.last_iters[1]};
+  C = NpgCG();
+  C.last_iters[0] = keep[0];
+  C.last_iters[1] = keep[1];
 }
 
 // ---- the two solves ------------------------------------------------------------
