@@ -788,13 +788,20 @@ __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restr
 // Laplacian": mass = ex ey ez, the weight of a face = its area in fine nodes
 // (ey ez across x, ...). One V-cycle (preconditioner input b, output x):
 // x0 = w D^-1 b; restrict b - A x0 to the next level; recurse; x = x0 + P e;
-// x += w D^-1 (b - A x). The coarsest level (n <= 8) takes kMgCoarse damped
-// Jacobi sweeps from zero. Smoothing before and after is the same symmetric
-// Jacobi step and the restriction is P^T, so the preconditioner is symmetric
-// and positive definite (w < 1 < 2 / rho(D^-1 A)).
+// x += w D^-1 (b - A x). A system coarsens until a level has at most kMgMinN
+// nodes per axis or it has kMgMaxLev coarse levels; its coarsest level takes
+// the same two damped Jacobi steps from zero with no coarser correction
+// (x0 = w D^-1 b, x = x0 + w D^-1 (b - A x0)). The mass term of a level grows
+// 8x per level and its Laplacian weights 4x, so D^-1 A is close to the
+// identity three levels down (lam / 8 at most 0.85 at the headline's 6.83):
+// two sweeps there give the iteration counts of a hierarchy down to 8^3 with
+// four sweeps at its bottom, in four fewer launches per cycle. Smoothing before
+// and after is the same symmetric Jacobi step and the restriction is P^T, so
+// the preconditioner is symmetric and positive definite
+// (w < 1 < 2 / rho(D^-1 A)).
 constexpr float kMgOmega = kMgOmegaW;
-constexpr int kMgCoarse = 4;
 constexpr int kMgMinN = 8;
+constexpr int kMgMaxLev = 3;
 constexpr int kMgB = 256;
 
 struct MgLvl {
@@ -980,10 +987,11 @@ __device__ __forceinline__ void mg_up_u4(const MgTask* tk, const float* __restri
   const int nb2[12] = {j, j, j, j, jm, jp, j, j, jm, jp, j, j};
   const int nc2[12] = {k, k, k, k, k, k, km, kp, k, k, km, kp};
   float4 vb[12], ve[12];
+  const bool has_e = nh > 0;  // false on a coarsest level: no coarser correction
 #pragma unroll
   for (int q = 0; q < 12; ++q) {
     vb[q] = B[(nc2[q] * R + nb2[q]) * R + na[q]];
-    ve[q] = E[((nc2[q] >> 1) * nh + (nb2[q] >> 1)) * nh + (na[q] >> 1)];
+    ve[q] = has_e ? E[((nc2[q] >> 1) * nh + (nb2[q] >> 1)) * nh + (na[q] >> 1)] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
   float4 xv[12];
 #pragma unroll
@@ -1106,6 +1114,7 @@ __device__ __forceinline__ void mg_up_node(const MgTask* tk, const float* __rest
   const MgNode nd = mg_node(i, j, k, lo);
   auto xat = [&](int a, int b2, int c2, float (&x)[4]) {
     mg_x0(bl, lo, a, b2, c2, x);
+    if (hi.n == 0) return;  // a coarsest level: no coarser correction
     float e[4];
     mg_load(eh + hi.off + mg_idx(a >> 1, b2 >> 1, c2 >> 1, hi.n) * hi.F, hi.F, e);
 #pragma unroll
@@ -1272,57 +1281,6 @@ __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, in
   store_partials<4>(acc, part, blk);
 }
 
-// Coarsest level of every system (n <= 8): one work-group per system, damped
-// Jacobi sweeps from zero in LDS.
-constexpr int kMgCN = 512 * 4;
-__global__ __launch_bounds__(512) void k_mg_coarse(const MgTask* __restrict__ T, const int* __restrict__ active,
-                                                   int check_active, const float* __restrict__ b,
-                                                   float* __restrict__ x) {
-  const MgTask task = T[blockIdx.x];
-  if (check_active && !active[task.sys]) return;
-  const MgLvl& L = task.lo;
-  __shared__ float sb[kMgCN], sx[2][kMgCN];
-  const int nodes = L.n * L.n * L.n;
-  const int m = threadIdx.x;
-  int i = 0, j = 0, k = 0;
-  MgNode nd{};
-  float f = 0.f;
-  if (m < nodes) {
-    i = m % L.n;
-    j = (m / L.n) % L.n;
-    k = m / (L.n * L.n);
-    nd = mg_node(i, j, k, L);
-    f = kMgOmega / nd.diag;
-    for (int c = 0; c < L.F; ++c) {
-      const float v = b[L.off + (int64_t)m * L.F + c];
-      sb[m * 4 + c] = v;
-      sx[0][m * 4 + c] = f * v;
-    }
-  }
-  __syncthreads();
-  const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
-  for (int it = 1; it < kMgCoarse; ++it) {
-    const float* xs = sx[(it - 1) & 1];
-    float* xd = sx[it & 1];
-    if (m < nodes) {
-      const float w[6] = {nd.wx, nd.wx, nd.wy, nd.wy, nd.wz, nd.wz};
-      for (int c = 0; c < L.F; ++c) {
-        const float xc = xs[m * 4 + c];
-        float ax = nd.mass * xc;
-        for (int d = 0; d < 6; ++d)
-          if (nd.mask & (1 << d)) {
-            const int mn = ((k + dk[d]) * L.n + (j + dj[d])) * L.n + (i + di[d]);
-            ax += L.lam * w[d] * (xc - xs[mn * 4 + c]);
-          }
-        xd[m * 4 + c] = xc + f * (sb[m * 4 + c] - ax);
-      }
-    }
-    __syncthreads();
-  }
-  if (m < nodes)
-    for (int c = 0; c < L.F; ++c) x[L.off + (int64_t)m * L.F + c] = sx[(kMgCoarse - 1) & 1][m * 4 + c];
-}
-
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 inline unsigned mg_grid(int nb) { return (unsigned)((nb + kXCD - 1) / kXCD * kXCD); }
 inline unsigned xcd_grid(int nb) { return (unsigned)((nb + kXCD * kXG - 1) / (kXCD * kXG) * (kXCD * kXG)); }
@@ -1331,10 +1289,11 @@ inline unsigned xcd_grid(int nb) { return (unsigned)((nb + kXCD * kXG - 1) / (kX
 
 // V-cycle hierarchy of every system and its launch table. Launch l (l = 0 ..
 // nlev-2) restricts level l to l+1, launch nlev-1+l prolongs level l+1 back
-// to l, launch 2(nlev-1) solves every system's coarsest level. A system has
-// at least two levels (the grid and one coarser) and coarsens until a level
-// has at most kMgMinN nodes per axis; it takes part in the launches of the
-// levels it has.
+// to l, launch 2(nlev-1) solves every system's coarsest level (the
+// prolongation kernel with no coarser level: hi.n = 0). A system has at least
+// two levels (the grid and one coarser) and coarsens until a level has at
+// most kMgMinN nodes per axis or kMgMaxLev coarse levels exist; it takes part
+// in the launches of the levels it has.
 static npg_status mg_setup(npg_plan* P) {
   NpgCG& C = P->cg;
   std::vector<std::vector<MgLvl>> lv(P->n_sys);
@@ -1354,7 +1313,7 @@ static npg_status mg_setup(npg_plan* P) {
       L.fn = make_fastdiv((uint32_t)L.n);
       L.fn2 = make_fastdiv((uint32_t)L.n * (uint32_t)L.n);
       lv[sy].push_back(L);
-      if (lv[sy].size() >= 2 && L.n <= kMgMinN) break;
+      if (lv[sy].size() >= 2 && (L.n <= kMgMinN || (int)lv[sy].size() > kMgMaxLev)) break;
       L.n = (L.n + 1) / 2;
       L.s *= 2;
       L.off = coarse;
@@ -1403,20 +1362,32 @@ static npg_status mg_setup(npg_plan* P) {
   };
   for (int l = 0; l + 1 < nlev; ++l) add_launch(l, l, false);
   for (int l = 0; l + 1 < nlev; ++l) add_launch(nlev - 1 + l, l, true);
-  {  // coarsest levels: one work-group per system
+  {  // coarsest levels: two Jacobi steps, the prolongation kernel without a coarser level
     const int li = 2 * (nlev - 1);
     C.mg_l_task0[li] = (int)tasks.size();
+    int blk = 0;
     for (int sy = 0; sy < P->n_sys; ++sy) {
       MgTask t{};
       t.sys = sy;
-      t.blk0 = sy;
+      t.blk0 = blk;
       t.lo = lv[sy].back();
+      t.hi = MgLvl{};  // n = 0: no coarser correction
       t.nodes = (int64_t)t.lo.n * t.lo.n * t.lo.n;
-      if (t.nodes * 4 > kMgCN || t.lo.F > 4) return npg_fail(NPG_EINVAL, "multigrid: coarsest level too large");
+      t.fast = t.lo.F == 4 && t.lo.off % 4 == 0 && t.lo.R % t.lo.s == 0;
+      if (t.fast) {
+        const float sz = (float)t.lo.s;
+        t.mass = sz * sz * sz;
+        t.lw = t.lo.lam * sz * sz;
+        const int nx = (t.lo.n + 1) / 2;
+        t.fx = make_fastdiv((uint32_t)nx);
+        t.fx2 = make_fastdiv((uint32_t)nx * (uint32_t)t.lo.n);
+        t.nodes = (int64_t)nx * t.lo.n * t.lo.n;
+      }
+      blk += (int)((t.nodes + kMgB - 1) / kMgB);
       tasks.push_back(t);
     }
     C.mg_l_ntask[li] = P->n_sys;
-    C.mg_l_nblk[li] = P->n_sys;
+    C.mg_l_nblk[li] = blk;
   }
   // the finest prolongation runs over the CG work-group table (its tasks are
   // looked up by system: every system takes part, in order)
@@ -1456,8 +1427,8 @@ static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_acti
       hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(C.mg_l_nblk[l])), dim3(kMgB), 0, s, T + C.mg_l_task0[l], blk0(l),
                          C.mg_l_nblk[l], C.active, check_active, l == 0 ? r : C.mgB, C.mgB);
   const int lc = 2 * (nl - 1);
-  hipLaunchKernelGGL(k_mg_coarse, dim3(C.mg_l_nblk[lc]), dim3(512), 0, s, T + C.mg_l_task0[lc], C.active,
-                     check_active, C.mgB, C.mgX);
+  hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[lc])), dim3(kMgB), 0, s, T + C.mg_l_task0[lc], blk0(lc),
+                     C.mg_l_nblk[lc], C.active, check_active, C.mgB, C.mgX, C.mgX);
   for (int l = nl - 2; l >= 1; --l) {
     const int li = nl - 1 + l;
     if (C.mg_l_nblk[li] > 0)
