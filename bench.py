@@ -65,6 +65,8 @@ def parse():
                          "animal (quadruped workload: 50000 vertices, 1000 frames, CG)")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the 100-step BF16/FP32 quality comparison (for counter runs)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes (no autotuner runs; for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="finish with one plain 1 GiB device copy (reference dispatch for HBM counters)")
     return ap.parse_args()
@@ -233,6 +235,9 @@ def stage_roofline(cfg, data, stage_ms, precision, prof=None):
     return out
 
 
+TUNE = True  # autotune the launch shapes of every benchmarked plan (bench.py --no-tune: defaults)
+
+
 def run_form(cfg, data, P0, steps, warmup, profile, graph=False):
     """Time `steps` full optimization steps of one form (graph: each step
     replayed as the captured HIP graph, npg_step_graph). Every step is
@@ -246,9 +251,10 @@ def run_form(cfg, data, P0, steps, warmup, profile, graph=False):
     plan.set_state(torch.from_numpy(npg.pack_params(cfg, P0)).cuda(), adam_steps=0)
     # autotuned launch shapes: nearest-neighbour work-group size, decode
     # backward frame chunks, CG tile depth
-    nn_threads, nn_ms = plan.tune_nn(0)
-    mlp_chunks, mlp_cand, mlp_ms = plan.tune_mlp(0)
-    cg_zs, cg_ms = plan.tune_cg(0) if cfg.get("precond", "cg") == "cg" else (None, None)
+    cgf = cfg.get("precond", "cg") == "cg"
+    nn_threads, nn_ms = plan.tune_nn(0 if TUNE else 128)
+    mlp_chunks, mlp_cand, mlp_ms = plan.tune_mlp(0) if TUNE else (None, [], [])
+    cg_zs, cg_ms = (plan.tune_cg(0) if TUNE else (64, None)) if cgf else (None, None)
     E = cfg["n_steps"]
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     step = plan.step_graph if graph else plan.step
@@ -520,6 +526,8 @@ def run_animal(steps=2, warmup=1):
 
 def main():
     args = parse()
+    global TUNE
+    TUNE = not args.no_tune
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the method is single-GPU; sharding is described, "
               f"not built): --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -573,13 +581,28 @@ def main():
     achieved = (prof["cg_bytes"] / 1e9) / (prof["cg_ms"] / 1e3) if prof["cg_ms"] > 0 else 0.0
     achieved_mg = (prof["cg_bytes_mg"] / 1e9) / (prof["cg_ms"] / 1e3) if prof["cg_ms"] > 0 else 0.0
     traffic = traffic_from_profile()
+    # algorithmic bytes of one iteration with every grid active (the unit the
+    # counter summary measures): 6 passes over the grid unknowns, and for the
+    # V-cycle form 8 passes plus 4 over every coarse level's unknowns (levels
+    # halve per axis, at most 3, down to 8 nodes per axis)
+    systems = [(R, cfg["feat_p"]) for R in cfg["levels"]] + [(cfg["res_n"], cfg["feat_n"])]
+    n_fine = sum(R ** 3 * F for R, F in systems)
+    n_coarse = 0
+    for R, F in systems:
+        n, lev = R, 0
+        while True:
+            n, lev = (n + 1) // 2, lev + 1
+            n_coarse += n ** 3 * F
+            if n <= 8 or lev >= 3:
+                break
+    full6, full_mg = 24.0 * n_fine, 32.0 * n_fine + 16.0 * n_coarse
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=traffic,
-                    traffic_unit=("HBM bytes per preconditioned CG iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                  "copy-calibrated)"),
-                    traffic_over_algorithmic=(None if traffic is None else round(
-                        traffic * n_it / max(prof["cg_bytes"], 1), 4)),
+                    traffic_unit=("HBM bytes per preconditioned CG iteration with every grid active (rocprofv3 "
+                                  "FETCH_SIZE + WRITE_SIZE, copy-calibrated)"),
+                    traffic_over_algorithmic=(None if traffic is None else round(traffic / full6, 4)),
+                    alg_bytes_full_iteration=full6,
                     kernel=("preconditioned CG iteration (k_cg_dir_ap, k_cg_reduce, k_cg_update, the V-cycle: "
                             "k_mg_down0, k_mg_down, k_mg_coarse, k_mg_up, k_mg_up0, and k_cg_reduce)"),
                     alg_bytes_definition=("per iteration a grid takes: 6 float32 passes over its R^3 F unknowns "
@@ -590,8 +613,8 @@ def main():
                     vcycle_form_bytes={
                         "alg_bytes_per_iteration": round(prof["cg_bytes_mg"] / n_it),
                         "achieved": round(achieved_mg, 1), "frac": round(achieved_mg / HBM_PEAK_GBS, 4),
-                        "traffic_over_these_bytes": (None if traffic is None else round(
-                            traffic * n_it / max(prof["cg_bytes_mg"], 1), 4)),
+                        "alg_bytes_full_iteration": full_mg,
+                        "traffic_over_these_bytes": (None if traffic is None else round(traffic / full_mg, 4)),
                         "definition": ("the same iterations counting also the preconditioned residual z (written "
                                        "and read) and every coarse V-cycle level's right-hand side and correction "
                                        "(written and read)")})
