@@ -284,6 +284,8 @@ def run_form(cfg, data, P0, steps, warmup, profile, graph=False):
         prof["steps"] = steps
     relres = plan.precond_residuals() if cfg.get("precond", "cg") == "cg" else None
     plan.close()
+    print(f"bench: form precond={cfg.get('precond', 'cg')} precision={cfg.get('precision', 'fp32')} "
+          f"graph={graph}: {1e3 * t_total / steps:.2f} ms per step", file=sys.stderr, flush=True)
     return dict(value=steps / t_total, ms_per_step=1e3 * t_total / steps,
                 event_ms={"median": round(float(np.median(ev_ms)), 4), "p90": round(float(np.percentile(ev_ms, 90)), 4),
                           "min": round(float(ev_ms.min()), 4)},
@@ -358,6 +360,7 @@ def run_quality(cfg, steps=300):
     pts = data["pts"].astype(np.float64)
     out = {}
     for prec in ("fp32", "bf16"):
+        print(f"bench: quality run {prec} ({steps} steps)", file=sys.stderr, flush=True)
         c = dict(cfg, precond="cg", precision=prec)
         plan = npg.plan_from_workload(c, data)
         plan.set_state(torch.from_numpy(npg.pack_params(c, synth.init_params(c))).cuda(), adam_steps=0)
@@ -407,32 +410,46 @@ def run_quality(cfg, steps=300):
     return res
 
 
-def _batch_time(cfgs, datas, steps, warmup, state, graph=False, per_stream=True):
+def _batch_time(cfgs, datas, steps, warmup, state, modes=("eager",)):
+    """One batch of the sequences (autotuned once); for every timing mode
+    ("eager": npg_batch_step; "graph": npg_batch_step_graph with each
+    recording on its sequence's stream; "one_graph": one batch graph) the
+    state is reset, `warmup` steps run, then `steps` are timed. Returns
+    {mode: seconds per batch step}, the final mean Chamfer distances of the
+    last mode, the tuned launch shapes and the step statuses."""
     import torch
 
     import paper_2602_22212_amd as npg
     import synth
     batch = npg.Batch(cfgs, datas)
-    tuned = []
+    tuned, states = [], []
     for k, (c, p) in enumerate(zip(cfgs, batch.plans)):
         P = synth.random_state(c, 900 + k, grid_std=0.05) if state == "random" else synth.init_params(c)
-        p.set_state(torch.from_numpy(npg.pack_params(c, P)).cuda(), adam_steps=0)
-        tuned.append((p.tune_nn(0)[0], p.tune_mlp(0)[0], p.tune_cg(0)[0] if c.get("precond", "cg") == "cg" else None))
-    if graph:
-        batch.graph_mode(per_stream)
-    step = batch.step_graph if graph else batch.step
-    for e in range(warmup):
-        step(e, max(steps + warmup, 500))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    statuses = set()
-    for e in range(steps):
-        statuses.add(int(step(warmup + e, max(steps + warmup, 500))))
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+        states.append(torch.from_numpy(npg.pack_params(c, P)).cuda())
+        p.set_state(states[-1], adam_steps=0)
+        cgf = c.get("precond", "cg") == "cg"
+        tuned.append((p.tune_nn(0 if TUNE else 128)[0], p.tune_mlp(0)[0] if TUNE else None,
+                      (p.tune_cg(0)[0] if TUNE else 64) if cgf else None))
+    E = max(steps + warmup, 500)
+    out, statuses = {}, set()
+    for mode in modes:
+        for p, st in zip(batch.plans, states):
+            p.set_state(st, adam_steps=0)
+        if mode != "eager":
+            batch.graph_mode(mode == "graph")
+        step = batch.step if mode == "eager" else batch.step_graph
+        for e in range(warmup):
+            step(e, E)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in range(steps):
+            statuses.add(int(step(warmup + e, E)))
+        torch.cuda.synchronize()
+        out[mode] = (time.perf_counter() - t0) / steps
+        print(f"bench: batch {mode} {1e3 * out[mode]:.1f} ms per batch step", file=sys.stderr, flush=True)
     final = [plan_cd(p) for p in batch.plans]
     batch.close()
-    return dt, final, tuned, sorted(statuses)
+    return out, final, tuned, sorted(statuses)
 
 
 def plan_cd(plan):
@@ -466,18 +483,19 @@ def run_batch(steps=3, warmup=2, quality_steps=20):
     import synth
     cfgs = synth.config_c5()
     t0 = time.perf_counter()
-    datas = [synth.make_workload(c) for c in cfgs]
+    datas = []
+    for c in cfgs:
+        datas.append(synth.make_workload(c))
+        print(f"bench: batch workload {len(datas)} of {len(cfgs)} generated", file=sys.stderr, flush=True)
     t_gen = time.perf_counter() - t0
     res = {}
     for prec in ("bf16", "fp32"):
         cs = [dict(c, precision=prec) for c in cfgs]
-        dt, _, tuned, st = _batch_time(cs, datas, steps, warmup, "random", graph=True)
-        d1, _, _, st1 = _batch_time(cs, datas, steps, warmup, "random", graph=True, per_stream=False)
-        de, _, _, ste = _batch_time(cs, datas, steps, warmup, "random")
-        dq, final, _, _ = _batch_time([dict(c, precond="dct") for c in cs], datas, quality_steps, 0, "init",
-                                      graph=True)
-        res[prec] = dict(dt=dt, d1=d1, de=de, dq=dq, final=final, tuned=tuned,
-                         status=sorted(set(st) | set(st1) | set(ste)))
+        t, _, tuned, st = _batch_time(cs, datas, steps, warmup, "random", modes=("eager", "graph", "one_graph"))
+        tq, final, _, _ = _batch_time([dict(c, precond="dct") for c in cs], datas, quality_steps, 0, "init",
+                                      modes=("eager",))
+        res[prec] = dict(dt=t["graph"], d1=t["one_graph"], de=t["eager"], dq=tq["eager"], final=final, tuned=tuned,
+                         status=st)
     pairs = sum(len(d["xyz"]) * int(d["frame_off"][-1]) for d in datas)
     samples = sum(len(d["xyz"]) * d["T"] for d in datas)
     b, f = res["bf16"], res["fp32"]
@@ -514,6 +532,7 @@ def run_animal(steps=2, warmup=1):
     ~7600 points per frame (5 % dropped), CG preconditioner, FP32."""
     import synth
     cfg = dict(synth.config_c3(), precond="cg")
+    print("bench: generating the quadruped workload", file=sys.stderr, flush=True)
     data = synth.make_workload(cfg)
     r = run_form(cfg, data, synth.random_state(cfg, 9, grid_std=0.05), steps, warmup, profile=False)
     return {"value": round(r["value"], 4), "unit": "steps/s", "ms_per_step": round(r["ms_per_step"], 2),
@@ -685,6 +704,8 @@ def main():
     if "animal" in forms:
         out["animal"] = run_animal()
     if not args.no_cpu_baseline:
+        print("bench: CPU baselines (oracle, then oracle with k-d tree nearest neighbours)", file=sys.stderr,
+              flush=True)
         cb = cpu_baseline(cfg, data, P0, args.cpu_frames)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["stage_seconds"] = cb["stage_seconds"]
