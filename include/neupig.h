@@ -83,6 +83,14 @@ enum { NPG_ROT_EXPMAP = 0, NPG_ROT_QUAT = 1 };
  * transform, the loss, the preconditioner and the float32 master parameters
  * and Adam state are unchanged. */
 enum { NPG_PREC_FP32 = 0, NPG_PREC_BF16 = 1 };
+/* Nearest-neighbour search of the Chamfer distance (Sec. 3.5): both give the
+ * same indices and distances bit for bit. PRUNED (the default) visits the
+ * points of a frame in Morton-ordered tiles and skips a tile whose bounding
+ * box is provably farther than every current minimum of a wave of queries;
+ * EXHAUSTIVE evaluates every vertex-point pair in one pass for both
+ * directions. A plan with more than 131072 vertices, or a frame with more
+ * than 131072 points, takes the exhaustive search under either setting. */
+enum { NPG_NN_PRUNED = 0, NPG_NN_EXHAUSTIVE = 1 };
 
 /* Hyper-parameters. Every reading the paper leaves open is a field here. */
 typedef struct npg_config {
@@ -115,6 +123,7 @@ typedef struct npg_config {
   int32_t precision;              /* NPG_PREC_FP32 or NPG_PREC_BF16                 */
   int32_t cg_mg;                  /* CG form: 1 preconditions every solve with a     */
                                   /* multigrid V-cycle, 0 runs plain CG             */
+  int32_t nn_search;              /* NPG_NN_PRUNED (default) or NPG_NN_EXHAUSTIVE   */
 } npg_config;
 
 typedef struct npg_plan npg_plan;
@@ -339,7 +348,8 @@ npg_status npg_decode_fwd(npg_plan* plan, const float* params_dev, const float* 
 /*
  * Sec. 3.5. Per frame: a_i = argmin_j |x^_i - p_j|^2 and b_j = argmin_i, with
  * the lowest index on exact ties (distances in float32, direct form
- * (x-p).(x-p) with a fixed operation order), and
+ * (x-p).(x-p) with a fixed operation order; the config's nn_search picks the
+ * pruned or the exhaustive search, with identical results), and
  * cd_t = mean_i da_i + mean_j db_j summed in float64.
  *   a_dev [T][V] int32 (index within frame t), da_dev [T][V] float32,
  *   b_dev [sum N_t] int32 (vertex index), db_dev [sum N_t] float32,

@@ -20,6 +20,7 @@ NPG_ACT_RELU, NPG_ACT_LEAKY = 0, 1
 NPG_PRECOND_CG, NPG_PRECOND_DCT = 0, 1
 NPG_ROT_EXPMAP, NPG_ROT_QUAT = 0, 1
 NPG_PREC_FP32, NPG_PREC_BF16 = 0, 1
+NPG_NN_PRUNED, NPG_NN_EXHAUSTIVE = 0, 1
 STAGES = ("encode", "decode", "chamfer+loss", "chamfer_bwd", "iso", "decode_bwd", "encode_bwd", "precond", "adam")
 
 
@@ -41,7 +42,7 @@ class npg_config(ctypes.Structure):
         ("conf_weight", ctypes.c_int32), ("t_key", ctypes.c_int32),
         ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precond", ctypes.c_int32),
         ("rot_head", ctypes.c_int32), ("w_iso", ctypes.c_float), ("precision", ctypes.c_int32),
-        ("cg_mg", ctypes.c_int32),
+        ("cg_mg", ctypes.c_int32), ("nn_search", ctypes.c_int32),
     ]
 
 
@@ -143,6 +144,10 @@ def make_config(cfg):
     c.cg_rtol, c.cg_maxit = float(cfg["cg_rtol"]), int(cfg["cg_maxit"])
     c.precond = NPG_PRECOND_DCT if cfg.get("precond", "cg") == "dct" else NPG_PRECOND_CG
     c.cg_mg = int(cfg.get("cg_mg", 1))
+    nn = cfg.get("nn_search", "pruned")
+    if nn not in ("pruned", "exhaustive"):
+        raise ValueError(f"nn_search must be 'pruned' or 'exhaustive', not {nn!r}")
+    c.nn_search = NPG_NN_EXHAUSTIVE if nn == "exhaustive" else NPG_NN_PRUNED
     head = cfg.get("rot_head", "expmap")
     if head not in ("expmap", "quat"):
         raise ValueError(f"rot_head must be 'expmap' or 'quat', not {head!r}")

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libneupig.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["plan.hip", "setup.hip", "encode.hip", "mlp.hip", "chamfer.hip", "precond.hip", "dct.hip", "iso.hip", "metrics.hip", "batch.hip", "chain.hip", "adam.hip"]
+SOURCES = ["plan.hip", "setup.hip", "encode.hip", "mlp.hip", "chamfer.hip", "nn.hip", "precond.hip", "dct.hip", "iso.hip", "metrics.hip", "batch.hip", "chain.hip", "adam.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]

@@ -321,9 +321,15 @@ hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pt
   return hipGetLastError();
 }
 
+// Both directions for the plan's own points, by the search the config names.
+hipError_t npg_launch_nn_step(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b, float* db) {
+  if (P->cfg.nn_search == NPG_NN_PRUNED && P->nn) return npg_launch_nn_pruned(P, xhat, a, da, b, db);
+  return npg_launch_nn(P, xhat, P->pts, P->d_off, P->pt_frame, P->Ntot, P->Nmax, P->colpart, a, da, b, db);
+}
+
 hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b,
                                   float* db, double* cd) {
-  hipError_t e = npg_launch_nn(P, xhat, P->pts, P->d_off, P->pt_frame, P->Ntot, P->Nmax, P->colpart, a, da, b, db);
+  hipError_t e = npg_launch_nn_step(P, xhat, a, da, b, db);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_frame_sums, dim3(P->T), dim3(256), 0, P->stream, da, db, P->d_off, P->V, cd);
   return hipGetLastError();

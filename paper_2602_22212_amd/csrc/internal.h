@@ -45,6 +45,7 @@ struct NpgCG {  // conjugate-gradient workspace
 };
 
 struct NpgDct;
+struct NpgNn;
 
 // Per-step scalars the loss and Adam kernels of a graph-captured step read
 // from device memory (the eager step passes them as kernel arguments).
@@ -100,7 +101,7 @@ struct npg_plan {
   double* w_g;             // [T] confidence weights times an upstream factor (npg_objective_bwd)
   // chamfer workspace
   int nvb;                 // vertex blocks per frame of the NN main pass
-  int nn_threads;          // its work-group size (64, 128, 256; npg_tune_nn)
+  int nn_threads;          // its work-group size and that of the pruned search (64, 128, 256; npg_tune_nn)
   int nvb_max;             // vertex blocks at 64 threads (colpart sizing)
   float* colpart;          // [T][nvb][Nmax] 64-bit column records (2 floats each)
   int64_t Nmax;
@@ -125,6 +126,7 @@ struct npg_plan {
   // preconditioner workspaces
   NpgCG cg;
   NpgDct* dct;
+  NpgNn* nn;               // pruned nearest-neighbour search tables (nn.hip)
   // isometry term: vertex -> incident-edge table (row [V+1]; per entry the
   // other endpoint and the edge id with the ownership bit 31), loss partials
   int64_t n_edges;
@@ -213,6 +215,13 @@ npg_status npg_run_metrics_noalloc(npg_plan* P, const float4* xhat, const float4
                                    const float4* gtn, float tau, double* out);
 // nT: frames in this launch (xhat, a, da hold nT frames of V vertices; off
 // [nT+1] and pt_frame index the nT frames' points); 0 means all T frames
+// nn.hip: the pruned search (both directions, the plan's own points)
+npg_status npg_nn_setup(npg_plan* P);
+void npg_nn_free(npg_plan* P);
+hipError_t npg_launch_nn_pruned(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b,
+                                float* db);
+// the plan's own points, by the search cfg.nn_search names (chamfer.hip)
+hipError_t npg_launch_nn_step(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b, float* db);
 hipError_t npg_launch_nn(const npg_plan* P, const float4* xhat, const float4* pts, const int64_t* off,
                          const int* pt_frame, int64_t Ntot, int64_t Nmax, void* colpart, int32_t* a, float* da,
                          int32_t* b, float* db, int nT = 0);

@@ -94,6 +94,8 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->cg_maxit >= 1 && c->cg_rtol > 0.0, "cg_maxit >= 1 and cg_rtol > 0 are required");
   CHECK_ARG(c->precond == NPG_PRECOND_CG || c->precond == NPG_PRECOND_DCT, "precond must be CG or DCT");
   CHECK_ARG(c->cg_mg == 0 || c->cg_mg == 1, "cg_mg must be 0 or 1");
+  CHECK_ARG(c->nn_search == NPG_NN_PRUNED || c->nn_search == NPG_NN_EXHAUSTIVE,
+            "nn_search must be NPG_NN_PRUNED or NPG_NN_EXHAUSTIVE");
   CHECK_ARG(c->rot_head == NPG_ROT_EXPMAP || c->rot_head == NPG_ROT_QUAT, "rot_head must be EXPMAP or QUAT");
   CHECK_ARG(c->w_iso >= 0.f && std::isfinite(c->w_iso), "w_iso must be finite and >= 0");
   CHECK_ARG(c->precision == NPG_PREC_FP32 || c->precision == NPG_PREC_BF16, "precision must be FP32 or BF16");
@@ -327,6 +329,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
   if (P->d_scal) hipFree(P->d_scal);
   npg_cg_free(P);
   npg_dct_free(P);
+  npg_nn_free(P);
   npg_iso_free(P);
   for (auto& e : P->ev)
     if (e) hipEventDestroy(e);
@@ -470,6 +473,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   P->nvb = (int)((V + npg_chamfer_vblock(128) - 1) / npg_chamfer_vblock(128));
   P->nvb_max = (int)((V + npg_chamfer_vblock(64) - 1) / npg_chamfer_vblock(64));
   TRYP(dalloc(&P->colpart, 2 * (int64_t)T * P->nvb_max * Nmax));
+  if (cfg->nn_search == NPG_NN_PRUNED) TRYP(npg_nn_setup(P));
   TRYP(dalloc(&P->acc, 3 * TV));
   TRYP(dalloc(&P->mlpA, V * P->W));
   TRYP(dalloc(&P->mlpB, (int64_t)T * P->W));
@@ -853,12 +857,10 @@ npg_status npg_tune_nn(npg_plan* P, int32_t threads, int32_t* chosen, float* ms)
     int best_kt = 128;
     for (int k = 0; k < 3; ++k) {
       set(cand[k]);
-      NPG_HIP(npg_launch_nn(P, P->xhat, P->pts, P->d_off, P->pt_frame, P->Ntot, P->Nmax, P->colpart, P->a, P->da,
-                            P->b, P->db));  // warm-up
+      NPG_HIP(npg_launch_nn_step(P, P->xhat, P->a, P->da, P->b, P->db));  // warm-up
       NPG_HIP(hipEventRecord(P->ev[0], P->stream));
       for (int r = 0; r < 2; ++r)
-        NPG_HIP(npg_launch_nn(P, P->xhat, P->pts, P->d_off, P->pt_frame, P->Ntot, P->Nmax, P->colpart, P->a, P->da,
-                              P->b, P->db));
+        NPG_HIP(npg_launch_nn_step(P, P->xhat, P->a, P->da, P->b, P->db));
       NPG_HIP(hipEventRecord(P->ev[1], P->stream));
       NPG_HIP(hipEventSynchronize(P->ev[1]));
       float t = 0.f;
