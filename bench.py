@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames in the oracle's timed sample")
-    ap.add_argument("--forms", default="cg,cg_plain,dct,graph,quat,iso,metrics,bf16,batch,animal",
+    ap.add_argument("--forms", default="cg,nn,cg_plain,dct,graph,quat,iso,metrics,bf16,batch,animal",
                     help="forms to time: cg (headline: CG preconditioned by a multigrid V-cycle), "
+                         "nn (the Chamfer forward with the pruned and the exhaustive nearest-neighbour search), "
                          "cg_plain (the same solves by plain CG), dct (exact DCT preconditioner), "
                          "graph (the DCT-form step replayed as one captured HIP graph, on the human "
                          "workload and on the small icosphere one, against the eager step), "
@@ -296,6 +297,55 @@ def run_form(cfg, data, P0, steps, warmup, profile, graph=False):
                          "mlp_ms": {str(c): round(m, 3) for c, m in zip(mlp_cand, mlp_ms) if c},
                          "cg_tile_z": cg_zs, "cg_ms_32_64_128": None if cg_ms is None else [round(m, 3) for m in cg_ms]},
                 cg_relres_max=None if relres is None else max(relres))
+
+
+def run_nn_compare(cfg, data, P0, reps=5):
+    """The Chamfer forward (npg_chamfer_fwd: both nearest-neighbour directions
+    and the per-frame sums) with the pruned and with the exhaustive search on
+    the same deformed vertices, at the benchmark state and at the identity
+    start (last layer zero: x^ = x); HIP events on the plans' stream. Both
+    searches give bitwise the same indices and distances."""
+    import numpy as np
+    import torch
+
+    import paper_2602_22212_amd as npg
+    import synth
+    T, V = data["T"], len(data["xyz"])
+    plans = {m: npg.plan_from_workload(dict(cfg, nn_search=m), data) for m in ("pruned", "exhaustive")}
+    out = {}
+    for state, P in (("benchmark", P0), ("identity", synth.init_params(cfg))):
+        flat = torch.from_numpy(npg.pack_params(cfg, P)).cuda()
+        z = torch.empty(V * plans["pruned"].Fz, device="cuda")
+        xh = torch.empty(T * V * 4, device="cuda")
+        plans["pruned"].encode_fwd(flat, z)
+        plans["pruned"].decode_fwd(flat, z, xh)
+        res = {}
+        for m, plan in plans.items():
+            plan.set_state(flat, adam_steps=0)
+            plan.tune_nn(0 if TUNE else 128)
+            a = torch.empty(T * V, dtype=torch.int32, device="cuda")
+            da = torch.empty(T * V, device="cuda")
+            b = torch.empty(plan.Ntot, dtype=torch.int32, device="cuda")
+            db = torch.empty(plan.Ntot, device="cuda")
+            cd = torch.empty(T, dtype=torch.float64, device="cuda")
+            plan.chamfer_fwd(xh, a, da, b, db, cd)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                plan.chamfer_fwd(xh, a, da, b, db, cd)
+            e1.record()
+            torch.cuda.synchronize()
+            res[m] = (e0.elapsed_time(e1) / reps, [x.cpu().numpy() for x in (a, da, b, db, cd)])
+        same = all(np.array_equal(u, v) for u, v in zip(res["pruned"][1], res["exhaustive"][1]))
+        out[state] = {"pruned_ms": round(res["pruned"][0], 3), "exhaustive_ms": round(res["exhaustive"][0], 3),
+                      "speedup": round(res["exhaustive"][0] / res["pruned"][0], 2), "bitwise_equal": bool(same)}
+    for plan in plans.values():
+        plan.close()
+    print("bench: nearest-neighbour searches compared", file=sys.stderr, flush=True)
+    out["note"] = ("npg_chamfer_fwd on the human workload with nn_search = pruned (the step's search) and "
+                   "exhaustive; stage_roofline's chamfer entry counts every vertex-point pair as algorithmic work")
+    return out
 
 
 def run_metrics(cfg, P0, reps=3):
@@ -687,6 +737,7 @@ def main():
             "stage_ms": iso["stage_ms"], "edges": int(len(data["edges"])),
             "note": "objective L_def + 100 L_iso (Sec. 3.5) with the DCT preconditioner; compare precond_dct"},
         "evaluation": run_metrics(cfg, P0) if "metrics" in forms else None,
+        "nn_search": run_nn_compare(cfg, data, P0) if "nn" in forms else None,
         "bf16": None,
         "batch": None,
         "cpu_baseline": None,

@@ -457,11 +457,13 @@ npg_status npg_iso(npg_plan* plan, const float* xhat_dev, float* gxhat_dev, doub
                    int8_t* sign_dev);
 
 /*
- * Autotuner of the nearest-neighbour main pass (npg_chamfer_fwd, the
- * metrics and every step): its work-group size, 64, 128 (the default) or 256
- * threads of 16 vertices each. threads = 0 times the three candidates on the
- * plan's current deformed vertices and point sets (one warm-up and two timed
- * calls each, HIP events on the plan's stream) and keeps the fastest;
+ * Autotuner of the nearest-neighbour search (npg_chamfer_fwd, the metrics
+ * and every step): its work-group size, 64, 128 (the default) or 256 threads
+ * (the exhaustive pass: threads of 16 vertices; the pruned search: 1, 2 or 4
+ * independent waves). threads = 0 times the three candidates of the plan's
+ * search (nn_search) on its current deformed vertices and point sets (one
+ * warm-up and two timed calls each, HIP events on the plan's stream) and keeps
+ * the fastest; the metrics always use the exhaustive pass;
  * threads = 64, 128 or 256 sets it without timing. chosen_host [1] (may be
  * NULL) receives the work-group size in use; ms_host [3] (may be NULL) the
  * measured milliseconds per call for 64, 128, 256 (0 when not timed). Indices,
