@@ -232,7 +232,12 @@ def stage_roofline(cfg, data, stage_ms, precision, prof=None):
             a = w / 1e12 / (ms / 1e3)
             out[k] = {"bound": "alu", "algorithmic": w, "unit": "TFLOP/s", "achieved": round(a, 2),
                       "peak": VALU_F32_PEAK_TFS, "frac": round(a / VALU_F32_PEAK_TFS, 4),
-                      "frac_of_unpacked_issue_limit": round(a / VALU_F32_UNPACKED_TFS, 4)}
+                      "frac_of_unpacked_issue_limit": round(a / VALU_F32_UNPACKED_TFS, 4),
+                      "search": cfg.get("nn_search", "pruned"),
+                      "note": ("algorithmic work counts every vertex-point pair (10 FLOP each); the pruned "
+                               "search evaluates only the tiles it cannot rule out, so its rate can exceed "
+                               "the issue limit of the pairs it evaluates (nn_search gives both searches' "
+                               "times)")}
     return out
 
 
