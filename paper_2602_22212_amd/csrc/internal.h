@@ -37,6 +37,11 @@ struct NpgCG {  // conjugate-gradient workspace
   float* z;                    // [n_grid_params] preconditioned residual
   float *mgB, *mgX;            // coarse levels of every system: right-hand sides, corrections
   double* part2;               // [n_blocks][4] partial r.z (the CG work-group table)
+  double* part3;               // level-1 r.z partials of the large grids (their launches' blocks)
+  int2* r3;                    // [n_sys] range of part3 of each system (empty: none)
+  int* sys_split;              // [n_sys] 1: r.z split over the finest restriction and level 1
+  int n_split;                 // systems with the split (large grids)
+  std::vector<int> mg_l_p3;    // per launch: first part3 block of its level-1 tasks, -1 if none
   void* mg_tasks;              // device table of the V-cycle launches (struct MgTask)
   std::vector<std::vector<int>> mg_l_blk0;  // per launch: first block of each task, padded with INT_MAX
   std::vector<int> mg_l_task0, mg_l_ntask, mg_l_nblk;  // per launch: first task, tasks, blocks

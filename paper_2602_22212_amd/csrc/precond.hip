@@ -32,6 +32,7 @@
 // in contiguous node chunks. Work-groups are dispatched largest grid first.
 #include <algorithm>
 #include <climits>
+#include <functional>
 
 #include "internal.h"
 
@@ -542,6 +543,24 @@ __device__ void zm_dir_ap(const NpgGrid& g, const Tile& t, const double* st, int
   store_partials<4>(acc, part, blk);
 }
 
+// p.(A p) of a direction the V-cycle's finest prolongation already formed
+// (the large grids of the multigrid form): p is only read.
+__device__ void zm_pap(const NpgGrid& g, const Tile& t, const float* p, double* part, int blk) {
+  const float lam = g.lam;
+  const float4* Pp = reinterpret_cast<const float4*>(p + g.poff);
+  double acc[4] = {0, 0, 0, 0};
+  zm_walk<Raw1, NoExtra>(
+      g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t) { return NoExtra{}; },
+      [&](const Raw1& v) { return v.a; },
+      [&](int64_t, const float4& lap, const float4& pn, const NoExtra&) {
+        acc[0] += (double)pn.x * (double)fmaf(lam, lap.x, pn.x);
+        acc[1] += (double)pn.y * (double)fmaf(lam, lap.y, pn.y);
+        acc[2] += (double)pn.z * (double)fmaf(lam, lap.z, pn.z);
+        acc[3] += (double)pn.w * (double)fmaf(lam, lap.w, pn.w);
+      });
+  store_partials<4>(acc, part, blk);
+}
+
 struct Raw3 {
   float4 a, b, c;
 };
@@ -628,14 +647,15 @@ __global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G,
                                                   const int64_t* __restrict__ blk_start,
                                                   const int* __restrict__ active, const double* __restrict__ st,
                                                   const float* __restrict__ r, const float* __restrict__ p_old,
-                                                  float* __restrict__ p_new, double* __restrict__ part) {
+                                                  float* __restrict__ p_new, double* __restrict__ part, int mgp) {
   const int blk = logical_block(nb);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   if (!active[s]) return;
   const NpgGrid g = G[s];
   if (use_zm(g)) {
-    zm_dir_ap(g, unpack_tile(blk_start[blk]), st, s, r, p_old, p_new, part, blk);
+    if (mgp) zm_pap(g, unpack_tile(blk_start[blk]), p_new, part, blk);
+    else zm_dir_ap(g, unpack_tile(blk_start[blk]), st, s, r, p_old, p_new, part, blk);
     return;
   }
   NPG_F_SWITCH(g, (dir_ap_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, r, p_old, p_new, part, blk)));
@@ -726,22 +746,36 @@ __device__ __forceinline__ void reduce_range(const double* part, int b0, int b1,
 // mode 0: after init (bb, rho); 1: alpha = rho / pq; 2: beta = rho_new / rho
 // and the convergence test on r.r (defer: the update left this iteration's x
 // term pending). part2 (NULL without the V-cycle): the r.z partials, blocks
-// [blk0_2[s], blk0_2[s+1]) of system s.
+// [blk0_2[s], blk0_2[s+1]) of system s, plus (part3 not NULL) the blocks
+// [r3[s].x, r3[s].y) of part3: for the large grids of the multigrid form, r.z
+// is the finest restriction's term plus the level-1 term (see k_mg_up0).
+// filter: -1 every system, 0 only systems without that split, 1 only those
+// with it (sys_split[s]).
 __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restrict__ G,
                                                           const int* __restrict__ sys_blk0, int* __restrict__ active,
                                                           const double* __restrict__ part,
                                                           const double* __restrict__ part2,
                                                           const int* __restrict__ blk0_2, double* __restrict__ st,
-                                                          int mode, double rtol, int defer) {
+                                                          int mode, double rtol, int defer,
+                                                          const double* __restrict__ part3, const int2* __restrict__ r3,
+                                                          const int* __restrict__ sys_split, int filter) {
   const int s = blockIdx.x;
   if (mode != 0 && !active[s]) return;
-  __shared__ double red[4][kR_WAVES], red2[4][kR_WAVES];
+  if (filter >= 0 && sys_split && (sys_split[s] != 0) != (filter != 0)) return;
+  __shared__ double red[4][kR_WAVES], red2[4][kR_WAVES], red3[4][kR_WAVES];
   const int F = G[s].F;
   double vv[4], rho[4];
   reduce_range(part, sys_blk0[s], sys_blk0[s + 1], red, vv);
-  if (part2 && mode != 1) reduce_range(part2, blk0_2[s], blk0_2[s + 1], red2, rho);
-  else
+  if (part2 && mode != 1) {
+    reduce_range(part2, blk0_2[s], blk0_2[s + 1], red2, rho);
+    if (part3) {
+      double rc[4];
+      reduce_range(part3, r3[s].x, r3[s].y, red3, rc);
+      for (int c = 0; c < 4; ++c) rho[c] += rc[c];
+    }
+  } else {
     for (int c = 0; c < 4; ++c) rho[c] = vv[c];
+  }
   if (threadIdx.x != 0) return;
   int any = 0;
   for (int c = 0; c < F; ++c) {
@@ -822,6 +856,7 @@ struct MgTask {
   float mass, lw;
   FastDiv fx, fx2;
   int zm0;  // finest restriction of a grid walked in z-column tiles (k_mg_down0)
+  int rz1;  // prolongation onto level 1 of such a grid: b1 . e1 partials (the coarse r.z term)
 };
 
 __device__ __forceinline__ int mg_ext(int i, const MgLvl& L) { return min(L.s, L.R - L.s * i); }
@@ -1015,7 +1050,7 @@ __device__ __forceinline__ void mg_up_u4(const MgTask* tk, const float* __restri
     const int dc = mg_deg1(i, R) + mg_deg1(j, R) + mg_deg1(k, R);
     const float4 z = ident ? bc : f4axpy(mg_f(tk, dc), f4sub(bc, ax), xc);
     Z[n] = z;
-    if (fine) {
+    if (fine || tk->rz1) {
       acc[0] += (double)bc.x * (double)z.x;
       acc[1] += (double)bc.y * (double)z.y;
       acc[2] += (double)bc.z * (double)z.z;
@@ -1146,20 +1181,23 @@ __device__ __forceinline__ void mg_up_node(const MgTask* tk, const float* __rest
 }
 
 // Prolongation and post-smoothing from level l+1 to l >= 1 (l = 0: k_mg_up0).
+// part3 (may be NULL): the b . out partials of every block of an rz1 task.
 __global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, MgBlk0 B0, int nblk,
                                                 const int* __restrict__ active, int check_active,
                                                 const float* __restrict__ bl, const float* __restrict__ eh,
-                                                float* __restrict__ out) {
+                                                float* __restrict__ out, double* __restrict__ part3) {
   const int blk = mg_block(nblk);
   if (blk < 0) return;
   const MgTask task = T[mg_task_of(B0, blk)];
   const MgTask* tk = &task;
   if (check_active && !active[tk->sys]) return;
   const int64_t m = (int64_t)(blk - tk->blk0) * kMgB + threadIdx.x;
-  if (m >= tk->nodes) return;
   double acc[4] = {0, 0, 0, 0};
-  if (tk->fast) mg_up_u4(tk, bl, eh, out, (int)m, acc);
-  else mg_up_node(tk, bl, eh, out, m, acc);
+  if (m < tk->nodes) {
+    if (tk->fast) mg_up_u4(tk, bl, eh, out, (int)m, acc);
+    else mg_up_node(tk, bl, eh, out, m, acc);
+  }
+  if (part3 && tk->rz1) store_partials<4>(acc, part3, blk);
 }
 
 // Restriction from the finest level of a large grid over its z-column tiles
@@ -1168,8 +1206,10 @@ __global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, Mg
 // z-adjacent planes (registers), and written by the even lane of the even
 // wave at the odd plane (or at the last plane of an odd-sized grid). Tiles
 // start at even x, y and z, so no 2x2x2 block straddles two tiles.
+// acc: the fine-level term of r.z, sum of x0 (2 b - A x0) (b . b when lam = 0,
+// where the preconditioner is the identity); see k_mg_up0.
 __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, const float* __restrict__ r,
-                            float* __restrict__ bh) {
+                            float* __restrict__ bh, double (&acc)[4]) {
   __shared__ float4 ys[2][kTY / 2][kTX];
   const int R = g.R;
   const int nh = tk->hi.n;
@@ -1188,6 +1228,11 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
       },
       [&](int64_t, const float4& lap, const float4& xc, const Raw1& e, int) {
         rs = f4sub(e.a, f4axpy(lam, lap, xc));
+        const float4 u = lam == 0.f ? e.a : xc;
+        acc[0] += (double)u.x * ((double)e.a.x + (double)(lam == 0.f ? 0.f : rs.x));
+        acc[1] += (double)u.y * ((double)e.a.y + (double)(lam == 0.f ? 0.f : rs.y));
+        acc[2] += (double)u.z * ((double)e.a.z + (double)(lam == 0.f ? 0.f : rs.z));
+        acc[3] += (double)u.w * ((double)e.a.w + (double)(lam == 0.f ? 0.f : rs.w));
       },
       [&](int z) {
         float4 v = f4add(rs, make_float4(__shfl_xor(rs.x, 1), __shfl_xor(rs.y, 1), __shfl_xor(rs.z, 1),
@@ -1209,7 +1254,7 @@ __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, 
                                                  const int64_t* __restrict__ blk_start,
                                                  const int* __restrict__ active, int check_active,
                                                  const MgTask* __restrict__ T0, const float* __restrict__ r,
-                                                 float* __restrict__ bh) {
+                                                 float* __restrict__ bh, double* __restrict__ part2) {
   const int blk = logical_block(nb);
   if (blk < 0) return;
   const int s = blk_sys[blk];
@@ -1217,51 +1262,64 @@ __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, 
   const MgTask* tk = T0 + s;
   if (!tk->zm0) return;
   const NpgGrid g = G[s];
-  mg_down0_zm(g, unpack_tile(blk_start[blk]), tk, r, bh);
+  double acc[4] = {0, 0, 0, 0};
+  mg_down0_zm(g, unpack_tile(blk_start[blk]), tk, r, bh, acc);
+  store_partials<4>(acc, part2, blk);
 }
 
 // Prolongation and post-smoothing onto the finest level (z = M^-1 r) over the
 // CG work-group table: the z-column walk for the large grids (each row read
 // once; x = w D^-1 r + P e formed as it is loaded), node chunks otherwise;
 // r.z partials per work-group. T0: the system's task (system order).
+//
+// On the large grids z is never stored: the kernel writes the next search
+// direction p = z + beta p_old itself (beta = 0 on the first call of a
+// solve), which needs beta = r.z / rho_old before z exists. With x0 = w D^-1 r,
+// the post-smoothed V-cycle is z = x0 + (I - w D^-1 A)(P e) + w D^-1 (r - A x0),
+// e = C P^T (r - A x0) for the symmetric coarse-level cycle C, so
+//   r.z = x0 . (2 r - A x0) + b1 . e1,   b1 = P^T (r - A x0), e1 = C b1:
+// the first sum is formed by the finest restriction (k_mg_down0) and the second
+// by the prolongation onto level 1 (k_mg_up, rz1 tasks), both before this
+// kernel runs.
 __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, const float* __restrict__ r,
-                          const float* __restrict__ eh, float* __restrict__ z, double (&acc)[4]) {
+                          const float* __restrict__ eh, const float* __restrict__ p_old, float* __restrict__ p_new,
+                          const float (&be)[4]) {
   const int R = g.R;
   const int nh = tk->hi.n;
   const float lam = g.lam;
   const float4* B = reinterpret_cast<const float4*>(r + g.poff);
   const float4* E = reinterpret_cast<const float4*>(eh + tk->hi.off);
-  float4* Z = reinterpret_cast<float4*>(z + g.poff);
+  const float4* Po = reinterpret_cast<const float4*>(p_old + g.poff);
+  float4* Pn = reinterpret_cast<float4*>(p_new + g.poff);
   const ZmCols cols = zm_cols(t, R, lam, nh);
   const int nh2 = nh * nh;
-  zm_walk_post<Raw2, Raw1>(
+  zm_walk_post<Raw2, Raw2>(
       g, t,
       [&](int64_t m, int s, int zz) { return Raw2{B[m], E[(zz >> 1) * nh2 + cols.pxy[s]]}; },
-      [&](int64_t m) { return Raw1{B[m]}; },
+      [&](int64_t m) { return Raw2{B[m], Po[m]}; },
       [&](const Raw2& v, int s, int zz) {
         const float f = (zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s];
         return f4add(f4scale(f, v.a), v.b);
       },
-      [&](int64_t n, const float4& lap, const float4& xc, const Raw1& e, int zz) {
+      [&](int64_t n, const float4& lap, const float4& xc, const Raw2& e, int zz) {
         const float4 bc = e.a;
         const float4 ax = f4axpy(lam, lap, xc);
         const float f = (zz == 0 || zz == R - 1) ? cols.fbd[0] : cols.fin[0];
         const float4 zv = lam == 0.f ? bc : f4axpy(f, f4sub(bc, ax), xc);
-        Z[n] = zv;
-        acc[0] += (double)bc.x * (double)zv.x;
-        acc[1] += (double)bc.y * (double)zv.y;
-        acc[2] += (double)bc.z * (double)zv.z;
-        acc[3] += (double)bc.w * (double)zv.w;
+        Pn[n] = f4fma(e.b, be, zv);  // p = z + beta p_old, the float32 form of the direction update
       },
       [](int) {});
 }
 
+// Large grids: p_new = z + beta p_old (first: beta = 0), no partials;
+// otherwise z and its r.z partials.
 __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, int nb,
                                                const int* __restrict__ blk_sys, const int64_t* __restrict__ blk_start,
                                                const int* __restrict__ active, int check_active,
                                                const MgTask* __restrict__ T0, const float* __restrict__ r,
                                                const float* __restrict__ eh, float* __restrict__ z,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, const double* __restrict__ st,
+                                               const float* __restrict__ p_old, float* __restrict__ p_new, int first) {
   const int blk = logical_block(nb);
   if (blk < 0) return;
   const int s = blk_sys[blk];
@@ -1270,7 +1328,11 @@ __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, in
   const MgTask* tk = T0 + s;
   double acc[4] = {0, 0, 0, 0};
   if (use_zm(g)) {  // the block table holds z-column tiles for these grids
-    mg_up0_zm(g, unpack_tile(blk_start[blk]), tk, r, eh, z, acc);
+    float be[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) be[c] = first ? 0.f : (float)st[(s * 4 + c) * kS + 4];
+    mg_up0_zm(g, unpack_tile(blk_start[blk]), tk, r, eh, p_old, p_new, be);
+    return;
   } else {
     for (int k = 0; k < kPer; ++k) {
       const int64_t n = blk_start[blk] + k * kB + threadIdx.x;
@@ -1393,6 +1455,39 @@ static npg_status mg_setup(npg_plan* P) {
   // looked up by system: every system takes part, in order)
   if (C.mg_l_ntask[0] != P->n_sys || C.mg_l_ntask[nlev - 1] != P->n_sys)
     return npg_fail(NPG_EINVAL, "multigrid: finest level table");
+  // Large grids (z-column tiles) form r.z from the finest restriction's term
+  // and the level-1 term of the launch that produces level 1 (the up launch
+  // from level 2, or the coarsest launch of a two-level hierarchy), whose
+  // blocks write partials into their own range of part3 (lam = 0: no level-1
+  // term, the preconditioner being the identity).
+  std::vector<int> split(P->n_sys, 0);
+  std::vector<int2> r3(P->n_sys, make_int2(0, 0));
+  C.mg_l_p3.assign(2 * nlev - 1, -1);
+  int p3 = 0;
+  for (int sy = 0; sy < P->n_sys; ++sy) {
+    const NpgGrid& g = P->g[sy];
+    split[sy] = g.R >= kZmR && g.F == 4 && g.poff % 4 == 0;
+    if (!split[sy] || g.lam == 0.f) continue;
+    const int li = (int)lv[sy].size() >= 3 ? nlev : 2 * (nlev - 1);
+    MgTask* tk = nullptr;
+    for (int q = 0; q < C.mg_l_ntask[li]; ++q)
+      if (tasks[C.mg_l_task0[li] + q].sys == sy) tk = &tasks[C.mg_l_task0[li] + q];
+    if (!tk || tk->lo.s != 2) return npg_fail(NPG_EINVAL, "multigrid: level-1 task");
+    tk->rz1 = 1;
+    if (C.mg_l_p3[li] < 0) {
+      C.mg_l_p3[li] = p3;
+      p3 += C.mg_l_nblk[li];
+    }
+    const int b0 = C.mg_l_p3[li] + tk->blk0;
+    r3[sy] = make_int2(b0, b0 + (int)((tk->nodes + kMgB - 1) / kMgB));
+  }
+  C.n_split = 0;
+  for (int v : split) C.n_split += v;
+  NPG_HIP(hipMalloc(&C.part3, (int64_t)std::max(p3, 1) * 4 * 8));
+  NPG_HIP(hipMalloc(&C.r3, P->n_sys * sizeof(int2)));
+  NPG_HIP(hipMalloc(&C.sys_split, P->n_sys * sizeof(int)));
+  NPG_HIP(hipMemcpy(C.r3, r3.data(), P->n_sys * sizeof(int2), hipMemcpyHostToDevice));
+  NPG_HIP(hipMemcpy(C.sys_split, split.data(), P->n_sys * sizeof(int), hipMemcpyHostToDevice));
   C.mg_nlev = nlev;
   NPG_HIP(hipMalloc(&C.z, P->n_grid_params * 4));
   NPG_HIP(hipMalloc(&C.mgB, std::max<int64_t>(coarse, 1) * 4));
@@ -1409,34 +1504,49 @@ static npg_status mg_setup(npg_plan* P) {
 }
 
 // z = M^-1 r (one V-cycle for every system; with check_active only the
-// systems still iterating), r.z partials into part2.
-static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_active) {
+// systems still iterating). Small grids: z and its r.z partials (part2). Large
+// grids (split): the r.z terms (part2 from the finest restriction, part3 from
+// level 1), then `beta` (when not NULL) reduces them, updates their scalars
+// (k_cg_reduce mode 2 of the split systems: beta, convergence), and the finest
+// prolongation writes their next direction p_dst = z + beta p_src (first:
+// beta = 0).
+struct MgDir {
+  const float* p_src;
+  float* p_dst;
+  const double* st;
+  int first;
+};
+static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_active, const MgDir& d,
+                           const std::function<void()>& beta) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nl = C.mg_nlev;
   const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
   hipLaunchKernelGGL(k_mg_down0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
-                     C.blk_start, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB);
+                     C.blk_start, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2);
   auto blk0 = [&](int li) {
     MgBlk0 b;
     for (int q = 0; q < kMgTaskMax; ++q) b.b[q] = C.mg_l_blk0[li][q];
     return b;
   };
+  auto p3 = [&](int li) { return C.mg_l_p3[li] >= 0 ? C.part3 + (int64_t)C.mg_l_p3[li] * 4 : nullptr; };
   for (int l = 0; l + 1 < nl; ++l)
     if (C.mg_l_nblk[l] > 0)
       hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(C.mg_l_nblk[l])), dim3(kMgB), 0, s, T + C.mg_l_task0[l], blk0(l),
                          C.mg_l_nblk[l], C.active, check_active, l == 0 ? r : C.mgB, C.mgB);
   const int lc = 2 * (nl - 1);
   hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[lc])), dim3(kMgB), 0, s, T + C.mg_l_task0[lc], blk0(lc),
-                     C.mg_l_nblk[lc], C.active, check_active, C.mgB, C.mgX, C.mgX);
+                     C.mg_l_nblk[lc], C.active, check_active, C.mgB, C.mgX, C.mgX, p3(lc));
   for (int l = nl - 2; l >= 1; --l) {
     const int li = nl - 1 + l;
     if (C.mg_l_nblk[li] > 0)
       hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[li])), dim3(kMgB), 0, s, T + C.mg_l_task0[li],
-                         blk0(li), C.mg_l_nblk[li], C.active, check_active, C.mgB, C.mgX, C.mgX);
+                         blk0(li), C.mg_l_nblk[li], C.active, check_active, C.mgB, C.mgX, C.mgX, p3(li));
   }
+  if (beta) beta();
   hipLaunchKernelGGL(k_mg_up0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
-                     C.blk_start, C.active, check_active, T + C.mg_l_task0[nl - 1], r, C.mgX, z, C.part2);
+                     C.blk_start, C.active, check_active, T + C.mg_l_task0[nl - 1], r, C.mgX, z, C.part2, d.st,
+                     d.p_src, d.p_dst, d.first);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
@@ -1492,7 +1602,7 @@ npg_status npg_cg_setup(npg_plan* P) {
 void npg_cg_free(npg_plan* P) {
   NpgCG& C = P->cg;
   void* bufs[] = {C.x, C.r, C.p, C.q, C.part, C.st, C.active, C.blk_sys, C.blk_start, C.sys_blk0,
-                  C.z, C.mgB, C.mgX, C.part2, C.mg_tasks};
+                  C.z, C.mgB, C.mgX, C.part2, C.mg_tasks, C.part3, C.r3, C.sys_split};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   const int keep[2] = {C.last_iters[0], C.last_iters[1]};
@@ -1541,14 +1651,26 @@ CgCtx cg_ctx(const npg_plan* P, int which) {
   return c;
 }
 
+// The scalar update of every system (filter -1), of the systems whose r.z is
+// split over the finest restriction and level 1 (filter 1), or of the others
+// (filter 0); see k_cg_reduce.
+void cg_reduce(npg_plan* P, const CgCtx& c, int mode, int defer, int filter) {
+  NpgCG& C = P->cg;
+  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, P->stream, P->d_g, C.sys_blk0, C.active,
+                     C.part, c.part2, C.sys_blk0, c.st, mode, P->cfg.cg_rtol, defer, c.mg ? C.part3 : nullptr,
+                     c.mg ? C.r3 : nullptr, c.mg ? C.sys_split : nullptr, filter);
+}
+
+// Iteration 0 treats C.q as its direction: the start writes p_0 = z_0 there
+// (large grids of the multigrid form, in the V-cycle's finest prolongation;
+// the other grids form it in k_cg_dir_ap from z with beta = 0).
 npg_status cg_start(npg_plan* P, const CgCtx& c, const float* b, float* x) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   hipLaunchKernelGGL(k_cg_init, c.grid, c.blk, 0, s, P->d_g, C.n_blocks, C.blk_sys, C.blk_start, b, x, C.r, C.p,
                      C.part);
-  if (c.mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0));
-  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                     c.part2, C.sys_blk0, c.st, 0, P->cfg.cg_rtol, 0);
+  if (c.mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
+  cg_reduce(P, c, 0, 0, -1);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
@@ -1566,18 +1688,24 @@ npg_status cg_iteration(npg_plan* P, const CgCtx& c, float* x, int k) {
   const bool prof = P->prof_cg && P->prof_n + 2 <= (int)P->prof_ev.size();
   if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n], s));
   hipLaunchKernelGGL(k_cg_dir_ap, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active, c.st,
-                     c.dir_src, p_old, p_new, C.part);
-  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                     c.part2, C.sys_blk0, c.st, 1, P->cfg.cg_rtol, 0);
+                     c.dir_src, p_old, p_new, C.part, (int)c.mg);
+  cg_reduce(P, c, 1, 0, -1);
   if (odd)
     hipLaunchKernelGGL(k_cg_update<1>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
                        c.st, x, C.r, p_new, p_old, C.part);
   else
     hipLaunchKernelGGL(k_cg_update<0>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
                        c.st, x, C.r, p_new, p_old, C.part);
-  if (c.mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 1));
-  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, s, P->d_g, C.sys_blk0, C.active, C.part,
-                     c.part2, C.sys_blk0, c.st, 2, P->cfg.cg_rtol, (int)!odd);
+  if (c.mg) {
+    // large grids: beta (and the convergence test) before the prolongation,
+    // which writes their next direction over p_old (its x term is added by
+    // this iteration's update, the odd one); the other grids after it
+    const std::function<void()> beta = [&]() { cg_reduce(P, c, 2, (int)!odd, 1); };
+    NPG_TRY_ST(mg_apply(P, C.r, C.z, 1, MgDir{p_new, p_old, c.st, 0}, C.n_split > 0 ? beta : nullptr));
+    cg_reduce(P, c, 2, (int)!odd, 0);
+  } else {
+    cg_reduce(P, c, 2, (int)!odd, -1);
+  }
   if (prof) {
     NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], s));
     P->prof_n += 2;
@@ -1662,7 +1790,8 @@ npg_status npg_cg_report(npg_plan* P, int32_t* iters) {
       // and correction (written, read)
       const double fine = (double)g.nodes * g.F;
       P->cg_alg_bytes += m * 4.0 * 6.0 * fine;
-      P->cg_alg_bytes_mg += m * 4.0 * (mg ? 8.0 * fine + 4.0 * C.mg_elems[sy] : 6.0 * fine);
+      const bool split = g.R >= kZmR && g.F == 4 && g.poff % 4 == 0;  // no stored z
+      P->cg_alg_bytes_mg += m * 4.0 * (mg ? (split ? 6.0 : 8.0) * fine + 4.0 * C.mg_elems[sy] : 6.0 * fine);
       P->cg_iters_sum += (int64_t)m;
     }
     C.last_iters[which] = taken >= P->cfg.cg_maxit ? 0 : taken;
