@@ -80,6 +80,7 @@ struct npg_plan {
   int t_key;
   // static device data
   float4 *xyz, *nrm, *pts;
+  int32_t* vperm;      // [V] vertices in Morton order of their rest positions (encode, pruned search)
   int64_t* d_off;
   int* pt_frame;
   NpgGrid* d_g;
@@ -220,7 +221,8 @@ npg_status npg_run_metrics_noalloc(npg_plan* P, const float4* xhat, const float4
                                    const float4* gtn, float tau, double* out);
 // nT: frames in this launch (xhat, a, da hold nT frames of V vertices; off
 // [nT+1] and pt_frame index the nT frames' points); 0 means all T frames
-// nn.hip: the pruned search (both directions, the plan's own points)
+// nn.hip: the plan's vertex order; the pruned search (both directions, the plan's own points)
+npg_status npg_vertex_order(npg_plan* P);
 npg_status npg_nn_setup(npg_plan* P);
 void npg_nn_free(npg_plan* P);
 hipError_t npg_launch_nn_pruned(const npg_plan* P, const float4* xhat, int32_t* a, float* da, int32_t* b,

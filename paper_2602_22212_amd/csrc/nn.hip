@@ -5,7 +5,7 @@
 // operation order, which is symmetric in its operands bit for bit), and on
 // equal distances the lowest original index.
 //
-// Both directions run the same kernel: one wave takes 64 x kNQ queries of one
+// Both directions run the same kernel: one wave takes 64 x NQ queries of one
 // frame and scans the frame's targets in tiles of kNT. Queries and targets
 // are in Morton order (vertices by their rest position, points per frame by
 // position), so a wave's queries and a tile's targets each occupy a compact
@@ -30,9 +30,9 @@
 
 namespace {
 
-constexpr int kNQ = 2;          // queries per lane
+constexpr int kNQV = 2;         // queries per lane, vertex queries (over point tiles)
+constexpr int kNQP = 2;         // queries per lane, point queries (over vertex tiles)
 constexpr int kNT = 128;        // targets per tile
-constexpr int kQG = 64 * kNQ;   // queries per wave
 constexpr int kMaxTL = 16;      // tiles per lane of the ordered walk: at most 64 kMaxTL tiles per frame
 
 __device__ __forceinline__ float dist2(float4 x, float4 p) {
@@ -405,7 +405,7 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
 
 struct NpgNn {
-  int32_t* perm_v = nullptr;    // [V] sorted vertex -> original vertex
+  const int32_t* perm_v = nullptr;  // [V] sorted vertex -> original vertex (the plan's vperm)
   float4* pts_s = nullptr;      // [Ntot] points sorted within each frame
   int32_t* perm_p = nullptr;    // [Ntot] sorted point -> original index within its frame
   float4* pbox = nullptr;       // [point tiles][2]
@@ -425,7 +425,7 @@ struct NpgNn {
 void npg_nn_free(npg_plan* P) {
   NpgNn* N = P->nn;
   if (!N) return;
-  void* bufs[] = {N->perm_v, N->pts_s, N->perm_p, N->pbox, N->ptile_off, N->pgrp,
+  void* bufs[] = {N->pts_s, N->perm_p, N->pbox, N->ptile_off, N->pgrp,
                   N->xs, N->vbox, N->vtile_off, N->vx_off, N->vgrp};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -444,13 +444,10 @@ npg_status npg_nn_setup(npg_plan* P) {
   if (V > 64 * kMaxTL * kNT || P->Nmax > 64 * kMaxTL * kNT) return NPG_OK;  // exhaustive search (P->nn stays NULL)
   NpgNn* N = new NpgNn();
   P->nn = N;
-  std::vector<float4> xyz((size_t)V), pts((size_t)Ntot);
-  NPG_HIP(hipMemcpyAsync(xyz.data(), P->xyz, V * sizeof(float4), hipMemcpyDeviceToHost, P->stream));
+  std::vector<float4> pts((size_t)Ntot);
   NPG_HIP(hipMemcpyAsync(pts.data(), P->pts, Ntot * sizeof(float4), hipMemcpyDeviceToHost, P->stream));
   NPG_HIP(hipStreamSynchronize(P->stream));
-
-  std::vector<int32_t> pv;
-  morton_order(reinterpret_cast<const float*>(xyz.data()), V, pv);
+  N->perm_v = P->vperm;
   N->ntv = (int)((V + kNT - 1) / kNT);
 
   std::vector<float4> ps((size_t)Ntot), pbox;
@@ -475,8 +472,8 @@ npg_status npg_nn_setup(npg_plan* P) {
       pbox.push_back(hi);
     }
     ptoff[t + 1] = ptoff[t] + (int)((n + kNT - 1) / kNT);
-    for (int64_t q0 = 0; q0 < n; q0 += kQG) pg.push_back(make_int2(t, (int)q0));
-    for (int64_t q0 = 0; q0 < V; q0 += kQG) vg.push_back(make_int2(t, (int)q0));
+    for (int64_t q0 = 0; q0 < n; q0 += 64 * kNQP) pg.push_back(make_int2(t, (int)q0));
+    for (int64_t q0 = 0; q0 < V; q0 += 64 * kNQV) vg.push_back(make_int2(t, (int)q0));
   }
   std::vector<int> vtoff(T + 1);
   std::vector<int64_t> vxoff(T + 1);
@@ -499,7 +496,6 @@ npg_status npg_nn_setup(npg_plan* P) {
     return NPG_OK;
   };
   npg_status st;
-  if ((st = up(&N->perm_v, pv)) != NPG_OK) return st;
   if ((st = up(&N->pts_s, ps)) != NPG_OK) return st;
   if ((st = up(&N->perm_p, pp)) != NPG_OK) return st;
   if ((st = up(&N->pbox, pbox)) != NPG_OK) return st;
@@ -512,6 +508,22 @@ npg_status npg_nn_setup(npg_plan* P) {
       hipMalloc((void**)&N->vbox, (size_t)T * N->ntv * 2 * sizeof(float4)) != hipSuccess)
     return npg_fail(NPG_ENOMEM, "hipMalloc of the nearest-neighbour workspace failed");
   NPG_HIP(hipStreamSynchronize(P->stream));
+  return NPG_OK;
+}
+
+// The plan's vertex order (P->vperm, synchronizes): the reference vertices in
+// Morton order of their rest positions, equal codes by index. The encode
+// walks vertices in this order and the pruned search builds its query waves
+// and target tiles from it.
+npg_status npg_vertex_order(npg_plan* P) {
+  std::vector<float4> xyz((size_t)P->V);
+  NPG_HIP(hipMemcpyAsync(xyz.data(), P->xyz, P->V * sizeof(float4), hipMemcpyDeviceToHost, P->stream));
+  NPG_HIP(hipStreamSynchronize(P->stream));
+  std::vector<int32_t> pv;
+  morton_order(reinterpret_cast<const float*>(xyz.data()), P->V, pv);
+  if (hipMalloc((void**)&P->vperm, (size_t)P->V * sizeof(int32_t)) != hipSuccess)
+    return npg_fail(NPG_ENOMEM, "hipMalloc of the vertex order failed");
+  NPG_HIP(hipMemcpy(P->vperm, pv.data(), (size_t)P->V * sizeof(int32_t), hipMemcpyHostToDevice));
   return NPG_OK;
 }
 
@@ -530,7 +542,11 @@ hipError_t npg_launch_nn_pruned(const npg_plan* P, const float4* xhat, int32_t* 
     const NnArgs& A = d == 0 ? rows : cols;
     const int tl = d == 0 ? N->tl_rows : N->tl_cols;
     const unsigned grid = nblk(A.ngroups, wpb);
-#define NPG_NN_LAUNCH(W, TLV) hipLaunchKernelGGL((k_nn_pruned<W, kNQ, TLV>), dim3(grid), dim3(W), 0, P->stream, A)
+#define NPG_NN_LAUNCH(W, TLV)                                                                                \
+  do {                                                                                                       \
+    if (d == 0) hipLaunchKernelGGL((k_nn_pruned<W, kNQV, TLV>), dim3(grid), dim3(W), 0, P->stream, A);      \
+    else hipLaunchKernelGGL((k_nn_pruned<W, kNQP, TLV>), dim3(grid), dim3(W), 0, P->stream, A);             \
+  } while (0)
 #define NPG_NN_TL(W)                            \
   switch (tl) {                                 \
     case 2: NPG_NN_LAUNCH(W, 2); break;         \

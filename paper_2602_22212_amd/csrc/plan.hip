@@ -318,7 +318,7 @@ npg_status npg_param_count(const npg_config* cfg, int64_t* count) {
 npg_status npg_plan_destroy(npg_plan* P) {
   if (!P) return NPG_OK;
   hipStreamSynchronize(P->stream);
-  void* bufs[] = {P->xyz, P->nrm, P->pts, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
+  void* bufs[] = {P->xyz, P->nrm, P->pts, P->vperm, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
                   P->seg_chunk0, P->chunk_start, P->chunk_sum, P->chunk_sys, P->params, P->m, P->v, P->grad,
                   P->z, P->gz, P->xhat, P->gxhat, P->a, P->b, P->da, P->db, P->cd, P->w, P->loss, P->colpart,
                   P->w_g, P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->fl_part, P->gam, P->d_flag};
@@ -446,6 +446,7 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   HIPP(hipGetLastError());
 
   TRYP(npg_build_scatter_table(P));
+  TRYP(npg_vertex_order(P));
 
   // optimizer state and intermediates
   const int64_t NP = P->n_params;
