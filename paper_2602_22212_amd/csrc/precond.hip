@@ -168,22 +168,19 @@ __device__ __forceinline__ Nb neighbours(uint32_t n, int R, const FastDiv& fR, c
   return b;
 }
 
+// r = p = b and the b.b partials. x is not written: the first odd update
+// writes it without reading it, or k_cg_flush when a solve stops earlier.
 template <int FV, int F = (FV < 0 ? -FV : FV)>
-__device__ void init_body(const NpgGrid& g, int64_t n0, const float* b, float* x, float* r, float* p, double* part,
-                          int blk) {
+__device__ void init_body(const NpgGrid& g, int64_t n0, const float* b, float* r, float* p, double* part, int blk) {
   double acc[4] = {0, 0, 0, 0};
   for (int k = 0; k < kPer; ++k) {
     const int64_t n = n0 + k * kB + threadIdx.x;
     if (n >= g.nodes) break;
     const int64_t e = g.poff + n * F;
-    float v[F], z[F];
+    float v[F];
     Vec<FV>::load(b + e, v);
 #pragma unroll
-    for (int c = 0; c < F; ++c) {
-      z[c] = 0.f;
-      acc[c] += (double)v[c] * (double)v[c];
-    }
-    Vec<FV>::store(x + e, z);
+    for (int c = 0; c < F; ++c) acc[c] += (double)v[c] * (double)v[c];
     Vec<FV>::store(r + e, v);
     Vec<FV>::store(p + e, v);
   }
@@ -234,11 +231,14 @@ __device__ void dir_ap_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
   store_partials<F>(acc, part, blk);
 }
 
-// r -= alpha A p; rr partial. XM = 1: also x += alpha_prev p_prev, then
-// x += alpha p (the term of the previous iteration and this one's).
+// r = r_in - alpha A p (r_in: r, or b in the first iteration); rr partial.
+// XM = 1: also x += alpha_prev p_prev, then x += alpha p (the term of the
+// previous iteration and this one's); XM = 2 (the first odd iteration): the
+// same from x = 0, which is not read.
 template <int XM, int FV, int F = (FV < 0 ? -FV : FV)>
 __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& fR2, int64_t n0, const double* st,
-                            int s, float* x, float* r, const float* p, const float* p_prev, double* part, int blk) {
+                            int s, float* x, const float* r_in, float* r, const float* p, const float* p_prev,
+                            double* part, int blk) {
   float al[F], ap[F];
 #pragma unroll
   for (int c = 0; c < F; ++c) {
@@ -268,13 +268,18 @@ __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
     }
     if (XM) {
       float xc[F], pp[F];
-      Vec<FV>::load(x + e, xc);
+      if (XM == 1) {
+        Vec<FV>::load(x + e, xc);
+      } else {
+#pragma unroll
+        for (int c = 0; c < F; ++c) xc[c] = 0.f;
+      }
       Vec<FV>::load(p_prev + e, pp);
 #pragma unroll
       for (int c = 0; c < F; ++c) xc[c] = fmaf(al[c], pc[c], fmaf(ap[c], pp[c], xc[c]));
       Vec<FV>::store(x + e, xc);
     }
-    Vec<FV>::load(r + e, rc);
+    Vec<FV>::load(r_in + e, rc);
 #pragma unroll
     for (int c = 0; c < F; ++c) {
       rc[c] = fmaf(-al[c], fmaf(lam, lap[c], pc[c]), rc[c]);
@@ -494,14 +499,16 @@ __device__ __forceinline__ ZmCols zm_cols(const Tile& t, int R, float lam, int n
   return c;
 }
 
-__device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* x, float* r, float* p, double* part,
+// b.b partials; r = p = b unless the grid is split (the V-cycle reads b
+// itself, the first update reads r from b, and the start's prolongation
+// writes the first direction). x is not written (see init_body).
+__device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* r, float* p, int split, double* part,
                         int blk) {
   const int R = g.R;
   const int64_t R2 = (int64_t)R * R;
   const int xx = t.x0 + (int)(threadIdx.x & (kTX - 1));
   const int yy = t.y0 + (int)(threadIdx.x / kTX);
   const float4* B = reinterpret_cast<const float4*>(b + g.poff);
-  float4* X = reinterpret_cast<float4*>(x + g.poff);
   float4* Rr = reinterpret_cast<float4*>(r + g.poff);
   float4* Pp = reinterpret_cast<float4*>(p + g.poff);
   double acc[4] = {0, 0, 0, 0};
@@ -509,9 +516,10 @@ __device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* 
     for (int z = t.z0; z < t.z1; ++z) {
       const int64_t n = (int64_t)z * R2 + (int64_t)yy * R + xx;
       const float4 v = B[n];
-      X[n] = make_float4(0.f, 0.f, 0.f, 0.f);
-      Rr[n] = v;
-      Pp[n] = v;
+      if (!split) {
+        Rr[n] = v;
+        Pp[n] = v;
+      }
       acc[0] += (double)v.x * v.x;
       acc[1] += (double)v.y * v.y;
       acc[2] += (double)v.z * v.z;
@@ -566,8 +574,8 @@ struct Raw3 {
 };
 
 template <int XM>
-__device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, float* x, float* r,
-                          const float* p, const float* p_prev, double* part, int blk) {
+__device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, float* x, const float* r_in,
+                          float* r, const float* p, const float* p_prev, double* part, int blk) {
   float al[4], ap[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -578,6 +586,7 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
   const float4* Pp = reinterpret_cast<const float4*>(p + g.poff);
   const float4* Pq = reinterpret_cast<const float4*>(p_prev + g.poff);
   float4* X = reinterpret_cast<float4*>(x + g.poff);
+  const float4* Ri = reinterpret_cast<const float4*>(r_in + g.poff);
   float4* Rr = reinterpret_cast<float4*>(r + g.poff);
   double acc[4] = {0, 0, 0, 0};
   auto r_update = [&](int64_t n, const float4& lap, const float4& pc, float4 rv) {
@@ -591,9 +600,23 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
     acc[2] += (double)rv.z * rv.z;
     acc[3] += (double)rv.w * rv.w;
   };
-  if (XM) {
+  if (XM == 2) {  // the first odd iteration: x = 0 + both terms, x not read
+    zm_walk<Raw1, Raw2>(
+        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw2{Ri[n], Pq[n]}; },
+        [&](const Raw1& v) { return v.a; },
+        [&](int64_t n, const float4& lap, const float4& pc, const Raw2& e) {
+          const float4 pq = e.b;
+          float4 xv;
+          xv.x = fmaf(al[0], pc.x, fmaf(ap[0], pq.x, 0.f));
+          xv.y = fmaf(al[1], pc.y, fmaf(ap[1], pq.y, 0.f));
+          xv.z = fmaf(al[2], pc.z, fmaf(ap[2], pq.z, 0.f));
+          xv.w = fmaf(al[3], pc.w, fmaf(ap[3], pq.w, 0.f));
+          X[n] = xv;
+          r_update(n, lap, pc, e.a);
+        });
+  } else if (XM) {
     zm_walk<Raw1, Raw3>(
-        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw3{X[n], Rr[n], Pq[n]}; },
+        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw3{X[n], Ri[n], Pq[n]}; },
         [&](const Raw1& v) { return v.a; },
         [&](int64_t n, const float4& lap, const float4& pc, const Raw3& e) {
           float4 xv = e.a;
@@ -607,7 +630,7 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
         });
   } else {
     zm_walk<Raw1, Raw1>(
-        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw1{Rr[n]}; },
+        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw1{Ri[n]}; },
         [&](const Raw1& v) { return v.a; },
         [&](int64_t n, const float4& lap, const float4& pc, const Raw1& e) { r_update(n, lap, pc, e.a); });
   }
@@ -624,19 +647,21 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
     default: { constexpr int FF = 1; CALL; } break;                         \
   }
 
+// sys_split (NULL without the V-cycle): the systems whose direction the
+// V-cycle's finest prolongation forms (see zm_init).
 __global__ __launch_bounds__(kB) void k_cg_init(const NpgGrid* __restrict__ G, int nb, const int* __restrict__ blk_sys,
-                                                const int64_t* __restrict__ blk_start, const float* b, float* x,
+                                                const int64_t* __restrict__ blk_start, const float* __restrict__ b,
                                                 float* __restrict__ r, float* __restrict__ p,
-                                                double* __restrict__ part) {
+                                                const int* __restrict__ sys_split, double* __restrict__ part) {
   const int blk = logical_block(nb);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   const NpgGrid g = G[s];
   if (use_zm(g)) {
-    zm_init(g, unpack_tile(blk_start[blk]), b, x, r, p, part, blk);
+    zm_init(g, unpack_tile(blk_start[blk]), b, r, p, sys_split ? sys_split[s] : 0, part, blk);
     return;
   }
-  NPG_F_SWITCH(g, (init_body<FF>(g, blk_start[blk], b, x, r, p, part, blk)));
+  NPG_F_SWITCH(g, (init_body<FF>(g, blk_start[blk], b, r, p, part, blk)));
 }
 
 struct Divs {
@@ -661,30 +686,36 @@ __global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G,
   NPG_F_SWITCH(g, (dir_ap_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, r, p_old, p_new, part, blk)));
 }
 
+// r_b: the right-hand side in the first iteration of a solve (r is read from
+// it, r = b not having been stored), NULL later (r updated in place).
 template <int XM>
 __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G, Divs dv, int nb, const int* __restrict__ blk_sys,
                                                   const int64_t* __restrict__ blk_start,
                                                   const int* __restrict__ active, const double* __restrict__ st,
-                                                  float* __restrict__ x, float* __restrict__ r,
-                                                  const float* __restrict__ p, const float* __restrict__ p_prev,
-                                                  double* __restrict__ part) {
+                                                  float* __restrict__ x, const float* __restrict__ r_b,
+                                                  float* __restrict__ r, const float* __restrict__ p,
+                                                  const float* __restrict__ p_prev, double* __restrict__ part) {
   const int blk = logical_block(nb);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   if (!active[s]) return;
   const NpgGrid g = G[s];
+  const float* r_in = r_b ? r_b : r;
   if (use_zm(g)) {
-    zm_update<XM>(g, unpack_tile(blk_start[blk]), st, s, x, r, p, p_prev, part, blk);
+    zm_update<XM>(g, unpack_tile(blk_start[blk]), st, s, x, r_in, r, p, p_prev, part, blk);
     return;
   }
-  NPG_F_SWITCH(g, (update_body<XM, FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, x, r, p, p_prev, part, blk)));
+  NPG_F_SWITCH(g, (update_body<XM, FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, x, r_in, r, p, p_prev, part,
+                                       blk)));
 }
 
-// The pending x terms a solve left when it stopped after an even iteration:
-// x += alpha_pending q for every system and channel, the factors (float32 of
-// the float64 scalar 7) read from the solve's scalars on the device. One
-// launch covers every system; a system with nothing pending is skipped by
-// every work-group.
+// The end of a solve, from its scalars on the device (float32 of the
+// float64 scalar 7: the x term still pending when a system stopped after an
+// even iteration; scalar 6: iterations taken). A system whose first odd
+// iteration ran (two or more iterations) has x stored: x += alpha_pending q
+// where a term is pending, otherwise nothing to do. A system that stopped
+// earlier never stored x: x = alpha_pending q after one iteration, x = 0
+// after none (q not read). One launch covers every system.
 __global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G, int n_sys,
                                                   const double* __restrict__ st, float* __restrict__ x,
                                                   const float* __restrict__ q) {
@@ -692,16 +723,21 @@ __global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G,
     const NpgGrid g = G[s];
     float a[4];
     bool any = false;
+    double taken = 0.0;
     for (int c = 0; c < 4; ++c) {
       a[c] = c < g.F ? (float)st[(s * 4 + c) * kS + 7] : 0.f;
       any |= a[c] != 0.f;
+      if (c < g.F) taken = fmax(taken, st[(s * 4 + c) * kS + 6]);
     }
-    if (!any) continue;
+    const bool stored = taken >= 2.0;
+    if (stored && !any) continue;
     const int64_t n = g.nodes * g.F;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
       const int c = (int)(e % g.F);
       const float ac = c == 0 ? a[0] : (c == 1 ? a[1] : (c == 2 ? a[2] : a[3]));
-      x[g.poff + e] = fmaf(ac, q[g.poff + e], x[g.poff + e]);
+      float* xe = x + g.poff + e;
+      if (stored) *xe = fmaf(ac, q[g.poff + e], *xe);
+      else *xe = taken >= 1.0 ? fmaf(ac, q[g.poff + e], 0.f) : 0.f;
     }
   }
 }
@@ -1281,6 +1317,7 @@ __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, 
 // the first sum is formed by the finest restriction (k_mg_down0) and the second
 // by the prolongation onto level 1 (k_mg_up, rz1 tasks), both before this
 // kernel runs.
+template <bool FIRST>
 __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, const float* __restrict__ r,
                           const float* __restrict__ eh, const float* __restrict__ p_old, float* __restrict__ p_new,
                           const float (&be)[4]) {
@@ -1296,7 +1333,7 @@ __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, con
   zm_walk_post<Raw2, Raw2>(
       g, t,
       [&](int64_t m, int s, int zz) { return Raw2{B[m], E[(zz >> 1) * nh2 + cols.pxy[s]]}; },
-      [&](int64_t m) { return Raw2{B[m], Po[m]}; },
+      [&](int64_t m) { return Raw2{B[m], FIRST ? make_float4(0.f, 0.f, 0.f, 0.f) : Po[m]}; },
       [&](const Raw2& v, int s, int zz) {
         const float f = (zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s];
         return f4add(f4scale(f, v.a), v.b);
@@ -1306,13 +1343,13 @@ __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, con
         const float4 ax = f4axpy(lam, lap, xc);
         const float f = (zz == 0 || zz == R - 1) ? cols.fbd[0] : cols.fin[0];
         const float4 zv = lam == 0.f ? bc : f4axpy(f, f4sub(bc, ax), xc);
-        Pn[n] = f4fma(e.b, be, zv);  // p = z + beta p_old, the float32 form of the direction update
+        Pn[n] = FIRST ? zv : f4fma(e.b, be, zv);  // p = z + beta p_old (p = z first)
       },
       [](int) {});
 }
 
-// Large grids: p_new = z + beta p_old (first: beta = 0), no partials;
-// otherwise z and its r.z partials.
+// Large grids: p_new = z + beta p_old (first: p_new = z, p_old not read), no
+// partials; otherwise z and its r.z partials.
 __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, int nb,
                                                const int* __restrict__ blk_sys, const int64_t* __restrict__ blk_start,
                                                const int* __restrict__ active, int check_active,
@@ -1331,7 +1368,8 @@ __global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, in
     float be[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) be[c] = first ? 0.f : (float)st[(s * 4 + c) * kS + 4];
-    mg_up0_zm(g, unpack_tile(blk_start[blk]), tk, r, eh, p_old, p_new, be);
+    if (first) mg_up0_zm<true>(g, unpack_tile(blk_start[blk]), tk, r, eh, p_old, p_new, be);
+    else mg_up0_zm<false>(g, unpack_tile(blk_start[blk]), tk, r, eh, p_old, p_new, be);
     return;
   } else {
     for (int k = 0; k < kPer; ++k) {
@@ -1509,7 +1547,7 @@ static npg_status mg_setup(npg_plan* P) {
 // level 1), then `beta` (when not NULL) reduces them, updates their scalars
 // (k_cg_reduce mode 2 of the split systems: beta, convergence), and the finest
 // prolongation writes their next direction p_dst = z + beta p_src (first:
-// beta = 0).
+// p_dst = z; p_src is not read).
 struct MgDir {
   const float* p_src;
   float* p_dst;
@@ -1664,21 +1702,22 @@ void cg_reduce(npg_plan* P, const CgCtx& c, int mode, int defer, int filter) {
 // Iteration 0 treats C.q as its direction: the start writes p_0 = z_0 there
 // (large grids of the multigrid form, in the V-cycle's finest prolongation;
 // the other grids form it in k_cg_dir_ap from z with beta = 0).
-npg_status cg_start(npg_plan* P, const CgCtx& c, const float* b, float* x) {
+npg_status cg_start(npg_plan* P, const CgCtx& c, const float* b) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
-  hipLaunchKernelGGL(k_cg_init, c.grid, c.blk, 0, s, P->d_g, C.n_blocks, C.blk_sys, C.blk_start, b, x, C.r, C.p,
-                     C.part);
-  if (c.mg) NPG_TRY_ST(mg_apply(P, C.r, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
+  hipLaunchKernelGGL(k_cg_init, c.grid, c.blk, 0, s, P->d_g, C.n_blocks, C.blk_sys, C.blk_start, b, C.r, C.p,
+                     c.mg ? C.sys_split : nullptr, C.part);
+  // r = b: the first V-cycle reads b (the split grids never store r = b)
+  if (c.mg) NPG_TRY_ST(mg_apply(P, b, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
   cg_reduce(P, c, 0, 0, -1);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
 
-// Iteration k (0-based) of a solve. With profiling on, HIP events bracket
-// the whole iteration (both streaming kernels, the V-cycle and both
-// reductions), resolved after the step.
-npg_status cg_iteration(npg_plan* P, const CgCtx& c, float* x, int k) {
+// Iteration k (0-based) of a solve of right-hand side b. With profiling on,
+// HIP events bracket the whole iteration (both streaming kernels, the V-cycle
+// and both reductions), resolved after the step.
+npg_status cg_iteration(npg_plan* P, const CgCtx& c, const float* b, float* x, int k) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const int nb = C.n_blocks;
@@ -1690,12 +1729,17 @@ npg_status cg_iteration(npg_plan* P, const CgCtx& c, float* x, int k) {
   hipLaunchKernelGGL(k_cg_dir_ap, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active, c.st,
                      c.dir_src, p_old, p_new, C.part, (int)c.mg);
   cg_reduce(P, c, 1, 0, -1);
-  if (odd)
+  // the first iteration reads r from b; the first odd one writes x from 0
+  const float* r_b = k == 0 ? b : nullptr;
+  if (k == 1)
+    hipLaunchKernelGGL(k_cg_update<2>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
+                       c.st, x, r_b, C.r, p_new, p_old, C.part);
+  else if (odd)
     hipLaunchKernelGGL(k_cg_update<1>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
-                       c.st, x, C.r, p_new, p_old, C.part);
+                       c.st, x, r_b, C.r, p_new, p_old, C.part);
   else
     hipLaunchKernelGGL(k_cg_update<0>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
-                       c.st, x, C.r, p_new, p_old, C.part);
+                       c.st, x, r_b, C.r, p_new, p_old, C.part);
   if (c.mg) {
     // large grids: beta (and the convergence test) before the prolongation,
     // which writes their next direction over p_old (its x term is added by
@@ -1731,7 +1775,7 @@ npg_status cg_solve_eager(npg_plan* P, int which, const float* b, float* x, bool
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const CgCtx c = cg_ctx(P, which);
-  NPG_TRY_ST(cg_start(P, c, b, x));
+  NPG_TRY_ST(cg_start(P, c, b));
   std::vector<int> act(P->n_sys);
   const int maxit = P->cfg.cg_maxit;
   const int last = C.last_iters[which];
@@ -1741,7 +1785,7 @@ npg_status cg_solve_eager(npg_plan* P, int which, const float* b, float* x, bool
   while (it < maxit) {
     const int want = it == 0 ? first : (last > 0 ? 2 : 16);
     const int chunk = std::min(want, maxit - it);
-    for (int k = 0; k < chunk; ++k) NPG_TRY_ST(cg_iteration(P, c, x, it + k));
+    for (int k = 0; k < chunk; ++k) NPG_TRY_ST(cg_iteration(P, c, b, x, it + k));
     it += chunk;
     NPG_HIP(hipMemcpyAsync(act.data(), C.active, P->n_sys * 4, hipMemcpyDeviceToHost, s));
     NPG_HIP(hipStreamSynchronize(s));
@@ -1817,8 +1861,8 @@ npg_status npg_run_precond_cg_fixed(npg_plan* P, float* grad, const int n_iter[2
   float* x[2] = {P->cg.x, grad};
   for (int which = 0; which < 2; ++which) {
     const CgCtx c = cg_ctx(P, which);
-    NPG_TRY_ST(cg_start(P, c, b[which], x[which]));
-    for (int k = 0; k < n_iter[which]; ++k) NPG_TRY_ST(cg_iteration(P, c, x[which], k));
+    NPG_TRY_ST(cg_start(P, c, b[which]));
+    for (int k = 0; k < n_iter[which]; ++k) NPG_TRY_ST(cg_iteration(P, c, b[which], x[which], k));
     const int bit = n_iter[which] >= P->cfg.cg_maxit ? 4 : (1 << which);
     hipLaunchKernelGGL(k_cg_done, dim3(1), dim3(64), 0, P->stream, P->cg.active, P->n_sys, state_dev, bit);
     NPG_HIP(hipGetLastError());

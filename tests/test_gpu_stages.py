@@ -378,6 +378,41 @@ def test_preconditioner_large_grids(levels, feat, method):
     plan.close()
 
 
+@pytest.mark.parametrize("method", ["cg", "cg_plain"])
+def test_preconditioner_early_stops_on_large_grids(method):
+    """Solves that stop before their first odd iteration on the z-column
+    grids: a zero right-hand side (no iteration: the result is exactly 0) and
+    lambda = 0 (one iteration: the identity), next to a grid that iterates.
+    The workspace and the gradient buffer hold a previous call's values, so a
+    result that is not written in full shows up."""
+    import torch
+
+    import paper_2602_22212_amd as npg
+    cfg = synth.config_small(levels=[100, 129, 20], lam=[0.0, 3.0, 1.0], feat_p=4, mlp_width=32, V=3000, T=1,
+                             N=10, t_key=0, seed=34, precond="cg", cg_mg=int(method == "cg"))
+    data = synth.make_workload(cfg)
+    plan = gpu_plan(cfg, data)
+    n_grid = dict((name, o) for name, o, _ in npg.param_layout(cfg)[0])["W0"]
+    lay = dict((name, (o, int(np.prod(s)))) for name, o, s in npg.param_layout(cfg)[0])
+    torch.manual_seed(5)
+    warm = torch.randn(plan.n_params, device="cuda")
+    assert plan.precond(warm)[1] == npg.NPG_OK
+    grad = torch.randn(plan.n_params, device="cuda")
+    o1, k1 = lay["grid_p1"]
+    grad[o1:o1 + k1] = 0.0
+    g_in = npg.unpack_params(cfg, to_np(grad))
+    its, st = plan.precond(grad)
+    assert st == npg.NPG_OK, its
+    got = npg.unpack_params(cfg, to_np(grad))
+    print("iterations per solve and system:", its)
+    assert rel(got["grid_p"][0], g_in["grid_p"][0]) < 1e-7  # lambda = 0
+    assert not np.any(got["grid_p"][1])                      # zero in, zero out
+    assert rel(got["grid_p"][2], O.precond_dct(g_in["grid_p"][2].astype(np.float64), 20, 1.0)) < TOL
+    assert rel(got["grid_n"], O.precond_dct(g_in["grid_n"].astype(np.float64), cfg["res_n"], cfg["lam_n"])) < TOL
+    assert np.array_equal(to_np(grad[n_grid:]), npg.pack_params(cfg, g_in)[n_grid:])
+    plan.close()
+
+
 def test_multigrid_preconditioned_cg_cuts_iterations():
     """The V-cycle preconditioned solves and plain CG reach the exact operator
     within the tolerance on the same input (smoothness up to the headline's
