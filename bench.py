@@ -185,13 +185,22 @@ def cpu_fast(cfg, data, P0, frames):
                 stage_seconds={k: round(v, 3) for k, v in t.items()})
 
 
+def keeps_activations(cfg, V, T):
+    """Whether the library's step keeps the decoder's hidden activations of
+    layers 2..H for its backward (the rule of plan creation: FP32 form, H > 1,
+    at most 8 GiB), so that the backward does not recompute them."""
+    W, H = cfg["mlp_width"], cfg["mlp_hidden"]
+    return cfg.get("precision", "fp32") != "bf16" and H > 1 and V * T * (H - 1) * W * 4 <= (8 << 30)
+
+
 def stage_roofline(cfg, data, stage_ms, precision, prof=None):
     """Per-stage algorithmic work over the measured stage time, against the
     roofline that bounds each stage: HBM bytes for the grid encode and its
     scatter, Adam and the CG preconditioner; MFMA FLOPs for the decoder (the
-    backward counts its recomputed forward, the back-propagation and the
-    weight gradient); FP32 vector FLOPs (10 per vertex-point pair and
-    direction pair) for the nearest-neighbour Chamfer."""
+    backward: back-propagation and weight gradient, twice the forward's
+    FLOPs; a recomputed forward is not counted, `recomputes_forward` says
+    whether the step does one); FP32 vector FLOPs (10 per vertex-point pair
+    and direction pair) for the nearest-neighbour Chamfer."""
     import paper_2602_22212_amd as npg
     V, T = len(data["xyz"]), data["T"]
     Ntot = int(data["frame_off"][-1])
@@ -208,7 +217,7 @@ def stage_roofline(cfg, data, stage_ms, precision, prof=None):
         "decode": ("mfma", fl_fwd),
         "chamfer+loss": ("alu", 10.0 * V * Ntot),
         "chamfer_bwd": ("hbm", T * V * 28 + Ntot * 16),
-        "decode_bwd": ("mfma", 3 * fl_fwd),
+        "decode_bwd": ("mfma", 2 * fl_fwd),
         "encode_bwd": ("hbm", V * (F + Fn) * 4 + n_grid * 4),
         "adam": ("hbm", 28 * n_par),
     }
@@ -228,6 +237,8 @@ def stage_roofline(cfg, data, stage_ms, precision, prof=None):
             pk = MFMA_PEAK_TFS[precision]
             out[k] = {"bound": "mfma", "dtype": precision, "algorithmic": w, "unit": "TFLOP/s", "achieved": round(a, 2),
                       "peak": pk, "frac": round(a / pk, 4)}
+            if k == "decode_bwd":
+                out[k]["recomputes_forward"] = not keeps_activations(cfg, V, T)
         else:
             a = w / 1e12 / (ms / 1e3)
             out[k] = {"bound": "alu", "algorithmic": w, "unit": "TFLOP/s", "achieved": round(a, 2),

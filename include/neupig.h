@@ -199,6 +199,10 @@ npg_status npg_state_export(npg_plan* plan, float* params_dev, float* m_dev, flo
  *              forward pass
  *   cd_dev     [T] float64 (may be NULL): per-frame Chamfer distances
  * Returns NPG_ENOTCONV (after completing the step) if a CG solve hit its cap.
+ * In the FP32 form the step's decoder forward keeps the hidden activations
+ * of layers 2..H for its backward (a plan buffer of T V (H-1) W floats,
+ * allocated at plan creation when it takes at most 8 GiB; larger plans
+ * recompute them): the same results, bitwise.
  * With the CG preconditioner the call synchronizes between batches of
  * iterations to test convergence (the first batch as long as the previous
  * call's same solve, at most 128, and 16 after a solve that reached the cap;
@@ -401,8 +405,9 @@ npg_status npg_objective_bwd(npg_plan* plan, const float* xhat_dev, const int32_
                              const double* w_dev, const double* g_dev, float* gxhat_dev);
 
 /*
- * Backward of decode: recomputes the MLP forward per tile (activations are
- * never stored), back-propagates gxhat through the transform and the MLP.
+ * Backward of decode: recomputes the MLP forward per tile (this entry point
+ * never reads stored activations), back-propagates gxhat through the
+ * transform and the MLP.
  *   grad_dev [P]: the MLP block of the flat gradient is overwritten (grid
  *                 blocks untouched); gz_dev [V][F_n+F_p] = sum over frames of
  *                 the decoder-input gradient's z part.

@@ -8,6 +8,9 @@
 #include "../../include/neupig.h"
 
 #define NPG_MAX_SYS (NPG_MAX_LEVELS + 1)
+// Largest buffer of stored hidden activations (npg_plan::act); a step whose
+// activations take more recomputes them in the backward.
+constexpr int64_t kActMaxBytes = int64_t(8) << 30;
 
 // One grid "system": a position level or the normal grid.
 struct NpgGrid {
@@ -118,6 +121,8 @@ struct npg_plan {
   uint16_t* wpack16;       // bfloat16 copy of wpack (BF16 form only)
   float* gam;              // [T][Din-Fz] time code
   float *Gv, *Gt, *Gt_part, *gW_part;
+  float* act;              // [T][V][H-1][W] hidden activations of layers 2..H, written by the step's forward
+                           // for its backward (FP32 form, when at most kActMaxBytes), else NULL
   int n_vblk_mlp;
   int64_t gw_part_len;
   // MLP backward schedule (both precisions): n_vblk_mlp 64-vertex blocks x
@@ -185,10 +190,13 @@ npg_status npg_build_scatter_table(npg_plan* P);
 hipError_t npg_launch_encode_fwd(const npg_plan* P, const float* params, float* z);
 hipError_t npg_launch_encode_bwd(const npg_plan* P, const float* gz, float* grad);
 // mlp.hip
+// act (FP32 form, H > 1; NULL: none): the forward also writes the hidden
+// activations of layers 2..H there, and the backward reads them instead of
+// recomputing (only for the parameters and z of the forward that wrote them)
 hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat,
-                                 float4* nhat = nullptr);
+                                 float4* nhat = nullptr, float* act = nullptr);
 hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const float* z,
-                                 const float4* gxhat, float* grad, float* gz);
+                                 const float4* gxhat, float* grad, float* gz, const float* act = nullptr);
 // chamfer.hip
 hipError_t npg_launch_chamfer_fwd(const npg_plan* P, const float4* xhat, int32_t* a, float* da,
                                   int32_t* b, float* db, double* cd);

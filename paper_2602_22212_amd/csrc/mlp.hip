@@ -372,14 +372,16 @@ __device__ __forceinline__ void mlp_hidden(v4f (&h)[H][W / 16], const float* __r
 
 // ---------------------------------------------------------------------------
 // Forward: 8 waves per work-group share the hidden and output weights in LDS;
-// each wave decodes 16-sample tiles in a grid-stride loop.
+// each wave decodes 16-sample tiles in a grid-stride loop. STORE: the hidden
+// activations of layers 2..H are also written to act ([T][V][H-1][W], sample
+// s = t V + i), for a backward that then does not recompute them.
 // ---------------------------------------------------------------------------
-template <int W, int H>
+template <int W, int H, bool STORE>
 __global__ __launch_bounds__(512) void k_decode_fwd(const float* __restrict__ wp, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float4* __restrict__ xyz,
                                                     float4* __restrict__ xhat, int64_t V, int T, ActP ap,
                                                     float alpha, int quat, const float4* __restrict__ nrm,
-                                                    float4* __restrict__ nhat) {
+                                                    float4* __restrict__ nhat, float* __restrict__ act) {
   constexpr int NT = W / 16;
   constexpr int LD = W + 4;  // padded LDS row
   extern __shared__ float lds[];
@@ -425,6 +427,15 @@ __global__ __launch_bounds__(512) void k_decode_fwd(const float* __restrict__ wp
     const int64_t t = s / V, i = s - t * V;
     v4f h[H][NT];
     mlp_hidden<W, H>(h, A, B, i, t, q, ap, whl, bh);
+    if (STORE && valid) {
+      float* dst = act + s * (int64_t)((H - 1) * W) + 4 * q;
+#pragma unroll
+      for (int l = 1; l < H; ++l)
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+          *reinterpret_cast<float4*>(dst + (l - 1) * W + 16 * mt) =
+              make_float4(h[l][mt][0], h[l][mt][1], h[l][mt][2], h[l][mt][3]);
+    }
     v4f o = dense_out<NT>(h[H - 1], boi, wol);
     float o4 = __shfl(o[0], (lane + 16) & 63);
     float o5 = __shfl(o[1], (lane + 16) & 63);
@@ -450,12 +461,16 @@ constexpr size_t bwd_lds_floats() {
   return (size_t)H * W * kSP + (size_t)W * kSP + (H - 1) * W + 16 + 4 * W;
 }
 
-template <int W, int H>
+// STORED: the hidden activations of layers 2..H are read from act (written
+// by the forward of the same parameters, bitwise what the recompute gives)
+// instead of recomputed; the first layer's act(A_i + B_t) is always formed.
+template <int W, int H, bool STORED>
 __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp, const float* __restrict__ A,
                                                     const float* __restrict__ B, const float4* __restrict__ xyz,
                                                     const float4* __restrict__ gxhat, int64_t V, int T, ActP ap,
                                                     float alpha, int quat, int nvb, int nch, float* __restrict__ Gv,
-                                                    float* __restrict__ Gt_part, float* __restrict__ gW_part) {
+                                                    float* __restrict__ Gt_part, float* __restrict__ gW_part,
+                                                    const float* __restrict__ act) {
   constexpr int NT = W / 16;
   constexpr int NTT = (NT * NT + 3) / 4;  // owned hidden weight-gradient tiles per wave
   constexpr int NTO = (NT + 3) / 4;       // owned output weight-gradient tiles per wave
@@ -560,22 +575,36 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
 #pragma unroll
         for (int r = 0; r < 4; ++r) at(sH, mt, r) = h[mt][r];
       }
+      if (STORED) {
+        const float* src = act + ((int64_t)t * V + i) * ((H - 1) * W) + 4 * q;
 #pragma unroll
-      for (int l = 1; l < H; ++l) {
-        v4f o[NT];
+        for (int l = 1; l < H; ++l)
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          float4 b = *reinterpret_cast<const float4*>(wpl + P.bh + (l - 1) * W + 16 * mt + 4 * q);
-          o[mt] = v4f{b.x, b.y, b.z, b.w};
-        }
-        dense<NT>(h, o, [&](int mt, int kt) {
-          return *reinterpret_cast<const float4*>(Wh + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt + 4 * q);
-        });
+          for (int mt = 0; mt < NT; ++mt) {
+            const float4 v = *reinterpret_cast<const float4*>(src + (l - 1) * W + 16 * mt);
+            h[mt] = v4f{v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          h[mt] = v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)};
+            for (int r = 0; r < 4; ++r) at(sH + l * W * kSP, mt, r) = h[mt][r];
+          }
+      } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) at(sH + l * W * kSP, mt, r) = h[mt][r];
+        for (int l = 1; l < H; ++l) {
+          v4f o[NT];
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) {
+            float4 b = *reinterpret_cast<const float4*>(wpl + P.bh + (l - 1) * W + 16 * mt + 4 * q);
+            o[mt] = v4f{b.x, b.y, b.z, b.w};
+          }
+          dense<NT>(h, o, [&](int mt, int kt) {
+            return *reinterpret_cast<const float4*>(Wh + (int64_t)(l - 1) * W * W + (16 * mt + c) * W + 16 * kt +
+                                                    4 * q);
+          });
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) {
+            h[mt] = v4f{actf(o[mt][0], ap), actf(o[mt][1], ap), actf(o[mt][2], ap), actf(o[mt][3], ap)};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) at(sH + l * W * kSP, mt, r) = h[mt][r];
+          }
         }
       }
       v4f o = dense_out<NT>(h, boi, [&](int kt) {
@@ -1482,28 +1511,38 @@ size_t bwd_lds() {
   return sizeof(float) * bwd_lds_floats<W, H>();
 }
 
-template <int W, int H>
-hipError_t launch_fwd(const npg_plan* P, float4* xhat, ActP ap, float4* nhat) {
+template <int W, int H, bool STORE>
+hipError_t launch_fwd_k(const npg_plan* P, float4* xhat, ActP ap, float4* nhat, float* act) {
   size_t lds = fwd_lds<W, H>();
-  hipError_t e = hipFuncSetAttribute((const void*)k_decode_fwd<W, H>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_decode_fwd<W, H, STORE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode_fwd<W, H>), dim3(P->n_cu), dim3(512), lds, P->stream, P->wpack, P->mlpA,
+  hipLaunchKernelGGL((k_decode_fwd<W, H, STORE>), dim3(P->n_cu), dim3(512), lds, P->stream, P->wpack, P->mlpA,
                      P->mlpB, P->xyz, xhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->nrm,
-                     nhat);
+                     nhat, act);
   return hipGetLastError();
 }
-
 template <int W, int H>
-hipError_t launch_bwd(const npg_plan* P, const float4* gxhat, ActP ap) {
+hipError_t launch_fwd(const npg_plan* P, float4* xhat, ActP ap, float4* nhat, float* act) {
+  if (H > 1 && act) return launch_fwd_k<W, H, (H > 1)>(P, xhat, ap, nhat, act);
+  return launch_fwd_k<W, H, false>(P, xhat, ap, nhat, nullptr);
+}
+
+template <int W, int H, bool STORED>
+hipError_t launch_bwd_k(const npg_plan* P, const float4* gxhat, ActP ap, const float* act) {
   size_t lds = bwd_lds<W, H>();
-  hipError_t e = hipFuncSetAttribute((const void*)k_decode_bwd<W, H>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_decode_bwd<W, H, STORED>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_decode_bwd<W, H>), dim3(P->mlp_grid), dim3(256), lds, P->stream, P->wpack, P->mlpA,
-                     P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7), P->n_vblk_mlp,
-                     P->mlp_nch, P->mlp_nch > 1 ? P->Gv_part : P->Gv, P->Gt_part, P->gW_part);
+  hipLaunchKernelGGL((k_decode_bwd<W, H, STORED>), dim3(P->mlp_grid), dim3(256), lds, P->stream, P->wpack,
+                     P->mlpA, P->mlpB, P->xyz, gxhat, P->V, P->T, ap, P->cfg.alpha_t, (int)(P->n_out == 7),
+                     P->n_vblk_mlp, P->mlp_nch, P->mlp_nch > 1 ? P->Gv_part : P->Gv, P->Gt_part, P->gW_part, act);
   return hipGetLastError();
+}
+template <int W, int H>
+hipError_t launch_bwd(const npg_plan* P, const float4* gxhat, ActP ap, const float* act) {
+  if (H > 1 && act) return launch_bwd_k<W, H, (H > 1)>(P, gxhat, ap, act);
+  return launch_bwd_k<W, H, false>(P, gxhat, ap, nullptr);
 }
 
 inline int is_bf16(const npg_plan* P) { return P->cfg.precision == NPG_PREC_BF16; }
@@ -1627,7 +1666,7 @@ int npg_mlp_bf16_frames() { return kB16TC; }
 int64_t npg_first_layer_blocks(int64_t V) { return (V + kFLV - 1) / kFLV; }
 
 hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const float* z, float4* xhat,
-                                 float4* nhat) {
+                                 float4* nhat, float* act) {
   hipError_t e = prep(P, params, z);
   if (e != hipSuccess) return e;
   const bool relu = P->cfg.act == NPG_ACT_RELU;
@@ -1635,7 +1674,7 @@ hipError_t npg_launch_decode_fwd(const npg_plan* P, const float* params, const f
   if (is_bf16(P)) {
     NPG_DISPATCH(launch_fwd16, P, xhat, ap, nhat);
   }
-  NPG_DISPATCH(launch_fwd, P, xhat, ap, nhat);
+  NPG_DISPATCH(launch_fwd, P, xhat, ap, nhat, act);
 }
 
 static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const float* z, float* grad, float* gz) {
@@ -1662,13 +1701,13 @@ static hipError_t decode_bwd_tail(const npg_plan* P, const float* params, const 
 }
 
 hipError_t npg_launch_decode_bwd(const npg_plan* P, const float* params, const float* z, const float4* gxhat,
-                                 float* grad, float* gz) {
+                                 float* grad, float* gz, const float* act) {
   hipError_t e = prep(P, params, z);
   if (e != hipSuccess) return e;
   const bool relu = P->cfg.act == NPG_ACT_RELU;
   ActP ap{relu, relu ? 0.f : P->cfg.leaky_slope};
   e = is_bf16(P) ? [&]() -> hipError_t { NPG_DISPATCH(launch_bwd16, P, gxhat, ap); }()
-                 : [&]() -> hipError_t { NPG_DISPATCH(launch_bwd, P, gxhat, ap); }();
+                 : [&]() -> hipError_t { NPG_DISPATCH(launch_bwd, P, gxhat, ap, act); }();
   if (e != hipSuccess) return e;
   return decode_bwd_tail(P, params, z, grad, gz);
 }

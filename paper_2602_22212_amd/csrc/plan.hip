@@ -151,12 +151,12 @@ npg_status capture_step(npg_plan* P) {
   NPG_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeRelaxed));
   auto enqueue = [&]() -> npg_status {
     NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
-    NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+    NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat, nullptr, P->act));
     NPG_HIP(npg_launch_chamfer_fwd(P, P->xhat, P->a, P->da, P->b, P->db, P->cd));
     NPG_HIP(npg_launch_loss(P, P->cd, 0, 1, P->w, P->loss, P->d_scal));
     NPG_HIP(npg_launch_chamfer_bwd(P, P->xhat, P->a, P->b, P->w, P->gxhat));
     if (P->cfg.w_iso > 0.f) NPG_HIP(npg_launch_iso(P, P->xhat, P->gxhat, P->iso_val, nullptr, P->loss));
-    NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz));
+    NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz, P->act));
     NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
     npg_status st = P->cfg.precond == NPG_PRECOND_DCT
                         ? npg_run_precond_dct(P, P->grad)
@@ -321,7 +321,7 @@ npg_status npg_plan_destroy(npg_plan* P) {
   void* bufs[] = {P->xyz, P->nrm, P->pts, P->vperm, P->d_off, P->pt_frame, P->d_g, P->e_vert, P->e_w, P->seg_key,
                   P->seg_chunk0, P->chunk_start, P->chunk_sum, P->chunk_sys, P->params, P->m, P->v, P->grad,
                   P->z, P->gz, P->xhat, P->gxhat, P->a, P->b, P->da, P->db, P->cd, P->w, P->loss, P->colpart,
-                  P->w_g, P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->fl_part, P->gam, P->d_flag};
+                  P->w_g, P->acc, P->mlpA, P->mlpB, P->wpack, P->wpack16, P->Gv, P->Gt, P->Gt_part, P->gW_part, P->Gv_part, P->fl_part, P->gam, P->d_flag, P->act};
   for (void* b : bufs)
     if (b) hipFree(b);
   npg_graph_reset(P);
@@ -496,6 +496,12 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   P->mlp_nch_alloc = P->mlp_nch > 1 ? P->mlp_nch : 0;
   P->mlp_grid_alloc = P->mlp_grid;
   TRYP(dalloc(&P->fl_part, npg_first_layer_blocks(V) * P->W * 8));
+  {
+    // the step's forward keeps the hidden activations of layers 2..H for its
+    // backward (FP32 form) when they fit kActMaxBytes; otherwise they are recomputed
+    const int64_t n_act = TV * (P->H - 1) * P->W;
+    if (cfg->precision != NPG_PREC_BF16 && P->H > 1 && n_act * 4 <= kActMaxBytes) TRYP(dalloc(&P->act, n_act));
+  }
   if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
   else TRYP(npg_cg_setup(P));
   for (auto& e : P->ev) HIPP(hipEventCreate(&e));
@@ -632,7 +638,7 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
   NPG_HIP(hipEventRecord(P->ev[0], s));
   NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
   NPG_HIP(hipEventRecord(P->ev[1], s));
-  NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+  NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat, nullptr, P->act));
   NPG_HIP(hipEventRecord(P->ev[2], s));
   NPG_HIP(npg_launch_chamfer_fwd(P, P->xhat, P->a, P->da, P->b, P->db, P->cd));
   NPG_HIP(npg_launch_loss(P, P->cd, epoch, n_epochs, P->w, P->loss));
@@ -641,7 +647,7 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
   NPG_HIP(hipEventRecord(P->ev[4], s));
   if (P->cfg.w_iso > 0.f) NPG_HIP(npg_launch_iso(P, P->xhat, P->gxhat, P->iso_val, nullptr, P->loss));
   NPG_HIP(hipEventRecord(P->ev[5], s));
-  NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz));
+  NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->gxhat, P->grad, P->gz, P->act));
   NPG_HIP(hipEventRecord(P->ev[6], s));
   NPG_HIP(npg_launch_encode_bwd(P, P->gz, P->grad));
   NPG_HIP(hipEventRecord(P->ev[7], s));
@@ -902,7 +908,7 @@ npg_status npg_tune_mlp(npg_plan* P, int32_t nch, int32_t* chosen, int32_t* cand
     // the plan's current decoder input and deformed vertices (the latter as
     // the upstream gradient: finite values of the right shape)
     NPG_HIP(npg_launch_encode_fwd(P, P->params, P->z));
-    NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat));
+    NPG_HIP(npg_launch_decode_fwd(P, P->params, P->z, P->xhat, nullptr, P->act));
     float best = 0.f;
     int best_n = h;
     for (size_t k = 0; k < c.size(); ++k) {
@@ -911,7 +917,7 @@ npg_status npg_tune_mlp(npg_plan* P, int32_t nch, int32_t* chosen, int32_t* cand
       TRY(time_calls(
           P,
           [&]() -> npg_status {
-            NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->xhat, P->grad, P->gz));
+            NPG_HIP(npg_launch_decode_bwd(P, P->params, P->z, P->xhat, P->grad, P->gz, P->act));
             return NPG_OK;
           },
           &t));
