@@ -558,6 +558,16 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
     const float4 xi = xyz[i];
 #pragma unroll
     for (int k = 0; k < NT; ++k) gv[k] = v4f{0.f, 0.f, 0.f, 0.f};
+    // the stored activations of the frame to come, loaded one frame ahead
+    float4 hn[STORED ? H - 1 : 1][NT];
+    auto load_act = [&](int t) {
+      const float* src = act + ((int64_t)t * V + i) * ((H - 1) * W) + 4 * q;
+#pragma unroll
+      for (int l = 1; l < H; ++l)
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) hn[l - 1][mt] = *reinterpret_cast<const float4*>(src + (l - 1) * W + 16 * mt);
+    };
+    if (STORED) load_act(t0);
     for (int t = t0; t < t1; ++t) {
       // Opaque copies of the weight pointers: keeps the compiler from hoisting
       // every (loop-invariant) weight load of the frame loop into registers.
@@ -576,16 +586,16 @@ __global__ __launch_bounds__(256) void k_decode_bwd(const float* __restrict__ wp
         for (int r = 0; r < 4; ++r) at(sH, mt, r) = h[mt][r];
       }
       if (STORED) {
-        const float* src = act + ((int64_t)t * V + i) * ((H - 1) * W) + 4 * q;
 #pragma unroll
         for (int l = 1; l < H; ++l)
 #pragma unroll
           for (int mt = 0; mt < NT; ++mt) {
-            const float4 v = *reinterpret_cast<const float4*>(src + (l - 1) * W + 16 * mt);
+            const float4 v = hn[l - 1][mt];
             h[mt] = v4f{v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int r = 0; r < 4; ++r) at(sH + l * W * kSP, mt, r) = h[mt][r];
           }
+        if (t + 1 < t1) load_act(t + 1);
       } else {
 #pragma unroll
         for (int l = 1; l < H; ++l) {
