@@ -891,7 +891,7 @@ struct MgTask {
   int fast;
   float mass, lw;
   FastDiv fx, fx2;
-  int zm0;  // finest restriction of a grid walked in z-column tiles (k_mg_down0)
+  int zm0;  // a finest restriction: runs in k_mg_down0 over the CG work-group table
   int rz1;  // prolongation onto level 1 of such a grid: b1 . e1 partials (the coarse r.z term)
 };
 
@@ -1285,9 +1285,14 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
       });
 }
 
+// The finest restriction of every grid, over the CG work-group table: the
+// z-column walk (with the fine r.z term) for the large grids; for the others
+// the grid's work-groups take its coarse nodes in turn (one thread per coarse
+// node, as in k_mg_down), so the V-cycle needs no separate launch for them.
 __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, int nb,
                                                  const int* __restrict__ blk_sys,
                                                  const int64_t* __restrict__ blk_start,
+                                                 const int* __restrict__ sys_blk0,
                                                  const int* __restrict__ active, int check_active,
                                                  const MgTask* __restrict__ T0, const float* __restrict__ r,
                                                  float* __restrict__ bh, double* __restrict__ part2) {
@@ -1298,6 +1303,14 @@ __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, 
   const MgTask* tk = T0 + s;
   if (!tk->zm0) return;
   const NpgGrid g = G[s];
+  if (!use_zm(g)) {
+    const int b0 = sys_blk0[s], nbs = sys_blk0[s + 1] - b0;
+    for (int64_t m = (int64_t)(blk - b0) * kB + threadIdx.x; m < tk->nodes; m += (int64_t)nbs * kB) {
+      if (tk->fast) mg_down_u4(tk, r, bh, (int)m);
+      else mg_down_gen(tk, r, bh, m);
+    }
+    return;
+  }
   double acc[4] = {0, 0, 0, 0};
   mg_down0_zm(g, unpack_tile(blk_start[blk]), tk, r, bh, acc);
   store_partials<4>(acc, part2, blk);
@@ -1442,7 +1455,7 @@ static npg_status mg_setup(npg_plan* P) {
       t.fast = t.lo.F == 4 && t.lo.off % 4 == 0 && t.hi.off % 4 == 0 && t.lo.R % t.lo.s == 0;
       // the z-column tiles of the CG table (same test as use_zm; every coarse
       // level is 16-byte aligned, so the float4 access to level 1 holds too)
-      t.zm0 = !up && l == 0 && t.lo.R >= kZmR && t.lo.F == 4 && t.lo.off % 4 == 0;
+      t.zm0 = !up && l == 0;  // every finest restriction runs in k_mg_down0
       if (t.fast) {
         const float sz = (float)t.lo.s;
         t.mass = sz * sz * sz;
@@ -1561,7 +1574,7 @@ static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_acti
   const int nl = C.mg_nlev;
   const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
   hipLaunchKernelGGL(k_mg_down0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
-                     C.blk_start, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2);
+                     C.blk_start, C.sys_blk0, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2);
   auto blk0 = [&](int li) {
     MgBlk0 b;
     for (int q = 0; q < kMgTaskMax; ++q) b.b[q] = C.mg_l_blk0[li][q];
