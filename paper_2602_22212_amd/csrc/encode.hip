@@ -150,11 +150,17 @@ __global__ void k_encode_bwd_chunks(const int32_t* __restrict__ chunk_start, con
 __global__ void k_encode_bwd_nodes(const int32_t* __restrict__ seg_key, const int32_t* __restrict__ seg_chunk0,
                                    int64_t n_seg, const float* __restrict__ chunk_sum,
                                    const NpgGrid* __restrict__ g, int n_sys, float* __restrict__ grad) {
+  // the systems' node offsets, read at the same addresses by every thread
+  // (one scalar batch) before the search, which then runs in registers
+  int64_t noff[NPG_MAX_SYS];
+#pragma unroll
+  for (int k = 0; k < NPG_MAX_SYS; ++k) noff[k] = k < n_sys ? g[k].noff : INT64_MAX;
   int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (u >= n_seg) return;
   const int64_t key = seg_key[u];
   int s = 0;
-  while (s + 1 < n_sys && key >= g[s + 1].noff) ++s;
+#pragma unroll
+  for (int k = 1; k < NPG_MAX_SYS; ++k) s += key >= noff[k];
   const int F = g[s].F;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   for (int c = seg_chunk0[u]; c < seg_chunk0[u + 1]; ++c)
