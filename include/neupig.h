@@ -201,8 +201,8 @@ npg_status npg_state_export(npg_plan* plan, float* params_dev, float* m_dev, flo
  * Returns NPG_ENOTCONV (after completing the step) if a CG solve hit its cap.
  * In the FP32 form the step's decoder forward keeps the hidden activations
  * of layers 2..H for its backward (a plan buffer of T V (H-1) W floats,
- * allocated at plan creation when it takes at most 8 GiB; larger plans
- * recompute them): the same results, bitwise.
+ * allocated at plan creation when it takes at most 8 GiB and the device has
+ * the memory; other plans recompute them): the same results, bitwise.
  * With the CG preconditioner the call synchronizes between batches of
  * iterations to test convergence (the first batch as long as the previous
  * call's same solve, at most 128, and 16 after a solve that reached the cap;

@@ -498,9 +498,14 @@ npg_status npg_plan_create(const npg_config* cfg, int64_t V, const float* xyz, c
   TRYP(dalloc(&P->fl_part, npg_first_layer_blocks(V) * P->W * 8));
   {
     // the step's forward keeps the hidden activations of layers 2..H for its
-    // backward (FP32 form) when they fit kActMaxBytes; otherwise they are recomputed
+    // backward (FP32 form) when they fit kActMaxBytes and device memory;
+    // otherwise (act stays NULL) the backward recomputes them
     const int64_t n_act = TV * (P->H - 1) * P->W;
-    if (cfg->precision != NPG_PREC_BF16 && P->H > 1 && n_act * 4 <= kActMaxBytes) TRYP(dalloc(&P->act, n_act));
+    if (cfg->precision != NPG_PREC_BF16 && P->H > 1 && n_act * 4 <= kActMaxBytes &&
+        hipMalloc(&P->act, n_act * sizeof(float)) != hipSuccess) {
+      P->act = nullptr;
+      (void)hipGetLastError();  // clear the failed allocation's error
+    }
   }
   if (cfg->precond == NPG_PRECOND_DCT) TRYP(npg_dct_setup(P));
   else TRYP(npg_cg_setup(P));
