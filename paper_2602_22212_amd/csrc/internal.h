@@ -50,6 +50,16 @@ struct NpgCG {  // conjugate-gradient workspace
   std::vector<int> mg_l_task0, mg_l_ntask, mg_l_nblk;  // per launch: first task, tasks, blocks
   int mg_nlev;                 // levels of the deepest hierarchy
   double mg_elems[NPG_MAX_SYS];  // per system: coarse-level floats summed over the levels
+  // Iterations in two groups of grids on two streams (n_grp = 2): group g
+  // holds systems [grp_sys[g], grp_sys[g+1]) and work-groups [grp_blk[g],
+  // grp_blk[g+1]) of the table; group 1 (the largest grid and the systems
+  // after it) runs on the plan's stream, group 0 on stream2; per V-cycle
+  // launch, group 0's blocks are [0, mg_split[l]), group 1's the rest
+  int n_grp = 1;
+  int grp_sys[3] = {0, 0, 0}, grp_blk[3] = {0, 0, 0};
+  std::vector<int> mg_split;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct NpgDct;
@@ -150,7 +160,7 @@ struct npg_plan {
   int* d_flag;             // non-finite flag
   hipEvent_t ev[10];
   float stage_ms[8];
-  // optional per-launch timing of the CG iteration kernels (profiling only)
+  // optional timing of the CG iterations (profiling only)
   int prof_cg;
   std::vector<hipEvent_t> prof_ev;
   // graph-captured step (npg_step_graph): its scalars, graph and capture stream
@@ -161,9 +171,10 @@ struct npg_plan {
   unsigned char* scratch = nullptr;  // this device's copy of the library's fixed scratch array
   int graph_iters[2] = {0, 0};       // CG form: iterations recorded for each solve
   int64_t graph_gen = 0;             // incremented by every recording (batch graphs compare it)
-  int prof_n;                       // events recorded in the current step
-  double prof_cg_ms;                // accumulated kernel time of resolved steps
-  int64_t prof_cg_launches;         // accumulated CG iterations (kernel pairs)
+  int prof_n;                       // events recorded in the current step (one pair per batch of iterations)
+  int prof_it;                      // iterations those pairs bracket
+  double prof_cg_ms;                // accumulated time of resolved steps' iteration batches
+  int64_t prof_cg_launches;         // accumulated CG iterations
   double prof_cg_bytes;             // accumulated algorithmic bytes
   double cg_alg_bytes;              // algorithmic bytes of the last preconditioner call (6 passes)
   double cg_alg_bytes_mg;           // the same counting z and the V-cycle's coarse levels

@@ -671,12 +671,13 @@ npg_status npg_step(npg_plan* P, int32_t epoch, int32_t n_epochs, double* loss_o
       NPG_HIP(hipEventElapsedTime(&a, P->prof_ev[k], P->prof_ev[k + 1]));
       P->prof_cg_ms += (double)a;
     }
-    P->prof_cg_launches += P->prof_n / 2;
+    P->prof_cg_launches += P->prof_it;
     if (P->cfg.precond == NPG_PRECOND_CG) {
       P->prof_cg_bytes += P->cg_alg_bytes;
       P->prof_cg_bytes_mg += P->cg_alg_bytes_mg;
     }
     P->prof_n = 0;
+    P->prof_it = 0;
   }
   if (loss_out) NPG_HIP(hipMemcpyAsync(loss_out, P->loss, 8, hipMemcpyDeviceToDevice, s));
   if (cd_out) NPG_HIP(hipMemcpyAsync(cd_out, P->cd, 8 * (size_t)P->T, hipMemcpyDeviceToDevice, s));
@@ -718,6 +719,7 @@ npg_status npg_profile(npg_plan* P, int32_t enable) {
   }
   P->prof_cg = enable ? 1 : 0;
   P->prof_n = 0;
+  P->prof_it = 0;
   P->prof_cg_ms = 0.0;
   P->prof_cg_launches = 0;
   P->prof_cg_bytes = 0.0;

@@ -106,14 +106,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 // row, so tiles that are y-neighbours (and share halo rows) run on the same
 // XCD and meet in its L2. The block table is walked in reverse, so the
 // largest grids (last in the table) are dispatched first. Launches are padded
-// to a multiple of 8 kXG work-groups; the padding returns at once.
+// to a multiple of 8 kXG work-groups; the padding returns at once. A launch
+// may cover the range [lo, nb) of the table (one group of grids).
 constexpr int kXCD = 8, kXG = 16;
-__device__ __forceinline__ int logical_block(int nb) {
+__device__ __forceinline__ int logical_block(int nb, int lo = 0) {
   const int b = (int)blockIdx.x;
   const int round = b / kXCD;
   const int fwd = (round / kXG) * (kXCD * kXG) + (b % kXCD) * kXG + round % kXG;
   const int lb = nb - 1 - fwd;
-  return lb >= 0 ? lb : -1;
+  return lb >= lo ? lb : -1;
 }
 
 // Block partials of F channels, part[blk*4 + c]: wave sums, then the 4
@@ -306,7 +307,7 @@ constexpr int kZmR = 100;  // grids with R >= kZmR, F = 4 and 16-byte alignment
 constexpr int kTX = 64, kTY = 4;  // tile columns; the z planes per tile are the plan's cg_zs (even)
 static_assert(kTX * kTY == kB, "one wave per tile row");
 
-__device__ __forceinline__ bool use_zm(const NpgGrid& g) { return g.R >= kZmR && g.F == 4 && (g.poff % 4) == 0; }
+__host__ __device__ __forceinline__ bool use_zm(const NpgGrid& g) { return g.R >= kZmR && g.F == 4 && (g.poff % 4) == 0; }
 
 struct Tile {
   int x0, y0, z0, z1;
@@ -668,12 +669,13 @@ struct Divs {
   FastDiv r[NPG_MAX_SYS], r2[NPG_MAX_SYS];
 };
 
-__global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G, Divs dv, int nb, const int* __restrict__ blk_sys,
+__global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G, Divs dv, int nb, int lo,
+                                                  const int* __restrict__ blk_sys,
                                                   const int64_t* __restrict__ blk_start,
                                                   const int* __restrict__ active, const double* __restrict__ st,
                                                   const float* __restrict__ r, const float* __restrict__ p_old,
                                                   float* __restrict__ p_new, double* __restrict__ part, int mgp) {
-  const int blk = logical_block(nb);
+  const int blk = logical_block(nb, lo);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   if (!active[s]) return;
@@ -689,13 +691,14 @@ __global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G,
 // r_b: the right-hand side in the first iteration of a solve (r is read from
 // it, r = b not having been stored), NULL later (r updated in place).
 template <int XM>
-__global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G, Divs dv, int nb, const int* __restrict__ blk_sys,
+__global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G, Divs dv, int nb, int lo,
+                                                  const int* __restrict__ blk_sys,
                                                   const int64_t* __restrict__ blk_start,
                                                   const int* __restrict__ active, const double* __restrict__ st,
                                                   float* __restrict__ x, const float* __restrict__ r_b,
                                                   float* __restrict__ r, const float* __restrict__ p,
                                                   const float* __restrict__ p_prev, double* __restrict__ part) {
-  const int blk = logical_block(nb);
+  const int blk = logical_block(nb, lo);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   if (!active[s]) return;
@@ -794,8 +797,8 @@ __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restr
                                                           const int* __restrict__ blk0_2, double* __restrict__ st,
                                                           int mode, double rtol, int defer,
                                                           const double* __restrict__ part3, const int2* __restrict__ r3,
-                                                          const int* __restrict__ sys_split, int filter) {
-  const int s = blockIdx.x;
+                                                          const int* __restrict__ sys_split, int filter, int s0) {
+  const int s = s0 + (int)blockIdx.x;
   if (mode != 0 && !active[s]) return;
   if (filter >= 0 && sys_split && (sys_split[s] != 0) != (filter != 0)) return;
   __shared__ double red[4][kR_WAVES], red2[4][kR_WAVES], red3[4][kR_WAVES];
@@ -937,11 +940,12 @@ __device__ __forceinline__ void mg_x0(const float* b, const MgLvl& L, int i, int
 // eighth of the logical blocks in order, so the neighbour rows and planes a
 // block reads were fetched into the same L2 by the blocks just before it.
 // -1 for the padding.
-__device__ __forceinline__ int mg_block(int nblk) {
-  const int per = (nblk + kXCD - 1) / kXCD;
+__device__ __forceinline__ int mg_block(int nblk, int lo = 0) {  // blocks [lo, nblk)
+  const int n = nblk - lo;
+  const int per = (n + kXCD - 1) / kXCD;
   const int b = (int)blockIdx.x;
   const int L = (b % kXCD) * per + b / kXCD;
-  return L < nblk ? L : -1;
+  return L < n ? lo + L : -1;
 }
 // The first block of each task of one launch (tasks sorted by blk0, at most
 // one per system; unused slots hold INT_MAX), passed by value so the lookup
@@ -1152,10 +1156,10 @@ __device__ __forceinline__ void mg_down_gen(const MgTask* tk, const float* __res
 
 // Restriction of the smoothed residual: thread per coarse node J,
 // bh[J] = sum over the children j of (b - A x0)[j], x0 = w D^-1 b.
-__global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, MgBlk0 B0, int nblk,
+__global__ __launch_bounds__(kMgB) void k_mg_down(const MgTask* __restrict__ T, MgBlk0 B0, int nblk, int lo,
                                                   const int* __restrict__ active, int check_active,
                                                   const float* __restrict__ bl, float* __restrict__ bh) {
-  const int blk = mg_block(nblk);
+  const int blk = mg_block(nblk, lo);
   if (blk < 0) return;
   const MgTask task = T[mg_task_of(B0, blk)];
   const MgTask* tk = &task;
@@ -1218,11 +1222,11 @@ __device__ __forceinline__ void mg_up_node(const MgTask* tk, const float* __rest
 
 // Prolongation and post-smoothing from level l+1 to l >= 1 (l = 0: k_mg_up0).
 // part3 (may be NULL): the b . out partials of every block of an rz1 task.
-__global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, MgBlk0 B0, int nblk,
+__global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, MgBlk0 B0, int nblk, int lo,
                                                 const int* __restrict__ active, int check_active,
                                                 const float* __restrict__ bl, const float* __restrict__ eh,
                                                 float* __restrict__ out, double* __restrict__ part3) {
-  const int blk = mg_block(nblk);
+  const int blk = mg_block(nblk, lo);
   if (blk < 0) return;
   const MgTask task = T[mg_task_of(B0, blk)];
   const MgTask* tk = &task;
@@ -1289,14 +1293,14 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
 // z-column walk (with the fine r.z term) for the large grids; for the others
 // the grid's work-groups take its coarse nodes in turn (one thread per coarse
 // node, as in k_mg_down), so the V-cycle needs no separate launch for them.
-__global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, int nb,
+__global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, int nb, int lo,
                                                  const int* __restrict__ blk_sys,
                                                  const int64_t* __restrict__ blk_start,
                                                  const int* __restrict__ sys_blk0,
                                                  const int* __restrict__ active, int check_active,
                                                  const MgTask* __restrict__ T0, const float* __restrict__ r,
                                                  float* __restrict__ bh, double* __restrict__ part2) {
-  const int blk = logical_block(nb);
+  const int blk = logical_block(nb, lo);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   if (check_active && !active[s]) return;
@@ -1363,14 +1367,14 @@ __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, con
 
 // Large grids: p_new = z + beta p_old (first: p_new = z, p_old not read), no
 // partials; otherwise z and its r.z partials.
-__global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, int nb,
+__global__ __launch_bounds__(kB) void k_mg_up0(const NpgGrid* __restrict__ G, int nb, int lo,
                                                const int* __restrict__ blk_sys, const int64_t* __restrict__ blk_start,
                                                const int* __restrict__ active, int check_active,
                                                const MgTask* __restrict__ T0, const float* __restrict__ r,
                                                const float* __restrict__ eh, float* __restrict__ z,
                                                double* __restrict__ part, const double* __restrict__ st,
                                                const float* __restrict__ p_old, float* __restrict__ p_new, int first) {
-  const int blk = logical_block(nb);
+  const int blk = logical_block(nb, lo);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   if (check_active && !active[s]) return;
@@ -1440,6 +1444,7 @@ static npg_status mg_setup(npg_plan* P) {
   C.mg_l_task0.assign(2 * nlev - 1, 0);
   C.mg_l_ntask.assign(2 * nlev - 1, 0);
   C.mg_l_nblk.assign(2 * nlev - 1, 0);
+  C.mg_split.assign(2 * nlev - 1, 0);
   auto add_launch = [&](int li, int l, bool up) {
     C.mg_l_task0[li] = (int)tasks.size();
     int blk = 0;
@@ -1472,6 +1477,12 @@ static npg_status mg_setup(npg_plan* P) {
     }
     C.mg_l_ntask[li] = (int)tasks.size() - C.mg_l_task0[li];
     C.mg_l_nblk[li] = blk;
+    C.mg_split[li] = blk;  // group 1's tasks (systems from grp_sys[1] on) start here
+    for (int q = C.mg_l_task0[li]; q < (int)tasks.size(); ++q)
+      if (tasks[q].sys >= C.grp_sys[1]) {
+        C.mg_split[li] = tasks[q].blk0;
+        break;
+      }
   };
   for (int l = 0; l + 1 < nlev; ++l) add_launch(l, l, false);
   for (int l = 0; l + 1 < nlev; ++l) add_launch(nlev - 1 + l, l, true);
@@ -1501,6 +1512,12 @@ static npg_status mg_setup(npg_plan* P) {
     }
     C.mg_l_ntask[li] = P->n_sys;
     C.mg_l_nblk[li] = blk;
+    C.mg_split[li] = blk;
+    for (int q = C.mg_l_task0[li]; q < (int)tasks.size(); ++q)
+      if (tasks[q].sys >= C.grp_sys[1]) {
+        C.mg_split[li] = tasks[q].blk0;
+        break;
+      }
   }
   // the finest prolongation runs over the CG work-group table (its tasks are
   // looked up by system: every system takes part, in order)
@@ -1567,37 +1584,62 @@ struct MgDir {
   const double* st;
   int first;
 };
-static npg_status mg_apply(npg_plan* P, const float* r, float* z, int check_active, const MgDir& d,
+// The grids of one V-cycle or CG call: systems [s_lo, s_hi) and CG
+// work-groups [b_lo, b_hi) on `stream`; grp is the group (0 or 1) of a
+// two-group plan, -1 for every system.
+struct CgGrp {
+  int grp, s_lo, s_hi, b_lo, b_hi;
+  hipStream_t stream;
+  bool split;  // a system of the range is split (its r.z taken in the V-cycle)
+};
+
+static CgGrp cg_all(const npg_plan* P) {
+  return CgGrp{-1, 0, P->n_sys, 0, P->cg.n_blocks, P->stream, P->cg.n_split > 0};
+}
+
+static CgGrp cg_grp(const npg_plan* P, int g) {
+  const NpgCG& C = P->cg;
+  if (C.n_grp == 1) return cg_all(P);
+  CgGrp G{g, C.grp_sys[g], C.grp_sys[g + 1], C.grp_blk[g], C.grp_blk[g + 1], g == 0 ? C.stream2 : P->stream, false};
+  for (int sy = G.s_lo; sy < G.s_hi; ++sy) G.split |= use_zm(P->g[sy]);
+  return G;
+}
+
+static npg_status mg_apply(npg_plan* P, const CgGrp& G, const float* r, float* z, int check_active, const MgDir& d,
                            const std::function<void()>& beta) {
   NpgCG& C = P->cg;
-  hipStream_t s = P->stream;
+  hipStream_t s = G.stream;
   const int nl = C.mg_nlev;
   const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
-  hipLaunchKernelGGL(k_mg_down0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
-                     C.blk_start, C.sys_blk0, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2);
+  const unsigned gb = xcd_grid(G.b_hi - G.b_lo);
+  hipLaunchKernelGGL(k_mg_down0, dim3(gb), dim3(kB), 0, s, P->d_g, G.b_hi, G.b_lo, C.blk_sys, C.blk_start,
+                     C.sys_blk0, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2);
   auto blk0 = [&](int li) {
     MgBlk0 b;
     for (int q = 0; q < kMgTaskMax; ++q) b.b[q] = C.mg_l_blk0[li][q];
     return b;
   };
   auto p3 = [&](int li) { return C.mg_l_p3[li] >= 0 ? C.part3 + (int64_t)C.mg_l_p3[li] * 4 : nullptr; };
+  // this range's blocks of launch li: [lo, hi)
+  auto range = [&](int li, int& lo, int& hi) {
+    lo = G.grp == 1 ? C.mg_split[li] : 0;
+    hi = G.grp == 0 ? C.mg_split[li] : C.mg_l_nblk[li];
+    return hi > lo;
+  };
+  int lo, hi;
   for (int l = 0; l + 1 < nl; ++l)
-    if (C.mg_l_nblk[l] > 0)
-      hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(C.mg_l_nblk[l])), dim3(kMgB), 0, s, T + C.mg_l_task0[l], blk0(l),
-                         C.mg_l_nblk[l], C.active, check_active, l == 0 ? r : C.mgB, C.mgB);
-  const int lc = 2 * (nl - 1);
-  hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[lc])), dim3(kMgB), 0, s, T + C.mg_l_task0[lc], blk0(lc),
-                     C.mg_l_nblk[lc], C.active, check_active, C.mgB, C.mgX, C.mgX, p3(lc));
-  for (int l = nl - 2; l >= 1; --l) {
-    const int li = nl - 1 + l;
-    if (C.mg_l_nblk[li] > 0)
-      hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(C.mg_l_nblk[li])), dim3(kMgB), 0, s, T + C.mg_l_task0[li],
-                         blk0(li), C.mg_l_nblk[li], C.active, check_active, C.mgB, C.mgX, C.mgX, p3(li));
+    if (range(l, lo, hi))
+      hipLaunchKernelGGL(k_mg_down, dim3(mg_grid(hi - lo)), dim3(kMgB), 0, s, T + C.mg_l_task0[l], blk0(l), hi, lo,
+                         C.active, check_active, l == 0 ? r : C.mgB, C.mgB);
+  for (int l = nl - 1; l >= 1; --l) {
+    const int li = l == nl - 1 ? 2 * (nl - 1) : nl - 1 + l;  // the coarsest solve, then the prolongations
+    if (range(li, lo, hi))
+      hipLaunchKernelGGL(k_mg_up, dim3(mg_grid(hi - lo)), dim3(kMgB), 0, s, T + C.mg_l_task0[li], blk0(li), hi, lo,
+                         C.active, check_active, C.mgB, C.mgX, C.mgX, p3(li));
   }
   if (beta) beta();
-  hipLaunchKernelGGL(k_mg_up0, dim3(xcd_grid(C.n_blocks)), dim3(kB), 0, s, P->d_g, C.n_blocks, C.blk_sys,
-                     C.blk_start, C.active, check_active, T + C.mg_l_task0[nl - 1], r, C.mgX, z, C.part2, d.st,
-                     d.p_src, d.p_dst, d.first);
+  hipLaunchKernelGGL(k_mg_up0, dim3(gb), dim3(kB), 0, s, P->d_g, G.b_hi, G.b_lo, C.blk_sys, C.blk_start, C.active,
+                     check_active, T + C.mg_l_task0[nl - 1], r, C.mgX, z, C.part2, d.st, d.p_src, d.p_dst, d.first);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
@@ -1642,6 +1684,31 @@ npg_status npg_cg_setup(npg_plan* P) {
   NPG_HIP(hipMemcpy(C.blk_sys, bsys.data(), C.n_blocks * 4, hipMemcpyHostToDevice));
   NPG_HIP(hipMemcpy(C.blk_start, bstart.data(), C.n_blocks * 8, hipMemcpyHostToDevice));
   NPG_HIP(hipMemcpy(C.sys_blk0, s0.data(), (P->n_sys + 1) * 4, hipMemcpyHostToDevice));
+  // Two groups when the largest grid is walked in z-column tiles and other
+  // grids come before it: the largest and the systems after it (group 1, on
+  // the plan's stream) iterate beside the grids before it (group 0, on a
+  // second stream), so the short latency-bound launches of one group overlap
+  // the streaming kernels of the other. The systems are independent, so the
+  // results are those of one group.
+  {
+    int big = 0;
+    for (int sy = 1; sy < P->n_sys; ++sy)
+      if (P->g[sy].nodes * P->g[sy].F > P->g[big].nodes * P->g[big].F) big = sy;
+    const NpgGrid& gb = P->g[big];
+    const bool zm = gb.R >= kZmR && gb.F == 4 && gb.poff % 4 == 0;
+    C.n_grp = big > 0 && zm ? 2 : 1;
+    C.grp_sys[0] = 0;
+    C.grp_sys[1] = C.n_grp == 2 ? big : P->n_sys;
+    C.grp_sys[2] = P->n_sys;
+    C.grp_blk[0] = 0;
+    C.grp_blk[1] = s0[C.grp_sys[1]];
+    C.grp_blk[2] = C.n_blocks;
+    if (C.n_grp == 2) {
+      NPG_HIP(hipStreamCreateWithFlags(&C.stream2, hipStreamNonBlocking));
+      NPG_HIP(hipEventCreateWithFlags(&C.ev_fork, hipEventDisableTiming));
+      NPG_HIP(hipEventCreateWithFlags(&C.ev_join, hipEventDisableTiming));
+    }
+  }
   C.mg = P->cfg.cg_mg != 0;
   if (C.mg) {
     const npg_status st = mg_setup(P);
@@ -1656,6 +1723,9 @@ void npg_cg_free(npg_plan* P) {
                   C.z, C.mgB, C.mgX, C.part2, C.mg_tasks, C.part3, C.r3, C.sys_split};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  if (C.stream2) (void)hipStreamDestroy(C.stream2);
+  if (C.ev_fork) (void)hipEventDestroy(C.ev_fork);
+  if (C.ev_join) (void)hipEventDestroy(C.ev_join);
   const int keep[2] = {C.last_iters[0], C.last_iters[1]};
   C = NpgCG();
   C.last_iters[0] = keep[0];
@@ -1702,14 +1772,14 @@ CgCtx cg_ctx(const npg_plan* P, int which) {
   return c;
 }
 
-// The scalar update of every system (filter -1), of the systems whose r.z is
+// The scalar update of the range's systems (filter -1), of those whose r.z is
 // split over the finest restriction and level 1 (filter 1), or of the others
 // (filter 0); see k_cg_reduce.
-void cg_reduce(npg_plan* P, const CgCtx& c, int mode, int defer, int filter) {
+void cg_reduce(npg_plan* P, const CgCtx& c, const CgGrp& G, int mode, int defer, int filter) {
   NpgCG& C = P->cg;
-  hipLaunchKernelGGL(k_cg_reduce, dim3(P->n_sys), dim3(kR_THREADS), 0, P->stream, P->d_g, C.sys_blk0, C.active,
-                     C.part, c.part2, C.sys_blk0, c.st, mode, P->cfg.cg_rtol, defer, c.mg ? C.part3 : nullptr,
-                     c.mg ? C.r3 : nullptr, c.mg ? C.sys_split : nullptr, filter);
+  hipLaunchKernelGGL(k_cg_reduce, dim3(G.s_hi - G.s_lo), dim3(kR_THREADS), 0, G.stream, P->d_g, C.sys_blk0,
+                     C.active, C.part, c.part2, C.sys_blk0, c.st, mode, P->cfg.cg_rtol, defer,
+                     c.mg ? C.part3 : nullptr, c.mg ? C.r3 : nullptr, c.mg ? C.sys_split : nullptr, filter, G.s_lo);
 }
 
 // Iteration 0 treats C.q as its direction: the start writes p_0 = z_0 there
@@ -1718,56 +1788,81 @@ void cg_reduce(npg_plan* P, const CgCtx& c, int mode, int defer, int filter) {
 npg_status cg_start(npg_plan* P, const CgCtx& c, const float* b) {
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
+  const CgGrp all = cg_all(P);
   hipLaunchKernelGGL(k_cg_init, c.grid, c.blk, 0, s, P->d_g, C.n_blocks, C.blk_sys, C.blk_start, b, C.r, C.p,
                      c.mg ? C.sys_split : nullptr, C.part);
   // r = b: the first V-cycle reads b (the split grids never store r = b)
-  if (c.mg) NPG_TRY_ST(mg_apply(P, b, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
-  cg_reduce(P, c, 0, 0, -1);
+  if (c.mg) NPG_TRY_ST(mg_apply(P, all, b, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
+  cg_reduce(P, c, all, 0, 0, -1);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
 
-// Iteration k (0-based) of a solve of right-hand side b. With profiling on,
-// HIP events bracket the whole iteration (both streaming kernels, the V-cycle
-// and both reductions), resolved after the step.
-npg_status cg_iteration(npg_plan* P, const CgCtx& c, const float* b, float* x, int k) {
+// Iteration k (0-based) of a solve of right-hand side b over the grids of G,
+// on G's stream.
+npg_status cg_iteration(npg_plan* P, const CgCtx& c, const CgGrp& G, const float* b, float* x, int k) {
   NpgCG& C = P->cg;
-  hipStream_t s = P->stream;
-  const int nb = C.n_blocks;
+  hipStream_t s = G.stream;
+  const dim3 grid(xcd_grid(G.b_hi - G.b_lo));
+  const int nb = G.b_hi, lo = G.b_lo;
   const bool odd = (k & 1) != 0;
   float* p_old = odd ? C.q : C.p;
   float* p_new = odd ? C.p : C.q;
-  const bool prof = P->prof_cg && P->prof_n + 2 <= (int)P->prof_ev.size();
-  if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n], s));
-  hipLaunchKernelGGL(k_cg_dir_ap, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active, c.st,
+  hipLaunchKernelGGL(k_cg_dir_ap, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active, c.st,
                      c.dir_src, p_old, p_new, C.part, (int)c.mg);
-  cg_reduce(P, c, 1, 0, -1);
+  cg_reduce(P, c, G, 1, 0, -1);
   // the first iteration reads r from b; the first odd one writes x from 0
   const float* r_b = k == 0 ? b : nullptr;
   if (k == 1)
-    hipLaunchKernelGGL(k_cg_update<2>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
+    hipLaunchKernelGGL(k_cg_update<2>, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active,
                        c.st, x, r_b, C.r, p_new, p_old, C.part);
   else if (odd)
-    hipLaunchKernelGGL(k_cg_update<1>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
+    hipLaunchKernelGGL(k_cg_update<1>, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active,
                        c.st, x, r_b, C.r, p_new, p_old, C.part);
   else
-    hipLaunchKernelGGL(k_cg_update<0>, c.grid, c.blk, 0, s, P->d_g, c.dv, nb, C.blk_sys, C.blk_start, C.active,
+    hipLaunchKernelGGL(k_cg_update<0>, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active,
                        c.st, x, r_b, C.r, p_new, p_old, C.part);
   if (c.mg) {
     // large grids: beta (and the convergence test) before the prolongation,
     // which writes their next direction over p_old (its x term is added by
     // this iteration's update, the odd one); the other grids after it
-    const std::function<void()> beta = [&]() { cg_reduce(P, c, 2, (int)!odd, 1); };
-    NPG_TRY_ST(mg_apply(P, C.r, C.z, 1, MgDir{p_new, p_old, c.st, 0}, C.n_split > 0 ? beta : nullptr));
-    cg_reduce(P, c, 2, (int)!odd, 0);
+    const std::function<void()> beta = [&]() { cg_reduce(P, c, G, 2, (int)!odd, 1); };
+    NPG_TRY_ST(mg_apply(P, G, C.r, C.z, 1, MgDir{p_new, p_old, c.st, 0}, G.split ? beta : nullptr));
+    cg_reduce(P, c, G, 2, (int)!odd, 0);
   } else {
-    cg_reduce(P, c, 2, (int)!odd, -1);
-  }
-  if (prof) {
-    NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], s));
-    P->prof_n += 2;
+    cg_reduce(P, c, G, 2, (int)!odd, -1);
   }
   NPG_HIP(hipGetLastError());
+  return NPG_OK;
+}
+
+// Iterations [k0, k0 + n) of a solve over every system: with two groups, the
+// second stream waits for the plan's stream, each group's iterations go to
+// its own stream (interleaved, so that both are fed), and the plan's stream
+// waits for the second at the end. With profiling on, HIP events on the
+// plan's stream bracket the batch, resolved after the step.
+npg_status cg_iterations(npg_plan* P, const CgCtx& c, const float* b, float* x, int k0, int n) {
+  NpgCG& C = P->cg;
+  const bool prof = P->prof_cg && P->prof_n + 2 <= (int)P->prof_ev.size();
+  if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n], P->stream));
+  if (C.n_grp == 2) {
+    NPG_HIP(hipEventRecord(C.ev_fork, P->stream));
+    NPG_HIP(hipStreamWaitEvent(C.stream2, C.ev_fork, 0));
+  }
+  const CgGrp G0 = cg_grp(P, 0), G1 = cg_grp(P, 1);
+  for (int k = k0; k < k0 + n; ++k) {
+    NPG_TRY_ST(cg_iteration(P, c, G0, b, x, k));
+    if (C.n_grp == 2) NPG_TRY_ST(cg_iteration(P, c, G1, b, x, k));
+  }
+  if (C.n_grp == 2) {
+    NPG_HIP(hipEventRecord(C.ev_join, C.stream2));
+    NPG_HIP(hipStreamWaitEvent(P->stream, C.ev_join, 0));
+  }
+  if (prof) {
+    NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n + 1], P->stream));
+    P->prof_n += 2;
+    P->prof_it += n;
+  }
   return NPG_OK;
 }
 
@@ -1798,7 +1893,7 @@ npg_status cg_solve_eager(npg_plan* P, int which, const float* b, float* x, bool
   while (it < maxit) {
     const int want = it == 0 ? first : (last > 0 ? 2 : 16);
     const int chunk = std::min(want, maxit - it);
-    for (int k = 0; k < chunk; ++k) NPG_TRY_ST(cg_iteration(P, c, b, x, it + k));
+    NPG_TRY_ST(cg_iterations(P, c, b, x, it, chunk));
     it += chunk;
     NPG_HIP(hipMemcpyAsync(act.data(), C.active, P->n_sys * 4, hipMemcpyDeviceToHost, s));
     NPG_HIP(hipStreamSynchronize(s));
@@ -1875,7 +1970,7 @@ npg_status npg_run_precond_cg_fixed(npg_plan* P, float* grad, const int n_iter[2
   for (int which = 0; which < 2; ++which) {
     const CgCtx c = cg_ctx(P, which);
     NPG_TRY_ST(cg_start(P, c, b[which]));
-    for (int k = 0; k < n_iter[which]; ++k) NPG_TRY_ST(cg_iteration(P, c, b[which], x[which], k));
+    if (n_iter[which] > 0) NPG_TRY_ST(cg_iterations(P, c, b[which], x[which], 0, n_iter[which]));
     const int bit = n_iter[which] >= P->cfg.cg_maxit ? 4 : (1 << which);
     hipLaunchKernelGGL(k_cg_done, dim3(1), dim3(64), 0, P->stream, P->cg.active, P->n_sys, state_dev, bit);
     NPG_HIP(hipGetLastError());
