@@ -124,6 +124,12 @@ typedef struct npg_config {
   int32_t cg_mg;                  /* CG form: 1 preconditions every solve with a     */
                                   /* multigrid V-cycle, 0 runs plain CG             */
   int32_t nn_search;              /* NPG_NN_PRUNED (default) or NPG_NN_EXHAUSTIVE   */
+  int32_t cg_one_stream;          /* CG form: 0 (default) iterates the grids before */
+                                  /* the largest on a second stream beside it when  */
+                                  /* the largest is a z-column-tiled grid; 1 keeps  */
+                                  /* every launch on the plan's stream (the same    */
+                                  /* launches, one group after the other); the      */
+                                  /* results are the same bit for bit               */
 } npg_config;
 
 typedef struct npg_plan npg_plan;

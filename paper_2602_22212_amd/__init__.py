@@ -42,7 +42,7 @@ class npg_config(ctypes.Structure):
         ("conf_weight", ctypes.c_int32), ("t_key", ctypes.c_int32),
         ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precond", ctypes.c_int32),
         ("rot_head", ctypes.c_int32), ("w_iso", ctypes.c_float), ("precision", ctypes.c_int32),
-        ("cg_mg", ctypes.c_int32), ("nn_search", ctypes.c_int32),
+        ("cg_mg", ctypes.c_int32), ("nn_search", ctypes.c_int32), ("cg_one_stream", ctypes.c_int32),
     ]
 
 
@@ -144,6 +144,7 @@ def make_config(cfg):
     c.cg_rtol, c.cg_maxit = float(cfg["cg_rtol"]), int(cfg["cg_maxit"])
     c.precond = NPG_PRECOND_DCT if cfg.get("precond", "cg") == "dct" else NPG_PRECOND_CG
     c.cg_mg = int(cfg.get("cg_mg", 1))
+    c.cg_one_stream = int(cfg.get("cg_one_stream", 0))
     nn = cfg.get("nn_search", "pruned")
     if nn not in ("pruned", "exhaustive"):
         raise ValueError(f"nn_search must be 'pruned' or 'exhaustive', not {nn!r}")

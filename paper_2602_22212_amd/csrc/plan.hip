@@ -94,6 +94,7 @@ npg_status validate_cfg(const npg_config* c) {
   CHECK_ARG(c->cg_maxit >= 1 && c->cg_rtol > 0.0, "cg_maxit >= 1 and cg_rtol > 0 are required");
   CHECK_ARG(c->precond == NPG_PRECOND_CG || c->precond == NPG_PRECOND_DCT, "precond must be CG or DCT");
   CHECK_ARG(c->cg_mg == 0 || c->cg_mg == 1, "cg_mg must be 0 or 1");
+  CHECK_ARG(c->cg_one_stream == 0 || c->cg_one_stream == 1, "cg_one_stream must be 0 or 1");
   CHECK_ARG(c->nn_search == NPG_NN_PRUNED || c->nn_search == NPG_NN_EXHAUSTIVE,
             "nn_search must be NPG_NN_PRUNED or NPG_NN_EXHAUSTIVE");
   CHECK_ARG(c->rot_head == NPG_ROT_EXPMAP || c->rot_head == NPG_ROT_QUAT, "rot_head must be EXPMAP or QUAT");

@@ -1600,7 +1600,8 @@ static CgGrp cg_all(const npg_plan* P) {
 static CgGrp cg_grp(const npg_plan* P, int g) {
   const NpgCG& C = P->cg;
   if (C.n_grp == 1) return cg_all(P);
-  CgGrp G{g, C.grp_sys[g], C.grp_sys[g + 1], C.grp_blk[g], C.grp_blk[g + 1], g == 0 ? C.stream2 : P->stream, false};
+  hipStream_t s = g == 0 && C.stream2 ? C.stream2 : P->stream;
+  CgGrp G{g, C.grp_sys[g], C.grp_sys[g + 1], C.grp_blk[g], C.grp_blk[g + 1], s, false};
   for (int sy = G.s_lo; sy < G.s_hi; ++sy) G.split |= use_zm(P->g[sy]);
   return G;
 }
@@ -1687,9 +1688,9 @@ npg_status npg_cg_setup(npg_plan* P) {
   // Two groups when the largest grid is walked in z-column tiles and other
   // grids come before it: the largest and the systems after it (group 1, on
   // the plan's stream) iterate beside the grids before it (group 0, on a
-  // second stream), so the short latency-bound launches of one group overlap
-  // the streaming kernels of the other. The systems are independent, so the
-  // results are those of one group.
+  // second stream unless cfg.cg_one_stream), so the short latency-bound
+  // launches of one group overlap the streaming kernels of the other. The
+  // systems are independent, so the results do not depend on the grouping.
   {
     int big = 0;
     for (int sy = 1; sy < P->n_sys; ++sy)
@@ -1703,7 +1704,7 @@ npg_status npg_cg_setup(npg_plan* P) {
     C.grp_blk[0] = 0;
     C.grp_blk[1] = s0[C.grp_sys[1]];
     C.grp_blk[2] = C.n_blocks;
-    if (C.n_grp == 2) {
+    if (C.n_grp == 2 && !P->cfg.cg_one_stream) {
       NPG_HIP(hipStreamCreateWithFlags(&C.stream2, hipStreamNonBlocking));
       NPG_HIP(hipEventCreateWithFlags(&C.ev_fork, hipEventDisableTiming));
       NPG_HIP(hipEventCreateWithFlags(&C.ev_join, hipEventDisableTiming));
@@ -1836,16 +1837,16 @@ npg_status cg_iteration(npg_plan* P, const CgCtx& c, const CgGrp& G, const float
   return NPG_OK;
 }
 
-// Iterations [k0, k0 + n) of a solve over every system: with two groups, the
-// second stream waits for the plan's stream, each group's iterations go to
-// its own stream (interleaved, so that both are fed), and the plan's stream
-// waits for the second at the end. With profiling on, HIP events on the
+// Iterations [k0, k0 + n) of a solve over every system: with two groups on
+// two streams, the second stream waits for the plan's stream, each group's
+// iterations go to its own stream (interleaved, so that both are fed), and
+// the plan's stream waits for the second at the end. With profiling on, HIP events on the
 // plan's stream bracket the batch, resolved after the step.
 npg_status cg_iterations(npg_plan* P, const CgCtx& c, const float* b, float* x, int k0, int n) {
   NpgCG& C = P->cg;
   const bool prof = P->prof_cg && P->prof_n + 2 <= (int)P->prof_ev.size();
   if (prof) NPG_HIP(hipEventRecord(P->prof_ev[P->prof_n], P->stream));
-  if (C.n_grp == 2) {
+  if (C.stream2) {
     NPG_HIP(hipEventRecord(C.ev_fork, P->stream));
     NPG_HIP(hipStreamWaitEvent(C.stream2, C.ev_fork, 0));
   }
@@ -1854,7 +1855,7 @@ npg_status cg_iterations(npg_plan* P, const CgCtx& c, const float* b, float* x, 
     NPG_TRY_ST(cg_iteration(P, c, G0, b, x, k));
     if (C.n_grp == 2) NPG_TRY_ST(cg_iteration(P, c, G1, b, x, k));
   }
-  if (C.n_grp == 2) {
+  if (C.stream2) {
     NPG_HIP(hipEventRecord(C.ev_join, C.stream2));
     NPG_HIP(hipStreamWaitEvent(P->stream, C.ev_join, 0));
   }

@@ -38,17 +38,19 @@ def test_library_exports_every_declared_symbol():
 def test_config_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "neupig.h"\n'
-                    "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(npg_config),"
+                    "int main(){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(npg_config),"
                     " offsetof(npg_config, lam), offsetof(npg_config, cg_rtol),"
                     " offsetof(npg_config, cg_maxit), offsetof(npg_config, precond),"
                     " offsetof(npg_config, rot_head), offsetof(npg_config, precision),"
-                    " offsetof(npg_config, cg_mg), offsetof(npg_config, nn_search));return 0;}\n")
+                    " offsetof(npg_config, cg_mg), offsetof(npg_config, nn_search),"
+                    " offsetof(npg_config, cg_one_stream));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
     C = npg.npg_config
     assert vals == [ctypes.sizeof(C), C.lam.offset, C.cg_rtol.offset, C.cg_maxit.offset, C.precond.offset,
-                    C.rot_head.offset, C.precision.offset, C.cg_mg.offset, C.nn_search.offset]
+                    C.rot_head.offset, C.precision.offset, C.cg_mg.offset, C.nn_search.offset,
+                    C.cg_one_stream.offset]
 
 
 @pytest.mark.parametrize("name,head", [("c1", "expmap"), ("c2", "expmap"), ("c3", "expmap"), ("small", "expmap"),
@@ -107,6 +109,15 @@ def test_invalid_nn_search_is_rejected():
     assert "nn_search" in L.npg_last_error().decode()
     with pytest.raises(ValueError):
         npg.make_config(dict(synth.config_c1(), nn_search="kdtree"))
+
+
+def test_invalid_cg_one_stream_is_rejected():
+    L = _lib()
+    c = npg.make_config(synth.config_c1())
+    c.cg_one_stream = 2
+    n = ctypes.c_int64()
+    assert L.npg_param_count(ctypes.byref(c), ctypes.byref(n)) == npg.NPG_EINVAL
+    assert "cg_one_stream" in L.npg_last_error().decode()
 
 
 def _create_raw(cfg, V, T, off, xyz=1, nrm=1, pts=1):
