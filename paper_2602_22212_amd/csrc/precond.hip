@@ -500,11 +500,11 @@ __device__ __forceinline__ ZmCols zm_cols(const Tile& t, int R, float lam, int n
   return c;
 }
 
-// b.b partials; r = p = b unless the grid is split (the V-cycle reads b
-// itself, the first update reads r from b, and the start's prolongation
-// writes the first direction). x is not written (see init_body).
-__device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* r, float* p, int split, double* part,
-                        int blk) {
+// b.b partials and r = p = b (not for a split grid of the V-cycle form: the
+// V-cycle reads b itself, the first update reads r from b, the start's
+// prolongation writes the first direction and the start's finest restriction
+// forms the b.b partials). x is not written (see init_body).
+__device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* r, float* p, double* part, int blk) {
   const int R = g.R;
   const int64_t R2 = (int64_t)R * R;
   const int xx = t.x0 + (int)(threadIdx.x & (kTX - 1));
@@ -517,10 +517,8 @@ __device__ void zm_init(const NpgGrid& g, const Tile& t, const float* b, float* 
     for (int z = t.z0; z < t.z1; ++z) {
       const int64_t n = (int64_t)z * R2 + (int64_t)yy * R + xx;
       const float4 v = B[n];
-      if (!split) {
-        Rr[n] = v;
-        Pp[n] = v;
-      }
+      Rr[n] = v;
+      Pp[n] = v;
       acc[0] += (double)v.x * v.x;
       acc[1] += (double)v.y * v.y;
       acc[2] += (double)v.z * v.z;
@@ -649,7 +647,8 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
   }
 
 // sys_split (NULL without the V-cycle): the systems whose direction the
-// V-cycle's finest prolongation forms (see zm_init).
+// V-cycle's finest prolongation forms and whose b.b partials the start's
+// finest restriction forms (see zm_init); their work-groups return at once.
 __global__ __launch_bounds__(kB) void k_cg_init(const NpgGrid* __restrict__ G, int nb, const int* __restrict__ blk_sys,
                                                 const int64_t* __restrict__ blk_start, const float* __restrict__ b,
                                                 float* __restrict__ r, float* __restrict__ p,
@@ -659,7 +658,8 @@ __global__ __launch_bounds__(kB) void k_cg_init(const NpgGrid* __restrict__ G, i
   const int s = blk_sys[blk];
   const NpgGrid g = G[s];
   if (use_zm(g)) {
-    zm_init(g, unpack_tile(blk_start[blk]), b, r, p, sys_split ? sys_split[s] : 0, part, blk);
+    // split: nothing to store, and the start's V-cycle forms the b.b partials
+    if (!(sys_split && sys_split[s])) zm_init(g, unpack_tile(blk_start[blk]), b, r, p, part, blk);
     return;
   }
   NPG_F_SWITCH(g, (init_body<FF>(g, blk_start[blk], b, r, p, part, blk)));
@@ -732,16 +732,29 @@ __global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G,
       any |= a[c] != 0.f;
       if (c < g.F) taken = fmax(taken, st[(s * 4 + c) * kS + 6]);
     }
-    const bool stored = taken >= 2.0;
+    const bool stored = taken >= 2.0, one = taken >= 1.0;
     if (stored && !any) continue;
-    const int64_t n = g.nodes * g.F;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-      const int c = (int)(e % g.F);
-      const float ac = c == 0 ? a[0] : (c == 1 ? a[1] : (c == 2 ? a[2] : a[3]));
-      float* xe = x + g.poff + e;
-      if (stored) *xe = fmaf(ac, q[g.poff + e], *xe);
-      else *xe = taken >= 1.0 ? fmaf(ac, q[g.poff + e], 0.f) : 0.f;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g.F == 4 && g.poff % 4 == 0) {  // one node (float4) per thread and pass
+      float4* x4 = reinterpret_cast<float4*>(x + g.poff);
+      const float4* q4 = reinterpret_cast<const float4*>(q + g.poff);
+      for (int64_t v = tid; v < g.nodes; v += stride) {
+        const float4 xv = stored ? x4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 qv = stored || one ? q4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        x4[v] = stored || one ? make_float4(fmaf(a[0], qv.x, xv.x), fmaf(a[1], qv.y, xv.y), fmaf(a[2], qv.z, xv.z),
+                                            fmaf(a[3], qv.w, xv.w))
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      continue;
     }
+    for (int64_t v = tid; v < g.nodes; v += stride)
+      for (int c = 0; c < g.F; ++c) {
+        const float ac = c == 0 ? a[0] : (c == 1 ? a[1] : (c == 2 ? a[2] : a[3]));
+        float* xe = x + g.poff + v * g.F + c;
+        if (stored) *xe = fmaf(ac, q[g.poff + v * g.F + c], *xe);
+        else *xe = one ? fmaf(ac, q[g.poff + v * g.F + c], 0.f) : 0.f;
+      }
   }
 }
 
@@ -1248,8 +1261,9 @@ __global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, Mg
 // start at even x, y and z, so no 2x2x2 block straddles two tiles.
 // acc: the fine-level term of r.z, sum of x0 (2 b - A x0) (b . b when lam = 0,
 // where the preconditioner is the identity); see k_mg_up0.
+template <bool BB>
 __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, const float* __restrict__ r,
-                            float* __restrict__ bh, double (&acc)[4]) {
+                            float* __restrict__ bh, double (&acc)[4], double (&bb)[4]) {
   __shared__ float4 ys[2][kTY / 2][kTX];
   const int R = g.R;
   const int nh = tk->hi.n;
@@ -1273,6 +1287,12 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
         acc[1] += (double)u.y * ((double)e.a.y + (double)(lam == 0.f ? 0.f : rs.y));
         acc[2] += (double)u.z * ((double)e.a.z + (double)(lam == 0.f ? 0.f : rs.z));
         acc[3] += (double)u.w * ((double)e.a.w + (double)(lam == 0.f ? 0.f : rs.w));
+        if (BB) {  // r = b at the start: b.b, in the order of the other grids' k_cg_init
+          bb[0] += (double)e.a.x * e.a.x;
+          bb[1] += (double)e.a.y * e.a.y;
+          bb[2] += (double)e.a.z * e.a.z;
+          bb[3] += (double)e.a.w * e.a.w;
+        }
       },
       [&](int z) {
         float4 v = f4add(rs, make_float4(__shfl_xor(rs.x, 1), __shfl_xor(rs.y, 1), __shfl_xor(rs.z, 1),
@@ -1293,13 +1313,17 @@ __device__ void mg_down0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, c
 // z-column walk (with the fine r.z term) for the large grids; for the others
 // the grid's work-groups take its coarse nodes in turn (one thread per coarse
 // node, as in k_mg_down), so the V-cycle needs no separate launch for them.
+// BB (the start of a solve, r = b): the large grids' walks also write the
+// b.b partials of the work-group into part (k_cg_init leaves them out).
+template <bool BB>
 __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, int nb, int lo,
                                                  const int* __restrict__ blk_sys,
                                                  const int64_t* __restrict__ blk_start,
                                                  const int* __restrict__ sys_blk0,
                                                  const int* __restrict__ active, int check_active,
                                                  const MgTask* __restrict__ T0, const float* __restrict__ r,
-                                                 float* __restrict__ bh, double* __restrict__ part2) {
+                                                 float* __restrict__ bh, double* __restrict__ part2,
+                                                 double* __restrict__ part) {
   const int blk = logical_block(nb, lo);
   if (blk < 0) return;
   const int s = blk_sys[blk];
@@ -1315,9 +1339,10 @@ __global__ __launch_bounds__(kB) void k_mg_down0(const NpgGrid* __restrict__ G, 
     }
     return;
   }
-  double acc[4] = {0, 0, 0, 0};
-  mg_down0_zm(g, unpack_tile(blk_start[blk]), tk, r, bh, acc);
+  double acc[4] = {0, 0, 0, 0}, bb[4] = {0, 0, 0, 0};
+  mg_down0_zm<BB>(g, unpack_tile(blk_start[blk]), tk, r, bh, acc, bb);
   store_partials<4>(acc, part2, blk);
+  if (BB) store_partials<4>(bb, part, blk);
 }
 
 // Prolongation and post-smoothing onto the finest level (z = M^-1 r) over the
@@ -1613,8 +1638,13 @@ static npg_status mg_apply(npg_plan* P, const CgGrp& G, const float* r, float* z
   const int nl = C.mg_nlev;
   const MgTask* T = static_cast<const MgTask*>(C.mg_tasks);
   const unsigned gb = xcd_grid(G.b_hi - G.b_lo);
-  hipLaunchKernelGGL(k_mg_down0, dim3(gb), dim3(kB), 0, s, P->d_g, G.b_hi, G.b_lo, C.blk_sys, C.blk_start,
-                     C.sys_blk0, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2);
+  if (d.first)  // the start of a solve (r = b): also the large grids' b.b partials
+    hipLaunchKernelGGL(k_mg_down0<true>, dim3(gb), dim3(kB), 0, s, P->d_g, G.b_hi, G.b_lo, C.blk_sys, C.blk_start,
+                       C.sys_blk0, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2, C.part);
+  else
+    hipLaunchKernelGGL(k_mg_down0<false>, dim3(gb), dim3(kB), 0, s, P->d_g, G.b_hi, G.b_lo, C.blk_sys,
+                       C.blk_start, C.sys_blk0, C.active, check_active, T + C.mg_l_task0[0], r, C.mgB, C.part2,
+                       nullptr);
   auto blk0 = [&](int li) {
     MgBlk0 b;
     for (int q = 0; q < kMgTaskMax; ++q) b.b[q] = C.mg_l_blk0[li][q];
