@@ -27,6 +27,9 @@ struct NpgGrid {
 struct NpgCG {  // conjugate-gradient workspace
   float *x, *r, *p, *q;        // [n_grid_params] each, grid layout (p, q: ping-pong directions)
   int last_iters[2] = {0, 0};  // iterations the last first / second solve took (its first batch)
+  int last_grp[2][2] = {{0, 0}, {0, 0}};  // the same per solve and group of grids
+  int* act_host = nullptr;     // [n_sys] pinned host copy of the active flags (eager solves)
+  hipEvent_t ev_grp[2] = {nullptr, nullptr};  // per group: its last batch's flags are on the host
   double* part;                // [n_blocks][4 waves][4 channels] partial dots
   double* st;                  // [n_sys][4][8] per-system/channel scalars
   int* active;                 // [n_sys] any channel still iterating

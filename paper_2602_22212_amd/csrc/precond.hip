@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <climits>
 #include <functional>
+#include <thread>
 
 #include "internal.h"
 
@@ -649,11 +650,12 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
 // sys_split (NULL without the V-cycle): the systems whose direction the
 // V-cycle's finest prolongation forms and whose b.b partials the start's
 // finest restriction forms (see zm_init); their work-groups return at once.
-__global__ __launch_bounds__(kB) void k_cg_init(const NpgGrid* __restrict__ G, int nb, const int* __restrict__ blk_sys,
+__global__ __launch_bounds__(kB) void k_cg_init(const NpgGrid* __restrict__ G, int nb, int lo,
+                                                const int* __restrict__ blk_sys,
                                                 const int64_t* __restrict__ blk_start, const float* __restrict__ b,
                                                 float* __restrict__ r, float* __restrict__ p,
                                                 const int* __restrict__ sys_split, double* __restrict__ part) {
-  const int blk = logical_block(nb);
+  const int blk = logical_block(nb, lo);
   if (blk < 0) return;
   const int s = blk_sys[blk];
   const NpgGrid g = G[s];
@@ -718,11 +720,11 @@ __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G,
 // iteration ran (two or more iterations) has x stored: x += alpha_pending q
 // where a term is pending, otherwise nothing to do. A system that stopped
 // earlier never stored x: x = alpha_pending q after one iteration, x = 0
-// after none (q not read). One launch covers every system.
-__global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G, int n_sys,
+// after none (q not read). One launch covers the systems [s_lo, s_hi).
+__global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G, int s_lo, int s_hi,
                                                   const double* __restrict__ st, float* __restrict__ x,
                                                   const float* __restrict__ q) {
-  for (int s = 0; s < n_sys; ++s) {
+  for (int s = s_lo; s < s_hi; ++s) {
     const NpgGrid g = G[s];
     float a[4];
     bool any = false;
@@ -759,12 +761,13 @@ __global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G,
 }
 
 // After a fixed number of launched iterations: sets `bit` in *state when
-// some system is still iterating (one thread).
-__global__ void k_cg_done(const int* __restrict__ active, int n_sys, int* __restrict__ state, int bit) {
+// one of the systems [s_lo, s_hi) is still iterating (one thread; an atomic
+// OR, as the groups of grids check on their own streams).
+__global__ void k_cg_done(const int* __restrict__ active, int s_lo, int s_hi, int* __restrict__ state, int bit) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int any = 0;
-  for (int s = 0; s < n_sys; ++s) any |= active[s];
-  if (any) *state = *state | bit;
+  for (int s = s_lo; s < s_hi; ++s) any |= active[s];
+  if (any) atomicOr(state, bit);
 }
 
 // Sum of the block partials [b0, b1) of part per channel, in a fixed order
@@ -1739,6 +1742,8 @@ npg_status npg_cg_setup(npg_plan* P) {
       NPG_HIP(hipEventCreateWithFlags(&C.ev_fork, hipEventDisableTiming));
       NPG_HIP(hipEventCreateWithFlags(&C.ev_join, hipEventDisableTiming));
     }
+    for (auto& e : C.ev_grp) NPG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    NPG_HIP(hipHostMalloc((void**)&C.act_host, P->n_sys * sizeof(int), hipHostMallocDefault));
   }
   C.mg = P->cfg.cg_mg != 0;
   if (C.mg) {
@@ -1757,10 +1762,18 @@ void npg_cg_free(npg_plan* P) {
   if (C.stream2) (void)hipStreamDestroy(C.stream2);
   if (C.ev_fork) (void)hipEventDestroy(C.ev_fork);
   if (C.ev_join) (void)hipEventDestroy(C.ev_join);
+  for (auto e : C.ev_grp)
+    if (e) (void)hipEventDestroy(e);
+  if (C.act_host) (void)hipHostFree(C.act_host);
   const int keep[2] = {C.last_iters[0], C.last_iters[1]};
+  int keep_grp[2][2];
+  for (int w = 0; w < 2; ++w)
+    for (int g = 0; g < 2; ++g) keep_grp[w][g] = C.last_grp[w][g];
   C = NpgCG();
   C.last_iters[0] = keep[0];
   C.last_iters[1] = keep[1];
+  for (int w = 0; w < 2; ++w)
+    for (int g = 0; g < 2; ++g) C.last_grp[w][g] = keep_grp[w][g];
 }
 
 // ---- the two solves ------------------------------------------------------------
@@ -1816,15 +1829,13 @@ void cg_reduce(npg_plan* P, const CgCtx& c, const CgGrp& G, int mode, int defer,
 // Iteration 0 treats C.q as its direction: the start writes p_0 = z_0 there
 // (large grids of the multigrid form, in the V-cycle's finest prolongation;
 // the other grids form it in k_cg_dir_ap from z with beta = 0).
-npg_status cg_start(npg_plan* P, const CgCtx& c, const float* b) {
+npg_status cg_start(npg_plan* P, const CgCtx& c, const CgGrp& G, const float* b) {
   NpgCG& C = P->cg;
-  hipStream_t s = P->stream;
-  const CgGrp all = cg_all(P);
-  hipLaunchKernelGGL(k_cg_init, c.grid, c.blk, 0, s, P->d_g, C.n_blocks, C.blk_sys, C.blk_start, b, C.r, C.p,
-                     c.mg ? C.sys_split : nullptr, C.part);
+  hipLaunchKernelGGL(k_cg_init, dim3(xcd_grid(G.b_hi - G.b_lo)), c.blk, 0, G.stream, P->d_g, G.b_hi, G.b_lo,
+                     C.blk_sys, C.blk_start, b, C.r, C.p, c.mg ? C.sys_split : nullptr, C.part);
   // r = b: the first V-cycle reads b (the split grids never store r = b)
-  if (c.mg) NPG_TRY_ST(mg_apply(P, all, b, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
-  cg_reduce(P, c, all, 0, 0, -1);
+  if (c.mg) NPG_TRY_ST(mg_apply(P, G, b, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
+  cg_reduce(P, c, G, 0, 0, -1);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
@@ -1897,14 +1908,16 @@ npg_status cg_iterations(npg_plan* P, const CgCtx& c, const float* b, float* x, 
   return NPG_OK;
 }
 
-npg_status cg_finish(npg_plan* P, const CgCtx& c, float* x) {
-  hipLaunchKernelGGL(k_cg_flush, dim3((unsigned)(4 * P->n_cu)), dim3(256), 0, P->stream, P->d_g, P->n_sys, c.st, x,
-                     P->cg.q);
+npg_status cg_finish(npg_plan* P, const CgCtx& c, const CgGrp& G, float* x) {
+  hipLaunchKernelGGL(k_cg_flush, dim3((unsigned)(4 * P->n_cu)), dim3(256), 0, G.stream, P->d_g, G.s_lo, G.s_hi, c.st,
+                     x, P->cg.q);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
 
-// Eager solve: iterations launched in batches between host tests of the
+// Eager solve over every system, the groups of grids in step (the form
+// used with iteration profiling: events bracket each batch of iterations of
+// both groups): iterations launched in batches between host tests of the
 // active flags. The first batch is what the same solve of the previous call
 // took (16 the first time, at most kFirstMax, and not carried over from a
 // solve that reached the cap); later batches are 2 iterations long.
@@ -1914,7 +1927,8 @@ npg_status cg_solve_eager(npg_plan* P, int which, const float* b, float* x, bool
   NpgCG& C = P->cg;
   hipStream_t s = P->stream;
   const CgCtx c = cg_ctx(P, which);
-  NPG_TRY_ST(cg_start(P, c, b));
+  const CgGrp all = cg_all(P);
+  NPG_TRY_ST(cg_start(P, c, all, b));
   std::vector<int> act(P->n_sys);
   const int maxit = P->cfg.cg_maxit;
   const int last = C.last_iters[which];
@@ -1933,7 +1947,83 @@ npg_status cg_solve_eager(npg_plan* P, int which, const float* b, float* x, bool
     if (done) break;
   }
   if (!done) *capped = true;
-  return cg_finish(P, c, x);
+  return cg_finish(P, c, all, x);
+}
+
+// Both eager solves with every group of grids on its own stream and at its
+// own pace: a group's second solve starts as soon as its first has stopped
+// (the systems are independent: the results are those of cg_solve_eager),
+// so one group's start, flush and host tests overlap the other group's
+// iterations. Batches as in cg_solve_eager, counted per group (the first
+// batch of a solve is what the group's slowest system took in the same
+// solve of the previous call). Each batch ends with a copy of the group's
+// flags to pinned host memory and an event, which the host polls.
+npg_status cg_precond_pipelined(npg_plan* P, float* grad, bool* capped) {
+  NpgCG& C = P->cg;
+  const float* bs[2] = {grad, C.x};
+  float* xs[2] = {C.x, grad};
+  const int ng = C.n_grp, maxit = P->cfg.cg_maxit;
+  const CgCtx cx[2] = {cg_ctx(P, 0), cg_ctx(P, 1)};
+  CgGrp G[2];
+  for (int g = 0; g < ng; ++g) G[g] = cg_grp(P, g);
+  struct Run {
+    int which, it;
+    bool done;
+  } run[2] = {{0, 0, false}, {0, 0, false}};
+  auto batch = [&](int g) -> npg_status {
+    Run& R = run[g];
+    const int last = C.last_grp[R.which][g];
+    const int want = R.it == 0 ? (last > 0 ? std::min(last, kFirstMax) : 16) : (last > 0 ? 2 : 16);
+    const int n = std::min(want, maxit - R.it);
+    for (int k = R.it; k < R.it + n; ++k) NPG_TRY_ST(cg_iteration(P, cx[R.which], G[g], bs[R.which], xs[R.which], k));
+    R.it += n;
+    NPG_HIP(hipMemcpyAsync(C.act_host + G[g].s_lo, C.active + G[g].s_lo, (G[g].s_hi - G[g].s_lo) * sizeof(int),
+                           hipMemcpyDeviceToHost, G[g].stream));
+    NPG_HIP(hipEventRecord(C.ev_grp[g], G[g].stream));
+    return NPG_OK;
+  };
+  if (C.stream2) {
+    NPG_HIP(hipEventRecord(C.ev_fork, P->stream));
+    NPG_HIP(hipStreamWaitEvent(C.stream2, C.ev_fork, 0));
+  }
+  for (int g = 0; g < ng; ++g) {
+    NPG_TRY_ST(cg_start(P, cx[0], G[g], bs[0]));
+    NPG_TRY_ST(batch(g));
+  }
+  for (int left = ng; left > 0;) {
+    bool ready = false;
+    for (int g = 0; g < ng; ++g) {
+      Run& R = run[g];
+      if (R.done) continue;
+      const hipError_t e = hipEventQuery(C.ev_grp[g]);
+      if (e == hipErrorNotReady) continue;
+      NPG_HIP(e);
+      ready = true;
+      bool active = false;
+      for (int sy = G[g].s_lo; sy < G[g].s_hi; ++sy) active |= C.act_host[sy] != 0;
+      if (active && R.it < maxit) {
+        NPG_TRY_ST(batch(g));
+        continue;
+      }
+      if (active) *capped = true;
+      NPG_TRY_ST(cg_finish(P, cx[R.which], G[g], xs[R.which]));
+      if (R.which == 0) {
+        R.which = 1;
+        R.it = 0;
+        NPG_TRY_ST(cg_start(P, cx[1], G[g], bs[1]));
+        NPG_TRY_ST(batch(g));
+      } else {
+        R.done = true;
+        --left;
+      }
+    }
+    if (!ready) std::this_thread::yield();
+  }
+  if (C.stream2) {
+    NPG_HIP(hipEventRecord(C.ev_join, C.stream2));
+    NPG_HIP(hipStreamWaitEvent(P->stream, C.ev_join, 0));
+  }
+  return NPG_OK;
 }
 
 }  // namespace
@@ -1953,6 +2043,7 @@ npg_status npg_cg_report(npg_plan* P, int32_t* iters) {
   P->cg_iters_sum = 0;
   for (int which = 0; which < 2; ++which) {
     int taken = 0;  // iterations of the slowest system
+    int taken_grp[2] = {0, 0};
     for (int sy = 0; sy < P->n_sys; ++sy) {
       const NpgGrid& g = P->g[sy];
       const double* S0 = stv.data() + ((size_t)which * P->n_sys + sy) * 4 * kS;
@@ -1967,6 +2058,8 @@ npg_status npg_cg_report(npg_plan* P, int32_t* iters) {
       if (iters) iters[which * P->n_sys + sy] = (int32_t)m;
       P->cg_relres[which * P->n_sys + sy] = rel;
       taken = std::max(taken, (int)m);
+      const int grp = C.n_grp == 2 && sy >= C.grp_sys[1] ? 1 : 0;
+      taken_grp[grp] = std::max(taken_grp[grp], (int)m);
       // algorithmic traffic per iteration: 6 vector passes (x, r, p read and
       // written) over the grid's R^3 F float32 unknowns; the V-cycle form
       // also moves z (written, read) and each coarse level's right-hand side
@@ -1978,15 +2071,21 @@ npg_status npg_cg_report(npg_plan* P, int32_t* iters) {
       P->cg_iters_sum += (int64_t)m;
     }
     C.last_iters[which] = taken >= P->cfg.cg_maxit ? 0 : taken;
+    for (int g = 0; g < 2; ++g) C.last_grp[which][g] = taken_grp[g] >= P->cfg.cg_maxit ? 0 : taken_grp[g];
   }
   return NPG_OK;
 }
 
 npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters) {
   bool capped = false;
-  // y = A^-1 g into the workspace, then A^-1 y back into the gradient
-  NPG_TRY_ST(cg_solve_eager(P, 0, grad, P->cg.x, &capped));
-  NPG_TRY_ST(cg_solve_eager(P, 1, P->cg.x, grad, &capped));
+  // y = A^-1 g into the workspace, then A^-1 y back into the gradient; with
+  // iteration profiling the groups of grids go in step (each batch bracketed)
+  if (P->prof_cg) {
+    NPG_TRY_ST(cg_solve_eager(P, 0, grad, P->cg.x, &capped));
+    NPG_TRY_ST(cg_solve_eager(P, 1, P->cg.x, grad, &capped));
+  } else {
+    NPG_TRY_ST(cg_precond_pipelined(P, grad, &capped));
+  }
   NPG_TRY_ST(npg_cg_report(P, iters));
   return capped ? NPG_ENOTCONV : NPG_OK;
 }
@@ -1995,17 +2094,36 @@ npg_status npg_run_precond_cg(npg_plan* P, float* grad, int32_t* iters) {
 // exactly n_iter[which] iterations, then k_cg_done sets bit (1 << which) of
 // *state_dev if a system is still iterating, or bit 4 when the count is the
 // cap cg_maxit (the eager form's NPG_ENOTCONV case, whose result stands).
+// Each group of grids runs both solves on its own stream (a group's second
+// solve starts when its own first one ends); the launches of the groups are
+// issued interleaved, step by step.
 npg_status npg_run_precond_cg_fixed(npg_plan* P, float* grad, const int n_iter[2], int* state_dev) {
-  const float* b[2] = {grad, P->cg.x};
-  float* x[2] = {P->cg.x, grad};
+  NpgCG& C = P->cg;
+  const float* b[2] = {grad, C.x};
+  float* x[2] = {C.x, grad};
+  const int ng = C.n_grp;
+  CgGrp G[2];
+  for (int g = 0; g < ng; ++g) G[g] = cg_grp(P, g);
+  if (C.stream2) {
+    NPG_HIP(hipEventRecord(C.ev_fork, P->stream));
+    NPG_HIP(hipStreamWaitEvent(C.stream2, C.ev_fork, 0));
+  }
   for (int which = 0; which < 2; ++which) {
     const CgCtx c = cg_ctx(P, which);
-    NPG_TRY_ST(cg_start(P, c, b[which]));
-    if (n_iter[which] > 0) NPG_TRY_ST(cg_iterations(P, c, b[which], x[which], 0, n_iter[which]));
+    for (int g = 0; g < ng; ++g) NPG_TRY_ST(cg_start(P, c, G[g], b[which]));
+    for (int k = 0; k < n_iter[which]; ++k)
+      for (int g = 0; g < ng; ++g) NPG_TRY_ST(cg_iteration(P, c, G[g], b[which], x[which], k));
     const int bit = n_iter[which] >= P->cfg.cg_maxit ? 4 : (1 << which);
-    hipLaunchKernelGGL(k_cg_done, dim3(1), dim3(64), 0, P->stream, P->cg.active, P->n_sys, state_dev, bit);
-    NPG_HIP(hipGetLastError());
-    NPG_TRY_ST(cg_finish(P, c, x[which]));
+    for (int g = 0; g < ng; ++g) {
+      hipLaunchKernelGGL(k_cg_done, dim3(1), dim3(64), 0, G[g].stream, C.active, G[g].s_lo, G[g].s_hi, state_dev,
+                         bit);
+      NPG_HIP(hipGetLastError());
+      NPG_TRY_ST(cg_finish(P, c, G[g], x[which]));
+    }
+  }
+  if (C.stream2) {
+    NPG_HIP(hipEventRecord(C.ev_join, C.stream2));
+    NPG_HIP(hipStreamWaitEvent(P->stream, C.ev_join, 0));
   }
   return NPG_OK;
 }

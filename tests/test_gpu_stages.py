@@ -417,19 +417,22 @@ def test_preconditioner_early_stops_on_large_grids(method):
 @pytest.mark.parametrize("levels", [[100, 129, 20], [7, 33, 150, 50, 110]])
 def test_preconditioner_streams_are_bitwise_equal(levels, method):
     """With the largest grid z-column tiled and other grids before it, the
-    solves iterate the grids before it on a second stream; cg_one_stream = 1
-    runs the same launches on one stream. Both give the same result and
-    iteration counts bit for bit (the systems are independent), on two calls
-    in a row (the second starts from the first's iteration counts)."""
+    solves iterate the grids before it on a second stream, each group at its
+    own pace; cg_one_stream = 1 runs the same launches on one stream, and
+    with iteration profiling on the groups go in step. All three give the
+    same result and iteration counts bit for bit (the systems are
+    independent), on two calls in a row (the second starts from the first's
+    iteration counts)."""
     import torch
 
     import paper_2602_22212_amd as npg
     out = []
-    for one in (0, 1):
+    for one, prof in ((0, False), (1, False), (0, True)):
         cfg = synth.config_small(levels=levels, feat_p=4, mlp_width=32, V=3000, T=1, N=10, t_key=0, seed=35,
                                  precond="cg", cg_mg=int(method == "cg"), cg_one_stream=one)
         data = synth.make_workload(cfg)
         plan = gpu_plan(cfg, data)
+        plan.profile(prof)
         torch.manual_seed(6)
         res = []
         for _ in range(2):
@@ -439,10 +442,12 @@ def test_preconditioner_streams_are_bitwise_equal(levels, method):
             res.append((to_np(grad), np.array(its)))
         out.append(res)
         plan.close()
-    for (g0, i0), (g1, i1) in zip(*out):
+    for (g0, i0), (g1, i1), (g2, i2) in zip(*out):
         print("iterations per solve and system:", i0.tolist())
         np.testing.assert_array_equal(i0, i1)
         np.testing.assert_array_equal(g0, g1)
+        np.testing.assert_array_equal(i0, i2)
+        np.testing.assert_array_equal(g0, g2)
 
 
 def test_multigrid_preconditioned_cg_cuts_iterations():
