@@ -118,11 +118,12 @@ __device__ __forceinline__ int logical_block(int nb, int lo = 0) {
   return lb >= lo ? lb : -1;
 }
 
-// Block partials of F channels, part[blk*4 + c]: wave sums, then the 4
-// waves in order.
-template <int F>
+// Block partials of F channels, part[blk*4 + c]: wave sums, then the
+// waves in order (NT threads per work-group).
+template <int F, int NT = kB>
 __device__ __forceinline__ void store_partials(double (&acc)[4], double* part, int blk) {
-  __shared__ double ws[4][4];
+  constexpr int NW = NT / 64;
+  __shared__ double ws[NW][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < F; ++c) {
@@ -132,7 +133,10 @@ __device__ __forceinline__ void store_partials(double (&acc)[4], double* part, i
   __syncthreads();
   if ((int)threadIdx.x < F) {
     const int c = threadIdx.x;
-    part[(int64_t)blk * 4 + c] = ((ws[0][c] + ws[1][c]) + ws[2][c]) + ws[3][c];
+    double v = ws[0][c];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += ws[w][c];
+    part[(int64_t)blk * 4 + c] = v;
   }
 }
 
@@ -1253,7 +1257,7 @@ __global__ __launch_bounds__(kMgB) void k_mg_up(const MgTask* __restrict__ T, Mg
     if (tk->fast) mg_up_u4(tk, bl, eh, out, (int)m, acc);
     else mg_up_node(tk, bl, eh, out, m, acc);
   }
-  if (part3 && tk->rz1) store_partials<4>(acc, part3, blk);
+  if (part3 && tk->rz1) store_partials<4, kMgB>(acc, part3, blk);
 }
 
 // Restriction from the finest level of a large grid over its z-column tiles
