@@ -24,8 +24,14 @@ struct NpgGrid {
   float scale;      // 1/L for position levels, 1 for the normal grid
 };
 
+// Directions kept per CG solve: iteration k writes its direction into ring
+// slot k mod kCgDirs, and x takes the terms of kCgDirs iterations in one pass.
+constexpr int kCgDirs = 8;
+
 struct NpgCG {  // conjugate-gradient workspace
-  float *x, *r, *p, *q;        // [n_grid_params] each, grid layout (p, q: ping-pong directions)
+  float *x, *r;                // [n_grid_params] each, grid layout
+  float* pd[kCgDirs] = {};     // [n_grid_params] each: the ring of directions
+  double* ahist;               // [2 solves][n_sys][4][kCgDirs] alpha of each ring slot
   int last_iters[2] = {0, 0};  // iterations the last first / second solve took (its first batch)
   int last_grp[2][2] = {{0, 0}, {0, 0}};  // the same per solve and group of grids
   int* act_host = nullptr;     // [n_sys] pinned host copy of the active flags (eager solves)

@@ -50,7 +50,7 @@ constexpr int kPer = 8;       // nodes per thread
 constexpr int kChunk = kB * kPer;
 
 // per (system, channel) scalars: 0 rho (r.z with the V-cycle, else r.r), 1 bb, 2 rr, 3 alpha,
-// 4 beta, 5 active, 6 iterations, 7 alpha of the pending x term (0 when none)
+// 4 beta, 5 active, 6 iterations, 7 unused
 constexpr int kS = 8;
 constexpr float kMgOmegaW = 0.85f;  // Jacobi damping of the V-cycle (kMgOmega below)
 constexpr int kR_THREADS = 1024, kR_WAVES = kR_THREADS / 64;  // reduction work-group
@@ -238,19 +238,13 @@ __device__ void dir_ap_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
 }
 
 // r = r_in - alpha A p (r_in: r, or b in the first iteration); rr partial.
-// XM = 1: also x += alpha_prev p_prev, then x += alpha p (the term of the
-// previous iteration and this one's); XM = 2 (the first odd iteration): the
-// same from x = 0, which is not read.
-template <int XM, int FV, int F = (FV < 0 ? -FV : FV)>
+// x is not touched: k_cg_xacc adds the terms of kCgDirs iterations at once.
+template <int FV, int F = (FV < 0 ? -FV : FV)>
 __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& fR2, int64_t n0, const double* st,
-                            int s, float* x, const float* r_in, float* r, const float* p, const float* p_prev,
-                            double* part, int blk) {
-  float al[F], ap[F];
+                            int s, const float* r_in, float* r, const float* p, double* part, int blk) {
+  float al[F];
 #pragma unroll
-  for (int c = 0; c < F; ++c) {
-    al[c] = (float)st[(s * 4 + c) * kS + 3];
-    ap[c] = (float)st[(s * 4 + c) * kS + 7];
-  }
+  for (int c = 0; c < F; ++c) al[c] = (float)st[(s * 4 + c) * kS + 3];
   const float lam = g.lam;
   const float* pb = p + g.poff;
   double acc[4] = {0, 0, 0, 0};
@@ -271,19 +265,6 @@ __device__ void update_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& 
 #pragma unroll
         for (int c = 0; c < F; ++c) lap[c] += pc[c] - pm[c];
       }
-    }
-    if (XM) {
-      float xc[F], pp[F];
-      if (XM == 1) {
-        Vec<FV>::load(x + e, xc);
-      } else {
-#pragma unroll
-        for (int c = 0; c < F; ++c) xc[c] = 0.f;
-      }
-      Vec<FV>::load(p_prev + e, pp);
-#pragma unroll
-      for (int c = 0; c < F; ++c) xc[c] = fmaf(al[c], pc[c], fmaf(ap[c], pp[c], xc[c]));
-      Vec<FV>::store(x + e, xc);
     }
     Vec<FV>::load(r_in + e, rc);
 #pragma unroll
@@ -573,71 +554,32 @@ __device__ void zm_pap(const NpgGrid& g, const Tile& t, const float* p, double* 
   store_partials<4>(acc, part, blk);
 }
 
-struct Raw3 {
-  float4 a, b, c;
-};
 
-template <int XM>
-__device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, float* x, const float* r_in,
-                          float* r, const float* p, const float* p_prev, double* part, int blk) {
-  float al[4], ap[4];
+__device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, const float* r_in, float* r,
+                          const float* p, double* part, int blk) {
+  float al[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    al[c] = (float)st[(s * 4 + c) * kS + 3];
-    ap[c] = (float)st[(s * 4 + c) * kS + 7];
-  }
+  for (int c = 0; c < 4; ++c) al[c] = (float)st[(s * 4 + c) * kS + 3];
   const float lam = g.lam;
   const float4* Pp = reinterpret_cast<const float4*>(p + g.poff);
-  const float4* Pq = reinterpret_cast<const float4*>(p_prev + g.poff);
-  float4* X = reinterpret_cast<float4*>(x + g.poff);
   const float4* Ri = reinterpret_cast<const float4*>(r_in + g.poff);
   float4* Rr = reinterpret_cast<float4*>(r + g.poff);
   double acc[4] = {0, 0, 0, 0};
-  auto r_update = [&](int64_t n, const float4& lap, const float4& pc, float4 rv) {
-    rv.x = fmaf(-al[0], fmaf(lam, lap.x, pc.x), rv.x);
-    rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
-    rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
-    rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
-    Rr[n] = rv;
-    acc[0] += (double)rv.x * rv.x;
-    acc[1] += (double)rv.y * rv.y;
-    acc[2] += (double)rv.z * rv.z;
-    acc[3] += (double)rv.w * rv.w;
-  };
-  if (XM == 2) {  // the first odd iteration: x = 0 + both terms, x not read
-    zm_walk<Raw1, Raw2>(
-        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw2{Ri[n], Pq[n]}; },
-        [&](const Raw1& v) { return v.a; },
-        [&](int64_t n, const float4& lap, const float4& pc, const Raw2& e) {
-          const float4 pq = e.b;
-          float4 xv;
-          xv.x = fmaf(al[0], pc.x, fmaf(ap[0], pq.x, 0.f));
-          xv.y = fmaf(al[1], pc.y, fmaf(ap[1], pq.y, 0.f));
-          xv.z = fmaf(al[2], pc.z, fmaf(ap[2], pq.z, 0.f));
-          xv.w = fmaf(al[3], pc.w, fmaf(ap[3], pq.w, 0.f));
-          X[n] = xv;
-          r_update(n, lap, pc, e.a);
-        });
-  } else if (XM) {
-    zm_walk<Raw1, Raw3>(
-        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw3{X[n], Ri[n], Pq[n]}; },
-        [&](const Raw1& v) { return v.a; },
-        [&](int64_t n, const float4& lap, const float4& pc, const Raw3& e) {
-          float4 xv = e.a;
-          const float4 pq = e.c;
-          xv.x = fmaf(al[0], pc.x, fmaf(ap[0], pq.x, xv.x));
-          xv.y = fmaf(al[1], pc.y, fmaf(ap[1], pq.y, xv.y));
-          xv.z = fmaf(al[2], pc.z, fmaf(ap[2], pq.z, xv.z));
-          xv.w = fmaf(al[3], pc.w, fmaf(ap[3], pq.w, xv.w));
-          X[n] = xv;
-          r_update(n, lap, pc, e.b);
-        });
-  } else {
-    zm_walk<Raw1, Raw1>(
-        g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw1{Ri[n]}; },
-        [&](const Raw1& v) { return v.a; },
-        [&](int64_t n, const float4& lap, const float4& pc, const Raw1& e) { r_update(n, lap, pc, e.a); });
-  }
+  zm_walk<Raw1, Raw1>(
+      g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw1{Ri[n]}; },
+      [&](const Raw1& v) { return v.a; },
+      [&](int64_t n, const float4& lap, const float4& pc, const Raw1& e) {
+        float4 rv = e.a;
+        rv.x = fmaf(-al[0], fmaf(lam, lap.x, pc.x), rv.x);
+        rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
+        rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
+        rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
+        Rr[n] = rv;
+        acc[0] += (double)rv.x * rv.x;
+        acc[1] += (double)rv.y * rv.y;
+        acc[2] += (double)rv.z * rv.z;
+        acc[3] += (double)rv.w * rv.w;
+      });
   store_partials<4>(acc, part, blk);
 }
 
@@ -696,14 +638,12 @@ __global__ __launch_bounds__(kB) void k_cg_dir_ap(const NpgGrid* __restrict__ G,
 
 // r_b: the right-hand side in the first iteration of a solve (r is read from
 // it, r = b not having been stored), NULL later (r updated in place).
-template <int XM>
 __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G, Divs dv, int nb, int lo,
                                                   const int* __restrict__ blk_sys,
                                                   const int64_t* __restrict__ blk_start,
                                                   const int* __restrict__ active, const double* __restrict__ st,
-                                                  float* __restrict__ x, const float* __restrict__ r_b,
-                                                  float* __restrict__ r, const float* __restrict__ p,
-                                                  const float* __restrict__ p_prev, double* __restrict__ part) {
+                                                  const float* __restrict__ r_b, float* __restrict__ r,
+                                                  const float* __restrict__ p, double* __restrict__ part) {
   const int blk = logical_block(nb, lo);
   if (blk < 0) return;
   const int s = blk_sys[blk];
@@ -711,55 +651,109 @@ __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G,
   const NpgGrid g = G[s];
   const float* r_in = r_b ? r_b : r;
   if (use_zm(g)) {
-    zm_update<XM>(g, unpack_tile(blk_start[blk]), st, s, x, r_in, r, p, p_prev, part, blk);
+    zm_update(g, unpack_tile(blk_start[blk]), st, s, r_in, r, p, part, blk);
     return;
   }
-  NPG_F_SWITCH(g, (update_body<XM, FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, x, r_in, r, p, p_prev, part,
-                                       blk)));
+  NPG_F_SWITCH(g, (update_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, r_in, r, p, part, blk)));
 }
 
-// The end of a solve, from its scalars on the device (float32 of the
-// float64 scalar 7: the x term still pending when a system stopped after an
-// even iteration; scalar 6: iterations taken). A system whose first odd
-// iteration ran (two or more iterations) has x stored: x += alpha_pending q
-// where a term is pending, otherwise nothing to do. A system that stopped
-// earlier never stored x: x = alpha_pending q after one iteration, x = 0
-// after none (q not read). One launch covers the systems [s_lo, s_hi).
-__global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G, int s_lo, int s_hi,
-                                                  const double* __restrict__ st, float* __restrict__ x,
-                                                  const float* __restrict__ q) {
+// The ring of directions, by slot (passed by value).
+struct Dirs {
+  const float* p[kCgDirs];
+};
+
+// x of the systems [s_lo, s_hi) still iterating after iteration k (k + 1 a
+// multiple of kCgDirs): x = fmaf(alpha_j, p_j, x) for the iterations j of
+// the window k + 1 - kCgDirs .. k in order (ring slots 0 .. kCgDirs-1), from
+// x = 0 (not read) for the first window: the float32 chain that one update
+// per iteration would form.
+__global__ __launch_bounds__(256) void k_cg_xacc(const NpgGrid* __restrict__ G, int s_lo, int s_hi,
+                                                 const int* __restrict__ active, const double* __restrict__ ah,
+                                                 int first, float* __restrict__ x, Dirs d) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   for (int s = s_lo; s < s_hi; ++s) {
+    if (!active[s]) continue;
     const NpgGrid g = G[s];
-    float a[4];
-    bool any = false;
-    double taken = 0.0;
-    for (int c = 0; c < 4; ++c) {
-      a[c] = c < g.F ? (float)st[(s * 4 + c) * kS + 7] : 0.f;
-      any |= a[c] != 0.f;
-      if (c < g.F) taken = fmax(taken, st[(s * 4 + c) * kS + 6]);
-    }
-    const bool stored = taken >= 2.0, one = taken >= 1.0;
-    if (stored && !any) continue;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g.F == 4 && g.poff % 4 == 0) {  // one node (float4) per thread and pass
-      float4* x4 = reinterpret_cast<float4*>(x + g.poff);
-      const float4* q4 = reinterpret_cast<const float4*>(q + g.poff);
+    float a[kCgDirs][4];
+#pragma unroll
+    for (int j = 0; j < kCgDirs; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[j][c] = c < g.F ? (float)ah[(s * 4 + c) * kCgDirs + j] : 0.f;
+    if (g.F == 4 && g.poff % 4 == 0) {
+      float4* X = reinterpret_cast<float4*>(x + g.poff);
       for (int64_t v = tid; v < g.nodes; v += stride) {
-        const float4 xv = stored ? x4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float4 qv = stored || one ? q4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-        x4[v] = stored || one ? make_float4(fmaf(a[0], qv.x, xv.x), fmaf(a[1], qv.y, xv.y), fmaf(a[2], qv.z, xv.z),
-                                            fmaf(a[3], qv.w, xv.w))
-                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 xv = first ? make_float4(0.f, 0.f, 0.f, 0.f) : X[v];
+#pragma unroll
+        for (int j = 0; j < kCgDirs; ++j) {
+          const float4 pv = reinterpret_cast<const float4*>(d.p[j] + g.poff)[v];
+          xv = make_float4(fmaf(a[j][0], pv.x, xv.x), fmaf(a[j][1], pv.y, xv.y), fmaf(a[j][2], pv.z, xv.z),
+                           fmaf(a[j][3], pv.w, xv.w));
+        }
+        X[v] = xv;
       }
       continue;
     }
     for (int64_t v = tid; v < g.nodes; v += stride)
       for (int c = 0; c < g.F; ++c) {
-        const float ac = c == 0 ? a[0] : (c == 1 ? a[1] : (c == 2 ? a[2] : a[3]));
-        float* xe = x + g.poff + v * g.F + c;
-        if (stored) *xe = fmaf(ac, q[g.poff + v * g.F + c], *xe);
-        else *xe = one ? fmaf(ac, q[g.poff + v * g.F + c], 0.f) : 0.f;
+        const int64_t e = g.poff + v * g.F + c;
+        float xv = first ? 0.f : x[e];
+#pragma unroll
+        for (int j = 0; j < kCgDirs; ++j) xv = fmaf(a[j][c], d.p[j][e], xv);
+        x[e] = xv;
+      }
+  }
+}
+
+// The end of a solve, from its scalars on the device: a system that took
+// `taken` iterations (scalar 6, the largest over its channels) has had the
+// terms of its first floor(taken / kCgDirs) windows added to x by k_cg_xacc;
+// the rest, iterations kCgDirs floor(taken / kCgDirs) .. taken-1, are added
+// here in order, from x = 0 (not read) when no window was added. One launch
+// covers the systems [s_lo, s_hi).
+__global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G, int s_lo, int s_hi,
+                                                  const double* __restrict__ st, const double* __restrict__ ah,
+                                                  float* __restrict__ x, Dirs d) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int s = s_lo; s < s_hi; ++s) {
+    const NpgGrid g = G[s];
+    double tk = 0.0;
+    for (int c = 0; c < g.F; ++c) tk = fmax(tk, st[(s * 4 + c) * kS + 6]);
+    const int taken = (int)tk;
+    const int done = taken / kCgDirs * kCgDirs, pend = taken - done;
+    const bool stored = done > 0;
+    if (stored && pend == 0) continue;
+    float a[kCgDirs][4];
+#pragma unroll
+    for (int j = 0; j < kCgDirs; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[j][c] = c < g.F && j < pend ? (float)ah[(s * 4 + c) * kCgDirs + j] : 0.f;
+    if (g.F == 4 && g.poff % 4 == 0) {  // one node (float4) per thread and pass
+      float4* X = reinterpret_cast<float4*>(x + g.poff);
+      for (int64_t v = tid; v < g.nodes; v += stride) {
+        float4 xv = stored ? X[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < kCgDirs; ++j) {
+          if (j >= pend) break;
+          const float4 pv = reinterpret_cast<const float4*>(d.p[j] + g.poff)[v];
+          xv = make_float4(fmaf(a[j][0], pv.x, xv.x), fmaf(a[j][1], pv.y, xv.y), fmaf(a[j][2], pv.z, xv.z),
+                           fmaf(a[j][3], pv.w, xv.w));
+        }
+        X[v] = xv;
+      }
+      continue;
+    }
+    for (int64_t v = tid; v < g.nodes; v += stride)
+      for (int c = 0; c < g.F; ++c) {
+        const int64_t e = g.poff + v * g.F + c;
+        float xv = stored ? x[e] : 0.f;
+#pragma unroll
+        for (int j = 0; j < kCgDirs; ++j) {
+          if (j >= pend) break;
+          xv = fmaf(a[j][c], d.p[j][e], xv);
+        }
+        x[e] = xv;
       }
   }
 }
@@ -802,9 +796,9 @@ __device__ __forceinline__ void reduce_range(const double* part, int b0, int b1,
 
 // Per system (one work-group each): reduce the block partials in order and
 // update the scalars (S[0] rho = r.z, or r.r without the V-cycle; S[2] r.r).
-// mode 0: after init (bb, rho); 1: alpha = rho / pq; 2: beta = rho_new / rho
-// and the convergence test on r.r (defer: the update left this iteration's x
-// term pending). part2 (NULL without the V-cycle): the r.z partials, blocks
+// mode 0: after init (bb, rho); 1: alpha = rho / pq, also kept in ring slot
+// `slot` of ah (the x terms are added later, see k_cg_xacc); 2: beta =
+// rho_new / rho and the convergence test on r.r. part2 (NULL without the V-cycle): the r.z partials, blocks
 // [blk0_2[s], blk0_2[s+1]) of system s, plus (part3 not NULL) the blocks
 // [r3[s].x, r3[s].y) of part3: for the large grids of the multigrid form, r.z
 // is the finest restriction's term plus the level-1 term (see k_mg_up0).
@@ -815,7 +809,7 @@ __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restr
                                                           const double* __restrict__ part,
                                                           const double* __restrict__ part2,
                                                           const int* __restrict__ blk0_2, double* __restrict__ st,
-                                                          int mode, double rtol, int defer,
+                                                          int mode, double rtol, double* __restrict__ ah, int slot,
                                                           const double* __restrict__ part3, const int2* __restrict__ r3,
                                                           const int* __restrict__ sys_split, int filter, int s0) {
   const int s = s0 + (int)blockIdx.x;
@@ -851,8 +845,8 @@ __global__ __launch_bounds__(kR_THREADS) void k_cg_reduce(const NpgGrid* __restr
       S[5] = v > 0.0 ? 1.0 : 0.0;
     } else if (mode == 1) {
       S[3] = (S[5] != 0.0 && v > 0.0) ? S[0] / v : 0.0;
+      ah[(s * 4 + c) * kCgDirs + slot] = S[3];  // this iteration's x term, added later
     } else {
-      S[7] = defer ? S[3] : 0.0;  // this iteration's x term, when the update left it pending
       if (S[5] != 0.0) {
         S[4] = S[0] > 0.0 ? rho[c] / S[0] : 0.0;
         S[0] = rho[c];
@@ -1711,8 +1705,8 @@ npg_status npg_cg_setup(npg_plan* P) {
   const int64_t n = P->n_grid_params;
   NPG_HIP(hipMalloc(&C.x, n * 4));
   NPG_HIP(hipMalloc(&C.r, n * 4));
-  NPG_HIP(hipMalloc(&C.p, n * 4));
-  NPG_HIP(hipMalloc(&C.q, n * 4));
+  for (auto& d : C.pd) NPG_HIP(hipMalloc(&d, n * 4));
+  NPG_HIP(hipMalloc(&C.ahist, 2 * (int64_t)P->n_sys * 4 * kCgDirs * 8));
   NPG_HIP(hipMalloc(&C.part, (int64_t)C.n_blocks * 4 * 8));
   NPG_HIP(hipMalloc(&C.st, 2 * (int64_t)P->n_sys * 4 * kS * 8));  // one block per solve
   NPG_HIP(hipMalloc(&C.active, P->n_sys * 4));
@@ -1759,7 +1753,10 @@ npg_status npg_cg_setup(npg_plan* P) {
 
 void npg_cg_free(npg_plan* P) {
   NpgCG& C = P->cg;
-  void* bufs[] = {C.x, C.r, C.p, C.q, C.part, C.st, C.active, C.blk_sys, C.blk_start, C.sys_blk0,
+  for (auto d : C.pd)
+    if (d) (void)hipFree(d);
+  if (C.ahist) (void)hipFree(C.ahist);
+  void* bufs[] = {C.x, C.r, C.part, C.st, C.active, C.blk_sys, C.blk_start, C.sys_blk0,
                   C.z, C.mgB, C.mgX, C.part2, C.mg_tasks, C.part3, C.r3, C.sys_split};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -1783,11 +1780,14 @@ void npg_cg_free(npg_plan* P) {
 // ---- the two solves ------------------------------------------------------------
 // Solve (I + lam L) x = b for every system (b and x distinct buffers in the
 // grid-block layout); solve `which` (0 first, 1 second) keeps its scalars in
-// its own block of C.st. Iteration k writes p_k into C.q for even k and into
-// C.p for odd k; the update of an even iteration leaves its x term pending
-// (p_k stays in C.q: later iterations write only the blocks of systems still
-// active), the next odd one adds both terms, and a term still pending when a
-// system stops is added by k_cg_flush at the end. An iteration launched after
+// its own block of C.st. Iteration k writes p_k into ring slot k mod
+// kCgDirs and its alpha into the same slot of the solve's alpha history; the
+// updates leave x alone, and after iterations kCgDirs-1, 2 kCgDirs-1, ...
+// k_cg_xacc adds the window's kCgDirs terms to x in one pass (p_k is
+// overwritten kCgDirs iterations later, after its window was added; later
+// iterations write only the blocks of systems still active, so a stopped
+// system's last terms stay in the ring), and k_cg_flush adds the terms still
+// pending when a system stops. An iteration launched after
 // every system of the solve has converged changes nothing (each work-group
 // returns on the system's device-side active flag), so the result does not
 // depend on how many iterations are launched past convergence: the eager
@@ -1802,6 +1802,8 @@ struct CgCtx {
   double* part2;
   const float* dir_src;
   double* st;
+  double* ah;  // the solve's alpha of each ring slot
+  Dirs dirs;
 };
 
 CgCtx cg_ctx(const npg_plan* P, int which) {
@@ -1817,28 +1819,31 @@ CgCtx cg_ctx(const npg_plan* P, int which) {
   c.part2 = c.mg ? C.part2 : nullptr;
   c.dir_src = c.mg ? C.z : C.r;  // p = z + beta p (z = r without the V-cycle)
   c.st = C.st + (size_t)which * P->n_sys * 4 * kS;
+  c.ah = C.ahist + (size_t)which * P->n_sys * 4 * kCgDirs;
+  for (int j = 0; j < kCgDirs; ++j) c.dirs.p[j] = C.pd[j];
   return c;
 }
 
 // The scalar update of the range's systems (filter -1), of those whose r.z is
 // split over the finest restriction and level 1 (filter 1), or of the others
 // (filter 0); see k_cg_reduce.
-void cg_reduce(npg_plan* P, const CgCtx& c, const CgGrp& G, int mode, int defer, int filter) {
+void cg_reduce(npg_plan* P, const CgCtx& c, const CgGrp& G, int mode, int k, int filter) {
   NpgCG& C = P->cg;
   hipLaunchKernelGGL(k_cg_reduce, dim3(G.s_hi - G.s_lo), dim3(kR_THREADS), 0, G.stream, P->d_g, C.sys_blk0,
-                     C.active, C.part, c.part2, C.sys_blk0, c.st, mode, P->cfg.cg_rtol, defer,
+                     C.active, C.part, c.part2, C.sys_blk0, c.st, mode, P->cfg.cg_rtol, c.ah, k % kCgDirs,
                      c.mg ? C.part3 : nullptr, c.mg ? C.r3 : nullptr, c.mg ? C.sys_split : nullptr, filter, G.s_lo);
 }
 
-// Iteration 0 treats C.q as its direction: the start writes p_0 = z_0 there
-// (large grids of the multigrid form, in the V-cycle's finest prolongation;
-// the other grids form it in k_cg_dir_ap from z with beta = 0).
+// Iteration 0 takes ring slot 0 as its direction: the start writes p_0 = z_0
+// there on the large grids of the multigrid form (in the V-cycle's finest
+// prolongation); the other grids form it in k_cg_dir_ap from z with beta = 0
+// and the old direction in the last slot, which k_cg_init sets to b.
 npg_status cg_start(npg_plan* P, const CgCtx& c, const CgGrp& G, const float* b) {
   NpgCG& C = P->cg;
   hipLaunchKernelGGL(k_cg_init, dim3(xcd_grid(G.b_hi - G.b_lo)), c.blk, 0, G.stream, P->d_g, G.b_hi, G.b_lo,
-                     C.blk_sys, C.blk_start, b, C.r, C.p, c.mg ? C.sys_split : nullptr, C.part);
+                     C.blk_sys, C.blk_start, b, C.r, C.pd[kCgDirs - 1], c.mg ? C.sys_split : nullptr, C.part);
   // r = b: the first V-cycle reads b (the split grids never store r = b)
-  if (c.mg) NPG_TRY_ST(mg_apply(P, G, b, C.z, 0, MgDir{C.p, C.q, c.st, 1}, nullptr));
+  if (c.mg) NPG_TRY_ST(mg_apply(P, G, b, C.z, 0, MgDir{C.pd[kCgDirs - 1], C.pd[0], c.st, 1}, nullptr));
   cg_reduce(P, c, G, 0, 0, -1);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
@@ -1851,32 +1856,29 @@ npg_status cg_iteration(npg_plan* P, const CgCtx& c, const CgGrp& G, const float
   hipStream_t s = G.stream;
   const dim3 grid(xcd_grid(G.b_hi - G.b_lo));
   const int nb = G.b_hi, lo = G.b_lo;
-  const bool odd = (k & 1) != 0;
-  float* p_old = odd ? C.q : C.p;
-  float* p_new = odd ? C.p : C.q;
+  float* p_old = C.pd[(k + kCgDirs - 1) % kCgDirs];
+  float* p_new = C.pd[k % kCgDirs];
+  float* p_next = C.pd[(k + 1) % kCgDirs];
   hipLaunchKernelGGL(k_cg_dir_ap, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active, c.st,
                      c.dir_src, p_old, p_new, C.part, (int)c.mg);
-  cg_reduce(P, c, G, 1, 0, -1);
-  // the first iteration reads r from b; the first odd one writes x from 0
-  const float* r_b = k == 0 ? b : nullptr;
-  if (k == 1)
-    hipLaunchKernelGGL(k_cg_update<2>, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active,
-                       c.st, x, r_b, C.r, p_new, p_old, C.part);
-  else if (odd)
-    hipLaunchKernelGGL(k_cg_update<1>, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active,
-                       c.st, x, r_b, C.r, p_new, p_old, C.part);
-  else
-    hipLaunchKernelGGL(k_cg_update<0>, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active,
-                       c.st, x, r_b, C.r, p_new, p_old, C.part);
+  cg_reduce(P, c, G, 1, k, -1);
+  // the first iteration reads r from b
+  hipLaunchKernelGGL(k_cg_update, grid, c.blk, 0, s, P->d_g, c.dv, nb, lo, C.blk_sys, C.blk_start, C.active, c.st,
+                     k == 0 ? b : nullptr, C.r, p_new, C.part);
+  // the last iteration of a window: its kCgDirs x terms (before the
+  // convergence test, so a system that stops here has them all in x)
+  if (k % kCgDirs == kCgDirs - 1)
+    hipLaunchKernelGGL(k_cg_xacc, dim3((unsigned)(4 * P->n_cu)), dim3(256), 0, s, P->d_g, G.s_lo, G.s_hi, C.active,
+                       c.ah, (int)(k == kCgDirs - 1), x, c.dirs);
   if (c.mg) {
     // large grids: beta (and the convergence test) before the prolongation,
-    // which writes their next direction over p_old (its x term is added by
-    // this iteration's update, the odd one); the other grids after it
-    const std::function<void()> beta = [&]() { cg_reduce(P, c, G, 2, (int)!odd, 1); };
-    NPG_TRY_ST(mg_apply(P, G, C.r, C.z, 1, MgDir{p_new, p_old, c.st, 0}, G.split ? beta : nullptr));
-    cg_reduce(P, c, G, 2, (int)!odd, 0);
+    // which writes their next direction into the next ring slot (its old
+    // direction's x term was added with its window); the other grids after it
+    const std::function<void()> beta = [&]() { cg_reduce(P, c, G, 2, k, 1); };
+    NPG_TRY_ST(mg_apply(P, G, C.r, C.z, 1, MgDir{p_new, p_next, c.st, 0}, G.split ? beta : nullptr));
+    cg_reduce(P, c, G, 2, k, 0);
   } else {
-    cg_reduce(P, c, G, 2, (int)!odd, -1);
+    cg_reduce(P, c, G, 2, k, -1);
   }
   NPG_HIP(hipGetLastError());
   return NPG_OK;
@@ -1914,7 +1916,7 @@ npg_status cg_iterations(npg_plan* P, const CgCtx& c, const float* b, float* x, 
 
 npg_status cg_finish(npg_plan* P, const CgCtx& c, const CgGrp& G, float* x) {
   hipLaunchKernelGGL(k_cg_flush, dim3((unsigned)(4 * P->n_cu)), dim3(256), 0, G.stream, P->d_g, G.s_lo, G.s_hi, c.st,
-                     x, P->cg.q);
+                     c.ah, x, c.dirs);
   NPG_HIP(hipGetLastError());
   return NPG_OK;
 }
