@@ -657,6 +657,17 @@ __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G,
   NPG_F_SWITCH(g, (update_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, r_in, r, p, part, blk)));
 }
 
+// Streaming float4 access that bypasses the caches' retention (the x passes
+// read each direction and x once and write x once per window).
+typedef float npg_nt4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ldnt(const float4* p) {
+  const npg_nt4 v = __builtin_nontemporal_load(reinterpret_cast<const npg_nt4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stnt(float4* p, float4 v) {
+  __builtin_nontemporal_store(npg_nt4{v.x, v.y, v.z, v.w}, reinterpret_cast<npg_nt4*>(p));
+}
+
 // The ring of directions, by slot (passed by value).
 struct Dirs {
   const float* p[kCgDirs];
@@ -683,14 +694,14 @@ __global__ __launch_bounds__(256) void k_cg_xacc(const NpgGrid* __restrict__ G, 
     if (g.F == 4 && g.poff % 4 == 0) {
       float4* X = reinterpret_cast<float4*>(x + g.poff);
       for (int64_t v = tid; v < g.nodes; v += stride) {
-        float4 xv = first ? make_float4(0.f, 0.f, 0.f, 0.f) : X[v];
+        float4 xv = first ? make_float4(0.f, 0.f, 0.f, 0.f) : ldnt(X + v);
 #pragma unroll
         for (int j = 0; j < kCgDirs; ++j) {
-          const float4 pv = reinterpret_cast<const float4*>(d.p[j] + g.poff)[v];
+          const float4 pv = ldnt(reinterpret_cast<const float4*>(d.p[j] + g.poff) + v);
           xv = make_float4(fmaf(a[j][0], pv.x, xv.x), fmaf(a[j][1], pv.y, xv.y), fmaf(a[j][2], pv.z, xv.z),
                            fmaf(a[j][3], pv.w, xv.w));
         }
-        X[v] = xv;
+        stnt(X + v, xv);
       }
       continue;
     }
@@ -732,15 +743,15 @@ __global__ __launch_bounds__(256) void k_cg_flush(const NpgGrid* __restrict__ G,
     if (g.F == 4 && g.poff % 4 == 0) {  // one node (float4) per thread and pass
       float4* X = reinterpret_cast<float4*>(x + g.poff);
       for (int64_t v = tid; v < g.nodes; v += stride) {
-        float4 xv = stored ? X[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 xv = stored ? ldnt(X + v) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int j = 0; j < kCgDirs; ++j) {
           if (j >= pend) break;
-          const float4 pv = reinterpret_cast<const float4*>(d.p[j] + g.poff)[v];
+          const float4 pv = ldnt(reinterpret_cast<const float4*>(d.p[j] + g.poff) + v);
           xv = make_float4(fmaf(a[j][0], pv.x, xv.x), fmaf(a[j][1], pv.y, xv.y), fmaf(a[j][2], pv.z, xv.z),
                            fmaf(a[j][3], pv.w, xv.w));
         }
-        X[v] = xv;
+        stnt(X + v, xv);
       }
       continue;
     }
