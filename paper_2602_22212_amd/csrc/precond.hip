@@ -14,15 +14,14 @@
 // One CG iteration is two streaming kernels (plus the V-cycle):
 //   k_cg_dir_ap:  p = z + beta p, and p.(A p) with A p formed on the fly from
 //                 z and the old p at the 6 neighbours (p is written, A p is not)
-//   k_cg_update:  r -= alpha A p (A p recomputed from p) and r.r; x is
-//                 updated every second iteration only, with both pending terms
-//                 (x += alpha_{k-1} p_{k-1}, then x += alpha_k p_k: the same
-//                 float32 operations in the same order as one update per
-//                 iteration), the older direction read from the other
-//                 ping-pong buffer
-// i.e. 7.5 vector passes per iteration on average (z, p, p | p, r, r, and
-// every second iteration p_{k-1}, x, x) instead of 10 with A p stored. A
-// term left pending when a system stops is added by a flush pass.
+//   k_cg_update:  r -= alpha A p (A p recomputed from p) and r.r
+// and every kCgDirs iterations one pass (k_cg_xacc) adds the window's x
+// terms, x += alpha_j p_j in iteration order (the same float32 operations in
+// the same order as one update per iteration), the directions kept in a ring
+// of kCgDirs buffers: 6 + (kCgDirs + 2) / kCgDirs vector passes per iteration
+// (z, p, p | p, r, r, and the x pass) instead of 10 with A p stored and x
+// updated every iteration. The terms left when a system stops are added by
+// a flush pass.
 // A p = p + lam * sum over existing neighbours of (p_n - p_nb): sums of
 // differences keep the float32 rounding proportional to |A p|, not to
 // (1 + 12 lam)|p|.
@@ -174,8 +173,9 @@ __device__ __forceinline__ Nb neighbours(uint32_t n, int R, const FastDiv& fR, c
   return b;
 }
 
-// r = p = b and the b.b partials. x is not written: the first odd update
-// writes it without reading it, or k_cg_flush when a solve stops earlier.
+// r = p = b and the b.b partials. x is not written: the first window's x
+// pass writes it without reading it, or k_cg_flush when a solve stops before
+// the first window ends.
 template <int FV, int F = (FV < 0 ? -FV : FV)>
 __device__ void init_body(const NpgGrid& g, int64_t n0, const float* b, float* r, float* p, double* part, int blk) {
   double acc[4] = {0, 0, 0, 0};
@@ -194,7 +194,7 @@ __device__ void init_body(const NpgGrid& g, int64_t n0, const float* b, float* r
 }
 
 // p_new = r + beta p_old; pq partial with A p_new formed from r and p_old at
-// the neighbours. p_old and p_new are different buffers (ping-pong), so no
+// the neighbours. p_old and p_new are different ring slots, so no
 // work-group ever reads a value another one has already overwritten.
 template <int FV, int F = (FV < 0 ? -FV : FV)>
 __device__ void dir_ap_body(const NpgGrid& g, const FastDiv& fR, const FastDiv& fR2, int64_t n0, const double* st,
