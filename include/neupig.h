@@ -150,7 +150,12 @@ npg_status npg_param_count(const npg_config* cfg, int64_t* count_host);
  *   pts_dev      [sum N_t][3] all frames' points, frame after frame
  *   frame_off_host [T+1] int64 offsets of each frame into pts, off[0] = 0,
  *                        strictly increasing (every frame has >= 1 point)
- *   stream       hipStream_t (as void*) all work of this plan is enqueued on
+ *   stream       hipStream_t (as void*) all work of this plan is ordered on:
+ *                        enqueued on it, except that the CG solves run the
+ *                        grids before the largest on a second stream of the
+ *                        plan's own (cg_one_stream = 0), forked from this one
+ *                        by an event and joined back into it before the solve
+ *                        returns, so this stream still orders every result
  * Copies the inputs (they may be freed after return), validates them (finite
  * values, sizes), builds the static interpolation and scatter tables, and
  * allocates all workspace. Parameters start at zero and Adam at step 0.
