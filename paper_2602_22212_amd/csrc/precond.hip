@@ -1387,7 +1387,7 @@ __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, con
   zm_walk_post<Raw2, Raw2>(
       g, t,
       [&](int64_t m, int s, int zz) { return Raw2{B[m], E[(zz >> 1) * nh2 + cols.pxy[s]]}; },
-      [&](int64_t m) { return Raw2{B[m], FIRST ? make_float4(0.f, 0.f, 0.f, 0.f) : Po[m]}; },
+      [&](int64_t m) { return Raw2{B[m], FIRST ? make_float4(0.f, 0.f, 0.f, 0.f) : ldnt(Po + m)}; },
       [&](const Raw2& v, int s, int zz) {
         const float f = (zz == 0 || zz == R - 1) ? cols.fbd[s] : cols.fin[s];
         return f4add(f4scale(f, v.a), v.b);
@@ -1397,7 +1397,9 @@ __device__ void mg_up0_zm(const NpgGrid& g, const Tile& t, const MgTask* tk, con
         const float4 ax = f4axpy(lam, lap, xc);
         const float f = (zz == 0 || zz == R - 1) ? cols.fbd[0] : cols.fin[0];
         const float4 zv = lam == 0.f ? bc : f4axpy(f, f4sub(bc, ax), xc);
-        Pn[n] = FIRST ? zv : f4fma(e.b, be, zv);  // p = z + beta p_old (p = z first)
+        // p = z + beta p_old (p = z first); both directions streamed with the
+        // nontemporal hint (the grid's directions far exceed the caches)
+        stnt(Pn + n, FIRST ? zv : f4fma(e.b, be, zv));
       },
       [](int) {});
 }
