@@ -555,6 +555,18 @@ __device__ void zm_pap(const NpgGrid& g, const Tile& t, const float* p, double* 
 }
 
 
+// Streaming float4 access with the nontemporal hint, for the streams of a
+// grid's vectors that no other work-group reads back soon (every grid vector
+// of the large grids far exceeds the caches).
+typedef float npg_nt4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ldnt(const float4* p) {
+  const npg_nt4 v = __builtin_nontemporal_load(reinterpret_cast<const npg_nt4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stnt(float4* p, float4 v) {
+  __builtin_nontemporal_store(npg_nt4{v.x, v.y, v.z, v.w}, reinterpret_cast<npg_nt4*>(p));
+}
+
 __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, const float* r_in, float* r,
                           const float* p, double* part, int blk) {
   float al[4];
@@ -566,7 +578,7 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
   float4* Rr = reinterpret_cast<float4*>(r + g.poff);
   double acc[4] = {0, 0, 0, 0};
   zm_walk<Raw1, Raw1>(
-      g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw1{Ri[n]}; },
+      g, t, [&](int64_t n) { return Raw1{Pp[n]}; }, [&](int64_t n) { return Raw1{ldnt(Ri + n)}; },
       [&](const Raw1& v) { return v.a; },
       [&](int64_t n, const float4& lap, const float4& pc, const Raw1& e) {
         float4 rv = e.a;
@@ -574,7 +586,7 @@ __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int
         rv.y = fmaf(-al[1], fmaf(lam, lap.y, pc.y), rv.y);
         rv.z = fmaf(-al[2], fmaf(lam, lap.z, pc.z), rv.z);
         rv.w = fmaf(-al[3], fmaf(lam, lap.w, pc.w), rv.w);
-        Rr[n] = rv;
+        stnt(Rr + n, rv);
         acc[0] += (double)rv.x * rv.x;
         acc[1] += (double)rv.y * rv.y;
         acc[2] += (double)rv.z * rv.z;
@@ -655,17 +667,6 @@ __global__ __launch_bounds__(kB) void k_cg_update(const NpgGrid* __restrict__ G,
     return;
   }
   NPG_F_SWITCH(g, (update_body<FF>(g, dv.r[s], dv.r2[s], blk_start[blk], st, s, r_in, r, p, part, blk)));
-}
-
-// Streaming float4 access that bypasses the caches' retention (the x passes
-// read each direction and x once and write x once per window).
-typedef float npg_nt4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ldnt(const float4* p) {
-  const npg_nt4 v = __builtin_nontemporal_load(reinterpret_cast<const npg_nt4*>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void stnt(float4* p, float4 v) {
-  __builtin_nontemporal_store(npg_nt4{v.x, v.y, v.z, v.w}, reinterpret_cast<npg_nt4*>(p));
 }
 
 // The ring of directions, by slot (passed by value).
