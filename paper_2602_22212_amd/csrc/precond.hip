@@ -334,6 +334,18 @@ __device__ __forceinline__ float4 from_right(const float4& edge, const float4& v
                      dpp_from_right(edge.w, v.w));
 }
 
+// Streaming float4 access with the nontemporal hint, for the streams of a
+// grid's vectors that no other work-group reads back soon (every grid vector
+// of the large grids far exceeds the caches).
+typedef float npg_nt4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ldnt(const float4* p) {
+  const npg_nt4 v = __builtin_nontemporal_load(reinterpret_cast<const npg_nt4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void stnt(float4* p, float4 v) {
+  __builtin_nontemporal_store(npg_nt4{v.x, v.y, v.z, v.w}, reinterpret_cast<npg_nt4*>(p));
+}
+
 struct Raw1 {
   float4 a;
 };
@@ -554,18 +566,6 @@ __device__ void zm_pap(const NpgGrid& g, const Tile& t, const float* p, double* 
   store_partials<4>(acc, part, blk);
 }
 
-
-// Streaming float4 access with the nontemporal hint, for the streams of a
-// grid's vectors that no other work-group reads back soon (every grid vector
-// of the large grids far exceeds the caches).
-typedef float npg_nt4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ldnt(const float4* p) {
-  const npg_nt4 v = __builtin_nontemporal_load(reinterpret_cast<const npg_nt4*>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void stnt(float4* p, float4 v) {
-  __builtin_nontemporal_store(npg_nt4{v.x, v.y, v.z, v.w}, reinterpret_cast<npg_nt4*>(p));
-}
 
 __device__ void zm_update(const NpgGrid& g, const Tile& t, const double* st, int s, const float* r_in, float* r,
                           const float* p, double* part, int blk) {
